@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""LJ pair-interactions/s and MD steps/s on the 1,048,576-particle LJ fluid
+(density 0.8, T = 1.0, r_c = 2.5, skin 0.3, dt = 0.005), autotuned vs the
+plain fixed linked-cell configuration, on one GPU.
+
+A step is one velocity-Verlet time step of the whole hot path: integration
+and staging, the cell/list rebuild when due (with the skin check), the force
+pass, and -- for the autotuned run -- any tuning phase that falls inside the
+timed steps.  Inputs are resident on the GPU before timing starts.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_PAIR = 26  # FP32 flops per interacting unordered pair (d 3, r2 5, 1/r2 1, s2 1, q 2, phi 5, f 3, F_i/F_j 6)
+PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (published)
+PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return platform.processor() or "unknown"
+
+
+def make_cfg(M, n, box, kind, steps):
+    c = M.config_default(n, float(box[0]))
+    c.precision = M.MD_FP32
+    c.skin = 0.3
+    c.max_neighbors = 128
+    if kind == "plain":
+        c.container = M.MD_CONTAINER_LC
+        c.csf = 1.0
+        c.newton3 = M.MD_N3L_OFF
+        c.rebuild_interval = 10
+    elif kind == "vl":
+        c.container = M.MD_CONTAINER_VL
+        c.rebuild_interval = 10
+    else:  # autotuned, Predictive strategy
+        c.container = M.MD_CONTAINER_LC
+        c.rebuild_interval = 10
+        c.autotune = M.MD_TUNE_PREDICTIVE
+        c.tune_interval = max(1, steps // 4)
+        c.tune_trial_steps = 10
+        c.total_steps_hint = steps
+    return c
+
+
+def run(M, d, kind, steps, warmup, probe_steps=50):
+    import numpy as np
+    import torch
+    n = d["pos"].shape[1]
+    dev = "cuda"
+    cfg = make_cfg(M, n, d["box"], kind, steps)
+    h = M.md_create(cfg)
+    pos = torch.tensor(d["pos"], dtype=torch.float64, device=dev)
+    vel = torch.tensor(d["vel"], dtype=torch.float32, device=dev)
+    force = torch.zeros((3, n), dtype=torch.float32, device=dev)
+    typ = torch.zeros(n, dtype=torch.int32, device=dev)
+    ids = torch.arange(n, dtype=torch.int32, device=dev)
+    lj = torch.tensor([1.0, 1.0], dtype=torch.float64, device=dev)
+    im = torch.ones(1, dtype=torch.float64, device=dev)
+    M.md_build_cells(h, pos, vel, force, typ, ids)
+    M.md_build_neighbors(h, pos, typ)
+    M.md_compute_forces(h, pos, typ, lj, force)
+    if warmup > 0:
+        M.md_step(h, pos, vel, force, typ, ids, im, lj, 0.005, warmup)
+    torch.cuda.synchronize()
+    every = 10
+    logt = torch.zeros((steps // every, 4), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M.md_step(h, pos, vel, force, typ, ids, im, lj, 0.005, steps, every, logt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    lg = logt.cpu().numpy()
+    pairs_mean = float(lg[:, 3].mean()) if len(lg) else float("nan")
+    cnt = M.md_get_counters(h)
+    cfg_now = M.md_get_config(h)
+    # force-kernel time of the configuration in use, HIP events on the same stream
+    M.md_timing(h, True)
+    M.md_step(h, pos, vel, force, typ, ids, im, lj, 0.005, probe_steps)
+    torch.cuda.synchronize()
+    tm = M.md_timing(h, False)
+    force_ms = tm["force_ms"] / max(tm["force_passes"], 1)
+    build_ms = tm["build_ms"] / max(tm["builds"], 1) if tm["builds"] else None
+    E = lg[:, 0] - lg[:, 3] * (-0.016316891136) + lg[:, 1]
+    res = dict(kind=kind, steps=steps, wall_s=wall, ms_per_step=1e3 * wall / steps,
+               steps_per_s=steps / wall, pairs_per_step=pairs_mean,
+               pairs_per_s=pairs_mean * steps / wall,
+               force_kernel_ms=force_ms, build_ms=build_ms, counters=cnt,
+               final_config=dict(container=int(cfg_now.container), newton3=int(cfg_now.newton3),
+                                 csf=float(cfg_now.csf), rebuild_interval=int(cfg_now.rebuild_interval)),
+               energy_per_particle_first_last=[float(E[0] / n), float(E[-1] / n)] if len(E) else None)
+    h.close()
+    return res
+
+
+def cpu_baseline(d, target_s=12.0):
+    import numpy as np
+    from oracle import oracle as orc
+    pos, box = d["pos"], d["box"]
+    n = pos.shape[1]
+    p = orc.single()
+    rng = np.random.default_rng(7)
+    m = 128
+    t0 = time.perf_counter()
+    _, cnt = orc.forces_rows(pos, box, p, rng.choice(n, m, replace=False))
+    t = time.perf_counter() - t0
+    m2 = int(min(n, max(m, m * target_s / max(t, 1e-3))))
+    rows = rng.choice(n, m2, replace=False)
+    t0 = time.perf_counter()
+    _, cnt = orc.forces_rows(pos, box, p, rows)
+    t = time.perf_counter() - t0
+    # each row sums the pairs of one particle; a whole-system evaluation sees
+    # every unordered pair twice
+    pairs = float(cnt.sum()) / 2.0
+    return {"value": pairs / t, "unit": "pair-interactions/s", "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": "brute-force FP64 force rows of %d of %d particles (every row scans all %d), "
+                      "%.1f s on %s" % (m2, n, n, t, cpu_model()),
+            "pair_checks_per_s": float(m2) * (n - 1) / t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--ncell", type=int, default=64, help="FCC cells per side (64 -> 1,048,576 particles)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2505_03438_amd import mdlj as M
+    from paper_2505_03438_amd import workloads as W
+    M.lib()
+    assert torch.cuda.is_available(), "no GPU"
+    d = W.homogeneous_fluid(ncell=args.ncell)
+    n = d["pos"].shape[1]
+    log("workload: %d particles, L = %.4f" % (n, d["box"][0]))
+    auto = run(M, d, "auto", args.steps, args.warmup)
+    log("autotuned: %.3f ms/step, %.3e pairs/s, config %s" % (auto["ms_per_step"], auto["pairs_per_s"],
+                                                             auto["final_config"]))
+    plain = None
+    if not args.no_plain:
+        plain = run(M, d, "plain", args.steps, args.warmup)
+        log("plain LC: %.3f ms/step, %.3e pairs/s" % (plain["ms_per_step"], plain["pairs_per_s"]))
+    achieved = FLOPS_PER_PAIR * auto["pairs_per_step"] / (auto["force_kernel_ms"] * 1e-3)
+    kname = {0: "k_lc_f32", 1: "k_vl_f32", 2: "k_cluster_f32"}[auto["final_config"]["container"]]
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32, "traffic": None, "kernel": kname,
+            "kernel_ms": auto["force_kernel_ms"],
+            "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(d)
+        log("cpu oracle: %.3e pairs/s on %d threads" % (cpu["value"], cpu["cores"]))
+    res = {
+        "metric": "LJ pair-interactions/sec and MD steps/sec, 1M-particle fluid, autotuned vs plain",
+        "value": auto["pairs_per_s"],
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": auto["ms_per_step"],
+        "steps_per_s": auto["steps_per_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "lj-fluid-%d" % n, "n": n, "density": 0.8, "T": 1.0, "rc": 2.5,
+                   "skin": 0.3, "dt": 0.005, "positions": "f64", "pair_arithmetic": "f32",
+                   "strategy": "predictive", "parallelism": "single-gpu"},
+        "autotuned": auto,
+        "plain": plain,
+        "speedup_vs_plain": (auto["pairs_per_s"] / plain["pairs_per_s"]) if plain else None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,265 @@
+/*
+ * mdlj.h -- C-ABI of the MI355X (gfx950) short-range Lennard-Jones MD library.
+ *
+ * The library is a particle container in the sense of the paper (Sec. 2.2:
+ * a black-box container for a cutoff-based particle simulator): it finds
+ * interacting pairs (linked cells, Verlet lists with a skin, cluster-pair
+ * lists), evaluates the cutoff Lennard-Jones 12-6 forces, advances the
+ * Stormer-Verlet (velocity form) integrator, differentiates a force-matching
+ * loss, and selects its own algorithmic configuration at run time (Sec. 2.2.5
+ * tuning phases, Sec. 5.1 Predictive strategy).
+ *
+ * Conventions for every call:
+ *   - All particle arrays are caller-owned DEVICE buffers on the handle's
+ *     device, contiguous, SoA: pos is double[3][n] (x row, then y, then z),
+ *     positions in [0, box[d]).  vel and force are real[3][n] where real is
+ *     float for MD_FP32 and double for MD_FP64 (md_config.precision).
+ *     type and ids are int32[n]; types lie in [0, n_types).
+ *   - lj is a DEVICE array double[2 * n_types]: per-type epsilon
+ *     (eps_0 .. eps_{nt-1}) then per-type sigma (sig_0 .. sig_{nt-1}).  Pair
+ *     parameters follow Lorentz-Berthelot mixing: sig_ab = (sig_a + sig_b)/2,
+ *     eps_ab = sqrt(eps_a eps_b).  The per-pair cutoffs are fixed in the
+ *     config (rc2) and are not functions of lj.
+ *   - stream is a hipStream_t passed as void*; NULL means the default stream.
+ *     Every call only enqueues work on that stream and returns without
+ *     waiting, unless its comment says it synchronises.
+ *   - Every int-returning call returns MD_OK (0) or a negative MD_ERR_* code;
+ *     md_last_error() then describes the failure.  Nothing throws across the
+ *     ABI.  Invalid arguments are rejected before any work is enqueued.
+ *   - A pair interacts iff r^2 < rc2[type_i][type_j] (strict), with r the
+ *     periodic minimum-image distance (requires box >= 2 (r_c + skin)).
+ */
+#ifndef MDLJ_H
+#define MDLJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MD_MAX_TYPES 2
+
+/* return codes */
+#define MD_OK 0
+#define MD_ERR_INVALID_ARG (-1)
+#define MD_ERR_BOX_TOO_SMALL (-2)
+#define MD_ERR_LIST_OVERFLOW (-3)
+#define MD_ERR_NONFINITE (-4)
+#define MD_ERR_HIP (-5)
+#define MD_ERR_NOT_BUILT (-6)
+#define MD_ERR_NO_DEVICE (-7)
+
+/* precision of the pair arithmetic and of vel/force storage */
+#define MD_FP32 0
+#define MD_FP64 1
+
+/* containers (Sec. 2.2.1) */
+#define MD_CONTAINER_LC 0 /* linked cells                                  */
+#define MD_CONTAINER_VL 1 /* Verlet lists with skin, rebuilt every R steps  */
+#define MD_CONTAINER_CL 2 /* cluster-pair lists (8-particle clusters)       */
+
+/* traversal (Sec. 2.2.2, Table 1: N3L column) */
+#define MD_N3L_OFF 0 /* each pair evaluated from both sides, gather only  */
+#define MD_N3L_ON 1  /* each pair once, j-side scattered with atomics     */
+
+/* autotuning strategy (Sec. 2.2.5 Full Search, Sec. 5.1 Predictive) */
+#define MD_TUNE_OFF 0
+#define MD_TUNE_FULL 1
+#define MD_TUNE_PREDICTIVE 2
+
+/* md_status flag bits */
+#define MD_FLAG_LIST_OVERFLOW 1u  /* a neighbour row exceeded max_neighbors   */
+#define MD_FLAG_SKIN_EXCEEDED 2u  /* a particle moved >= skin/2 since a build */
+#define MD_FLAG_NONFINITE 4u      /* a non-finite force or position appeared  */
+
+typedef struct md_handle md_handle;
+
+typedef struct md_config {
+    int64_t n;             /* number of particles, >= 0                        */
+    int32_t n_types;       /* 1 .. MD_MAX_TYPES                                */
+    int32_t precision;     /* MD_FP32 (default) or MD_FP64                     */
+    double box[3];         /* periodic box lengths                             */
+    double rc2[MD_MAX_TYPES * MD_MAX_TYPES]; /* squared cutoff per type pair,
+                              row-major [a][b], symmetric; only the first
+                              n_types x n_types block (row stride n_types) is
+                              read                                             */
+    double skin;           /* Verlet skin >= 0                                 */
+    double csf;            /* cell size factor in (0, 1]: cell side >=
+                              csf (r_c,max + skin), stretched to fit the box  */
+    int32_t container;     /* MD_CONTAINER_*                                   */
+    int32_t newton3;       /* MD_N3L_OFF / MD_N3L_ON                           */
+    int32_t rebuild_interval; /* R >= 1: rebuild cells and lists every R steps */
+    int32_t max_neighbors; /* Verlet-list row capacity                         */
+    int32_t autotune;      /* MD_TUNE_*; on: md_step selects the configuration */
+    int32_t tune_interval; /* steps between tuning phases                      */
+    int32_t tune_trial_steps; /* steps each trialled configuration runs        */
+    int32_t total_steps_hint; /* expected steps of the run (retrial gap)       */
+} md_config;
+
+/* Fill *cfg with defaults for n particles in a cubic box of side L:
+ * one type, r_c = 2.5, skin 0.3, CSF 1, Verlet lists, gather-only, R = 10,
+ * FP32, no tuning.  Returns MD_OK or MD_ERR_INVALID_ARG (cfg NULL). */
+int md_config_default(md_config *cfg, int64_t n, double L);
+
+/* Create a handle on the current HIP device: validates cfg and allocates all
+ * internal buffers (cells, lists, staging, reduction scratch).  *out is set
+ * to NULL on failure.  Errors: MD_ERR_INVALID_ARG, MD_ERR_BOX_TOO_SMALL
+ * (box[d] < 2 (r_c,max + skin)), MD_ERR_NO_DEVICE, MD_ERR_HIP. */
+int md_create(const md_config *cfg, md_handle **out);
+
+/* Release the handle and its device memory (synchronises its device). */
+void md_destroy(md_handle *h);
+
+/* Linked cells (Sec. 2.2.1): bin the particles into cells of side
+ * >= csf (r_c,max + skin) stretched to fit the box, by a counting sort, and
+ * reorder pos, vel, force, type and ids IN PLACE into cell order (cells in
+ * x-fastest linear order; within a cell by ascending ids).  ids carries each
+ * particle's caller-defined identity through every reordering.  vel and force
+ * may be NULL (then they are not permuted).  Also stages the positions for
+ * the pair kernels and records them as the reference for the skin check. */
+int md_build_cells(md_handle *h, double *pos, void *vel, void *force,
+                   int32_t *type, int32_t *ids, void *stream);
+
+/* Verlet lists / cluster-pair lists (Sec. 2.2.1): for the current container,
+ * build the candidate structure from the cells: every pair with
+ * r^2 < (r_c,max + skin)^2 at the current positions (decided in FP64).  No-op
+ * for linked cells.  pos and type must be in the order md_build_cells left.
+ * Overflow of max_neighbors sets MD_FLAG_LIST_OVERFLOW (see md_status). */
+int md_build_neighbors(md_handle *h, const double *pos, const int32_t *type,
+                       void *stream);
+
+/* Forces (Sec. 2.1): force[i] = sum_j f_ij over pairs within the cutoff,
+ * f_ij = 24 eps q (2q - 1) / r^2 * d_ij, q = (sig^2/r^2)^3, with the current
+ * container.  pos/type in cell order; force written in the same order.
+ * If out (DEVICE double[4]) is not NULL it receives
+ * { U = sum_{i<j} 4 eps q (q - 1), W = sum_{i<j} r . f, n_pairs, 0 }. */
+int md_compute_forces(md_handle *h, const double *pos, const int32_t *type,
+                      const double *lj, void *force, double *out, void *stream);
+
+/* nsteps of velocity Verlet (Stormer-Verlet, Sec. 2.1):
+ *   v += dt/2 F/m; x += dt v (wrapped into the box); F = F(x); v += dt/2 F/m
+ * with cells/lists rebuilt every R steps (and whenever a particle has moved
+ * >= skin/2 since the last build: the affected steps are recomputed).  With
+ * autotune on, tuning phases trial configurations and keep the fastest.
+ * force must hold F(pos) on entry (call md_compute_forces first).  The arrays
+ * stay in cell order, reordered in place at each rebuild.  inv_mass is a
+ * DEVICE double[n_types].  If energy_every > 0 and log is not NULL (DEVICE
+ * double[nsteps / energy_every][4]), after every energy_every-th step it
+ * receives { U, K = 1/2 sum m v^2, W, n_pairs }.  Synchronises the stream
+ * once per rebuild interval (to read the skin check). */
+int md_step(md_handle *h, double *pos, void *vel, void *force, int32_t *type,
+            int32_t *ids, const double *inv_mass, const double *lj, double dt,
+            int32_t nsteps, int32_t energy_every, double *log, void *stream);
+
+/* Adjoint of md_compute_forces: given grad_force = dL/dF (real[3][n], cell
+ * order), writes grad_pos = dL/dx (DEVICE double[3][n]) and grad_lj = dL/dlj
+ * (DEVICE double[2 n_types], same layout as lj), the exact derivatives of the
+ * truncated forces at fixed cutoffs:
+ *   per pair, J = phi I + 2 (dphi/dr2) d d^T acts on (g_i - g_j);
+ *   dphi/deps_ab = phi/eps_ab, dphi/dsig_ab = 144 eps q (4q - 1)/(sig r^2),
+ * chained through the mixing rule.  Uses the current container's pairs. */
+int md_forces_backward(md_handle *h, const double *pos, const int32_t *type,
+                       const double *lj, const void *grad_force,
+                       double *grad_pos, double *grad_lj, void *stream);
+
+/* Live simulation statistics (Sec. 4) over bins that mimic a CSF-1 cell
+ * (side >= r_c,max + skin) of the given positions: out (HOST double[8]) =
+ * { mean, std/mean, median, max particles per bin, n_bins, n_empty_bins,
+ *   n_compute_units, skin }.  Synchronises the stream. */
+int md_live_stats(md_handle *h, const double *pos, double *out, void *stream);
+
+/* Copy the current Verlet lists out (Verlet-list container only): counts
+ * (DEVICE int32[n]) gets each particle's number of entries, rows (DEVICE
+ * int32[n][max_per_row], row-major) its entries, both in the cell order the
+ * arrays are in.  Rows longer than max_per_row are truncated.  For
+ * inspection and tests. */
+int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows,
+                     int32_t max_per_row, void *stream);
+
+/* Sticky device-side condition flags (MD_FLAG_* bits) accumulated since the
+ * last call, then cleared.  Synchronises the handle's work. */
+int md_status(md_handle *h, uint32_t *flags);
+
+/* Configuration the handle currently uses (after tuning decisions). */
+int md_get_config(md_handle *h, md_config *cfg);
+
+/* Counters since md_create: out (HOST int64[6]) = { rebuilds,
+ * forced_rebuilds (skin exceeded), tuning_phases, trials, current config
+ * index in the tuning space, neighbour-list entries at the last build }. */
+int md_get_counters(md_handle *h, int64_t *out);
+
+/* Kernel-class timing of md_step with HIP events recorded on the caller's
+ * stream around every force pass and every rebuild (the build and force
+ * times the tuning phases weigh, Sec. 2.2.5).  enable = 1 resets the totals
+ * and starts recording, 0 stops.  If out (HOST double[4]) is not NULL it
+ * receives { force_ms, force_passes, build_ms, builds } accumulated so far
+ * (this waits for the recorded events). */
+int md_timing(md_handle *h, int32_t enable, double *out);
+
+/* Thread-local description of the last failing call ("" if none). */
+const char *md_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* Batched systems: n_sys independent periodic systems advanced together
+ * (one launch per phase for all systems).  Particles of system s occupy
+ * [offsets[s], offsets[s+1]) of every particle array, and offsets (HOST
+ * int64[n_sys + 1]) is non-decreasing from 0.  boxes is HOST double[3 n_sys].
+ * The per-pair cutoffs, skin, csf and precision come from cfg (cfg->n and
+ * cfg->box are ignored).  Only linked cells, gather-only, FP32 or FP64. */
+typedef struct md_batch md_batch;
+
+int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_t *offsets,
+                    const double *boxes, md_batch **out);
+void md_batch_destroy(md_batch *b);
+
+/* Bin every system into its own cells and reorder the arrays in place (cell
+ * order within each system's range; systems keep their ranges). */
+int md_batch_build_cells(md_batch *b, double *pos, void *vel, void *force,
+                         int32_t *type, int32_t *ids, void *stream);
+
+/* Forces of every system; out (DEVICE double[4 n_sys] or NULL) receives each
+ * system's { U, W, n_pairs, 0 }. */
+int md_batch_compute_forces(md_batch *b, const double *pos, const int32_t *type,
+                            const double *lj, void *force, double *out,
+                            void *stream);
+
+/* nsteps of velocity Verlet for every system (rebuilding every R steps).
+ * use_graph != 0 captures one rebuild interval into a HIP graph and replays
+ * it; 0 launches every kernel directly. */
+int md_batch_step(md_batch *b, double *pos, void *vel, void *force,
+                  int32_t *type, int32_t *ids, const double *inv_mass,
+                  const double *lj, double dt, int32_t nsteps,
+                  int32_t use_graph, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Configuration-selection engine, usable on its own with externally measured
+ * scores (host only; needs no GPU).  Sec. 2.2.5 Full Search and Sec. 5.1
+ * Predictive: trial all in the first two phases; predict each configuration
+ * by the line through its last two (phase, score) points (clamped below at
+ * half its last score); trial those predicted within rel_threshold of the
+ * best prediction (inclusive) or not trialled for ceil(total_phases/4)
+ * phases; blacklist those measured above blacklist_factor x the phase's best;
+ * choose the lowest score (ties: lower index). */
+typedef struct md_tuner md_tuner;
+
+int md_tuner_create(int32_t strategy, int32_t n_configs, int32_t total_phases,
+                    double rel_threshold, double blacklist_factor,
+                    md_tuner **out);
+void md_tuner_destroy(md_tuner *t);
+/* Start the next phase; trial[n_configs] (HOST) gets 1 for configurations to
+ * trial, 0 otherwise.  Returns the number to trial (>= 0) or an error. */
+int md_tuner_begin_phase(md_tuner *t, int32_t *trial);
+/* Report the measured score (lower is better) of a trialled configuration. */
+int md_tuner_report(md_tuner *t, int32_t config, double score);
+/* Finish the phase: returns the chosen configuration index (>= 0) or an
+ * error if a trialled configuration has no score. */
+int md_tuner_end_phase(md_tuner *t);
+/* blacklisted[n_configs] (HOST) gets 1 for blacklisted configurations. */
+int md_tuner_blacklist(md_tuner *t, int32_t *blacklisted);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDLJ_H */

@@ -1,0 +1,990 @@
+// C-ABI of libmdlj: handle lifecycle, argument validation, cell geometry,
+// the rebuild policy of md_step (rebuild every R steps; steps that ran with a
+// structure a particle had outgrown by skin/2 are recomputed) and the
+// autotuned configuration switching.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "md_internal.h"
+#include "tuner.h"
+
+namespace mdlj {
+
+static thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ") in " + what;
+    return MD_ERR_HIP;
+}
+
+void launch_zero(void *p, int64_t bytes, hipStream_t s);
+
+// Cell geometry for csf and the cutoffs: n_d = floor(L_d / (csf r_l)) (>= 1),
+// side L_d / n_d, stencil reach ceil(r_l / side) with duplicate periodic
+// images of the same cell removed.
+int make_geom(const md_config &c, double csf, Geom &g)
+{
+    memset(&g, 0, sizeof(g));
+    int nt = c.n_types;
+    double rcmax2 = 0.0;
+    for (int a = 0; a < nt; a++)
+        for (int b = 0; b < nt; b++) rcmax2 = std::max(rcmax2, c.rc2[a * nt + b]);
+    double rl = sqrt(rcmax2) + c.skin;
+    g.rl2 = rl * rl;
+    g.nt = nt;
+    for (int d = 0; d < 3; d++) {
+        if (!(c.box[d] >= 2.0 * rl))
+            return fail(MD_ERR_BOX_TOO_SMALL, "box[" + std::to_string(d) + "] = " + std::to_string(c.box[d]) +
+                                                  " < 2 (r_c + skin) = " + std::to_string(2.0 * rl));
+        double side_min = csf * rl;
+        double ndd = floor(c.box[d] / side_min);
+        if (ndd > 4096.0) ndd = 4096.0;
+        int nd = ndd < 1.0 ? 1 : (int)ndd;
+        g.nc[d] = nd;
+        g.L[d] = c.box[d];
+        g.inv_w[d] = (double)nd / c.box[d];
+        g.S[d] = 4294967296.0 / c.box[d];
+        double w = c.box[d] / nd;
+        int reach = 1;
+        while (reach * w < rl) reach++;
+        if (2 * reach + 1 > kMaxOfs) return fail(MD_ERR_INVALID_ARG, "cell size factor too small (needs csf >= 0.5)");
+        int k = 0;
+        for (int o = -reach; o <= reach; o++) {
+            int sft = ((o % nd) + nd) % nd;
+            bool dup = false;
+            for (int m = 0; m < k; m++) dup |= g.ofs[d][m] == sft;
+            if (!dup) g.ofs[d][k++] = sft;
+        }
+        g.nofs[d] = k;
+    }
+    int64_t ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+    if (ncell > (int64_t)1 << 30) return fail(MD_ERR_INVALID_ARG, "too many cells");
+    g.ncell = (int)ncell;
+    g.ry = (float)(c.box[1] / c.box[0]);
+    g.rz = (float)(c.box[2] / c.box[0]);
+    g.iso = (c.box[0] == c.box[1] && c.box[1] == c.box[2]) ? 1 : 0;
+    double u = c.box[0] / 4294967296.0;
+    g.rl2_lo = (float)(g.rl2 / (u * u) * (1.0 - kBand));
+    g.rl2_hi = (float)(g.rl2 / (u * u) * (1.0 + kBand));
+    double h = 0.5 * c.skin;
+    g.disp2 = c.skin > 0.0 ? (float)(h * h * (1.0 - 1e-4) / (u * u)) : INFINITY;
+    return MD_OK;
+}
+
+}  // namespace mdlj
+
+using namespace mdlj;
+
+// ------------------------------------------------------------------ handle
+
+struct md_handle {
+    md_config cfg;           // current configuration (tuning may change it)
+    md_config base;          // configuration at creation
+    int device = 0;
+    Geom g;
+    Buffers b;
+    int64_t n = 0;
+    int64_t ncell_cap = 0;   // allocated cell-array entries
+    int64_t scan_cap = 0;
+    bool built = false;      // cells (and lists) valid for the staged positions
+    int age = 0;             // integrator steps since the last build
+    int64_t rebuilds = 0, forced = 0, phases = 0, trials = 0, list_entries = 0;
+    int32_t config_index = -1;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+    // kernel-class timing (md_timing)
+    struct TPair {
+        hipEvent_t a, b;
+        int kind;  // 0 force, 1 build
+    };
+    bool timing = false;
+    std::vector<hipEvent_t> tpool;
+    size_t tnext = 0;
+    std::vector<TPair> tpend;
+    double tsum[4] = {0, 0, 0, 0};
+    // autotuning
+    mdlj::Tuner *tuner = nullptr;
+    std::vector<md_config> space;
+    int64_t steps_done = 0;       // md_step steps since creation
+    uint32_t sticky = 0;          // flag bits already read back from the device
+    bool truncated = false;       // the current lists overflowed max_neighbors
+    bool replay_no_log = false;   // the next block replays: its first step's log entry is done
+    int64_t next_phase = 0;       // step index of the next tuning phase
+};
+
+static size_t real_size(const md_config &c) { return c.precision == MD_FP64 ? 8 : 4; }
+
+static void free_buffers(md_handle *h)
+{
+    Buffers &b = h->b;
+    void *ptrs[] = {b.cell_id, b.slot, b.perm, b.cell_count, b.cell_start, b.cell_sorted, b.scan_blocks,
+                    b.tmp_pos, b.tmp_vel, b.tmp_force, b.tmp_type, b.tmp_ids, b.stage, b.stage_ref,
+                    b.nbr, b.nbr_count, b.partials, b.kpart, b.flags, b.tab, b.facc, b.cl_start,
+                    b.cl_count, b.cl_bbox, b.cl_nbr, b.cl_nbr_count, b.snap_pos, b.snap_vel,
+                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (b.host_flags) (void)hipHostFree(b.host_flags);
+    b = Buffers();
+}
+
+template <typename T>
+static int dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    return MD_OK;
+}
+
+static int dalloc_bytes(void **p, size_t bytes)
+{
+    *p = nullptr;
+    hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    return MD_OK;
+}
+
+// Cell arrays sized for the geometry g (grown on demand, e.g. when tuning
+// switches to a smaller cell size factor).
+static int ensure_cells(md_handle *h, const Geom &g)
+{
+    int64_t need = (int64_t)g.ncell + 1;
+    if (need <= h->ncell_cap) return MD_OK;
+    if (h->b.cell_count) (void)hipFree(h->b.cell_count);
+    if (h->b.cell_start) (void)hipFree(h->b.cell_start);
+    if (h->b.scan_blocks) (void)hipFree(h->b.scan_blocks);
+    h->b.cell_count = h->b.cell_start = h->b.scan_blocks = nullptr;
+    int rc;
+    if ((rc = dalloc(&h->b.cell_count, need))) return rc;
+    if ((rc = dalloc(&h->b.cell_start, need))) return rc;
+    int64_t sc = scan_scratch_size(need) + 64;
+    if ((rc = dalloc(&h->b.scan_blocks, sc))) return rc;
+    h->ncell_cap = need;
+    return MD_OK;
+}
+
+static int ensure_list(md_handle *h, int64_t maxn)
+{
+    if (maxn <= h->b.nbr_cap && h->b.nbr) return MD_OK;
+    if (h->b.nbr) (void)hipFree(h->b.nbr);
+    h->b.nbr = nullptr;
+    int rc = dalloc(&h->b.nbr, (size_t)maxn * (size_t)std::max<int64_t>(h->n, 1));
+    if (rc) return rc;
+    h->b.nbr_cap = maxn;
+    return MD_OK;
+}
+
+static int validate_config(const md_config *c)
+{
+    if (!c) return fail(MD_ERR_INVALID_ARG, "config is NULL");
+    if (c->n < 0 || c->n > (int64_t)INT32_MAX / 3) return fail(MD_ERR_INVALID_ARG, "n out of range");
+    if (c->n_types < 1 || c->n_types > MD_MAX_TYPES) return fail(MD_ERR_INVALID_ARG, "n_types must be 1 or 2");
+    if (c->precision != MD_FP32 && c->precision != MD_FP64) return fail(MD_ERR_INVALID_ARG, "bad precision");
+    for (int d = 0; d < 3; d++)
+        if (!(c->box[d] > 0.0) || !isfinite(c->box[d])) return fail(MD_ERR_INVALID_ARG, "box must be positive");
+    int nt = c->n_types;
+    for (int a = 0; a < nt; a++)
+        for (int b = 0; b < nt; b++) {
+            double v = c->rc2[a * nt + b];
+            if (!(v > 0.0) || !isfinite(v)) return fail(MD_ERR_INVALID_ARG, "rc2 must be positive");
+            if (v != c->rc2[b * nt + a]) return fail(MD_ERR_INVALID_ARG, "rc2 must be symmetric");
+        }
+    if (!(c->skin >= 0.0) || !isfinite(c->skin)) return fail(MD_ERR_INVALID_ARG, "skin must be >= 0");
+    if (!(c->csf >= 0.5 && c->csf <= 1.0)) return fail(MD_ERR_INVALID_ARG, "csf must lie in [0.5, 1]");
+    if (c->container != MD_CONTAINER_LC && c->container != MD_CONTAINER_VL && c->container != MD_CONTAINER_CL)
+        return fail(MD_ERR_INVALID_ARG, "bad container");
+    if (c->newton3 != MD_N3L_OFF && c->newton3 != MD_N3L_ON) return fail(MD_ERR_INVALID_ARG, "bad newton3");
+    if (c->container == MD_CONTAINER_CL && c->newton3 != MD_N3L_OFF)
+        return fail(MD_ERR_INVALID_ARG, "cluster lists are gather-only (newton3 = MD_N3L_OFF)");
+    if (c->rebuild_interval < 1) return fail(MD_ERR_INVALID_ARG, "rebuild_interval must be >= 1");
+    if (c->max_neighbors < 1 || c->max_neighbors > 4096) return fail(MD_ERR_INVALID_ARG, "max_neighbors out of range");
+    if (c->autotune != MD_TUNE_OFF && c->autotune != MD_TUNE_FULL && c->autotune != MD_TUNE_PREDICTIVE)
+        return fail(MD_ERR_INVALID_ARG, "bad autotune");
+    if (c->autotune != MD_TUNE_OFF && (c->tune_interval < 1 || c->tune_trial_steps < 2))
+        return fail(MD_ERR_INVALID_ARG, "tune_interval >= 1 and tune_trial_steps >= 2 required");
+    return MD_OK;
+}
+
+extern "C" int md_config_default(md_config *cfg, int64_t n, double L)
+{
+    if (!cfg) return fail(MD_ERR_INVALID_ARG, "cfg is NULL");
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->n = n;
+    cfg->n_types = 1;
+    cfg->precision = MD_FP32;
+    cfg->box[0] = cfg->box[1] = cfg->box[2] = L;
+    for (int k = 0; k < MD_MAX_TYPES * MD_MAX_TYPES; k++) cfg->rc2[k] = 6.25;
+    cfg->skin = 0.3;
+    cfg->csf = 1.0;
+    cfg->container = MD_CONTAINER_VL;
+    cfg->newton3 = MD_N3L_OFF;
+    cfg->rebuild_interval = 10;
+    cfg->max_neighbors = 128;
+    cfg->autotune = MD_TUNE_OFF;
+    cfg->tune_interval = 500;
+    cfg->tune_trial_steps = 10;
+    cfg->total_steps_hint = 1000;
+    return MD_OK;
+}
+
+
+extern "C" int md_create(const md_config *cfg, md_handle **out)
+{
+    if (!out) return fail(MD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = validate_config(cfg);
+    if (rc) return rc;
+    Geom g;
+    if ((rc = make_geom(*cfg, cfg->csf, g))) return rc;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MD_ERR_NO_DEVICE, "no HIP device");
+    md_handle *h = new md_handle();
+    h->cfg = *cfg;
+    h->base = *cfg;
+    h->n = cfg->n;
+    h->g = g;
+    (void)hipGetDevice(&h->device);
+    int64_t n = std::max<int64_t>(cfg->n, 1);
+    size_t rs = real_size(*cfg);
+    Buffers &b = h->b;
+#define ALLOC(expr)                   \
+    do {                              \
+        if ((rc = (expr))) {          \
+            free_buffers(h);          \
+            delete h;                 \
+            return rc;                \
+        }                             \
+    } while (0)
+    ALLOC(dalloc(&b.cell_id, n));
+    ALLOC(dalloc(&b.slot, n));
+    ALLOC(dalloc(&b.perm, n));
+    ALLOC(dalloc(&b.cell_sorted, n));
+    ALLOC(dalloc(&b.tmp_pos, 3 * n));
+    ALLOC(dalloc_bytes(&b.tmp_vel, 3 * n * rs));
+    ALLOC(dalloc_bytes(&b.tmp_force, 3 * n * rs));
+    ALLOC(dalloc(&b.tmp_type, n));
+    ALLOC(dalloc(&b.tmp_ids, n));
+    ALLOC(dalloc(&b.stage, n));
+    ALLOC(dalloc(&b.stage_ref, n));
+    ALLOC(dalloc(&b.nbr_count, n));
+    ALLOC(dalloc(&b.partials, (size_t)kMaxPartials * 4));
+    ALLOC(dalloc(&b.kpart, (size_t)kMaxPartials));
+    ALLOC(dalloc(&b.gpart, (size_t)kMaxPartials * 8));
+    ALLOC(dalloc(&b.flags, 4));
+    ALLOC(dalloc(&b.tab, 1));
+    ALLOC(ensure_cells(h, g));
+    if (cfg->container == MD_CONTAINER_VL || cfg->autotune != MD_TUNE_OFF) ALLOC(ensure_list(h, cfg->max_neighbors));
+#undef ALLOC
+    if (hipHostMalloc((void **)&b.host_flags, 4 * sizeof(uint32_t), 0) != hipSuccess) {
+        free_buffers(h);
+        delete h;
+        return fail(MD_ERR_HIP, "hipHostMalloc failed");
+    }
+    (void)hipMemset(b.flags, 0, 4 * sizeof(int32_t));
+    int32_t init[4] = {0, INT32_MAX, 0, 0};
+    (void)hipMemcpy(b.flags, init, sizeof(init), hipMemcpyHostToDevice);
+    (void)hipEventCreate(&h->ev0);
+    (void)hipEventCreate(&h->ev1);
+    (void)hipEventCreate(&h->ev2);
+    if (cfg->autotune != MD_TUNE_OFF) {
+        tuning_space(*cfg, h->space);
+        int total_phases = std::max(1, (int)((cfg->total_steps_hint + cfg->tune_interval - 1) / cfg->tune_interval));
+        h->tuner = new Tuner(cfg->autotune, (int)h->space.size(), total_phases, 2.0, 10.0);
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        md_destroy(h);
+        return fail(MD_ERR_HIP, "device initialisation failed");
+    }
+    *out = h;
+    return MD_OK;
+}
+
+extern "C" void md_destroy(md_handle *h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    free_buffers(h);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->ev2) (void)hipEventDestroy(h->ev2);
+    for (hipEvent_t e : h->tpool) (void)hipEventDestroy(e);
+    delete h->tuner;
+    delete h;
+}
+
+// ------------------------------------------------------------------ building
+
+static int check_handle(md_handle *h)
+{
+    if (!h) return fail(MD_ERR_INVALID_ARG, "handle is NULL");
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return MD_OK;
+}
+
+// Counting sort into cells + gather into cell order + copy back in place.
+static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, int32_t *type, int32_t *ids,
+                            hipStream_t s)
+{
+    const Geom &g = h->g;
+    Buffers &b = h->b;
+    int n = (int)h->n;
+    size_t rs = real_size(h->cfg);
+    int rc = ensure_cells(h, g);
+    if (rc) return rc;
+    launch_fill_i32(b.cell_count, 0, g.ncell, s);
+    launch_cell_hist(n, pos, g, b.cell_id, b.slot, b.cell_count, b.flags, s);
+    launch_scan(b.cell_count, b.cell_start, g.ncell, b.scan_blocks, s);
+    launch_scatter(n, b.cell_id, b.slot, b.cell_start, b.perm, s);
+    launch_cell_sort(g.ncell, b.cell_start, ids, b.perm, s);
+    launch_gather(n, h->cfg.precision, b.perm, pos, vel, force, type, ids, b.tmp_pos, b.tmp_vel, b.tmp_force,
+                  b.tmp_type, b.tmp_ids, b.cell_id, b.cell_sorted, g, b.stage, b.stage_ref, s);
+    if (n > 0) {
+        MD_HIP(hipMemcpyAsync(pos, b.tmp_pos, 3 * (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (vel) MD_HIP(hipMemcpyAsync(vel, b.tmp_vel, 3 * (size_t)n * rs, hipMemcpyDeviceToDevice, s));
+        if (force) MD_HIP(hipMemcpyAsync(force, b.tmp_force, 3 * (size_t)n * rs, hipMemcpyDeviceToDevice, s));
+        MD_HIP(hipMemcpyAsync(type, b.tmp_type, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        MD_HIP(hipMemcpyAsync(ids, b.tmp_ids, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    launch_fill_i32(b.flags + 1, INT32_MAX, 1, s);
+    h->rebuilds++;
+    h->age = 0;
+    h->built = true;
+    return MD_OK;
+}
+
+namespace mdlj {
+int cluster_build_impl(md_handle *h, const double *pos, hipStream_t s);  // clusters.hip
+}
+
+static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
+{
+    Buffers &b = h->b;
+    int n = (int)h->n;
+    if (h->cfg.container == MD_CONTAINER_VL) {
+        int rc = ensure_list(h, h->cfg.max_neighbors);
+        if (rc) return rc;
+        launch_vl_build(n, b.stage, b.cell_start, b.cell_sorted, pos, h->g, h->cfg.newton3, b.nbr, b.nbr_count,
+                        n, h->cfg.max_neighbors, b.flags, s);
+    } else if (h->cfg.container == MD_CONTAINER_CL) {
+        return cluster_build_impl(h, pos, s);
+    }
+    return MD_OK;
+}
+
+static int check_particles(md_handle *h, const void *pos, const void *type)
+{
+    if (h->n > 0 && (!pos || !type)) return fail(MD_ERR_INVALID_ARG, "pos and type must not be NULL");
+    return MD_OK;
+}
+
+extern "C" int md_build_cells(md_handle *h, double *pos, void *vel, void *force, int32_t *type, int32_t *ids,
+                              void *stream)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if ((rc = check_particles(h, pos, type))) return rc;
+    if (h->n > 0 && !ids) return fail(MD_ERR_INVALID_ARG, "ids must not be NULL");
+    return build_cells_impl(h, pos, vel, force, type, ids, (hipStream_t)stream);
+}
+
+extern "C" int md_build_neighbors(md_handle *h, const double *pos, const int32_t *type, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if ((rc = check_particles(h, pos, type))) return rc;
+    if (!h->built) return fail(MD_ERR_NOT_BUILT, "md_build_cells must be called first");
+    hipStream_t s = (hipStream_t)stream;
+    launch_stage((int)h->n, pos, type, h->g, h->b.stage, s);
+    return build_lists_impl(h, pos, s);
+}
+
+// ------------------------------------------------------------------ forces
+
+static ForceArgs force_args(md_handle *h, const double *pos, const int32_t *type, void *force, bool energy)
+{
+    ForceArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = (int)h->n;
+    a.precision = h->cfg.precision;
+    a.container = h->cfg.container;
+    a.newton3 = h->cfg.newton3;
+    a.energy = energy;
+    a.pos = pos;
+    a.type = type;
+    a.stage = h->b.stage;
+    a.cell_start = h->b.cell_start;
+    a.cell_sorted = h->b.cell_sorted;
+    a.nbr = h->b.nbr;
+    a.nbr_count = h->b.nbr_count;
+    a.nbr_ld = h->n;
+    a.cl_start = h->b.cl_start;
+    a.cl_count = h->b.cl_count;
+    a.cl_nbr = h->b.cl_nbr;
+    a.cl_nbr_count = h->b.cl_nbr_count;
+    a.cl_ld = h->b.n_clusters_max;
+    a.n_clusters = h->b.n_clusters_max;
+    a.tab = h->b.tab;
+    a.force = force;
+    a.partials = h->b.partials;
+    a.flags = h->b.flags;
+    return a;
+}
+
+static int forces_impl(md_handle *h, const double *pos, const int32_t *type, void *force, bool energy,
+                       hipStream_t s)
+{
+    ForceArgs a = force_args(h, pos, type, force, energy);
+    if (force_blocks(a) > kMaxPartials) return fail(MD_ERR_INVALID_ARG, "too many particles for the reduction");
+    if (h->cfg.newton3 == MD_N3L_ON) launch_zero(force, 3 * h->n * (int64_t)real_size(h->cfg), s);
+    launch_force(a, h->g, s);
+    return MD_OK;
+}
+
+extern "C" int md_compute_forces(md_handle *h, const double *pos, const int32_t *type, const double *lj,
+                                 void *force, double *out, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if ((rc = check_particles(h, pos, type))) return rc;
+    if (!lj || (h->n > 0 && !force)) return fail(MD_ERR_INVALID_ARG, "lj and force must not be NULL");
+    if (!h->built) return fail(MD_ERR_NOT_BUILT, "md_build_cells (and md_build_neighbors) must be called first");
+    hipStream_t s = (hipStream_t)stream;
+    launch_prepare_tab(lj, h->cfg.rc2, h->g, h->b.tab, s);
+    launch_stage((int)h->n, pos, type, h->g, h->b.stage, s);
+    if ((rc = forces_impl(h, pos, type, force, out != nullptr, s))) return rc;
+    if (out) {
+        ForceArgs a = force_args(h, pos, type, force, true);
+        launch_reduce_out(h->b.partials, force_blocks(a), h->cfg.newton3 == MD_N3L_OFF, out, s);
+    }
+    return MD_OK;
+}
+
+// ------------------------------------------------------------------ time stepping
+
+struct StepCtx {
+    double *pos;
+    void *vel, *force;
+    int32_t *type, *ids;
+    const double *inv_mass, *lj;
+    double dt;
+    int32_t nsteps, energy_every;
+    double *log;
+    hipStream_t s;
+};
+
+static IntegrateArgs integ_args(md_handle *h, const StepCtx &c, int kick_prev, int start, int energy, int step)
+{
+    IntegrateArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = (int)h->n;
+    a.precision = h->cfg.precision;
+    a.pos = c.pos;
+    a.vel = c.vel;
+    a.force = c.force;
+    a.type = c.type;
+    a.inv_mass = c.inv_mass;
+    a.hdt = 0.5 * c.dt;
+    a.dt = c.dt;
+    a.kick_prev = kick_prev;
+    a.start = start;
+    a.energy = energy;
+    a.step_index = step;
+    a.stage = h->b.stage;
+    a.stage_ref = h->b.stage_ref;
+    a.flags = h->b.flags;
+    a.kpart = h->b.kpart;
+    return a;
+}
+
+static bool logs_step(const StepCtx &c, int s)  // log after step s (0-based)?
+{
+    return c.log && c.energy_every > 0 && (s + 1) % c.energy_every == 0;
+}
+
+// Events of the kernel-class timing: a pool reused once the recorded pairs
+// have been read back (at every block-end synchronisation).
+static hipEvent_t timing_event(md_handle *h)
+{
+    if (!h->timing) return nullptr;
+    if (h->tnext == h->tpool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->tpool.push_back(e);
+    }
+    return h->tpool[h->tnext++];
+}
+
+static void timing_collect(md_handle *h)
+{
+    for (const auto &p : h->tpend) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            h->tsum[2 * p.kind] += ms;
+            h->tsum[2 * p.kind + 1] += 1.0;
+        }
+    }
+    h->tpend.clear();
+    h->tnext = 0;
+}
+
+static int rebuild(md_handle *h, const StepCtx &c)
+{
+    int rc = build_cells_impl(h, c.pos, c.vel, c.force, c.type, c.ids, c.s);
+    if (rc) return rc;
+    return build_lists_impl(h, c.pos, c.s);
+}
+
+// One time step s: finish step s-1 (second kick, kinetic energy and, unless
+// suppressed, its log entry), start step s (kick, drift, stage, skin check),
+// rebuild when the structure is due (or when force_rebuild), then forces.
+static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, bool log_prev_ok = true)
+{
+    bool log_prev = s > 0 && logs_step(c, s - 1) && log_prev_ok;
+    launch_integrate(integ_args(h, c, s > 0, 1, log_prev, s), h->g, c.s);
+    if (log_prev) {
+        ForceArgs fa = force_args(h, c.pos, c.type, c.force, true);
+        launch_log_entry(h->b.partials, force_blocks(fa), h->cfg.newton3 == MD_N3L_OFF, h->b.kpart,
+                         integrate_blocks((int)h->n), c.log + 4 * (s / c.energy_every - 1), c.s);
+    }
+    h->age++;
+    if (force_rebuild || h->age >= h->cfg.rebuild_interval) {
+        hipEvent_t e0 = timing_event(h), e1 = nullptr;
+        if (e0) MD_HIP(hipEventRecord(e0, c.s));
+        int rc = rebuild(h, c);
+        if (rc) return rc;
+        if (e0 && (e1 = timing_event(h))) {
+            MD_HIP(hipEventRecord(e1, c.s));
+            h->tpend.push_back({e0, e1, 1});
+        }
+    }
+    hipEvent_t e0 = timing_event(h), e1 = nullptr;
+    if (e0) MD_HIP(hipEventRecord(e0, c.s));
+    int rc = forces_impl(h, c.pos, c.type, c.force, logs_step(c, s), c.s);
+    if (e0 && (e1 = timing_event(h))) {
+        MD_HIP(hipEventRecord(e1, c.s));
+        h->tpend.push_back({e0, e1, 0});
+    }
+    return rc;
+}
+
+static int snapshot(md_handle *h, const StepCtx &c, bool restore)
+{
+    Buffers &b = h->b;
+    size_t n = (size_t)h->n;
+    size_t rs = real_size(h->cfg);
+    int rc;
+    if (!b.snap_pos) {
+        if ((rc = dalloc(&b.snap_pos, 3 * n))) return rc;
+        if ((rc = dalloc_bytes(&b.snap_vel, 3 * n * rs))) return rc;
+        if ((rc = dalloc_bytes(&b.snap_force, 3 * n * rs))) return rc;
+        if ((rc = dalloc(&b.snap_type, n))) return rc;
+        if ((rc = dalloc(&b.snap_ids, n))) return rc;
+    }
+    if (n == 0) return MD_OK;
+    auto cp = [&](void *dst, const void *src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c.s);
+    };
+    if (!restore) {
+        MD_HIP(cp(b.snap_pos, c.pos, 3 * n * 8));
+        MD_HIP(cp(b.snap_vel, c.vel, 3 * n * rs));
+        MD_HIP(cp(b.snap_force, c.force, 3 * n * rs));
+        MD_HIP(cp(b.snap_type, c.type, n * 4));
+        MD_HIP(cp(b.snap_ids, c.ids, n * 4));
+    } else {
+        MD_HIP(cp(c.pos, b.snap_pos, 3 * n * 8));
+        MD_HIP(cp(c.vel, b.snap_vel, 3 * n * rs));
+        MD_HIP(cp(c.force, b.snap_force, 3 * n * rs));
+        MD_HIP(cp(c.type, b.snap_type, n * 4));
+        MD_HIP(cp(c.ids, b.snap_ids, n * 4));
+    }
+    return MD_OK;
+}
+
+// Read the device flags (synchronises the stream).
+static int read_flags(md_handle *h, hipStream_t s, int32_t out[2])
+{
+    MD_HIP(hipMemcpyAsync(h->b.host_flags, h->b.flags, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MD_HIP(hipStreamSynchronize(s));
+    out[0] = (int32_t)h->b.host_flags[0];
+    out[1] = (int32_t)h->b.host_flags[1];
+    timing_collect(h);
+    return MD_OK;
+}
+
+// Run one block of steps starting at s0: a rebuild can only happen at the
+// block's first step (after its integration, when the structure is due); the
+// block then runs until the step before the next due rebuild, or s_end - 1.
+// Afterwards the device flags are read.  If the skin check fired at a step v
+// whose forces used the block's structure, the block is replayed from its
+// snapshot (deterministically, same structure) up to v - 1 and rebuilt right
+// after the integration of v.  If the list overflowed at the block's rebuild,
+// the list grows and the block is replayed.  *next = first step not yet done.
+static int run_block(md_handle *h, const StepCtx &c, int s0, int s_end, int *next)
+{
+    int R = h->cfg.rebuild_interval;
+    int age0 = h->age;
+    bool rebuild_first = age0 + 1 >= R;
+    int len = rebuild_first ? R : R - age0 - 1;
+    int last = std::min(s_end - 1, s0 + std::max(len, 1) - 1);
+    int rc;
+    if ((rc = snapshot(h, c, false))) return rc;
+    launch_fill_i32(h->b.flags + 1, INT32_MAX, 1, c.s);
+    bool no_log_first = h->replay_no_log;
+    h->replay_no_log = false;
+    for (int st = s0; st <= last; st++)
+        if ((rc = one_step(h, c, st, false, st != s0 || !no_log_first))) return rc;
+    int32_t f[2];
+    if ((rc = read_flags(h, c.s, f))) return rc;
+    int v = f[1];
+    int first_used = rebuild_first ? s0 + 1 : s0;  // first step whose forces used the checked structure
+    bool overflow = (f[0] & MD_FLAG_LIST_OVERFLOW) != 0;
+    if (overflow && h->cfg.container == MD_CONTAINER_VL && h->cfg.max_neighbors < 4096) {
+        h->sticky |= (uint32_t)f[0] & ~MD_FLAG_LIST_OVERFLOW;
+        h->cfg.max_neighbors = std::min(4096, h->cfg.max_neighbors * 3 / 2 + 8);
+        if ((rc = ensure_list(h, h->cfg.max_neighbors))) return rc;
+        launch_fill_i32(h->b.flags, 0, 1, c.s);
+        if ((rc = snapshot(h, c, true))) return rc;
+        h->age = R;  // replay the block with a rebuild at its first step
+        *next = s0;
+        h->replay_no_log = true;
+        return MD_OK;
+    }
+    if (v >= first_used && v <= last) {
+        if ((rc = snapshot(h, c, true))) return rc;
+        h->age = age0;
+        for (int st = s0; st < v; st++)
+            if ((rc = one_step(h, c, st, false, st != s0))) return rc;
+        if ((rc = one_step(h, c, v, true, v != s0))) return rc;
+        h->forced++;
+        *next = v + 1;
+        return MD_OK;
+    }
+    *next = last + 1;
+    return MD_OK;
+}
+
+static int finish_steps(md_handle *h, const StepCtx &c)
+{
+    bool log_last = logs_step(c, c.nsteps - 1);
+    launch_integrate(integ_args(h, c, 1, 0, log_last, c.nsteps), h->g, c.s);
+    if (log_last) {
+        ForceArgs fa = force_args(h, c.pos, c.type, c.force, true);
+        launch_log_entry(h->b.partials, force_blocks(fa), h->cfg.newton3 == MD_N3L_OFF, h->b.kpart,
+                         integrate_blocks((int)h->n), c.log + 4 * (c.nsteps / c.energy_every - 1), c.s);
+    }
+    return MD_OK;
+}
+
+int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next);
+int apply_config(md_handle *h, const md_config &nc);
+static int run_steps(md_handle *h, const StepCtx &c, int s0, int s1);
+
+static int run_steps(md_handle *h, const StepCtx &c, int s0, int s1)
+{
+    int s = s0;
+    h->replay_no_log = false;
+    while (s < s1) {
+        int next = s;
+        int rc = run_block(h, c, s, s1, &next);
+        if (rc) return rc;
+        s = next;
+    }
+    return MD_OK;
+}
+
+extern "C" int md_step(md_handle *h, double *pos, void *vel, void *force, int32_t *type, int32_t *ids,
+                       const double *inv_mass, const double *lj, double dt, int32_t nsteps, int32_t energy_every,
+                       double *log, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if ((rc = check_particles(h, pos, type))) return rc;
+    if (h->n > 0 && (!vel || !force || !ids)) return fail(MD_ERR_INVALID_ARG, "vel, force, ids must not be NULL");
+    if (!inv_mass || !lj) return fail(MD_ERR_INVALID_ARG, "inv_mass and lj must not be NULL");
+    if (nsteps < 0) return fail(MD_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(MD_ERR_INVALID_ARG, "dt must be positive");
+    if (energy_every < 0) return fail(MD_ERR_INVALID_ARG, "energy_every must be >= 0");
+    if (nsteps == 0) return MD_OK;
+    StepCtx c{pos, vel, force, type, ids, inv_mass, lj, dt, nsteps, energy_every, log, (hipStream_t)stream};
+    launch_prepare_tab(lj, h->cfg.rc2, h->g, h->b.tab, c.s);
+    // lists truncated since the last look (a build before this call overflowed):
+    // grow them, rebuild and recompute the entry forces
+    int32_t f0[2];
+    if ((rc = read_flags(h, c.s, f0))) return rc;
+    if (f0[0] & MD_FLAG_LIST_OVERFLOW) {
+        h->sticky |= (uint32_t)f0[0];
+        h->truncated = true;
+        launch_fill_i32(h->b.flags, 0, 1, c.s);
+    }
+    if (h->truncated && h->cfg.container == MD_CONTAINER_VL) {
+        h->cfg.max_neighbors = std::min(4096, h->cfg.max_neighbors * 2);
+        if ((rc = ensure_list(h, h->cfg.max_neighbors))) return rc;
+        h->built = false;
+        h->truncated = false;
+        if ((rc = rebuild(h, c))) return rc;
+        if ((rc = forces_impl(h, c.pos, c.type, c.force, false, c.s))) return rc;
+        int32_t f1[2];
+        if ((rc = read_flags(h, c.s, f1))) return rc;
+        if (f1[0] & MD_FLAG_LIST_OVERFLOW) h->truncated = true;
+        if (h->truncated) return fail(MD_ERR_LIST_OVERFLOW, "neighbour rows exceed max_neighbors after growth");
+    }
+    if (!h->built) {
+        if ((rc = rebuild(h, c))) return rc;
+    }
+    int s = 0;
+    while (s < nsteps) {
+        int s_stop = nsteps;
+        if (h->tuner) {
+            if (h->steps_done + s >= h->next_phase) {
+                int next = s;
+                if ((rc = run_tuning_phase(h, c, s, &next))) return rc;
+                s = next;
+                continue;
+            }
+            s_stop = (int)std::min<int64_t>(nsteps, h->next_phase - h->steps_done);
+        }
+        if ((rc = run_steps(h, c, s, s_stop))) return rc;
+        s = s_stop;
+    }
+    h->steps_done += nsteps;
+    return finish_steps(h, c);
+}
+
+
+// ------------------------------------------------------------------ adjoint
+
+extern "C" int md_forces_backward(md_handle *h, const double *pos, const int32_t *type, const double *lj,
+                                  const void *grad_force, double *grad_pos, double *grad_lj, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if ((rc = check_particles(h, pos, type))) return rc;
+    if (!lj || !grad_lj || (h->n > 0 && (!grad_force || !grad_pos)))
+        return fail(MD_ERR_INVALID_ARG, "lj, grad_force, grad_pos and grad_lj must not be NULL");
+    if (!h->built) return fail(MD_ERR_NOT_BUILT, "md_build_cells must be called first");
+    if (adjoint_blocks((int)h->n) > kMaxPartials) return fail(MD_ERR_INVALID_ARG, "too many particles");
+    hipStream_t s = (hipStream_t)stream;
+    launch_prepare_tab(lj, h->cfg.rc2, h->g, h->b.tab, s);
+    launch_stage((int)h->n, pos, type, h->g, h->b.stage, s);
+    AdjointArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = (int)h->n;
+    a.precision = h->cfg.precision;
+    a.pos = pos;
+    a.type = type;
+    a.stage = h->b.stage;
+    a.cell_start = h->b.cell_start;
+    a.cell_sorted = h->b.cell_sorted;
+    a.tab = h->b.tab;
+    a.lj = lj;
+    a.grad_force = grad_force;
+    a.grad_pos = grad_pos;
+    a.gpart = h->b.gpart;
+    a.flags = h->b.flags;
+    launch_adjoint(a, h->g, s);
+    launch_adjoint_finish(h->b.gpart, h->n > 0 ? adjoint_blocks((int)h->n) : 0, lj, h->cfg.n_types, grad_lj, s);
+    return MD_OK;
+}
+
+// ------------------------------------------------------------------ statistics, status
+
+extern "C" int md_live_stats(md_handle *h, const double *pos, double *out, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!out || (h->n > 0 && !pos)) return fail(MD_ERR_INVALID_ARG, "pos and out must not be NULL");
+    Geom g;
+    if ((rc = make_geom(h->cfg, 1.0, g))) return rc;
+    if ((rc = ensure_cells(h, g))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    launch_fill_i32(h->b.cell_count, 0, g.ncell, s);
+    launch_bin_counts((int)h->n, pos, g, h->b.cell_count, s);
+    std::vector<int32_t> cnt(g.ncell);
+    MD_HIP(hipMemcpyAsync(cnt.data(), h->b.cell_count, g.ncell * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MD_HIP(hipStreamSynchronize(s));
+    // the histogram cells now hold counts, not a valid structure
+    h->built = false;
+    double sum = 0.0;
+    int64_t mx = 0, empty = 0;
+    for (int32_t v : cnt) {
+        sum += v;
+        mx = std::max<int64_t>(mx, v);
+        empty += v == 0;
+    }
+    int64_t nb = (int64_t)cnt.size();
+    double mean = sum / (double)nb;
+    double var = 0.0;
+    for (int32_t v : cnt) var += ((double)v - mean) * ((double)v - mean);
+    var /= (double)nb;
+    std::sort(cnt.begin(), cnt.end());
+    double med = (nb % 2) ? (double)cnt[nb / 2] : 0.5 * ((double)cnt[nb / 2 - 1] + (double)cnt[nb / 2]);
+    hipDeviceProp_t prop;
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) cus = prop.multiProcessorCount;
+    out[0] = mean;
+    out[1] = mean > 0.0 ? sqrt(var) / mean : 0.0;
+    out[2] = med;
+    out[3] = (double)mx;
+    out[4] = (double)nb;
+    out[5] = (double)empty;
+    out[6] = (double)cus;
+    out[7] = h->cfg.skin;
+    return MD_OK;
+}
+
+__global__ void k_copy_rows(int n, const int32_t *__restrict__ nbr, const int32_t *__restrict__ cnt, int64_t ld,
+                            int maxr, int32_t *__restrict__ counts, int32_t *__restrict__ rows)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = cnt[i];
+    counts[i] = c;
+    int m = c < maxr ? c : maxr;
+    for (int k = 0; k < m; k++) rows[(size_t)i * maxr + k] = nbr[(size_t)k * ld + i];
+}
+
+extern "C" int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows, int32_t max_per_row, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (h->cfg.container != MD_CONTAINER_VL) return fail(MD_ERR_INVALID_ARG, "not a Verlet-list container");
+    if (!h->built) return fail(MD_ERR_NOT_BUILT, "lists not built");
+    if (max_per_row < 1 || (h->n > 0 && (!counts || !rows))) return fail(MD_ERR_INVALID_ARG, "bad arguments");
+    int n = (int)h->n;
+    if (n > 0)
+        k_copy_rows<<<(n + kBlock - 1) / kBlock, kBlock, 0, (hipStream_t)stream>>>(
+            n, h->b.nbr, h->b.nbr_count, h->n, max_per_row, counts, rows);
+    return MD_OK;
+}
+
+extern "C" int md_status(md_handle *h, uint32_t *flags)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!flags) return fail(MD_ERR_INVALID_ARG, "flags is NULL");
+    MD_HIP(hipDeviceSynchronize());
+    uint32_t f = 0;
+    MD_HIP(hipMemcpy(&f, h->b.flags, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    uint32_t zero = 0;
+    MD_HIP(hipMemcpy(h->b.flags, &zero, sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (f & MD_FLAG_LIST_OVERFLOW) h->truncated = true;
+    *flags = f | h->sticky;
+    h->sticky = 0;
+    return MD_OK;
+}
+
+extern "C" int md_get_config(md_handle *h, md_config *cfg)
+{
+    if (!h || !cfg) return fail(MD_ERR_INVALID_ARG, "NULL argument");
+    *cfg = h->cfg;
+    return MD_OK;
+}
+
+extern "C" int md_get_counters(md_handle *h, int64_t *out)
+{
+    if (!h || !out) return fail(MD_ERR_INVALID_ARG, "NULL argument");
+    out[0] = h->rebuilds;
+    out[1] = h->forced;
+    out[2] = h->phases;
+    out[3] = h->trials;
+    out[4] = h->config_index;
+    out[5] = h->list_entries;
+    return MD_OK;
+}
+
+extern "C" int md_timing(md_handle *h, int32_t enable, double *out)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    timing_collect(h);
+    if (out)
+        for (int k = 0; k < 4; k++) out[k] = h->tsum[k];
+    if (enable && !h->timing)
+        for (int k = 0; k < 4; k++) h->tsum[k] = 0.0;
+    h->timing = enable != 0;
+    return MD_OK;
+}
+
+extern "C" const char *md_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ tuning
+
+// Switch the handle to configuration nc (same particles, box, cutoffs,
+// precision); the structures are rebuilt at the next step.
+int apply_config(md_handle *h, const md_config &nc)
+{
+    Geom g;
+    int rc = make_geom(nc, nc.csf, g);
+    if (rc) return rc;
+    if ((rc = ensure_cells(h, g))) return rc;
+    if (nc.container == MD_CONTAINER_VL && (rc = ensure_list(h, nc.max_neighbors))) return rc;
+    h->cfg = nc;
+    h->g = g;
+    h->built = false;
+    h->age = INT32_MAX / 2;
+    return MD_OK;
+}
+
+// One tuning phase (Sec. 2.2.5): trial the configurations the strategy asks
+// for, each for tune_trial_steps steps starting with a rebuild, score each by
+// its per-step time plus its build time spread over its rebuild interval
+// (the weighted average of build and force time), keep the best.  The trial
+// steps advance the simulation.  A phase that does not fit into the rest of
+// this md_step call is postponed to the next call.
+int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
+{
+    Tuner *t = h->tuner;
+    int T = h->base.tune_trial_steps;
+    int live = 0;
+    for (int k = 0; k < t->n(); k++) live += t->blacklisted(k) ? 0 : 1;
+    *next = s0;
+    if ((int64_t)live * T > (int64_t)(c.nsteps - s0)) {
+        h->next_phase = h->steps_done + c.nsteps;
+        return MD_OK;
+    }
+    std::vector<int> trial;
+    t->begin_phase(trial);
+    h->phases++;
+    int s = s0, last_k = -1, rc;
+    for (int k = 0; k < (int)trial.size(); k++) {
+        if (!trial[k]) continue;
+        const md_config &kc = h->space[k];
+        if ((rc = apply_config(h, kc))) return rc;
+        MD_HIP(hipEventRecord(h->ev0, c.s));
+        if ((rc = run_steps(h, c, s, s + 1))) return rc;
+        MD_HIP(hipEventRecord(h->ev1, c.s));
+        if ((rc = run_steps(h, c, s + 1, s + T))) return rc;
+        MD_HIP(hipEventRecord(h->ev2, c.s));
+        MD_HIP(hipEventSynchronize(h->ev2));
+        float t01 = 0.f, t12 = 0.f;
+        MD_HIP(hipEventElapsedTime(&t01, h->ev0, h->ev1));
+        MD_HIP(hipEventElapsedTime(&t12, h->ev1, h->ev2));
+        double per = (double)t12 / (double)(T - 1);
+        double build = std::max(0.0, (double)t01 - per);
+        t->report(k, per + build / (double)kc.rebuild_interval);
+        h->trials++;
+        last_k = k;
+        s += T;
+    }
+    int chosen = t->end_phase();
+    if (chosen < 0) return fail(MD_ERR_INVALID_ARG, "tuning phase without scores");
+    if (chosen != last_k && (rc = apply_config(h, h->space[chosen]))) return rc;
+    h->config_index = chosen;
+    h->next_phase = h->steps_done + s0 + h->base.tune_interval;
+    *next = s;
+    return MD_OK;
+}

@@ -1,0 +1,354 @@
+// Linked cells by a counting sort (Sec. 2.2.1): cell index + histogram,
+// exclusive scan, scatter, per-cell ordering by id, gather of the particle
+// arrays into cell order and fixed-point staging of the positions.
+#include <math.h>
+
+#include "md_internal.h"
+
+namespace mdlj {
+
+// ------------------------------------------------------------------ helpers
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    int64_t b = (n + kBlock - 1) / kBlock;
+    k_fill_i32<<<(unsigned)b, kBlock, 0, s>>>(p, v, n);
+}
+
+// Cell coordinate of x along one dimension: min(n-1, (int)(x * n/L)),
+// clamped to [0, n-1] so that an out-of-box or non-finite position cannot
+// index outside the cell arrays (it is flagged instead).
+__device__ __forceinline__ int cell_coord(double x, double inv_w, int nc, bool &bad)
+{
+    double t = x * inv_w;
+    if (!(t >= 0.0 && t < (double)nc + 1.0)) {  // also catches NaN
+        bad = true;
+        return t > 0.0 ? nc - 1 : 0;
+    }
+    int c = (int)t;
+    return c < nc - 1 ? c : nc - 1;
+}
+
+// Fixed-point staging: q = floor(x * 2^32 / L) as an unsigned 32-bit
+// integer.  Differences of two staged coordinates, taken modulo 2^32 and read
+// as signed, are the periodic minimum-image displacement in units of L/2^32.
+__device__ __forceinline__ uint32_t quantise(double x, double S)
+{
+    double q = x * S;
+    q = q < 0.0 ? 0.0 : (q > 4294967295.0 ? 4294967295.0 : q);
+    return (uint32_t)q;
+}
+
+__device__ __forceinline__ int4 stage_of(double x, double y, double z, int t, const Geom &g)
+{
+    int4 r;
+    r.x = (int)quantise(x, g.S[0]);
+    r.y = (int)quantise(y, g.S[1]);
+    r.z = (int)quantise(z, g.S[2]);
+    r.w = t;
+    return r;
+}
+
+// ------------------------------------------------------------------ K1: histogram
+
+__global__ void k_cell_hist(int n, const double *__restrict__ pos, Geom g, int32_t *__restrict__ cell_id,
+                            int32_t *__restrict__ slot, int32_t *__restrict__ count,
+                            int32_t *__restrict__ flags)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool bad = false;
+    int cx = cell_coord(pos[i], g.inv_w[0], g.nc[0], bad);
+    int cy = cell_coord(pos[n + i], g.inv_w[1], g.nc[1], bad);
+    int cz = cell_coord(pos[2 * (size_t)n + i], g.inv_w[2], g.nc[2], bad);
+    if (bad) atomicOr(&flags[0], (int)MD_FLAG_NONFINITE);
+    int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+    cell_id[i] = c;
+    slot[i] = atomicAdd(&count[c], 1);
+}
+
+void launch_cell_hist(int n, const double *pos, const Geom &g, int32_t *cell_id, int32_t *slot,
+                      int32_t *count, int32_t *flags, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_cell_hist<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(n, pos, g, cell_id, slot, count, flags);
+}
+
+// Count-only histogram for the live statistics.
+__global__ void k_bin_counts(int n, const double *__restrict__ pos, Geom g, int32_t *__restrict__ count)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool bad = false;
+    int cx = cell_coord(pos[i], g.inv_w[0], g.nc[0], bad);
+    int cy = cell_coord(pos[n + i], g.inv_w[1], g.nc[1], bad);
+    int cz = cell_coord(pos[2 * (size_t)n + i], g.inv_w[2], g.nc[2], bad);
+    atomicAdd(&count[(cz * g.nc[1] + cy) * g.nc[0] + cx], 1);
+}
+
+void launch_bin_counts(int n, const double *pos, const Geom &g, int32_t *count, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_bin_counts<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(n, pos, g, count);
+}
+
+// ------------------------------------------------------------------ K2: exclusive scan
+// Three passes: per-block totals, a scan of the totals in one block, and the
+// per-block scan plus offset.  out has n + 1 entries (out[n] = total).
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;  // 2048 elements per block
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int *sh, int &total)
+{
+    // Hillis-Steele over 256 threads in LDS; deterministic.
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        int add = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    total = sh[kBlock - 1];
+    int incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_scan_totals(const int32_t *__restrict__ in, int64_t n, int32_t *__restrict__ totals)
+{
+    __shared__ int sh[kBlock];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int s = 0;
+    for (int k = 0; k < kScanItems; k++)
+        if (base + k < n) s += in[base + k];
+    int total;
+    block_exclusive_scan(s, sh, total);
+    if (threadIdx.x == 0) totals[blockIdx.x] = total;
+}
+
+// Exclusive scan of at most kScanTile block totals in one block, in place.
+__global__ void k_scan_blocks(int32_t *__restrict__ totals, int nb)
+{
+    __shared__ int sh[kBlock];
+    int base = threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+    for (int k = 0; k < kScanItems; k++) {
+        v[k] = base + k < nb ? totals[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int ex = block_exclusive_scan(s, sh, total);
+    for (int k = 0; k < kScanItems; k++) {
+        if (base + k < nb) totals[base + k] = ex;
+        ex += v[k];
+    }
+}
+
+__global__ void k_scan_final(const int32_t *__restrict__ in, int64_t n, const int32_t *__restrict__ offs,
+                             int32_t *__restrict__ out)
+{
+    __shared__ int sh[kBlock];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+    for (int k = 0; k < kScanItems; k++) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int ex = block_exclusive_scan(s, sh, total) + offs[blockIdx.x];
+    for (int k = 0; k < kScanItems; k++) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    if (base <= n - 1 && n - 1 < base + kScanItems) out[n] = ex;  // grand total
+}
+
+// scratch must hold scan_scratch_size(n) ints.  Block totals are scanned in
+// one block when there are at most kScanTile of them, else recursively.
+int64_t scan_scratch_size(int64_t n)
+{
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb <= kScanTile) return nb + 1;
+    return 2 * (nb + 1) + scan_scratch_size(nb);
+}
+
+void launch_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch, hipStream_t s)
+{
+    if (n <= 0) {
+        launch_fill_i32(out, 0, 1, s);
+        return;
+    }
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    int32_t *totals = scratch;
+    k_scan_totals<<<(unsigned)nb, kBlock, 0, s>>>(in, n, totals);
+    const int32_t *offs = totals;
+    if (nb <= kScanTile) {
+        k_scan_blocks<<<1, kBlock, 0, s>>>(totals, (int)nb);
+    } else {
+        int32_t *scanned = totals + nb + 1;
+        launch_scan(totals, scanned, nb, scanned + nb + 1, s);
+        offs = scanned;
+    }
+    k_scan_final<<<(unsigned)nb, kBlock, 0, s>>>(in, n, offs, out);
+}
+
+// ------------------------------------------------------------------ K3: scatter + order
+
+__global__ void k_scatter(int n, const int32_t *__restrict__ cell_id, const int32_t *__restrict__ slot,
+                          const int32_t *__restrict__ start, int32_t *__restrict__ perm)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    perm[start[cell_id[i]] + slot[i]] = i;
+}
+
+void launch_scatter(int n, const int32_t *cell_id, const int32_t *slot, const int32_t *start,
+                    int32_t *perm, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_scatter<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(n, cell_id, slot, start, perm);
+}
+
+// The atomic histogram leaves each cell's members in arbitrary order; sort
+// every cell's segment by id (insertion sort, one thread per cell: cells hold
+// tens of particles) so the cell contents are deterministic.
+__global__ void k_cell_sort(int ncell, const int32_t *__restrict__ start, const int32_t *__restrict__ ids,
+                            int32_t *__restrict__ perm)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    int b = start[c], e = start[c + 1];
+    for (int k = b + 1; k < e; k++) {
+        int v = perm[k];
+        int key = ids[v];
+        int m = k - 1;
+        while (m >= b && ids[perm[m]] > key) {
+            perm[m + 1] = perm[m];
+            m--;
+        }
+        perm[m + 1] = v;
+    }
+}
+
+void launch_cell_sort(int ncell, const int32_t *start, const int32_t *ids, int32_t *perm, hipStream_t s)
+{
+    if (ncell <= 0) return;
+    k_cell_sort<<<(ncell + kBlock - 1) / kBlock, kBlock, 0, s>>>(ncell, start, ids, perm);
+}
+
+// ------------------------------------------------------------------ K4: gather + stage
+
+template <typename real>
+__global__ void k_gather(int n, const int32_t *__restrict__ perm, const double *__restrict__ pos,
+                         const real *__restrict__ vel, const real *__restrict__ force,
+                         const int32_t *__restrict__ type, const int32_t *__restrict__ ids,
+                         double *__restrict__ tpos, real *__restrict__ tvel, real *__restrict__ tforce,
+                         int32_t *__restrict__ ttype, int32_t *__restrict__ tids,
+                         const int32_t *__restrict__ cell_id, int32_t *__restrict__ cell_sorted, Geom g,
+                         int4 *__restrict__ stage, int4 *__restrict__ stage_ref)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int src = perm[k];
+    size_t N = (size_t)n;
+    double x = pos[src], y = pos[N + src], z = pos[2 * N + src];
+    tpos[k] = x;
+    tpos[N + k] = y;
+    tpos[2 * N + k] = z;
+    if (vel) {
+        tvel[k] = vel[src];
+        tvel[N + k] = vel[N + src];
+        tvel[2 * N + k] = vel[2 * N + src];
+    }
+    if (force) {
+        tforce[k] = force[src];
+        tforce[N + k] = force[N + src];
+        tforce[2 * N + k] = force[2 * N + src];
+    }
+    int t = type[src];
+    ttype[k] = t;
+    tids[k] = ids[src];
+    cell_sorted[k] = cell_id[src];
+    int4 q = stage_of(x, y, z, t, g);
+    stage[k] = q;
+    stage_ref[k] = q;
+}
+
+void launch_gather(int n, int precision, const int32_t *perm, const double *pos, const void *vel,
+                   const void *force, const int32_t *type, const int32_t *ids, double *tpos,
+                   void *tvel, void *tforce, int32_t *ttype, int32_t *tids, const int32_t *cell_id,
+                   int32_t *cell_sorted, const Geom &g, int4 *stage, int4 *stage_ref, hipStream_t s)
+{
+    if (n <= 0) return;
+    int nb = (n + kBlock - 1) / kBlock;
+    if (precision == MD_FP64)
+        k_gather<double><<<nb, kBlock, 0, s>>>(n, perm, pos, (const double *)vel, (const double *)force,
+                                               type, ids, tpos, (double *)tvel, (double *)tforce, ttype,
+                                               tids, cell_id, cell_sorted, g, stage, stage_ref);
+    else
+        k_gather<float><<<nb, kBlock, 0, s>>>(n, perm, pos, (const float *)vel, (const float *)force,
+                                              type, ids, tpos, (float *)tvel, (float *)tforce, ttype,
+                                              tids, cell_id, cell_sorted, g, stage, stage_ref);
+}
+
+__global__ void k_stage(int n, const double *__restrict__ pos, const int32_t *__restrict__ type, Geom g,
+                        int4 *__restrict__ stage)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    size_t N = (size_t)n;
+    stage[k] = stage_of(pos[k], pos[N + k], pos[2 * N + k], type[k], g);
+}
+
+void launch_stage(int n, const double *pos, const int32_t *type, const Geom &g, int4 *stage, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_stage<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(n, pos, type, g, stage);
+}
+
+// ------------------------------------------------------------------ pair tables
+
+// One thread: Lorentz-Berthelot mixing of the per-type parameters and the
+// derived per-pair constants of both precisions.
+__global__ void k_prepare_tab(const double *__restrict__ lj, double rc2_0, double rc2_1, double rc2_2,
+                              double rc2_3, Geom g, PairTab *__restrict__ tab)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int nt = g.nt;
+    double rc2[4] = {rc2_0, rc2_1, rc2_2, rc2_3};
+    double u = g.L[0] / 4294967296.0;  // fixed-point length unit
+    for (int a = 0; a < nt; a++)
+        for (int b = 0; b < nt; b++) {
+            int ab = a * nt + b;
+            double sig = 0.5 * (lj[nt + a] + lj[nt + b]);
+            double eps = sqrt(lj[a] * lj[b]);
+            tab->sig[ab] = sig;
+            tab->eps[ab] = eps;
+            tab->rc2[ab] = rc2[ab];
+            double r2u = rc2[ab] / (u * u);
+            tab->rc2_lo[ab] = (float)(r2u * (1.0 - kBand));
+            tab->rc2_hi[ab] = (float)(r2u * (1.0 + kBand));
+            tab->sig2[ab] = (float)(sig * sig / (u * u));
+            tab->eps24[ab] = (float)(24.0 * eps / u);
+            tab->eps4[ab] = (float)(4.0 * eps);
+            tab->eps24w[ab] = (float)(24.0 * eps);
+        }
+}
+
+void launch_prepare_tab(const double *lj, const double *rc2, const Geom &g, PairTab *tab, hipStream_t s)
+{
+    k_prepare_tab<<<1, 64, 0, s>>>(lj, rc2[0], rc2[1], rc2[2], rc2[3], g, tab);
+}
+
+}  // namespace mdlj

@@ -1,0 +1,202 @@
+// Internal declarations shared by the HIP translation units of libmdlj.
+// Nothing here is part of the C-ABI (include/mdlj.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "mdlj.h"
+
+namespace mdlj {
+
+// Guard band of the FP32 cutoff decisions: a squared distance within
+// rc2 * (1 +- 2^-19) of a cutoff is decided again in FP64 from the master
+// positions, exactly as the plain definition does, so that every pair set
+// equals the FP64 one.  The FP32 squared distance from the fixed-point
+// coordinates is within ~7e-7 relative of the FP64 one (fixed-point
+// quantisation <= 2 units per component, int->float rounding, three
+// products and two sums), well inside 2^-19 = 1.9e-6.
+constexpr double kBand = 1.0 / 524288.0;
+
+constexpr int kMaxOfs = 5;  // neighbour cell offsets per dimension (reach <= 2)
+
+// Per-type-pair constants, computed on the device from the per-type
+// parameters (Lorentz-Berthelot) so that parameters may live in device memory
+// and change between calls without a host round trip.
+struct PairTab {
+    // FP32 path, in fixed-point length units u = L_x / 2^32
+    float rc2_lo[4], rc2_hi[4];  // guard band around rc2 / u^2
+    float sig2[4];               // sig_ab^2 / u^2
+    float eps24[4];              // 24 eps_ab / u   (force per unit d)
+    float eps4[4];               // 4 eps_ab        (pair energy)
+    float eps24w[4];             // 24 eps_ab       (pair virial)
+    // FP64 path, physical units
+    double rc2[4], sig[4], eps[4];
+};
+
+// Cell geometry and fixed-point staging constants (passed by value).
+struct Geom {
+    int nc[3];        // cells per dimension
+    int ncell;        // nc[0] nc[1] nc[2]
+    int nofs[3];      // distinct neighbour offsets per dimension
+    int ofs[3][kMaxOfs];  // the offsets, as non-negative shifts mod nc[d]
+    double L[3];      // box
+    double inv_w[3];  // nc[d] / L[d]
+    double S[3];      // fixed-point scale 2^32 / L[d]
+    float ry, rz;     // L_y / L_x, L_z / L_x (anisotropic scale of y, z units)
+    int iso;          // 1 if all box lengths are equal
+    double rl2;       // (r_c,max + skin)^2, FP64
+    float rl2_lo, rl2_hi;  // guard band of rl2 in u^2
+    float disp2;      // (skin/2)^2 (1 - 1e-4) in u^2: skin check threshold
+    int nt;           // number of types
+};
+
+// Device buffers and state of one handle.
+struct Buffers {
+    int32_t *cell_id = nullptr, *slot = nullptr, *perm = nullptr;
+    int32_t *cell_count = nullptr, *cell_start = nullptr, *cell_sorted = nullptr;
+    int32_t *scan_blocks = nullptr;
+    double *tmp_pos = nullptr;
+    void *tmp_vel = nullptr, *tmp_force = nullptr;
+    int32_t *tmp_type = nullptr, *tmp_ids = nullptr;
+    int4 *stage = nullptr, *stage_ref = nullptr;
+    int32_t *nbr = nullptr, *nbr_count = nullptr;
+    int64_t nbr_cap = 0;  // entries per row allocated
+    double *partials = nullptr;  // [kMaxPartials][4]
+    double *kpart = nullptr;     // [kMaxPartials]
+    int32_t *flags = nullptr;    // device [4]: sticky bits, first skin step, spare
+    PairTab *tab = nullptr;
+    float *facc = nullptr;       // N3L accumulation scratch (unused when gather)
+    // clusters
+    int32_t *cl_start = nullptr, *cl_count = nullptr;  // per cluster
+    float *cl_bbox = nullptr;   // [n_clusters][6] lo xyz, hi xyz in u units (wrapped)
+    int32_t *cl_nbr = nullptr, *cl_nbr_count = nullptr;
+    int64_t cl_cap = 0;
+    int32_t n_clusters_max = 0;
+    // rollback snapshot (md_step)
+    double *snap_pos = nullptr;
+    void *snap_vel = nullptr, *snap_force = nullptr;
+    int32_t *snap_type = nullptr, *snap_ids = nullptr;
+    int4 *snap_stage = nullptr;
+    // adjoint
+    double *gpart = nullptr;     // per-block parameter-gradient partials [blocks][8]
+    uint32_t *host_flags = nullptr;  // pinned
+};
+
+constexpr int kBlock = 256;
+constexpr int kMaxPartials = 65536;  // per-block reduction slots
+
+// Set the thread-local error string; returns code.
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define MD_HIP(call)                                              \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::mdlj::hip_fail(e_, #call); \
+    } while (0)
+
+// ------------------------------------------------------------------ launchers
+// cells.hip
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void launch_cell_hist(int n, const double *pos, const Geom &g, int32_t *cell_id, int32_t *slot,
+                      int32_t *count, int32_t *flags, hipStream_t s);
+int64_t scan_scratch_size(int64_t n);
+void launch_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch, hipStream_t s);
+void launch_scatter(int n, const int32_t *cell_id, const int32_t *slot, const int32_t *start,
+                    int32_t *perm, hipStream_t s);
+void launch_cell_sort(int ncell, const int32_t *start, const int32_t *ids, int32_t *perm,
+                      hipStream_t s);
+void launch_gather(int n, int precision, const int32_t *perm, const double *pos, const void *vel,
+                   const void *force, const int32_t *type, const int32_t *ids, double *tpos,
+                   void *tvel, void *tforce, int32_t *ttype, int32_t *tids, const int32_t *cell_id,
+                   int32_t *cell_sorted, const Geom &g, int4 *stage, int4 *stage_ref,
+                   hipStream_t s);
+void launch_stage(int n, const double *pos, const int32_t *type, const Geom &g, int4 *stage,
+                  hipStream_t s);
+void launch_prepare_tab(const double *lj, const double *rc2_host, const Geom &g, PairTab *tab,
+                        hipStream_t s);
+void launch_bin_counts(int n, const double *pos, const Geom &g, int32_t *count, hipStream_t s);
+
+// force.hip
+struct ForceArgs {
+    int n;
+    int precision;
+    int container;
+    int newton3;
+    bool energy;
+    const double *pos;
+    const int32_t *type;
+    const int4 *stage;
+    const int32_t *cell_start, *cell_sorted;
+    const int32_t *nbr, *nbr_count;
+    int64_t nbr_ld;
+    const int32_t *cl_start, *cl_count, *cl_nbr, *cl_nbr_count;
+    int64_t cl_ld;
+    int n_clusters;
+    const PairTab *tab;
+    void *force;
+    double *partials;  // per-block {U, W, n_pairs, 0}
+    int32_t *flags;
+};
+int force_blocks(const ForceArgs &a);  // number of partial slots written when energy
+void launch_force(const ForceArgs &a, const Geom &g, hipStream_t s);
+void launch_vl_build(int n, const int4 *stage, const int32_t *cell_start, const int32_t *cell_sorted,
+                     const double *pos, const Geom &g, int half, int32_t *nbr, int32_t *cnt,
+                     int64_t ld, int maxn, int32_t *flags, hipStream_t s);
+void launch_reduce_out(const double *partials, int nblocks, int gather, double *out,
+                       hipStream_t s);
+
+// integrate.hip
+struct IntegrateArgs {
+    int n;
+    int precision;
+    double *pos;
+    void *vel;
+    const void *force;
+    const int32_t *type;
+    const double *inv_mass;
+    double hdt, dt;
+    int kick_prev;  // complete the previous step: v += dt/2 F/m (and kinetic energy)
+    int start;      // start a step: v += dt/2 F/m; x += dt v; wrap; stage; skin check
+    int energy;
+    int step_index;
+    int4 *stage;
+    const int4 *stage_ref;
+    int32_t *flags;
+    double *kpart;
+};
+int integrate_blocks(int n);
+void launch_integrate(const IntegrateArgs &a, const Geom &g, hipStream_t s);
+void launch_log_entry(const double *fpart, int fblocks, int gather, const double *kpart,
+                      int kblocks, double *out4, hipStream_t s);
+
+// adjoint.hip
+struct AdjointArgs {
+    int n;
+    int precision;
+    const double *pos;
+    const int32_t *type;
+    const int4 *stage;
+    const int32_t *cell_start, *cell_sorted;
+    const PairTab *tab;
+    const double *lj;
+    const void *grad_force;
+    double *grad_pos;
+    double *gpart;  // per block [8]: dL/d(eps_ab) [4], dL/d(sig_ab) [4]
+    int32_t *flags;
+};
+int adjoint_blocks(int n);
+void launch_adjoint(const AdjointArgs &a, const Geom &g, hipStream_t s);
+void launch_adjoint_finish(const double *gpart, int nblocks, const double *lj, int nt,
+                           double *grad_lj, hipStream_t s);
+
+// clusters.hip
+void launch_cluster_build(int n, const int32_t *cell_start, const Geom &g, const int4 *stage,
+                          int32_t *cl_start, int32_t *cl_count, float *bbox, int *n_clusters_dev,
+                          hipStream_t s);
+
+}  // namespace mdlj

@@ -1,0 +1,132 @@
+"""Host-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, validates arguments without a device, and its configuration
+selection engine follows the same rules as the oracle's.  CPU only."""
+import os
+import random
+import re
+
+import pytest
+
+from oracle.tuner import FULL_SEARCH, PREDICTIVE, TunerOracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2505_03438_amd import mdlj
+    if not os.path.exists(mdlj.LIB_PATH):
+        from paper_2505_03438_amd import build
+        build.build(verbose=False)
+    mdlj.lib()
+    return mdlj
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "mdlj.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(md_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(M):
+    names = _declared()
+    assert len(names) >= 20
+    L = M.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(M._SIGS), "binding and header disagree"
+
+
+def test_config_default(M):
+    c = M.config_default(1000, 12.0)
+    assert c.n == 1000 and list(c.box) == [12.0] * 3 and c.rc2[0] == 6.25
+    assert c.skin == 0.3 and c.csf == 1.0 and c.rebuild_interval == 10
+    assert c.container == M.MD_CONTAINER_VL and c.precision == M.MD_FP32
+
+
+def _create_rc(M, c):
+    import ctypes
+    h = ctypes.c_void_p()
+    rc = M.lib().md_create(ctypes.byref(c), ctypes.byref(h))
+    if rc == 0:
+        M.lib().md_destroy(h)
+    return rc
+
+
+def test_create_rejects_bad_configs(M):
+    c = M.config_default(100, 12.0)
+    c.box[1] = 5.0  # < 2 (r_c + skin)
+    assert _create_rc(M, c) == M.MD_ERR_BOX_TOO_SMALL
+    assert "box[1]" in M.md_last_error()
+    for field, val in (("n_types", 3), ("csf", 0.3), ("rebuild_interval", 0), ("precision", 7),
+                       ("container", 9), ("skin", -1.0), ("max_neighbors", 0)):
+        c = M.config_default(100, 12.0)
+        setattr(c, field, val)
+        assert _create_rc(M, c) == M.MD_ERR_INVALID_ARG, field
+    c = M.config_default(100, 12.0)
+    c.n_types = 2
+    c.rc2[1] = 5.0  # rc2[0][1] != rc2[1][0]
+    assert _create_rc(M, c) == M.MD_ERR_INVALID_ARG
+    assert "symmetric" in M.md_last_error()
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
+                    reason="a device may be present")
+def test_create_without_device_fails_cleanly(M):
+    c = M.config_default(100, 12.0)
+    assert _create_rc(M, c) == M.MD_ERR_NO_DEVICE
+
+
+def _drive(strategy, n, phases, scores, M):
+    """Run the library tuner and the oracle on the same score table."""
+    lib_t = M.Tuner(strategy, n, phases)
+    orc_t = TunerOracle(strategy, n, phases)
+    for p in range(phases):
+        a = lib_t.begin_phase()
+        b = orc_t.begin_phase()
+        assert a == b, (p, a, b)
+        for c in a:
+            lib_t.report(c, scores[p][c])
+            orc_t.report(c, scores[p][c])
+        assert lib_t.end_phase() == orc_t.end_phase()
+        assert lib_t.blacklisted() == [c for c in range(n) if orc_t.blacklisted[c]]
+
+
+def test_tuner_matches_oracle_on_hand_trace(M):
+    import json
+    t = json.load(open(os.path.join(ROOT, "tests", "golden", "tuner_predictive_trace.json")))
+    tu = M.Tuner(t["strategy"], t["n_configs"], t["total_phases"])
+    for ph in t["phases"]:
+        assert tu.begin_phase() == ph["trial"]
+        for c in ph["trial"]:
+            tu.report(c, ph["scores"][str(c)])
+        assert tu.end_phase() == ph["chosen"]
+        assert tu.blacklisted() == ph["blacklisted_after"]
+
+
+@pytest.mark.parametrize("strategy", [FULL_SEARCH, PREDICTIVE])
+def test_tuner_matches_oracle_on_random_traces(M, strategy):
+    rng = random.Random(1234 + strategy)
+    for trial in range(40):
+        n = rng.randint(1, 12)
+        phases = rng.randint(1, 12)
+        base = [rng.uniform(1.0, 30.0) for _ in range(n)]
+        drift = [rng.uniform(-2.0, 2.0) for _ in range(n)]
+        scores = [[max(0.01, base[c] + drift[c] * p + rng.uniform(-1, 1)) for c in range(n)]
+                  for p in range(phases)]
+        # occasional ties
+        if n > 1 and trial % 5 == 0:
+            for p in range(phases):
+                scores[p][1] = scores[p][0]
+        _drive(strategy, n, phases, scores, M)
+
+
+def test_tuner_rejects_bad_use(M):
+    tu = M.Tuner(PREDICTIVE, 3, 4)
+    tr = tu.begin_phase()
+    with pytest.raises(RuntimeError):
+        tu.end_phase()  # nothing reported
+    with pytest.raises(RuntimeError):
+        tu.report(7, 1.0)
+    with pytest.raises(RuntimeError):
+        tu.report(tr[0], float("nan"))
