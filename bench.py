@@ -53,9 +53,13 @@ def make_cfg(M, n, box, kind, steps):
         c.csf = 1.0
         c.newton3 = M.MD_N3L_OFF
         c.rebuild_interval = 10
-    elif kind == "vl":
-        c.container = M.MD_CONTAINER_VL
-        c.rebuild_interval = 10
+    elif kind.startswith("fixed:"):
+        # fixed:<container>:<csf>:<n3l>:<R>, e.g. fixed:vl:1:0:5
+        _, cont, csf, n3, R = kind.split(":")
+        c.container = {"lc": M.MD_CONTAINER_LC, "vl": M.MD_CONTAINER_VL, "cl": M.MD_CONTAINER_CL}[cont]
+        c.csf = float(csf)
+        c.newton3 = int(n3)
+        c.rebuild_interval = int(R)
     else:  # autotuned, Predictive strategy
         c.container = M.MD_CONTAINER_LC
         c.rebuild_interval = 10
@@ -150,6 +154,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--extra", default="", help="comma-separated extra fixed configs to time, "
+                    "e.g. fixed:vl:1:0:5 (container:csf:n3l:R)")
     ap.add_argument("--ncell", type=int, default=64, help="FCC cells per side (64 -> 1,048,576 particles)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -171,6 +177,12 @@ def main():
     if not args.no_plain:
         plain = run(M, d, "plain", args.steps, args.warmup)
         log("plain LC: %.3f ms/step, %.3e pairs/s" % (plain["ms_per_step"], plain["pairs_per_s"]))
+    extra = {}
+    for kind in [k for k in args.extra.split(",") if k]:
+        extra[kind] = run(M, d, kind, args.steps, args.warmup)
+        log("%s: %.3f ms/step, %.3e pairs/s, force %.3f ms" % (kind, extra[kind]["ms_per_step"],
+                                                             extra[kind]["pairs_per_s"],
+                                                             extra[kind]["force_kernel_ms"]))
     achieved = FLOPS_PER_PAIR * auto["pairs_per_step"] / (auto["force_kernel_ms"] * 1e-3)
     kname = {0: "k_lc_f32", 1: "k_vl_f32", 2: "k_cluster_f32"}[auto["final_config"]["container"]]
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
@@ -200,6 +212,7 @@ def main():
                    "strategy": "predictive", "parallelism": "single-gpu"},
         "autotuned": auto,
         "plain": plain,
+        "fixed_configs": extra or None,
         "speedup_vs_plain": (auto["pairs_per_s"] / plain["pairs_per_s"]) if plain else None,
         "roofline": roof,
         "cpu_baseline": cpu,

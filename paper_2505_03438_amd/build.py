@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmdlj.so")
 INCLUDE = os.path.join(ROOT, "include")
 
-SOURCES = ["cells.hip", "force.hip", "integrate.hip", "adjoint.hip", "clusters.hip", "batch.hip",
+SOURCES = ["cells.hip", "force.hip", "window.hip", "integrate.hip", "adjoint.hip", "clusters.hip", "batch.hip",
            "api.hip", "tuner.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -31,6 +31,8 @@ template <typename real, bool ISO>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a, Geom g)
 {
     __shared__ double sh[8 * kBlock / 64];
+    __shared__ int so[3][kMaxOfs];
+    load_offsets(g, so);
     int i = blockIdx.x * kBlock + threadIdx.x;
     const int nt = g.nt;
     double gp[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // eps_ab[4], sig_ab[4]
@@ -46,12 +48,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a, Geom g)
         int cx, cy, cz;
         cell_xyz_a(a.cell_sorted[i], g, cx, cy, cz);
         for (int aa = 0; aa < g.nofs[2]; aa++) {
-            int zz = wrap_add_a(cz, g.ofs[2][aa], g.nc[2]);
+            int zz = wrap_add_a(cz, so[2][aa], g.nc[2]);
             for (int b = 0; b < g.nofs[1]; b++) {
-                int yy = wrap_add_a(cy, g.ofs[1][b], g.nc[1]);
+                int yy = wrap_add_a(cy, so[1][b], g.nc[1]);
                 int row = (zz * g.nc[1] + yy) * g.nc[0];
                 for (int e = 0; e < g.nofs[0]; e++) {
-                    int cj = row + wrap_add_a(cx, g.ofs[0][e], g.nc[0]);
+                    int cj = row + wrap_add_a(cx, so[0][e], g.nc[0]);
                     int jb = a.cell_start[cj], je = a.cell_start[cj + 1];
                     for (int j = jb; j < je; j++) {
                         if (j == i) continue;

@@ -67,6 +67,7 @@ int make_geom(const md_config &c, double csf, Geom &g)
             if (!dup) g.ofs[d][k++] = sft;
         }
         g.nofs[d] = k;
+        g.reach[d] = reach;
     }
     int64_t ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
     if (ncell > (int64_t)1 << 30) return fail(MD_ERR_INVALID_ARG, "too many cells");
@@ -118,6 +119,7 @@ struct md_handle {
     int64_t steps_done = 0;       // md_step steps since creation
     uint32_t sticky = 0;          // flag bits already read back from the device
     bool truncated = false;       // the current lists overflowed max_neighbors
+    bool energy_gather = true;    // the last energy partials saw each pair twice
     bool replay_no_log = false;   // the next block replays: its first step's log entry is done
     int64_t next_phase = 0;       // step index of the next tuning phase
 };
@@ -127,11 +129,12 @@ static size_t real_size(const md_config &c) { return c.precision == MD_FP64 ? 8 
 static void free_buffers(md_handle *h)
 {
     Buffers &b = h->b;
-    void *ptrs[] = {b.cell_id, b.slot, b.perm, b.cell_count, b.cell_start, b.cell_sorted, b.scan_blocks,
+    void *ptrs[] = {b.cell_id, b.slot, b.perm, b.perm2, b.cell_count, b.cell_start, b.cell_sorted, b.scan_blocks,
                     b.tmp_pos, b.tmp_vel, b.tmp_force, b.tmp_type, b.tmp_ids, b.stage, b.stage_ref,
                     b.nbr, b.nbr_count, b.partials, b.kpart, b.flags, b.tab, b.facc, b.cl_start,
                     b.cl_count, b.cl_bbox, b.cl_nbr, b.cl_nbr_count, b.snap_pos, b.snap_vel,
-                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart};
+                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart, b.w_i0, b.w_i1,
+                    b.w_c0, b.w_c1, b.w_rown, b.w_rowb, b.w_nbr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (b.host_flags) (void)hipHostFree(b.host_flags);
@@ -270,6 +273,7 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
     ALLOC(dalloc(&b.cell_id, n));
     ALLOC(dalloc(&b.slot, n));
     ALLOC(dalloc(&b.perm, n));
+    ALLOC(dalloc(&b.perm2, n));
     ALLOC(dalloc(&b.cell_sorted, n));
     ALLOC(dalloc(&b.tmp_pos, 3 * n));
     ALLOC(dalloc_bytes(&b.tmp_vel, 3 * n * rs));
@@ -285,7 +289,6 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
     ALLOC(dalloc(&b.flags, 4));
     ALLOC(dalloc(&b.tab, 1));
     ALLOC(ensure_cells(h, g));
-    if (cfg->container == MD_CONTAINER_VL || cfg->autotune != MD_TUNE_OFF) ALLOC(ensure_list(h, cfg->max_neighbors));
 #undef ALLOC
     if (hipHostMalloc((void **)&b.host_flags, 4 * sizeof(uint32_t), 0) != hipSuccess) {
         free_buffers(h);
@@ -336,6 +339,9 @@ static int check_handle(md_handle *h)
 }
 
 // Counting sort into cells + gather into cell order + copy back in place.
+static bool use_window(const md_config &c, const Geom &g);
+static int build_blocks(md_handle *h, hipStream_t s);
+
 static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, int32_t *type, int32_t *ids,
                             hipStream_t s)
 {
@@ -349,8 +355,8 @@ static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, i
     launch_cell_hist(n, pos, g, b.cell_id, b.slot, b.cell_count, b.flags, s);
     launch_scan(b.cell_count, b.cell_start, g.ncell, b.scan_blocks, s);
     launch_scatter(n, b.cell_id, b.slot, b.cell_start, b.perm, s);
-    launch_cell_sort(g.ncell, b.cell_start, ids, b.perm, s);
-    launch_gather(n, h->cfg.precision, b.perm, pos, vel, force, type, ids, b.tmp_pos, b.tmp_vel, b.tmp_force,
+    launch_cell_sort(n, b.cell_start, ids, b.cell_id, b.perm, b.slot, b.cell_sorted, b.perm2, s);
+    launch_gather(n, h->cfg.precision, b.perm2, pos, vel, force, type, ids, b.tmp_pos, b.tmp_vel, b.tmp_force,
                   b.tmp_type, b.tmp_ids, b.cell_id, b.cell_sorted, g, b.stage, b.stage_ref, s);
     if (n > 0) {
         MD_HIP(hipMemcpyAsync(pos, b.tmp_pos, 3 * (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -363,6 +369,7 @@ static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, i
     h->rebuilds++;
     h->age = 0;
     h->built = true;
+    if (use_window(h->cfg, h->g)) return build_blocks(h, s);
     return MD_OK;
 }
 
@@ -370,13 +377,75 @@ namespace mdlj {
 int cluster_build_impl(md_handle *h, const double *pos, hipStream_t s);  // clusters.hip
 }
 
+// FP32 gather-only Verlet lists live in LDS windows (16-bit entries); the
+// Newton's-third-law half lists and the FP64 path use global 32-bit lists.
+static bool use_window(const md_config &c, const Geom &g)
+{
+    return (c.container == MD_CONTAINER_VL || c.container == MD_CONTAINER_LC) && c.precision == MD_FP32 &&
+           c.newton3 == MD_N3L_OFF && window_geometry_ok(g);
+}
+
+static int ensure_window(md_handle *h, int64_t maxn)
+{
+    Buffers &b = h->b;
+    int rc;
+    int64_t cap = window_block_cap(h->n, h->g);
+    if (cap > b.w_cap) {
+        for (int32_t **p : {&b.w_i0, &b.w_i1, &b.w_c0, &b.w_c1}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+            if ((rc = dalloc(p, cap))) return rc;
+        }
+        b.w_cap = cap;
+    }
+    int64_t rows = (int64_t)h->g.nc[1] * h->g.nc[2] + 1;
+    if (rows > b.w_rows_cap) {
+        for (int32_t **p : {&b.w_rown, &b.w_rowb}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+            if ((rc = dalloc(p, rows))) return rc;
+        }
+        b.w_rows_cap = rows;
+    }
+    if (h->cfg.container == MD_CONTAINER_VL && (maxn > b.w_nbr_cap || !b.w_nbr)) {
+        if (b.w_nbr) (void)hipFree(b.w_nbr);
+        b.w_nbr = nullptr;
+        int64_t rows8 = (maxn + 7) / 8 * 8;  // entries are stored in chunks of eight
+        if ((rc = dalloc(&b.w_nbr, (size_t)rows8 * (size_t)std::max<int64_t>(h->n, 1)))) return rc;
+        b.w_nbr_cap = maxn;
+    }
+    return MD_OK;
+}
+
+// Blocks of the windowed traversals (after every cell build).
+static int build_blocks(md_handle *h, hipStream_t s)
+{
+    Buffers &b = h->b;
+    int rc = ensure_window(h, h->cfg.max_neighbors);
+    if (rc) return rc;
+    // the per-cell counts are no longer needed once the cells are built: the
+    // same buffer holds the window column sums of the packer
+    launch_blocks(h->g, b.cell_start, b.cell_count, b.w_rown, b.w_rowb, b.scan_blocks, b.w_i0, b.w_i1, b.w_c0,
+                  b.w_c1, (int)b.w_cap, b.flags, s);
+    return MD_OK;
+}
+
 static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
 {
     Buffers &b = h->b;
     int n = (int)h->n;
-    if (h->cfg.container == MD_CONTAINER_VL) {
+    if (use_window(h->cfg, h->g) && h->cfg.container == MD_CONTAINER_VL) {
+        int rc = ensure_window(h, h->cfg.max_neighbors);
+        if (rc) return rc;
+        const Geom &g = h->g;
+        int nrows = g.nc[1] * g.nc[2];
+        launch_fill_i32(b.flags + 2, 0, 1, s);
+        launch_vlw_build(b.stage, b.cell_start, b.cell_sorted, pos, g, n, b.w_rowb + nrows, b.w_i0, b.w_i1, b.w_c0,
+                         b.w_c1, b.w_nbr, b.nbr_count, h->cfg.max_neighbors, b.flags, s);
+    } else if (h->cfg.container == MD_CONTAINER_VL) {
         int rc = ensure_list(h, h->cfg.max_neighbors);
         if (rc) return rc;
+        launch_fill_i32(b.flags + 2, 0, 1, s);
         launch_vl_build(n, b.stage, b.cell_start, b.cell_sorted, pos, h->g, h->cfg.newton3, b.nbr, b.nbr_count,
                         n, h->cfg.max_neighbors, b.flags, s);
     } else if (h->cfg.container == MD_CONTAINER_CL) {
@@ -441,6 +510,15 @@ static ForceArgs force_args(md_handle *h, const double *pos, const int32_t *type
     a.force = force;
     a.partials = h->b.partials;
     a.flags = h->b.flags;
+    a.window = use_window(h->cfg, h->g);
+    if (a.window) {
+        a.w_nblk = h->b.w_rowb + (int64_t)h->g.nc[1] * h->g.nc[2];
+        a.w_i0 = h->b.w_i0;
+        a.w_i1 = h->b.w_i1;
+        a.w_c0 = h->b.w_c0;
+        a.w_c1 = h->b.w_c1;
+        a.w_nbr = h->b.w_nbr;
+    }
     return a;
 }
 
@@ -451,6 +529,7 @@ static int forces_impl(md_handle *h, const double *pos, const int32_t *type, voi
     if (force_blocks(a) > kMaxPartials) return fail(MD_ERR_INVALID_ARG, "too many particles for the reduction");
     if (h->cfg.newton3 == MD_N3L_ON) launch_zero(force, 3 * h->n * (int64_t)real_size(h->cfg), s);
     launch_force(a, h->g, s);
+    if (energy) h->energy_gather = h->cfg.newton3 == MD_N3L_OFF;
     return MD_OK;
 }
 
@@ -551,13 +630,17 @@ static int rebuild(md_handle *h, const StepCtx &c)
 // One time step s: finish step s-1 (second kick, kinetic energy and, unless
 // suppressed, its log entry), start step s (kick, drift, stage, skin check),
 // rebuild when the structure is due (or when force_rebuild), then forces.
-static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, bool log_prev_ok = true)
+static int snapshot(md_handle *h, const StepCtx &c, bool restore, bool with_force);
+static int step_forces(md_handle *h, const StepCtx &c, int s);
+
+static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, bool log_prev_ok = true,
+                    bool snap_after_rebuild = false)
 {
     bool log_prev = s > 0 && logs_step(c, s - 1) && log_prev_ok;
     launch_integrate(integ_args(h, c, s > 0, 1, log_prev, s), h->g, c.s);
     if (log_prev) {
         ForceArgs fa = force_args(h, c.pos, c.type, c.force, true);
-        launch_log_entry(h->b.partials, force_blocks(fa), h->cfg.newton3 == MD_N3L_OFF, h->b.kpart,
+        launch_log_entry(h->b.partials, force_blocks(fa), h->energy_gather, h->b.kpart,
                          integrate_blocks((int)h->n), c.log + 4 * (s / c.energy_every - 1), c.s);
     }
     h->age++;
@@ -570,7 +653,14 @@ static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, b
             MD_HIP(hipEventRecord(e1, c.s));
             h->tpend.push_back({e0, e1, 1});
         }
+        if (snap_after_rebuild && (rc = snapshot(h, c, false, false))) return rc;
     }
+    return step_forces(h, c, s);
+}
+
+// The force pass of step s (energy partials when step s is logged).
+static int step_forces(md_handle *h, const StepCtx &c, int s)
+{
     hipEvent_t e0 = timing_event(h), e1 = nullptr;
     if (e0) MD_HIP(hipEventRecord(e0, c.s));
     int rc = forces_impl(h, c.pos, c.type, c.force, logs_step(c, s), c.s);
@@ -581,7 +671,10 @@ static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, b
     return rc;
 }
 
-static int snapshot(md_handle *h, const StepCtx &c, bool restore)
+// Snapshot of the state a block may be replayed from: positions and
+// velocities, plus forces when the snapshot precedes an integration.  Types
+// and ids change only at rebuilds, which never fall inside a replayed span.
+static int snapshot(md_handle *h, const StepCtx &c, bool restore, bool with_force)
 {
     Buffers &b = h->b;
     size_t n = (size_t)h->n;
@@ -591,8 +684,6 @@ static int snapshot(md_handle *h, const StepCtx &c, bool restore)
         if ((rc = dalloc(&b.snap_pos, 3 * n))) return rc;
         if ((rc = dalloc_bytes(&b.snap_vel, 3 * n * rs))) return rc;
         if ((rc = dalloc_bytes(&b.snap_force, 3 * n * rs))) return rc;
-        if ((rc = dalloc(&b.snap_type, n))) return rc;
-        if ((rc = dalloc(&b.snap_ids, n))) return rc;
     }
     if (n == 0) return MD_OK;
     auto cp = [&](void *dst, const void *src, size_t bytes) {
@@ -601,27 +692,27 @@ static int snapshot(md_handle *h, const StepCtx &c, bool restore)
     if (!restore) {
         MD_HIP(cp(b.snap_pos, c.pos, 3 * n * 8));
         MD_HIP(cp(b.snap_vel, c.vel, 3 * n * rs));
-        MD_HIP(cp(b.snap_force, c.force, 3 * n * rs));
-        MD_HIP(cp(b.snap_type, c.type, n * 4));
-        MD_HIP(cp(b.snap_ids, c.ids, n * 4));
+        if (with_force) MD_HIP(cp(b.snap_force, c.force, 3 * n * rs));
     } else {
         MD_HIP(cp(c.pos, b.snap_pos, 3 * n * 8));
         MD_HIP(cp(c.vel, b.snap_vel, 3 * n * rs));
-        MD_HIP(cp(c.force, b.snap_force, 3 * n * rs));
-        MD_HIP(cp(c.type, b.snap_type, n * 4));
-        MD_HIP(cp(c.ids, b.snap_ids, n * 4));
+        if (with_force) MD_HIP(cp(c.force, b.snap_force, 3 * n * rs));
     }
     return MD_OK;
 }
 
 // Read the device flags (synchronises the stream).
-static int read_flags(md_handle *h, hipStream_t s, int32_t out[2])
+static int read_flags(md_handle *h, hipStream_t s, int32_t out[3])
 {
-    MD_HIP(hipMemcpyAsync(h->b.host_flags, h->b.flags, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MD_HIP(hipMemcpyAsync(h->b.host_flags, h->b.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     MD_HIP(hipStreamSynchronize(s));
     out[0] = (int32_t)h->b.host_flags[0];
     out[1] = (int32_t)h->b.host_flags[1];
+    out[2] = (int32_t)h->b.host_flags[2];
     timing_collect(h);
+    if (h->b.host_flags[3])
+        return fail(MD_ERR_INVALID_ARG, "a cell neighbourhood exceeds the windowed traversal's LDS tile "
+                                        "(density far above liquid); use MD_N3L_ON or csf 0.5");
     return MD_OK;
 }
 
@@ -641,35 +732,57 @@ static int run_block(md_handle *h, const StepCtx &c, int s0, int s_end, int *nex
     int len = rebuild_first ? R : R - age0 - 1;
     int last = std::min(s_end - 1, s0 + std::max(len, 1) - 1);
     int rc;
-    if ((rc = snapshot(h, c, false))) return rc;
+    // rebuild_first: snapshot right after the rebuild of step s0 (cell order
+    // of the block); otherwise before step s0, forces included.
+    if (!rebuild_first && (rc = snapshot(h, c, false, true))) return rc;
     launch_fill_i32(h->b.flags + 1, INT32_MAX, 1, c.s);
-    bool no_log_first = h->replay_no_log;
-    h->replay_no_log = false;
     for (int st = s0; st <= last; st++)
-        if ((rc = one_step(h, c, st, false, st != s0 || !no_log_first))) return rc;
-    int32_t f[2];
+        if ((rc = one_step(h, c, st, false, true, rebuild_first && st == s0))) return rc;
+    int32_t f[3];
     if ((rc = read_flags(h, c.s, f))) return rc;
     int v = f[1];
     int first_used = rebuild_first ? s0 + 1 : s0;  // first step whose forces used the checked structure
     bool overflow = (f[0] & MD_FLAG_LIST_OVERFLOW) != 0;
-    if (overflow && h->cfg.container == MD_CONTAINER_VL && h->cfg.max_neighbors < 4096) {
+    if (overflow && rebuild_first && h->cfg.container == MD_CONTAINER_VL && h->cfg.max_neighbors < 4096) {
+        // the lists built at step s0 were truncated: grow them, rebuild the
+        // lists from the snapshot (the cells are still valid for it) and redo
+        // step s0's forces; the rest of the block is run again
         h->sticky |= (uint32_t)f[0] & ~MD_FLAG_LIST_OVERFLOW;
-        h->cfg.max_neighbors = std::min(4096, h->cfg.max_neighbors * 3 / 2 + 8);
-        if ((rc = ensure_list(h, h->cfg.max_neighbors))) return rc;
+        h->cfg.max_neighbors = std::min(4096, std::max(h->cfg.max_neighbors * 3 / 2, f[2] + 16));
         launch_fill_i32(h->b.flags, 0, 1, c.s);
-        if ((rc = snapshot(h, c, true))) return rc;
-        h->age = R;  // replay the block with a rebuild at its first step
-        *next = s0;
-        h->replay_no_log = true;
+        if ((rc = snapshot(h, c, true, false))) return rc;
+        if ((rc = build_lists_impl(h, c.pos, c.s))) return rc;
+        if ((rc = step_forces(h, c, s0))) return rc;
+        h->age = 0;
+        *next = s0 + 1;
         return MD_OK;
     }
     if (v >= first_used && v <= last) {
-        if ((rc = snapshot(h, c, true))) return rc;
-        h->age = age0;
-        for (int st = s0; st < v; st++)
-            if ((rc = one_step(h, c, st, false, st != s0))) return rc;
+        // replay deterministically with the same structure, then rebuild
+        // right after the integration of step v
+        if (rebuild_first) {
+            if ((rc = snapshot(h, c, true, false))) return rc;
+            if ((rc = step_forces(h, c, s0))) return rc;
+            h->age = 0;
+            for (int st = s0 + 1; st < v; st++)
+                if ((rc = one_step(h, c, st, false))) return rc;
+        } else {
+            if ((rc = snapshot(h, c, true, true))) return rc;
+            h->age = age0;
+            for (int st = s0; st < v; st++)
+                if ((rc = one_step(h, c, st, false, st != s0))) return rc;
+        }
         if ((rc = one_step(h, c, v, true, v != s0))) return rc;
         h->forced++;
+        // the forced rebuild's lists must not be truncated either
+        if ((rc = read_flags(h, c.s, f))) return rc;
+        if ((f[0] & MD_FLAG_LIST_OVERFLOW) && h->cfg.container == MD_CONTAINER_VL) {
+            h->sticky |= (uint32_t)f[0] & ~MD_FLAG_LIST_OVERFLOW;
+            h->cfg.max_neighbors = std::min(4096, std::max(h->cfg.max_neighbors * 3 / 2, f[2] + 16));
+            launch_fill_i32(h->b.flags, 0, 1, c.s);
+            if ((rc = build_lists_impl(h, c.pos, c.s))) return rc;
+            if ((rc = step_forces(h, c, v))) return rc;
+        }
         *next = v + 1;
         return MD_OK;
     }
@@ -683,7 +796,7 @@ static int finish_steps(md_handle *h, const StepCtx &c)
     launch_integrate(integ_args(h, c, 1, 0, log_last, c.nsteps), h->g, c.s);
     if (log_last) {
         ForceArgs fa = force_args(h, c.pos, c.type, c.force, true);
-        launch_log_entry(h->b.partials, force_blocks(fa), h->cfg.newton3 == MD_N3L_OFF, h->b.kpart,
+        launch_log_entry(h->b.partials, force_blocks(fa), h->energy_gather, h->b.kpart,
                          integrate_blocks((int)h->n), c.log + 4 * (c.nsteps / c.energy_every - 1), c.s);
     }
     return MD_OK;
@@ -723,7 +836,7 @@ extern "C" int md_step(md_handle *h, double *pos, void *vel, void *force, int32_
     launch_prepare_tab(lj, h->cfg.rc2, h->g, h->b.tab, c.s);
     // lists truncated since the last look (a build before this call overflowed):
     // grow them, rebuild and recompute the entry forces
-    int32_t f0[2];
+    int32_t f0[3];
     if ((rc = read_flags(h, c.s, f0))) return rc;
     if (f0[0] & MD_FLAG_LIST_OVERFLOW) {
         h->sticky |= (uint32_t)f0[0];
@@ -731,13 +844,12 @@ extern "C" int md_step(md_handle *h, double *pos, void *vel, void *force, int32_
         launch_fill_i32(h->b.flags, 0, 1, c.s);
     }
     if (h->truncated && h->cfg.container == MD_CONTAINER_VL) {
-        h->cfg.max_neighbors = std::min(4096, h->cfg.max_neighbors * 2);
-        if ((rc = ensure_list(h, h->cfg.max_neighbors))) return rc;
+        h->cfg.max_neighbors = std::min(4096, std::max(h->cfg.max_neighbors * 3 / 2, f0[2] + 16));
         h->built = false;
         h->truncated = false;
         if ((rc = rebuild(h, c))) return rc;
         if ((rc = forces_impl(h, c.pos, c.type, c.force, false, c.s))) return rc;
-        int32_t f1[2];
+        int32_t f1[3];
         if ((rc = read_flags(h, c.s, f1))) return rc;
         if (f1[0] & MD_FLAG_LIST_OVERFLOW) h->truncated = true;
         if (h->truncated) return fail(MD_ERR_LIST_OVERFLOW, "neighbour rows exceed max_neighbors after growth");
@@ -865,9 +977,15 @@ extern "C" int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows, in
     if (!h->built) return fail(MD_ERR_NOT_BUILT, "lists not built");
     if (max_per_row < 1 || (h->n > 0 && (!counts || !rows))) return fail(MD_ERR_INVALID_ARG, "bad arguments");
     int n = (int)h->n;
-    if (n > 0)
+    if (use_window(h->cfg, h->g)) {
+        const Geom &g = h->g;
+        launch_vlw_decode(h->b.cell_start, g, n, h->b.w_rowb + (int64_t)g.nc[1] * g.nc[2], h->b.w_i0, h->b.w_i1,
+                          h->b.w_c0, h->b.w_c1, h->b.w_nbr, h->b.nbr_count, max_per_row, counts, rows,
+                          (hipStream_t)stream);
+    } else if (n > 0) {
         k_copy_rows<<<(n + kBlock - 1) / kBlock, kBlock, 0, (hipStream_t)stream>>>(
             n, h->b.nbr, h->b.nbr_count, h->n, max_per_row, counts, rows);
+    }
     return MD_OK;
 }
 
@@ -931,7 +1049,6 @@ int apply_config(md_handle *h, const md_config &nc)
     int rc = make_geom(nc, nc.csf, g);
     if (rc) return rc;
     if ((rc = ensure_cells(h, g))) return rc;
-    if (nc.container == MD_CONTAINER_VL && (rc = ensure_list(h, nc.max_neighbors))) return rc;
     h->cfg = nc;
     h->g = g;
     h->built = false;
@@ -967,15 +1084,28 @@ int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
         MD_HIP(hipEventRecord(h->ev0, c.s));
         if ((rc = run_steps(h, c, s, s + 1))) return rc;
         MD_HIP(hipEventRecord(h->ev1, c.s));
+        int64_t rb1 = h->rebuilds;
         if ((rc = run_steps(h, c, s + 1, s + T))) return rc;
         MD_HIP(hipEventRecord(h->ev2, c.s));
         MD_HIP(hipEventSynchronize(h->ev2));
+        int64_t nrb = h->rebuilds - rb1;  // scheduled and forced rebuilds after the first step
         float t01 = 0.f, t12 = 0.f;
         MD_HIP(hipEventElapsedTime(&t01, h->ev0, h->ev1));
         MD_HIP(hipEventElapsedTime(&t12, h->ev1, h->ev2));
-        double per = (double)t12 / (double)(T - 1);
-        double build = std::max(0.0, (double)t01 - per);
-        t->report(k, per + build / (double)kc.rebuild_interval);
+        // first step = one step + one build; later steps = (T-1) steps + nrb
+        // builds (replays inflate the per-step part): solve for both, then
+        // charge builds at the rate this configuration needs them
+        double score;
+        if (T - 1 - nrb > 0) {
+            double per = ((double)t12 - (double)nrb * t01) / (double)(T - 1 - nrb);
+            per = std::max(per, 0.0);
+            double build = std::max(0.0, (double)t01 - per);
+            double rate = std::max(1.0 / kc.rebuild_interval, (double)nrb / (double)(T - 1));
+            score = per + build * rate;
+        } else {
+            score = ((double)t01 + (double)t12) / (double)T;
+        }
+        t->report(k, score);
         h->trials++;
         last_k = k;
         s += T;

@@ -1,29 +1,703 @@
-// Batched independent systems.
-#include "md_internal.h"
+// Many independent periodic systems advanced together: every phase of a time
+// step (integration, cell build, forces) is one launch over all particles of
+// all systems, and one rebuild interval of steps is captured into a HIP graph
+// and replayed.  Each system has its own cubic box, cells and fixed-point
+// scale; one particle type; linked cells, gather-only.
+//
+// Particles of system s occupy [offsets[s], offsets[s+1]) of every array.
+// Global cell ids are system-major (cell_base[s] + local id), so the counting
+// sort keeps every system inside its own range.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "pair.h"
+
+namespace mdlj {
+
+int make_geom(const md_config &c, double csf, Geom &g);
+void launch_zero(void *p, int64_t bytes, hipStream_t s);
+
+// Per-system constants (device table).
+struct BSys {
+    int nc, nofs;           // cells per dimension (cubic box), distinct offsets
+    int ofs[kMaxOfs];       // neighbour cell shifts mod nc
+    int cell_base;          // first global cell id
+    double L, inv_w, S;     // box, cells per length, fixed-point scale
+    float disp2;            // skin check threshold in fixed-point units
+    // pair constants in this box's fixed-point units (filled from lj on the device)
+    float lo, hi, sig2, eps24, eps4, eps24w;
+    double rc2, eps, sig;
+};
+
+__global__ void k_bprep(BSys *__restrict__ sys, int n_sys, const double *__restrict__ lj, double rc2)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sys) return;
+    BSys &b = sys[s];
+    double u = b.L / 4294967296.0;
+    double sig = lj[1], eps = lj[0];
+    double r2u = rc2 / (u * u);
+    b.lo = (float)(r2u * (1.0 - kBand));
+    b.hi = (float)(r2u * (1.0 + kBand));
+    b.sig2 = (float)(sig * sig / (u * u));
+    b.eps24 = (float)(24.0 * eps / u);
+    b.eps4 = (float)(4.0 * eps);
+    b.eps24w = (float)(24.0 * eps);
+    b.rc2 = rc2;
+    b.eps = eps;
+    b.sig = sig;
+}
+
+__device__ __forceinline__ int bcoord(double x, double inv_w, int nc, bool &bad)
+{
+    double t = x * inv_w;
+    if (!(t >= 0.0 && t < (double)nc + 1.0)) {
+        bad = true;
+        return t > 0.0 ? nc - 1 : 0;
+    }
+    int c = (int)t;
+    return c < nc - 1 ? c : nc - 1;
+}
+
+__device__ __forceinline__ uint32_t bquant(double x, double S)
+{
+    double q = x * S;
+    q = q < 0.0 ? 0.0 : (q > 4294967295.0 ? 4294967295.0 : q);
+    return (uint32_t)q;
+}
+
+// Cell of every particle in its own system's grid; one atomic per run of
+// equal cells in a wavefront.
+__global__ void k_bhist(int n, const double *__restrict__ pos, const int32_t *__restrict__ sys_of,
+                        const BSys *__restrict__ sys, int32_t *__restrict__ cell_id, int32_t *__restrict__ slot,
+                        int32_t *__restrict__ count, int32_t *__restrict__ flags)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int lane = threadIdx.x & 63;
+    int c = -1;
+    if (i < n) {
+        const BSys &b = sys[sys_of[i]];
+        bool bad = false;
+        size_t N = (size_t)n;
+        int cx = bcoord(pos[i], b.inv_w, b.nc, bad);
+        int cy = bcoord(pos[N + i], b.inv_w, b.nc, bad);
+        int cz = bcoord(pos[2 * N + i], b.inv_w, b.nc, bad);
+        if (bad) atomicOr(&flags[0], (int)MD_FLAG_NONFINITE);
+        c = b.cell_base + (cz * b.nc + cy) * b.nc + cx;
+        cell_id[i] = c;
+    }
+    int prev = __shfl_up(c, 1, 64);
+    bool head = lane == 0 || prev != c;
+    uint64_t heads = __ballot(head);
+    uint64_t mask = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    int hl = 63 - __builtin_clzll(heads & mask);
+    uint64_t above = heads & ~mask;
+    int next = above ? __builtin_ctzll(above) : 64;
+    int base = 0;
+    if (head && c >= 0) base = atomicAdd(&count[c], next - lane);
+    base = __shfl(base, hl, 64);
+    if (c >= 0) slot[i] = base + (lane - hl);
+}
+
+template <typename real>
+__global__ void k_bgather(int n, const int32_t *__restrict__ perm, const int32_t *__restrict__ sys_of,
+                          const BSys *__restrict__ sys, const double *__restrict__ pos, const real *__restrict__ vel,
+                          const real *__restrict__ force, const int32_t *__restrict__ type,
+                          const int32_t *__restrict__ ids, double *__restrict__ tpos, real *__restrict__ tvel,
+                          real *__restrict__ tforce, int32_t *__restrict__ ttype, int32_t *__restrict__ tids,
+                          const int32_t *__restrict__ cell_id, int32_t *__restrict__ cell_sorted,
+                          int4 *__restrict__ stage, int4 *__restrict__ stage_ref)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int src = perm[k];
+    size_t N = (size_t)n;
+    double x = pos[src], y = pos[N + src], z = pos[2 * N + src];
+    tpos[k] = x;
+    tpos[N + k] = y;
+    tpos[2 * N + k] = z;
+    for (int d = 0; d < 3; d++) {
+        tvel[d * N + k] = vel[d * N + src];
+        tforce[d * N + k] = force[d * N + src];
+    }
+    int t = type[src];
+    ttype[k] = t;
+    tids[k] = ids[src];
+    cell_sorted[k] = cell_id[src];
+    double S = sys[sys_of[k]].S;  // systems keep their particle ranges
+    int4 q;
+    q.x = (int)bquant(x, S);
+    q.y = (int)bquant(y, S);
+    q.z = (int)bquant(z, S);
+    q.w = t;
+    stage[k] = q;
+    stage_ref[k] = q;
+}
+
+__global__ void k_bstage(int n, const double *__restrict__ pos, const int32_t *__restrict__ type,
+                         const int32_t *__restrict__ sys_of, const BSys *__restrict__ sys, int4 *__restrict__ stage)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    size_t N = (size_t)n;
+    double S = sys[sys_of[k]].S;
+    stage[k] = make_int4((int)bquant(pos[k], S), (int)bquant(pos[N + k], S), (int)bquant(pos[2 * N + k], S), type[k]);
+}
+
+// Linked-cell gather force, one thread per particle, its system's geometry.
+// Writes per-particle energy partials when pe != nullptr.
+template <typename real>
+__global__ __launch_bounds__(256) void k_bforce(int n, const int4 *__restrict__ st, const double *__restrict__ pos,
+                                                const int32_t *__restrict__ sys_of, const BSys *__restrict__ sys,
+                                                const int32_t *__restrict__ cs, const int32_t *__restrict__ cell_sorted,
+                                                real *__restrict__ F, double *__restrict__ pe)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    size_t N = (size_t)n;
+    const BSys &b = sys[sys_of[i]];
+    int nc = b.nc, nofs = b.nofs;
+    int local = cell_sorted[i] - b.cell_base;
+    int cx = local % nc, cy = (local / nc) % nc, cz = local / (nc * nc);
+    double eu = 0.0, ew = 0.0, np = 0.0;
+    real fx = 0, fy = 0, fz = 0;
+    if (sizeof(real) == 4) {
+        int4 pi = st[i];
+        float lo = b.lo, hi = b.hi, sig2 = b.sig2, eps24 = b.eps24;
+        float eus = 0.f, ews = 0.f;
+        for (int a = 0; a < nofs; a++) {
+            int zz = cz + b.ofs[a];
+            zz = zz >= nc ? zz - nc : zz;
+            for (int bb = 0; bb < nofs; bb++) {
+                int yy = cy + b.ofs[bb];
+                yy = yy >= nc ? yy - nc : yy;
+                int row = b.cell_base + (zz * nc + yy) * nc;
+                for (int e = 0; e < nofs; e++) {
+                    int xx = cx + b.ofs[e];
+                    xx = xx >= nc ? xx - nc : xx;
+                    int jb = cs[row + xx], je = cs[row + xx + 1];
+                    for (int j = jb; j < je; j++) {
+                        if (j == i) continue;
+                        int4 pj = st[j];
+                        float dx, dy, dz;
+                        dx = (float)(int)((uint32_t)pi.x - (uint32_t)pj.x);
+                        dy = (float)(int)((uint32_t)pi.y - (uint32_t)pj.y);
+                        dz = (float)(int)((uint32_t)pi.z - (uint32_t)pj.z);
+                        float r2 = dx * dx + dy * dy + dz * dz;
+                        bool in = r2 < lo;
+                        if (r2 >= lo && r2 < hi) in = exact_r2(pos, n, i, j, b.L, b.L, b.L) < b.rc2;
+                        float ir2 = __builtin_amdgcn_rcpf(r2);
+                        float s2 = sig2 * ir2;
+                        float q = s2 * s2 * s2;
+                        float aa = q * (2.0f * q - 1.0f);
+                        float phi = in ? eps24 * ir2 * aa : 0.0f;
+                        fx += phi * dx;
+                        fy += phi * dy;
+                        fz += phi * dz;
+                        if (pe) {
+                            eus += in ? b.eps4 * q * (q - 1.0f) : 0.0f;
+                            ews += in ? b.eps24w * aa : 0.0f;
+                            np += in ? 1.0 : 0.0;
+                        }
+                    }
+                }
+            }
+        }
+        eu = eus;
+        ew = ews;
+    } else {
+#pragma clang fp contract(off)
+        double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
+        for (int a = 0; a < nofs; a++) {
+            int zz = cz + b.ofs[a];
+            zz = zz >= nc ? zz - nc : zz;
+            for (int bb = 0; bb < nofs; bb++) {
+                int yy = cy + b.ofs[bb];
+                yy = yy >= nc ? yy - nc : yy;
+                int row = b.cell_base + (zz * nc + yy) * nc;
+                for (int e = 0; e < nofs; e++) {
+                    int xx = cx + b.ofs[e];
+                    xx = xx >= nc ? xx - nc : xx;
+                    int jb = cs[row + xx], je = cs[row + xx + 1];
+                    for (int j = jb; j < je; j++) {
+                        if (j == i) continue;
+                        double dx = min_image(xi - pos[j], b.L);
+                        double dy = min_image(yi - pos[N + j], b.L);
+                        double dz = min_image(zi - pos[2 * N + j], b.L);
+                        double r2 = dx * dx + dy * dy + dz * dz;
+                        if (!(r2 < b.rc2)) continue;
+                        double phi, u;
+                        lj_f64(r2, b.eps, b.sig, phi, u);
+                        fx += (real)(phi * dx);
+                        fy += (real)(phi * dy);
+                        fz += (real)(phi * dz);
+                        eu += u;
+                        ew += phi * r2;
+                        np += 1.0;
+                    }
+                }
+            }
+        }
+    }
+    F[i] = fx;
+    F[N + i] = fy;
+    F[2 * N + i] = fz;
+    if (pe) {
+        pe[i] = eu;
+        pe[N + i] = ew;
+        pe[2 * N + i] = np;
+    }
+}
+
+// Velocity Verlet pass (as the single-system integrator) with per-system box.
+template <typename real>
+__global__ __launch_bounds__(256) void k_bintegrate(int n, double *__restrict__ pos, real *__restrict__ v,
+                                                    const real *__restrict__ F, const int32_t *__restrict__ type,
+                                                    const double *__restrict__ inv_mass, const int32_t *__restrict__ sys_of,
+                                                    const BSys *__restrict__ sys, double hdt, double dt, int kick_prev,
+                                                    int start, int step, int4 *__restrict__ stage,
+                                                    const int4 *__restrict__ stage_ref, int32_t *__restrict__ flags)
+{
+#pragma clang fp contract(off)
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    size_t N = (size_t)n;
+    int t = type[i];
+    real c = (real)(hdt * inv_mass[t]);
+    real vx = v[i], vy = v[N + i], vz = v[2 * N + i];
+    real ax = c * F[i], ay = c * F[N + i], az = c * F[2 * N + i];
+    if (kick_prev) {
+        vx += ax;
+        vy += ay;
+        vz += az;
+    }
+    if (start) {
+        vx += ax;
+        vy += ay;
+        vz += az;
+        const BSys &b = sys[sys_of[i]];
+        double L = b.L;
+        double xs[3] = {pos[i] + dt * (double)vx, pos[N + i] + dt * (double)vy, pos[2 * N + i] + dt * (double)vz};
+        uint32_t q[3];
+        for (int d = 0; d < 3; d++) {
+            double x = xs[d];
+            if (x >= L) x -= L;
+            else if (x < 0.0) x += L;
+            if (x >= L) x = 0.0;
+            pos[d * N + i] = x;
+            q[d] = bquant(x, b.S);
+            if (!(x == x)) atomicOr(&flags[0], (int)MD_FLAG_NONFINITE);
+        }
+        stage[i] = make_int4((int)q[0], (int)q[1], (int)q[2], t);
+        int4 r = stage_ref[i];
+        float dx = (float)(int)(q[0] - (uint32_t)r.x);
+        float dy = (float)(int)(q[1] - (uint32_t)r.y);
+        float dz = (float)(int)(q[2] - (uint32_t)r.z);
+        if (dx * dx + dy * dy + dz * dz >= b.disp2) {
+            atomicOr(&flags[0], (int)MD_FLAG_SKIN_EXCEEDED);
+            atomicMin(&flags[1], step);
+        }
+    }
+    v[i] = vx;
+    v[N + i] = vy;
+    v[2 * N + i] = vz;
+}
+
+// Per-system sums of the per-particle energy partials, in a fixed order.
+__global__ void k_bsys_reduce(int n, const int64_t *__restrict__ offs, const double *__restrict__ pe, int fp32,
+                              double *__restrict__ out)
+{
+    __shared__ double sh[16];
+    int s = blockIdx.x;
+    size_t N = (size_t)n;
+    double v[4] = {0, 0, 0, 0};
+    for (int64_t i = offs[s] + threadIdx.x; i < offs[s + 1]; i += blockDim.x) {
+        v[0] += pe[i];
+        v[1] += pe[N + i];
+        v[2] += pe[2 * N + i];
+    }
+    block_sum4(v, sh);
+    if (threadIdx.x == 0) {
+        out[4 * s + 0] = 0.5 * v[0];
+        out[4 * s + 1] = 0.5 * v[1];
+        out[4 * s + 2] = 0.5 * v[2];
+        out[4 * s + 3] = 0.0;
+    }
+    (void)fp32;
+}
+
+}  // namespace mdlj
 
 using namespace mdlj;
 
+// ------------------------------------------------------------------ handle
+
 struct md_batch {
-    int dummy;
+    md_config cfg;
+    int n_sys = 0;
+    int64_t n = 0;
+    int device = 0;
+    std::vector<int64_t> offsets;
+    std::vector<BSys> hsys;
+    BSys *sys = nullptr;
+    int64_t *d_offs = nullptr;
+    int32_t *sys_of = nullptr;
+    int64_t ncell = 0;
+    int32_t *cell_id = nullptr, *slot = nullptr, *perm = nullptr, *perm2 = nullptr, *count = nullptr,
+            *cell_start = nullptr, *cell_sorted = nullptr, *scan = nullptr;
+    double *tpos = nullptr;
+    void *tvel = nullptr, *tforce = nullptr;
+    int32_t *ttype = nullptr, *tids = nullptr;
+    int4 *stage = nullptr, *stage_ref = nullptr;
+    double *pe = nullptr;
+    double *snap_pos = nullptr;
+    void *snap_vel = nullptr;
+    int32_t *flags = nullptr;
+    uint32_t *host_flags = nullptr;
+    bool built = false;
+    // captured rebuild interval
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    const void *graph_key[8] = {nullptr};
+    double graph_dt = 0.0;
+    int graph_R = 0;
+    hipStream_t cap = nullptr;  // capture stream
 };
 
-extern "C" int md_batch_create(const md_config *, int32_t, const int64_t *, const double *, md_batch **out)
+static size_t bsize(const md_config &c) { return c.precision == MD_FP64 ? 8 : 4; }
+
+static void batch_free(md_batch *b)
 {
-    if (out) *out = nullptr;
-    return fail(MD_ERR_INVALID_ARG, "batched systems are not available in this build");
+    void *p[] = {b->sys,   b->d_offs, b->sys_of, b->cell_id,  b->slot,      b->perm,       b->perm2,
+                 b->count, b->cell_start, b->cell_sorted, b->scan, b->tpos,  b->tvel,       b->tforce,
+                 b->ttype, b->tids,   b->stage,  b->stage_ref, b->pe,       b->snap_pos,   b->snap_vel, b->flags};
+    for (void *q : p)
+        if (q) (void)hipFree(q);
+    if (b->host_flags) (void)hipHostFree(b->host_flags);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
 }
-extern "C" void md_batch_destroy(md_batch *b) { delete b; }
-extern "C" int md_batch_build_cells(md_batch *, double *, void *, void *, int32_t *, int32_t *, void *)
+
+extern "C" int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_t *offsets, const double *boxes,
+                               md_batch **out)
 {
-    return fail(MD_ERR_INVALID_ARG, "batched systems are not available in this build");
+    if (!out) return fail(MD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cfg || !offsets || !boxes || n_sys < 1) return fail(MD_ERR_INVALID_ARG, "bad arguments");
+    if (cfg->n_types != 1) return fail(MD_ERR_INVALID_ARG, "batched systems hold one particle type");
+    if (cfg->precision != MD_FP32 && cfg->precision != MD_FP64) return fail(MD_ERR_INVALID_ARG, "bad precision");
+    if (!(cfg->rc2[0] > 0.0) || !(cfg->skin >= 0.0) || !(cfg->csf >= 0.5 && cfg->csf <= 1.0))
+        return fail(MD_ERR_INVALID_ARG, "bad cutoff, skin or csf");
+    if (cfg->rebuild_interval < 1) return fail(MD_ERR_INVALID_ARG, "rebuild_interval must be >= 1");
+    if (offsets[0] != 0) return fail(MD_ERR_INVALID_ARG, "offsets[0] must be 0");
+    for (int s = 0; s < n_sys; s++)
+        if (offsets[s + 1] < offsets[s]) return fail(MD_ERR_INVALID_ARG, "offsets must be non-decreasing");
+    if (offsets[n_sys] > (int64_t)INT32_MAX / 3) return fail(MD_ERR_INVALID_ARG, "too many particles");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MD_ERR_NO_DEVICE, "no HIP device");
+    md_batch *b = new md_batch();
+    b->cfg = *cfg;
+    b->n_sys = n_sys;
+    b->n = offsets[n_sys];
+    b->offsets.assign(offsets, offsets + n_sys + 1);
+    (void)hipGetDevice(&b->device);
+    int64_t cells = 0;
+    for (int s = 0; s < n_sys; s++) {
+        const double *bx = boxes + 3 * s;
+        if (!(bx[0] > 0.0) || bx[0] != bx[1] || bx[1] != bx[2]) {
+            delete b;
+            return fail(MD_ERR_INVALID_ARG, "batched boxes must be cubic (system " + std::to_string(s) + ")");
+        }
+        md_config c = *cfg;
+        c.box[0] = c.box[1] = c.box[2] = bx[0];
+        Geom g;
+        int rc = make_geom(c, cfg->csf, g);
+        if (rc) {
+            delete b;
+            return fail(rc, "system " + std::to_string(s) + ": " + md_last_error());
+        }
+        BSys y;
+        memset(&y, 0, sizeof(y));
+        y.nc = g.nc[0];
+        y.nofs = g.nofs[0];
+        for (int k = 0; k < kMaxOfs; k++) y.ofs[k] = g.ofs[0][k];
+        y.cell_base = (int)cells;
+        y.L = bx[0];
+        y.inv_w = g.inv_w[0];
+        y.S = g.S[0];
+        y.disp2 = g.disp2;
+        cells += g.ncell;
+        if (cells > (int64_t)1 << 30) {
+            delete b;
+            return fail(MD_ERR_INVALID_ARG, "too many cells");
+        }
+        b->hsys.push_back(y);
+    }
+    b->ncell = cells;
+    int64_t n = std::max<int64_t>(b->n, 1);
+    size_t rs = bsize(*cfg);
+    std::vector<int32_t> sys_of(n, 0);
+    for (int s = 0; s < n_sys; s++)
+        for (int64_t i = offsets[s]; i < offsets[s + 1]; i++) sys_of[i] = s;
+    bool ok = true;
+    auto A = [&](void **p, size_t bytes) {
+        if (ok && hipMalloc(p, bytes ? bytes : 1) != hipSuccess) ok = false;
+    };
+    A((void **)&b->sys, sizeof(BSys) * n_sys);
+    A((void **)&b->d_offs, sizeof(int64_t) * (n_sys + 1));
+    A((void **)&b->sys_of, 4 * n);
+    A((void **)&b->cell_id, 4 * n);
+    A((void **)&b->slot, 4 * n);
+    A((void **)&b->perm, 4 * n);
+    A((void **)&b->perm2, 4 * n);
+    A((void **)&b->cell_sorted, 4 * n);
+    A((void **)&b->count, 4 * (cells + 1));
+    A((void **)&b->cell_start, 4 * (cells + 1));
+    A((void **)&b->scan, 4 * (scan_scratch_size(cells + 1) + 64));
+    A((void **)&b->tpos, 24 * n);
+    A(&b->tvel, 3 * rs * n);
+    A(&b->tforce, 3 * rs * n);
+    A((void **)&b->ttype, 4 * n);
+    A((void **)&b->tids, 4 * n);
+    A((void **)&b->stage, 16 * n);
+    A((void **)&b->stage_ref, 16 * n);
+    A((void **)&b->pe, 24 * n);
+    A((void **)&b->snap_pos, 24 * n);
+    A(&b->snap_vel, 3 * rs * n);
+    A((void **)&b->flags, 16);
+    if (ok && hipHostMalloc((void **)&b->host_flags, 16, 0) != hipSuccess) ok = false;
+    if (ok) ok = hipMemcpy(b->sys, b->hsys.data(), sizeof(BSys) * n_sys, hipMemcpyHostToDevice) == hipSuccess;
+    if (ok) ok = hipMemcpy(b->d_offs, offsets, sizeof(int64_t) * (n_sys + 1), hipMemcpyHostToDevice) == hipSuccess;
+    if (ok) ok = hipMemcpy(b->sys_of, sys_of.data(), 4 * n, hipMemcpyHostToDevice) == hipSuccess;
+    int32_t init[4] = {0, INT32_MAX, 0, 0};
+    if (ok) ok = hipMemcpy(b->flags, init, sizeof(init), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        batch_free(b);
+        delete b;
+        return fail(MD_ERR_HIP, "device allocation failed");
+    }
+    *out = b;
+    return MD_OK;
 }
-extern "C" int md_batch_compute_forces(md_batch *, const double *, const int32_t *, const double *, void *, double *,
-                                       void *)
+
+extern "C" void md_batch_destroy(md_batch *b)
 {
-    return fail(MD_ERR_INVALID_ARG, "batched systems are not available in this build");
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    batch_free(b);
+    delete b;
 }
-extern "C" int md_batch_step(md_batch *, double *, void *, void *, int32_t *, int32_t *, const double *,
-                             const double *, double, int32_t, int32_t, void *)
+
+static int bblocks(int64_t n) { return (int)((n + 255) / 256); }
+
+static int batch_rebuild(md_batch *b, double *pos, void *vel, void *force, int32_t *type, int32_t *ids,
+                         hipStream_t s)
 {
-    return fail(MD_ERR_INVALID_ARG, "batched systems are not available in this build");
+    int n = (int)b->n;
+    size_t rs = bsize(b->cfg);
+    launch_fill_i32(b->count, 0, b->ncell, s);
+    if (n > 0) k_bhist<<<bblocks(n), 256, 0, s>>>(n, pos, b->sys_of, b->sys, b->cell_id, b->slot, b->count, b->flags);
+    launch_scan(b->count, b->cell_start, b->ncell, b->scan, s);
+    launch_scatter(n, b->cell_id, b->slot, b->cell_start, b->perm, s);
+    launch_cell_sort(n, b->cell_start, ids, b->cell_id, b->perm, b->slot, b->cell_sorted, b->perm2, s);
+    if (n > 0) {
+        if (b->cfg.precision == MD_FP64)
+            k_bgather<double><<<bblocks(n), 256, 0, s>>>(
+                n, b->perm2, b->sys_of, b->sys, pos, (const double *)vel, (const double *)force, type, ids, b->tpos,
+                (double *)b->tvel, (double *)b->tforce, b->ttype, b->tids, b->cell_id, b->cell_sorted, b->stage,
+                b->stage_ref);
+        else
+            k_bgather<float><<<bblocks(n), 256, 0, s>>>(n, b->perm2, b->sys_of, b->sys, pos, (const float *)vel,
+                                                        (const float *)force, type, ids, b->tpos, (float *)b->tvel,
+                                                        (float *)b->tforce, b->ttype, b->tids, b->cell_id,
+                                                        b->cell_sorted, b->stage, b->stage_ref);
+        MD_HIP(hipMemcpyAsync(pos, b->tpos, 24 * (size_t)n, hipMemcpyDeviceToDevice, s));
+        MD_HIP(hipMemcpyAsync(vel, b->tvel, 3 * rs * n, hipMemcpyDeviceToDevice, s));
+        MD_HIP(hipMemcpyAsync(force, b->tforce, 3 * rs * n, hipMemcpyDeviceToDevice, s));
+        MD_HIP(hipMemcpyAsync(type, b->ttype, 4 * (size_t)n, hipMemcpyDeviceToDevice, s));
+        MD_HIP(hipMemcpyAsync(ids, b->tids, 4 * (size_t)n, hipMemcpyDeviceToDevice, s));
+    }
+    b->built = true;
+    return MD_OK;
+}
+
+static void batch_forces(md_batch *b, const double *pos, void *force, bool energy, hipStream_t s)
+{
+    int n = (int)b->n;
+    if (n <= 0) return;
+    if (b->cfg.precision == MD_FP64)
+        k_bforce<double><<<bblocks(n), 256, 0, s>>>(n, b->stage, pos, b->sys_of, b->sys, b->cell_start,
+                                                    b->cell_sorted, (double *)force, energy ? b->pe : nullptr);
+    else
+        k_bforce<float><<<bblocks(n), 256, 0, s>>>(n, b->stage, pos, b->sys_of, b->sys, b->cell_start,
+                                                   b->cell_sorted, (float *)force, energy ? b->pe : nullptr);
+}
+
+static void batch_integrate(md_batch *b, double *pos, void *vel, const void *force, const int32_t *type,
+                            const double *inv_mass, double dt, int kick_prev, int start, int step, hipStream_t s)
+{
+    int n = (int)b->n;
+    if (n <= 0) return;
+    if (b->cfg.precision == MD_FP64)
+        k_bintegrate<double><<<bblocks(n), 256, 0, s>>>(n, pos, (double *)vel, (const double *)force, type, inv_mass,
+                                                        b->sys_of, b->sys, 0.5 * dt, dt, kick_prev, start, step,
+                                                        b->stage, b->stage_ref, b->flags);
+    else
+        k_bintegrate<float><<<bblocks(n), 256, 0, s>>>(n, pos, (float *)vel, (const float *)force, type, inv_mass,
+                                                       b->sys_of, b->sys, 0.5 * dt, dt, kick_prev, start, step,
+                                                       b->stage, b->stage_ref, b->flags);
+}
+
+extern "C" int md_batch_build_cells(md_batch *b, double *pos, void *vel, void *force, int32_t *type, int32_t *ids,
+                                    void *stream)
+{
+    if (!b) return fail(MD_ERR_INVALID_ARG, "batch is NULL");
+    if (b->n > 0 && (!pos || !vel || !force || !type || !ids))
+        return fail(MD_ERR_INVALID_ARG, "pos, vel, force, type, ids must not be NULL");
+    MD_HIP(hipSetDevice(b->device));
+    return batch_rebuild(b, pos, vel, force, type, ids, (hipStream_t)stream);
+}
+
+extern "C" int md_batch_compute_forces(md_batch *b, const double *pos, const int32_t *type, const double *lj,
+                                       void *force, double *out, void *stream)
+{
+    if (!b) return fail(MD_ERR_INVALID_ARG, "batch is NULL");
+    if (!lj || (b->n > 0 && (!pos || !type || !force))) return fail(MD_ERR_INVALID_ARG, "NULL argument");
+    if (!b->built) return fail(MD_ERR_NOT_BUILT, "md_batch_build_cells must be called first");
+    MD_HIP(hipSetDevice(b->device));
+    hipStream_t s = (hipStream_t)stream;
+    k_bprep<<<(b->n_sys + 255) / 256, 256, 0, s>>>(b->sys, b->n_sys, lj, b->cfg.rc2[0]);
+    int n = (int)b->n;
+    if (n > 0) k_bstage<<<bblocks(n), 256, 0, s>>>(n, pos, type, b->sys_of, b->sys, b->stage);
+    batch_forces(b, pos, force, out != nullptr, s);
+    if (out) {
+        if (n == 0) launch_zero(b->pe, 24, s);
+        k_bsys_reduce<<<b->n_sys, 256, 0, s>>>(n, b->d_offs, b->pe, b->cfg.precision == MD_FP32, out);
+    }
+    return MD_OK;
+}
+
+// One rebuild interval starting at step s0 (first step: integrate, rebuild,
+// snapshot, forces; then R - 1 plain steps).  The skin-check step indices are
+// relative to the block, so the same sequence can be captured and replayed.
+struct BatchCtx {
+    double *pos;
+    void *vel, *force;
+    int32_t *type, *ids;
+    const double *inv_mass;
+    double dt;
+    hipStream_t s;
+};
+
+static int batch_block_ops(md_batch *b, const BatchCtx &c, int len, bool first_of_run)
+{
+    size_t rs = bsize(b->cfg);
+    size_t n = (size_t)b->n;
+    launch_fill_i32(b->flags + 1, INT32_MAX, 1, c.s);
+    batch_integrate(b, c.pos, c.vel, c.force, c.type, c.inv_mass, c.dt, first_of_run ? 0 : 1, 1, 0, c.s);
+    int rc = batch_rebuild(b, c.pos, c.vel, c.force, c.type, c.ids, c.s);
+    if (rc) return rc;
+    launch_fill_i32(b->flags + 1, INT32_MAX, 1, c.s);  // the check restarts from this build
+    if (n > 0) {
+        MD_HIP(hipMemcpyAsync(b->snap_pos, c.pos, 24 * n, hipMemcpyDeviceToDevice, c.s));
+        MD_HIP(hipMemcpyAsync(b->snap_vel, c.vel, 3 * rs * n, hipMemcpyDeviceToDevice, c.s));
+    }
+    batch_forces(b, c.pos, c.force, false, c.s);
+    for (int k = 1; k < len; k++) {
+        batch_integrate(b, c.pos, c.vel, c.force, c.type, c.inv_mass, c.dt, 1, 1, k, c.s);
+        batch_forces(b, c.pos, c.force, false, c.s);
+    }
+    return MD_OK;
+}
+
+static int batch_read_flags(md_batch *b, hipStream_t s, int32_t f[2])
+{
+    MD_HIP(hipMemcpyAsync(b->host_flags, b->flags, 8, hipMemcpyDeviceToHost, s));
+    MD_HIP(hipStreamSynchronize(s));
+    f[0] = (int32_t)b->host_flags[0];
+    f[1] = (int32_t)b->host_flags[1];
+    return MD_OK;
+}
+
+extern "C" int md_batch_step(md_batch *b, double *pos, void *vel, void *force, int32_t *type, int32_t *ids,
+                             const double *inv_mass, const double *lj, double dt, int32_t nsteps, int32_t use_graph,
+                             void *stream)
+{
+    if (!b) return fail(MD_ERR_INVALID_ARG, "batch is NULL");
+    if (!inv_mass || !lj || (b->n > 0 && (!pos || !vel || !force || !type || !ids)))
+        return fail(MD_ERR_INVALID_ARG, "NULL argument");
+    if (nsteps < 0 || !(dt > 0.0)) return fail(MD_ERR_INVALID_ARG, "bad nsteps or dt");
+    if (!b->built) return fail(MD_ERR_NOT_BUILT, "md_batch_build_cells must be called first");
+    if (nsteps == 0) return MD_OK;
+    MD_HIP(hipSetDevice(b->device));
+    hipStream_t s = (hipStream_t)stream;
+    k_bprep<<<(b->n_sys + 255) / 256, 256, 0, s>>>(b->sys, b->n_sys, lj, b->cfg.rc2[0]);
+    BatchCtx c{pos, vel, force, type, ids, inv_mass, dt, s};
+    int R = b->cfg.rebuild_interval;
+    size_t rs = bsize(b->cfg);
+    size_t n = (size_t)b->n;
+    const void *key[8] = {pos, vel, force, type, ids, inv_mass, lj, stream};
+    int st = 0;
+    while (st < nsteps) {
+        int len = std::min(R, nsteps - st);
+        bool graphable = use_graph && st > 0 && len == R;
+        int rc;
+        if (graphable) {
+            bool same = b->exec && b->graph_R == R && b->graph_dt == dt && memcmp(key, b->graph_key, sizeof(key)) == 0;
+            if (!same) {
+                if (b->exec) (void)hipGraphExecDestroy(b->exec);
+                if (b->graph) (void)hipGraphDestroy(b->graph);
+                b->exec = nullptr;
+                b->graph = nullptr;
+                // capture on a stream of our own (the caller's may be the
+                // null stream, which cannot be captured); replay on theirs
+                if (!b->cap) MD_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+                BatchCtx cc = c;
+                cc.s = b->cap;
+                MD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+                rc = batch_block_ops(b, cc, R, false);
+                hipGraph_t gr = nullptr;
+                hipError_t e = hipStreamEndCapture(b->cap, &gr);
+                if (rc) return rc;
+                if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+                b->graph = gr;
+                MD_HIP(hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0));
+                memcpy(b->graph_key, key, sizeof(key));
+                b->graph_dt = dt;
+                b->graph_R = R;
+            }
+            MD_HIP(hipGraphLaunch(b->exec, s));
+        } else {
+            if ((rc = batch_block_ops(b, c, len, st == 0))) return rc;
+        }
+        int32_t f[2];
+        if ((rc = batch_read_flags(b, s, f))) return rc;
+        int v = f[1];
+        if (v >= 1 && v < len) {
+            // a particle outgrew the skin at block step v: redo steps 1 .. v-1
+            // from the snapshot taken after the block's rebuild; the next
+            // block starts at step v with a rebuild
+            if (n > 0) {
+                MD_HIP(hipMemcpyAsync(pos, b->snap_pos, 24 * n, hipMemcpyDeviceToDevice, s));
+                MD_HIP(hipMemcpyAsync(vel, b->snap_vel, 3 * rs * n, hipMemcpyDeviceToDevice, s));
+            }
+            batch_forces(b, pos, force, false, s);
+            for (int k = 1; k < v; k++) {
+                batch_integrate(b, pos, vel, force, type, inv_mass, dt, 1, 1, k, s);
+                batch_forces(b, pos, force, false, s);
+            }
+            st += v;
+        } else {
+            st += len;
+        }
+    }
+    // final half kick
+    batch_integrate(b, pos, vel, force, type, inv_mass, dt, 1, 0, 0, s);
+    return MD_OK;
 }

@@ -58,20 +58,37 @@ __device__ __forceinline__ int4 stage_of(double x, double y, double z, int t, co
 
 // ------------------------------------------------------------------ K1: histogram
 
+// Particles arrive mostly in the previous cell order, so consecutive lanes
+// usually share a cell: one atomic per run of equal cells in a wavefront,
+// the run's lanes take consecutive slots.
 __global__ void k_cell_hist(int n, const double *__restrict__ pos, Geom g, int32_t *__restrict__ cell_id,
                             int32_t *__restrict__ slot, int32_t *__restrict__ count,
                             int32_t *__restrict__ flags)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    bool bad = false;
-    int cx = cell_coord(pos[i], g.inv_w[0], g.nc[0], bad);
-    int cy = cell_coord(pos[n + i], g.inv_w[1], g.nc[1], bad);
-    int cz = cell_coord(pos[2 * (size_t)n + i], g.inv_w[2], g.nc[2], bad);
-    if (bad) atomicOr(&flags[0], (int)MD_FLAG_NONFINITE);
-    int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
-    cell_id[i] = c;
-    slot[i] = atomicAdd(&count[c], 1);
+    int lane = threadIdx.x & 63;
+    int c = -1;
+    if (i < n) {
+        bool bad = false;
+        int cx = cell_coord(pos[i], g.inv_w[0], g.nc[0], bad);
+        int cy = cell_coord(pos[n + i], g.inv_w[1], g.nc[1], bad);
+        int cz = cell_coord(pos[2 * (size_t)n + i], g.inv_w[2], g.nc[2], bad);
+        if (bad) atomicOr(&flags[0], (int)MD_FLAG_NONFINITE);
+        c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+        cell_id[i] = c;
+    }
+    int prev = __shfl_up(c, 1, 64);
+    bool head = lane == 0 || prev != c;
+    uint64_t heads = __ballot(head);
+    // run of lane: from its head (highest head bit <= lane) to the next head
+    uint64_t below = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+    int hl = 63 - __builtin_clzll(below);
+    uint64_t above = heads & ~(lane == 63 ? ~0ull : ((2ull << lane) - 1));
+    int next = above ? __builtin_ctzll(above) : 64;
+    int base = 0;
+    if (head && c >= 0) base = atomicAdd(&count[c], next - lane);
+    base = __shfl(base, hl, 64);
+    if (c >= 0) slot[i] = base + (lane - hl);
 }
 
 void launch_cell_hist(int n, const double *pos, const Geom &g, int32_t *cell_id, int32_t *slot,
@@ -220,31 +237,43 @@ void launch_scatter(int n, const int32_t *cell_id, const int32_t *slot, const in
     k_scatter<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(n, cell_id, slot, start, perm);
 }
 
-// The atomic histogram leaves each cell's members in arbitrary order; sort
-// every cell's segment by id (insertion sort, one thread per cell: cells hold
-// tens of particles) so the cell contents are deterministic.
-__global__ void k_cell_sort(int ncell, const int32_t *__restrict__ start, const int32_t *__restrict__ ids,
-                            int32_t *__restrict__ perm)
+// The atomic histogram leaves each cell's members in arbitrary order; order
+// every cell's segment by id so that the cell contents are deterministic.
+// Slot k's key and cell are gathered first; then each slot's rank among its
+// cell's keys (ids are distinct) gives its final place.  Cells hold tens of
+// particles, so each rank is a short scan of contiguous keys.
+__global__ void k_cell_keys(int n, const int32_t *__restrict__ perm, const int32_t *__restrict__ ids,
+                            const int32_t *__restrict__ cell_id, int32_t *__restrict__ key,
+                            int32_t *__restrict__ cell_of_slot)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    int b = start[c], e = start[c + 1];
-    for (int k = b + 1; k < e; k++) {
-        int v = perm[k];
-        int key = ids[v];
-        int m = k - 1;
-        while (m >= b && ids[perm[m]] > key) {
-            perm[m + 1] = perm[m];
-            m--;
-        }
-        perm[m + 1] = v;
-    }
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int p = perm[k];
+    key[k] = ids[p];
+    cell_of_slot[k] = cell_id[p];
 }
 
-void launch_cell_sort(int ncell, const int32_t *start, const int32_t *ids, int32_t *perm, hipStream_t s)
+__global__ void k_cell_rank(int n, const int32_t *__restrict__ start, const int32_t *__restrict__ key,
+                            const int32_t *__restrict__ cell_of_slot, const int32_t *__restrict__ perm,
+                            int32_t *__restrict__ perm_out)
 {
-    if (ncell <= 0) return;
-    k_cell_sort<<<(ncell + kBlock - 1) / kBlock, kBlock, 0, s>>>(ncell, start, ids, perm);
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int c = cell_of_slot[k];
+    int b = start[c], e = start[c + 1];
+    int kk = key[k];
+    int r = 0;
+    for (int m = b; m < e; m++) r += key[m] < kk ? 1 : 0;
+    perm_out[b + r] = perm[k];
+}
+
+void launch_cell_sort(int n, const int32_t *start, const int32_t *ids, const int32_t *cell_id, const int32_t *perm,
+                      int32_t *key, int32_t *cell_of_slot, int32_t *perm_out, hipStream_t s)
+{
+    if (n <= 0) return;
+    int nb = (n + kBlock - 1) / kBlock;
+    k_cell_keys<<<nb, kBlock, 0, s>>>(n, perm, ids, cell_id, key, cell_of_slot);
+    k_cell_rank<<<nb, kBlock, 0, s>>>(n, start, key, cell_of_slot, perm, perm_out);
 }
 
 // ------------------------------------------------------------------ K4: gather + stage

@@ -101,6 +101,8 @@ __global__ __launch_bounds__(kBlock) void k_lc_f32(int n, const int4 *__restrict
                                                    double *__restrict__ partials)
 {
     __shared__ double sh[4 * kBlock / 64];
+    __shared__ int so[3][kMaxOfs];
+    load_offsets(g, so);
     TabF<NT> t;
     t.load(tabp);
     AccF32<NT, ISO, ENERGY, N3L> acc;
@@ -111,12 +113,12 @@ __global__ __launch_bounds__(kBlock) void k_lc_f32(int n, const int4 *__restrict
         int cx, cy, cz;
         cell_xyz(cell_sorted[i], g, cx, cy, cz);
         for (int a = 0; a < g.nofs[2]; a++) {
-            int zz = wrap_add(cz, g.ofs[2][a], g.nc[2]);
+            int zz = wrap_add(cz, so[2][a], g.nc[2]);
             for (int b = 0; b < g.nofs[1]; b++) {
-                int yy = wrap_add(cy, g.ofs[1][b], g.nc[1]);
+                int yy = wrap_add(cy, so[1][b], g.nc[1]);
                 int row = (zz * g.nc[1] + yy) * g.nc[0];
                 for (int e = 0; e < g.nofs[0]; e++) {
-                    int cj = row + wrap_add(cx, g.ofs[0][e], g.nc[0]);
+                    int cj = row + wrap_add(cx, so[0][e], g.nc[0]);
                     int jb = cell_start[cj], je = cell_start[cj + 1];
                     for (int j = jb; j < je; j++) {
                         if (N3L ? j <= i : j == i) continue;
@@ -214,6 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_lc_f64(int n, const int32_t *__restr
                                                    double *__restrict__ partials)
 {
     __shared__ double sh[4 * kBlock / 64];
+    __shared__ int so[3][kMaxOfs];
+    load_offsets(g, so);
     AccF64<N3L> acc;
     acc.i = blockIdx.x * kBlock + threadIdx.x;
     if (acc.i < n) {
@@ -226,12 +230,12 @@ __global__ __launch_bounds__(kBlock) void k_lc_f64(int n, const int32_t *__restr
         int cx, cy, cz;
         cell_xyz(cell_sorted[i], g, cx, cy, cz);
         for (int a = 0; a < g.nofs[2]; a++) {
-            int zz = wrap_add(cz, g.ofs[2][a], g.nc[2]);
+            int zz = wrap_add(cz, so[2][a], g.nc[2]);
             for (int b = 0; b < g.nofs[1]; b++) {
-                int yy = wrap_add(cy, g.ofs[1][b], g.nc[1]);
+                int yy = wrap_add(cy, so[1][b], g.nc[1]);
                 int row = (zz * g.nc[1] + yy) * g.nc[0];
                 for (int e = 0; e < g.nofs[0]; e++) {
-                    int cj = row + wrap_add(cx, g.ofs[0][e], g.nc[0]);
+                    int cj = row + wrap_add(cx, so[0][e], g.nc[0]);
                     int jb = cell_start[cj], je = cell_start[cj + 1];
                     for (int j = jb; j < je; j++) {
                         if (N3L ? j <= i : j == i) continue;
@@ -294,6 +298,8 @@ __global__ __launch_bounds__(kBlock) void k_vl_build(int n, const int4 *__restri
                                                      int32_t *__restrict__ nbr, int32_t *__restrict__ cnt,
                                                      int64_t ld, int maxn, int32_t *__restrict__ flags)
 {
+    __shared__ int so[3][kMaxOfs];
+    load_offsets(g, so);
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     int4 pi = st[i];
@@ -301,12 +307,12 @@ __global__ __launch_bounds__(kBlock) void k_vl_build(int n, const int4 *__restri
     cell_xyz(cell_sorted[i], g, cx, cy, cz);
     int c = 0;
     for (int a = 0; a < g.nofs[2]; a++) {
-        int zz = wrap_add(cz, g.ofs[2][a], g.nc[2]);
+        int zz = wrap_add(cz, so[2][a], g.nc[2]);
         for (int b = 0; b < g.nofs[1]; b++) {
-            int yy = wrap_add(cy, g.ofs[1][b], g.nc[1]);
+            int yy = wrap_add(cy, so[1][b], g.nc[1]);
             int row = (zz * g.nc[1] + yy) * g.nc[0];
             for (int e = 0; e < g.nofs[0]; e++) {
-                int cj = row + wrap_add(cx, g.ofs[0][e], g.nc[0]);
+                int cj = row + wrap_add(cx, so[0][e], g.nc[0]);
                 int jb = cell_start[cj], je = cell_start[cj + 1];
                 for (int j = jb; j < je; j++) {
                     if (half ? j <= i : j == i) continue;
@@ -322,6 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_vl_build(int n, const int4 *__restri
         }
     }
     if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
+    atomicMax(&flags[2], c);
     cnt[i] = c < maxn ? c : maxn;
 }
 
@@ -341,7 +348,12 @@ void launch_vl_build(int n, const int4 *stage, const int32_t *cell_start, const 
 
 // ------------------------------------------------------------------ dispatch
 
-int force_blocks(const ForceArgs &a) { return (a.n + kBlock - 1) / kBlock; }
+int force_blocks(const ForceArgs &a)
+{
+    if (a.n <= 0) return 0;
+    if (a.window) return window_force_blocks();
+    return (a.n + kBlock - 1) / kBlock;
+}
 
 template <int NT, bool ISO, bool EN, bool N3>
 static void launch_f32(const ForceArgs &a, const Geom &g, hipStream_t s)
@@ -386,6 +398,10 @@ void launch_force(const ForceArgs &a, const Geom &g, hipStream_t s)
     if (a.n <= 0) return;
     if (a.container == MD_CONTAINER_CL) {
         launch_cluster_force(a, g, s);
+        return;
+    }
+    if (a.window) {
+        launch_window_force(a, g, s);
         return;
     }
     if (a.precision == MD_FP64) {

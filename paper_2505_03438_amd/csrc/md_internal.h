@@ -52,11 +52,12 @@ struct Geom {
     float rl2_lo, rl2_hi;  // guard band of rl2 in u^2
     float disp2;      // (skin/2)^2 (1 - 1e-4) in u^2: skin check threshold
     int nt;           // number of types
+    int reach[3];     // stencil reach in cells per dimension
 };
 
 // Device buffers and state of one handle.
 struct Buffers {
-    int32_t *cell_id = nullptr, *slot = nullptr, *perm = nullptr;
+    int32_t *cell_id = nullptr, *slot = nullptr, *perm = nullptr, *perm2 = nullptr;
     int32_t *cell_count = nullptr, *cell_start = nullptr, *cell_sorted = nullptr;
     int32_t *scan_blocks = nullptr;
     double *tmp_pos = nullptr;
@@ -81,6 +82,11 @@ struct Buffers {
     void *snap_vel = nullptr, *snap_force = nullptr;
     int32_t *snap_type = nullptr, *snap_ids = nullptr;
     int4 *snap_stage = nullptr;
+    // Verlet lists over LDS windows (FP32 gather-only)
+    int32_t *w_i0 = nullptr, *w_i1 = nullptr, *w_c0 = nullptr, *w_c1 = nullptr;
+    int32_t *w_rown = nullptr, *w_rowb = nullptr;
+    uint16_t *w_nbr = nullptr;
+    int64_t w_cap = 0, w_rows_cap = 0, w_nbr_cap = 0;
     // adjoint
     double *gpart = nullptr;     // per-block parameter-gradient partials [blocks][8]
     uint32_t *host_flags = nullptr;  // pinned
@@ -108,8 +114,8 @@ int64_t scan_scratch_size(int64_t n);
 void launch_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch, hipStream_t s);
 void launch_scatter(int n, const int32_t *cell_id, const int32_t *slot, const int32_t *start,
                     int32_t *perm, hipStream_t s);
-void launch_cell_sort(int ncell, const int32_t *start, const int32_t *ids, int32_t *perm,
-                      hipStream_t s);
+void launch_cell_sort(int n, const int32_t *start, const int32_t *ids, const int32_t *cell_id, const int32_t *perm,
+                      int32_t *key, int32_t *cell_of_slot, int32_t *perm_out, hipStream_t s);
 void launch_gather(int n, int precision, const int32_t *perm, const double *pos, const void *vel,
                    const void *force, const int32_t *type, const int32_t *ids, double *tpos,
                    void *tvel, void *tforce, int32_t *ttype, int32_t *tids, const int32_t *cell_id,
@@ -141,9 +147,29 @@ struct ForceArgs {
     void *force;
     double *partials;  // per-block {U, W, n_pairs, 0}
     int32_t *flags;
+    // window lists
+    bool window;
+    const int32_t *w_nblk, *w_i0, *w_i1, *w_c0, *w_c1;
+    const uint16_t *w_nbr;
 };
 int force_blocks(const ForceArgs &a);  // number of partial slots written when energy
 void launch_force(const ForceArgs &a, const Geom &g, hipStream_t s);
+
+// window.hip
+int64_t window_block_cap(int64_t n, const Geom &g);
+int window_force_blocks();
+void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *row_n, int32_t *row_base,
+                   int32_t *scan_scratch, int32_t *i0, int32_t *i1, int32_t *c0, int32_t *c1, int cap,
+                   int32_t *flags, hipStream_t s);
+void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
+                      const Geom &g, int n, const int32_t *nblk_p, const int32_t *i0, const int32_t *i1,
+                      const int32_t *c0, const int32_t *c1, uint16_t *nbr, int32_t *cnt, int maxn, int32_t *flags,
+                      hipStream_t s);
+void launch_window_force(const ForceArgs &a, const Geom &g, hipStream_t s);
+bool window_geometry_ok(const Geom &g);
+void launch_vlw_decode(const int32_t *cs, const Geom &g, int n, const int32_t *nblk_p, const int32_t *i0,
+                       const int32_t *i1, const int32_t *c0, const int32_t *c1, const uint16_t *nbr,
+                       const int32_t *cnt, int maxr, int32_t *counts, int32_t *rows, hipStream_t s);
 void launch_vl_build(int n, const int4 *stage, const int32_t *cell_start, const int32_t *cell_sorted,
                      const double *pos, const Geom &g, int half, int32_t *nbr, int32_t *cnt,
                      int64_t ld, int maxn, int32_t *flags, hipStream_t s);

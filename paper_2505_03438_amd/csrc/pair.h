@@ -44,6 +44,21 @@ struct TabF {
     }
 };
 
+// Stencil offsets copied out of the by-value geometry with constant indices
+// into LDS: indexing the kernel-argument struct with a run-time index would
+// make the compiler copy the whole struct to scratch memory.  Ends with a
+// barrier.
+__device__ __forceinline__ void load_offsets(const Geom &g, int (*so)[kMaxOfs])
+{
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int k = 0; k < kMaxOfs; k++) so[d][k] = g.ofs[d][k];
+    }
+    __syncthreads();
+}
+
 // Exact FP64 squared minimum-image distance of particles i and j, in the
 // fixed order of the plain definition: d = x_i - x_j; if d > L/2, d -= L,
 // else if d < -L/2, d += L; r2 = dx*dx + dy*dy + dz*dz; no FMA contraction.

@@ -108,7 +108,7 @@ int Tuner::end_phase()
 void tuning_space(const md_config &base, std::vector<md_config> &space)
 {
     space.clear();
-    const int Rs[3] = {5, 10, 20};
+    const int Rs[3] = {4, 6, 10};
     for (int r = 0; r < 3; r++) {
         md_config c = base;
         c.rebuild_interval = Rs[r];

@@ -42,7 +42,7 @@ private:
 // The GPU configuration space the autotuner explores for a base config:
 // linked cells (CSF 1 and 0.5) and Verlet lists, gather-only or with
 // Newton's third law, cluster lists (gather-only), rebuild intervals
-// {5, 10, 20}.
+// {4, 6, 10}.
 void tuning_space(const md_config &base, std::vector<md_config> &space);
 
 }  // namespace mdlj

@@ -1,0 +1,650 @@
+// Pair traversals over LDS windows (FP32, gather-only).
+//
+// Particles are in linked-cell order (cells x-fastest, within a cell by id).
+// A block is a run of consecutive cells of one x-row holding at most 256
+// particles (one workgroup, one thread per particle).  Its window is the
+// union of its cells' stencils: for every neighbouring (y, z) row the
+// contiguous cell columns [x_first - 1, x_last + 1] (two particle ranges, or
+// pieces, when they wrap around the periodic box).  The block packer bounds
+// every window to the LDS tile.  A workgroup stages the window once, then:
+//   - linked cells: each thread scans its own stencil cells inside the
+//     window (the GPU analogue of the C01 traversal: no write conflicts);
+//   - Verlet lists: each thread walks its list of 16-bit window positions,
+//     stored in chunks of eight (one 16-byte load per chunk, the next chunk
+//     in flight while the current one is computed).
+// Blocks of neighbouring cells share most of their windows, so the blocks
+// are dealt to the eight XCDs in contiguous chunks (workgroup w runs on XCD
+// w mod 8) to keep the shared window data in one L2.
+#include "pair.h"
+
+namespace mdlj {
+
+constexpr int kWinMax = 3072;    // LDS window capacity (int4 entries, 48 KB)
+constexpr int kBlkCells = 32;    // maximum cells of a block along x
+constexpr int kMaxRows = 9;      // stencil rows of a reach-1 window (3 x 3)
+constexpr int kMaxCols = kBlkCells + 2;  // window columns of a reach-1 window
+constexpr int kLoadPer = (kWinMax + 255) / 256;
+constexpr int kWinGrid = 2048;   // persistent workgroups (multiple of 8)
+
+using Ofs = int (*)[kMaxOfs];
+using COfs = const int (*)[kMaxOfs];
+
+// ------------------------------------------------------------------ windows
+
+// Columns [lo, hi] of the window of a block spanning xa..xb (hi < lo when it
+// wraps); returns the number of columns.
+__device__ __forceinline__ int window_columns(const Geom &g, int xa, int xb, int &lo, int &hi)
+{
+    int nx = g.nc[0];
+    if (xb - xa + 3 >= nx) {
+        lo = 0;
+        hi = nx - 1;
+        return nx;
+    }
+    lo = xa == 0 ? nx - 1 : xa - 1;
+    hi = xb + 1 == nx ? 0 : xb + 1;
+    return xb - xa + 3;
+}
+
+// Linear id of the x = 0 cell of stencil row rr around row (cy, cz).
+__device__ __forceinline__ int row_cell_of(const Geom &g, COfs so, int cy, int cz, int rr)
+{
+    int a = rr / g.nofs[1], b = rr - a * g.nofs[1];
+    int zz = cz + so[2][a];
+    zz = zz >= g.nc[2] ? zz - g.nc[2] : zz;
+    int yy = cy + so[1][b];
+    yy = yy >= g.nc[1] ? yy - g.nc[1] : yy;
+    return (zz * g.nc[1] + yy) * g.nc[0];
+}
+
+// Window layout in LDS.  Column m of stencil row rr is cell column
+// (lo + m) mod nx; its particles occupy window positions
+// [col[rr][m], col[rr][m + 1]).  Piece k (two per row, the second empty
+// unless the columns wrap) holds particles [pc_start[k], ...) at window
+// positions [pc_win[k], pc_win[k + 1]).
+struct Window {
+    int nrow, ncols, lo, self_row, W;
+    int pc_start[2 * kMaxRows];
+    int pc_win[2 * kMaxRows + 1];
+    int col[kMaxRows][kMaxCols + 1];
+};
+
+// Lay out the window of the block with cells c0..c1 (one row).  All threads
+// take part; ends with a barrier.
+__device__ void make_window(const Geom &g, COfs so, const int32_t *__restrict__ cs, int c0, int c1, Window &w)
+{
+    int nx = g.nc[0];
+    int xa = c0 % nx, xb = c1 % nx;
+    int r = c0 / nx;
+    int cy = r % g.nc[1], cz = r / g.nc[1];
+    int lo, hi;
+    int ncols = window_columns(g, xa, xb, lo, hi);
+    int nrow = g.nofs[1] * g.nofs[2];
+    int t = threadIdx.x;
+    bool wrap = hi < lo;
+    int x1a = wrap ? nx - 1 : hi;
+    if (t < nrow) {
+        int rb = row_cell_of(g, so, cy, cz, t);
+        int s0 = cs[rb + lo], e0 = cs[rb + x1a + 1];
+        int s1 = cs[rb], e1 = wrap ? cs[rb + hi + 1] : s1;
+        w.pc_start[2 * t] = s0;
+        w.pc_start[2 * t + 1] = s1;
+        w.pc_win[2 * t] = e0 - s0;  // lengths for now
+        w.pc_win[2 * t + 1] = e1 - s1;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int pos = 0;
+        for (int k = 0; k < 2 * nrow; k++) {
+            int len = w.pc_win[k];
+            w.pc_win[k] = pos;
+            pos += len;
+        }
+        w.pc_win[2 * nrow] = pos;
+        w.W = pos;
+        w.nrow = nrow;
+        w.ncols = ncols;
+        w.lo = lo;
+        int a0 = 0, b0 = 0;
+        for (int a = 0; a < g.nofs[2]; a++)
+            if (so[2][a] == 0) a0 = a;
+        for (int b = 0; b < g.nofs[1]; b++)
+            if (so[1][b] == 0) b0 = b;
+        w.self_row = a0 * g.nofs[1] + b0;
+    }
+    __syncthreads();
+    int ncol0 = x1a - lo + 1;  // columns in the first piece
+    for (int e = t; e < nrow * (ncols + 1); e += blockDim.x) {
+        int rr = e / (ncols + 1), m = e - rr * (ncols + 1);
+        int v;
+        if (m == ncols) {
+            v = w.pc_win[2 * rr + 2];
+        } else {
+            int rb = row_cell_of(g, so, cy, cz, rr);
+            if (m < ncol0)
+                v = w.pc_win[2 * rr] + cs[rb + lo + m] - w.pc_start[2 * rr];
+            else
+                v = w.pc_win[2 * rr + 1] + cs[rb + m - ncol0] - w.pc_start[2 * rr + 1];
+        }
+        w.col[rr][m] = v;
+    }
+    __syncthreads();
+}
+
+// Piece holding window position p, searching forward from piece k.
+__device__ __forceinline__ int piece_from(const Window &w, int k, int p)
+{
+    while (k + 1 < 2 * w.nrow && w.pc_win[k + 1] <= p) k++;
+    return k;
+}
+
+// Global particle index of window position p (rare paths).
+__device__ __forceinline__ int window_global(const Window &w, int p)
+{
+    int k = piece_from(w, 0, p);
+    return w.pc_start[k] + (p - w.pc_win[k]);
+}
+
+// Stage the window into LDS, four loads in flight per thread (named
+// registers: an array here would be placed in scratch memory).
+__device__ __forceinline__ void load_window(const Window &w, const int4 *__restrict__ st, int4 *lds)
+{
+    int W = w.W;
+    int k = 0;
+    for (int p0 = threadIdx.x; p0 < W; p0 += 1024) {
+        int p1 = p0 + 256, p2 = p0 + 512, p3 = p0 + 768;
+        int4 a0, a1 = a0, a2 = a0, a3 = a0;
+        k = piece_from(w, k, p0);
+        a0 = st[w.pc_start[k] + (p0 - w.pc_win[k])];
+        if (p1 < W) {
+            k = piece_from(w, k, p1);
+            a1 = st[w.pc_start[k] + (p1 - w.pc_win[k])];
+        }
+        if (p2 < W) {
+            k = piece_from(w, k, p2);
+            a2 = st[w.pc_start[k] + (p2 - w.pc_win[k])];
+        }
+        if (p3 < W) {
+            k = piece_from(w, k, p3);
+            a3 = st[w.pc_start[k] + (p3 - w.pc_win[k])];
+        }
+        lds[p0] = a0;
+        if (p1 < W) lds[p1] = a1;
+        if (p2 < W) lds[p2] = a2;
+        if (p3 < W) lds[p3] = a3;
+    }
+}
+
+// XCD-aware block order: workgroup w runs on XCD w % 8; each XCD takes a
+// contiguous chunk of blocks.
+struct BlockIter {
+    int blk, end, stride;
+    __device__ BlockIter(int nblk)
+    {
+        int chunk = (nblk + 7) / 8;
+        int xcd = blockIdx.x & 7;
+        stride = gridDim.x >> 3;
+        blk = xcd * chunk + (blockIdx.x >> 3);
+        end = min(nblk, (xcd + 1) * chunk);
+    }
+};
+
+// Window range of the cell column x + (e-th x offset) in stencil row rr.
+__device__ __forceinline__ void stencil_range(const Geom &g, COfs so, const Window &w, int x, int rr, int e, int &b,
+                                              int &en)
+{
+    int nx = g.nc[0];
+    int xx = x + so[0][e];
+    xx = xx >= nx ? xx - nx : xx;
+    int m = xx - w.lo;
+    m = m < 0 ? m + nx : m;
+    b = w.col[rr][m];
+    en = w.col[rr][m + 1];
+}
+
+// ------------------------------------------------------------------ block partition
+
+// Particles in the 9 stencil rows at column x of each cell: the window of a
+// block spanning columns xa..xb is the sum over its window columns.
+__global__ void k_colsum(Geom g, const int32_t *__restrict__ cs, int32_t *__restrict__ colsum)
+{
+    __shared__ int so[3][kMaxOfs];
+    load_offsets(g, so);
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell) return;
+    int nx = g.nc[0];
+    int x = c % nx, r = c / nx;
+    int cy = r % g.nc[1], cz = r / g.nc[1];
+    int nrow = g.nofs[1] * g.nofs[2];
+    int s = 0;
+    for (int rr = 0; rr < nrow; rr++) {
+        int cell = row_cell_of(g, so, cy, cz, rr) + x;
+        s += cs[cell + 1] - cs[cell];
+    }
+    colsum[c] = s;
+}
+
+// Greedy packing of one x-row: a block starts at a non-empty cell and grows
+// while it holds <= 256 particles, spans at most kBlkCells columns and its
+// window fits the LDS tile.  emit == false only counts.  A single cell of
+// more than 256 particles, or whose window alone exceeds the tile, cannot be
+// held: flags[3] reports it.
+__device__ int pack_row(int row, const Geom &g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
+                        int base, int32_t *i0, int32_t *i1, int32_t *c0, int32_t *c1, bool emit, int cap,
+                        int32_t *flags)
+{
+    int nx = g.nc[0];
+    int rb = row * nx;
+    int rowsum = 0;
+    for (int x = 0; x < nx; x++) rowsum += colsum[rb + x];
+    auto col = [&](int k) { return colsum[rb + (k < 0 ? k + nx : (k >= nx ? k - nx : k))]; };
+    // window of a block spanning xa..xb: the column sums of xa-1 .. xb+1
+    // (the whole row once the columns cover it); extended one column at a
+    // time as a block grows
+    auto window_of = [&](int xa, int xb) {
+        if (xb - xa + 3 >= nx) return rowsum;
+        int s = 0;
+        for (int k = xa - 1; k <= xb + 1; k++) s += col(k);
+        return s;
+    };
+    int nb = 0;
+    int bs = -1, bp = 0, bx0 = 0, bxl = 0, bw = 0;  // open block: first particle, particles, x range, window
+    auto close = [&]() {
+        if (bs >= 0 && bp > 0) {
+            if (emit && base + nb < cap) {
+                i0[base + nb] = bs;
+                i1[base + nb] = bs + bp;
+                c0[base + nb] = rb + bx0;
+                c1[base + nb] = rb + bxl;
+            }
+            nb++;
+        }
+        bs = -1;
+        bp = 0;
+    };
+    for (int x = 0; x < nx; x++) {
+        int s = cs[rb + x], e = cs[rb + x + 1];
+        int m = e - s;
+        if (m == 0) continue;
+        if (bs >= 0) {
+            // window of [bx0, x] from that of [bx0, bxl]: add columns bxl+2 .. x+1
+            int w2;
+            if (x - bx0 + 3 >= nx) {
+                w2 = rowsum;
+            } else {
+                w2 = bw;
+                for (int k = bxl + 2; k <= x + 1; k++) w2 += col(k);
+            }
+            if (bp + m > 256 || x - bx0 >= kBlkCells || w2 > kWinMax) close();
+            else bw = w2;
+        }
+        if (bs < 0) {
+            bs = s;
+            bx0 = x;
+            bw = window_of(x, x);
+            if (emit && (m > 256 || bw > kWinMax)) atomicOr(&flags[3], 1);
+        }
+        bp += m;
+        bxl = x;
+    }
+    close();
+    (void)bw;
+    return nb;
+}
+
+__global__ void k_blk_count(const Geom g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
+                            int32_t *__restrict__ row_n)
+{
+    int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= g.nc[1] * g.nc[2]) return;
+    row_n[row] = pack_row(row, g, cs, colsum, 0, nullptr, nullptr, nullptr, nullptr, false, 0, nullptr);
+}
+
+__global__ void k_blk_write(const Geom g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
+                            const int32_t *__restrict__ row_base, int32_t *i0, int32_t *i1, int32_t *c0, int32_t *c1,
+                            int cap, int32_t *flags)
+{
+    int row = blockIdx.x * blockDim.x + threadIdx.x;
+    int nrows = g.nc[1] * g.nc[2];
+    if (row >= nrows) return;
+    pack_row(row, g, cs, colsum, row_base[row], i0, i1, c0, c1, true, cap, flags);
+}
+
+// Common head of the windowed kernels: lay out and stage the window of
+// block blk; returns false (uniformly) if it does not fit the tile.
+__device__ __forceinline__ bool setup_block(const Geom &g, COfs so, const int32_t *__restrict__ cs,
+                                            const int4 *__restrict__ st, int c0, int c1, Window &w, int4 *win,
+                                            int32_t *flags)
+{
+    __syncthreads();
+    make_window(g, so, cs, c0, c1, w);
+    if (w.W > kWinMax) {  // cannot happen for the blocks the packer makes; never overrun the tile
+        if (threadIdx.x == 0) atomicOr(&flags[3], 2);
+        return false;
+    }
+    load_window(w, st, win);
+    __syncthreads();
+    return true;
+}
+
+// Window position of particle i (in cell ci) itself.
+__device__ __forceinline__ int self_position(const Geom &g, const Window &w, const int32_t *__restrict__ cs, int i,
+                                             int ci, int &x)
+{
+    x = ci % g.nc[0];
+    int m = x - w.lo;
+    m = m < 0 ? m + g.nc[0] : m;
+    return w.col[w.self_row][m] + (i - cs[ci]);
+}
+
+// ------------------------------------------------------------------ linked cells
+
+template <int NT, bool ISO, bool ENERGY>
+__global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
+                                                 const int32_t *__restrict__ cell_sorted, Geom g, int n,
+                                                 const int32_t *__restrict__ nblk_p, int cap,
+                                                 const int32_t *__restrict__ bi0, const int32_t *__restrict__ bi1,
+                                                 const int32_t *__restrict__ bc0, const int32_t *__restrict__ bc1,
+                                                 const PairTab *__restrict__ tabp, const double *__restrict__ pos,
+                                                 float *__restrict__ F, double *__restrict__ partials,
+                                                 int32_t *__restrict__ flags)
+{
+    __shared__ int4 win[kWinMax];
+    __shared__ Window w;
+    __shared__ double sh[16];
+    __shared__ int so[3][kMaxOfs];
+    load_offsets(g, so);
+    TabF<NT> t;
+    t.load(tabp);
+    float eu = 0.f, ew = 0.f;
+    int np = 0;
+    size_t N = (size_t)n;
+    for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
+        int blk = it.blk;
+        if (!setup_block(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
+        int i = bi0[blk] + threadIdx.x;
+        if (i >= bi1[blk]) continue;
+        int x;
+        int self = self_position(g, w, cs, i, cell_sorted[i], x);
+        int4 pi = win[self];
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        for (int rr = 0; rr < w.nrow; rr++)
+            for (int e = 0; e < g.nofs[0]; e++) {
+                int b, en;
+                stencil_range(g, so, w, x, rr, e, b, en);
+                for (int p = b; p < en; p++) {
+                    if (p == self) continue;
+                    int4 pj = win[p];
+                    float dx, dy, dz;
+                    staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+                    float r2 = dx * dx + dy * dy + dz * dz;
+                    int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
+                    float lo = t.pick(t.lo, ab), hi = t.pick(t.hi, ab);
+                    bool in = r2 < lo;
+                    if (r2 >= lo && r2 < hi)
+                        in = exact_r2(pos, n, i, window_global(w, p), g.L[0], g.L[1], g.L[2]) < t.pickd(t.rc2, ab);
+                    float phi = lj_f32<NT, ENERGY>(r2, ab, in, t, eu, ew, np);
+                    fx += phi * dx;
+                    fy += phi * dy;
+                    fz += phi * dz;
+                }
+            }
+        F[i] = fx;
+        F[N + i] = fy;
+        F[2 * N + i] = fz;
+    }
+    if (ENERGY) {
+        double v[4] = {(double)eu, (double)ew, (double)np, 0.0};
+        block_sum4(v, sh);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 4; k++) partials[blockIdx.x * 4 + k] = v[k];
+    }
+}
+
+// ------------------------------------------------------------------ Verlet lists
+
+// List entry c of particle i: nbr[((c / 8) * n + i) * 8 + c % 8].
+__device__ __forceinline__ size_t list_slot(int c, int i, size_t N) { return ((size_t)(c >> 3) * N + i) * 8 + (c & 7); }
+
+template <bool ISO>
+__global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
+                                                   const int32_t *__restrict__ cell_sorted,
+                                                   const double *__restrict__ pos, Geom g, int n,
+                                                   const int32_t *__restrict__ nblk_p, int cap,
+                                                   const int32_t *__restrict__ bi0, const int32_t *__restrict__ bi1,
+                                                   const int32_t *__restrict__ bc0, const int32_t *__restrict__ bc1,
+                                                   uint16_t *__restrict__ nbr, int32_t *__restrict__ cnt, int maxn,
+                                                   int32_t *__restrict__ flags)
+{
+    __shared__ int4 win[kWinMax];
+    __shared__ Window w;
+    __shared__ int so[3][kMaxOfs];
+    load_offsets(g, so);
+    size_t N = (size_t)n;
+    int cmax = 0;
+    for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
+        int blk = it.blk;
+        if (!setup_block(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
+        int i = bi0[blk] + threadIdx.x;
+        if (i >= bi1[blk]) continue;
+        int x;
+        int self = self_position(g, w, cs, i, cell_sorted[i], x);
+        int4 pi = win[self];
+        int c = 0;
+        for (int rr = 0; rr < w.nrow; rr++)
+            for (int e = 0; e < g.nofs[0]; e++) {
+                int b, en;
+                stencil_range(g, so, w, x, rr, e, b, en);
+                for (int p = b; p < en; p++) {
+                    if (p == self) continue;
+                    float dx, dy, dz;
+                    staged_delta<ISO>(pi, win[p], g, dx, dy, dz);
+                    float r2 = dx * dx + dy * dy + dz * dz;
+                    bool in = r2 < g.rl2_lo;
+                    if (r2 >= g.rl2_lo && r2 < g.rl2_hi)
+                        in = exact_r2(pos, n, i, window_global(w, p), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                    if (in) {
+                        if (c < maxn) nbr[list_slot(c, i, N)] = (uint16_t)p;
+                        c++;
+                    }
+                }
+            }
+        if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
+        cmax = max(cmax, c);
+        cnt[i] = c < maxn ? c : maxn;
+    }
+    if (cmax > 0) atomicMax(&flags[2], cmax);
+}
+
+template <int NT, bool ISO, bool ENERGY>
+__global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs, Geom g,
+                                                 int n, const int32_t *__restrict__ nblk_p, int cap,
+                                                 const int32_t *__restrict__ bi0, const int32_t *__restrict__ bi1,
+                                                 const int32_t *__restrict__ bc0, const int32_t *__restrict__ bc1,
+                                                 const uint16_t *__restrict__ nbr, const int32_t *__restrict__ cnt,
+                                                 const PairTab *__restrict__ tabp, const double *__restrict__ pos,
+                                                 float *__restrict__ F, double *__restrict__ partials,
+                                                 int32_t *__restrict__ flags)
+{
+    __shared__ int4 win[kWinMax];
+    __shared__ Window w;
+    __shared__ double sh[16];
+    __shared__ int so[3][kMaxOfs];
+    load_offsets(g, so);
+    TabF<NT> t;
+    t.load(tabp);
+    float eu = 0.f, ew = 0.f;
+    int np = 0;
+    size_t N = (size_t)n;
+    const uint4 *chunks = (const uint4 *)nbr;
+    for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
+        int blk = it.blk;
+        if (!setup_block(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
+        int i = bi0[blk] + threadIdx.x;
+        if (i >= bi1[blk]) continue;
+        int4 pi = st[i];
+        int c = cnt[i];
+        int nch = (c + 7) >> 3;
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        uint4 cur = nch > 0 ? chunks[i] : make_uint4(0, 0, 0, 0);
+        for (int ch = 0; ch < nch; ch++) {
+            uint4 nxt = ch + 1 < nch ? chunks[(size_t)(ch + 1) * N + i] : cur;
+            int valid = min(8, c - ch * 8);
+            uint32_t amb = 0;  // entries inside the guard band, decided below
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                uint32_t word = u < 2 ? cur.x : (u < 4 ? cur.y : (u < 6 ? cur.z : cur.w));
+                int p = (word >> ((u & 1) * 16)) & 0xffff;
+                if (u >= valid) p = 0;
+                int4 pj = win[p];
+                float dx, dy, dz;
+                staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+                float r2 = dx * dx + dy * dy + dz * dz;
+                int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
+                float lo = t.pick(t.lo, ab), hi = t.pick(t.hi, ab);
+                bool in = r2 < lo && u < valid;
+                amb |= (r2 >= lo && r2 < hi && u < valid) ? 1u << u : 0u;
+                float phi = lj_f32<NT, ENERGY>(r2, ab, in, t, eu, ew, np);
+                fx += phi * dx;
+                fy += phi * dy;
+                fz += phi * dz;
+            }
+            // rare: pairs within the guard band of the cutoff are decided
+            // from the FP64 positions, and added when inside
+            while (amb) {
+                int u = __builtin_ctz(amb);
+                amb &= amb - 1;
+                uint32_t word = u < 2 ? cur.x : (u < 4 ? cur.y : (u < 6 ? cur.z : cur.w));
+                int p = (word >> ((u & 1) * 16)) & 0xffff;
+                int4 pj = win[p];
+                int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
+                if (exact_r2(pos, n, i, window_global(w, p), g.L[0], g.L[1], g.L[2]) < t.pickd(t.rc2, ab)) {
+                    float dx, dy, dz;
+                    staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+                    float r2 = dx * dx + dy * dy + dz * dz;
+                    float phi = lj_f32<NT, ENERGY>(r2, ab, true, t, eu, ew, np);
+                    fx += phi * dx;
+                    fy += phi * dy;
+                    fz += phi * dz;
+                }
+            }
+            cur = nxt;
+        }
+        F[i] = fx;
+        F[N + i] = fy;
+        F[2 * N + i] = fz;
+    }
+    if (ENERGY) {
+        double v[4] = {(double)eu, (double)ew, (double)np, 0.0};
+        block_sum4(v, sh);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 4; k++) partials[blockIdx.x * 4 + k] = v[k];
+    }
+}
+
+// Decode the window lists back to global indices (inspection).
+__global__ void k_vlw_decode(const int32_t *__restrict__ cs, Geom g, int n, const int32_t *__restrict__ nblk_p, int cap,
+                             const int32_t *__restrict__ bi0, const int32_t *__restrict__ bi1,
+                             const int32_t *__restrict__ bc0, const int32_t *__restrict__ bc1,
+                             const uint16_t *__restrict__ nbr, const int32_t *__restrict__ cnt, int maxr,
+                             int32_t *__restrict__ counts, int32_t *__restrict__ rows)
+{
+    __shared__ Window w;
+    __shared__ int so[3][kMaxOfs];
+    load_offsets(g, so);
+    size_t N = (size_t)n;
+    int nblk = min(*nblk_p, cap);
+    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        __syncthreads();
+        make_window(g, so, cs, bc0[blk], bc1[blk], w);
+        int i = bi0[blk] + threadIdx.x;
+        if (i >= bi1[blk]) continue;
+        int c = cnt[i];
+        counts[i] = c;
+        for (int k = 0; k < c && k < maxr; k++) rows[(size_t)i * maxr + k] = window_global(w, nbr[list_slot(k, i, N)]);
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+int64_t window_block_cap(int64_t n, const Geom &g) { return n + (int64_t)g.nc[1] * g.nc[2] + 16; }
+
+bool window_geometry_ok(const Geom &g)
+{
+    return g.reach[0] == 1 && g.reach[1] == 1 && g.reach[2] == 1 && g.nofs[1] * g.nofs[2] <= kMaxRows;
+}
+
+void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *row_n, int32_t *row_base,
+                   int32_t *scan_scratch, int32_t *i0, int32_t *i1, int32_t *c0, int32_t *c1, int cap,
+                   int32_t *flags, hipStream_t s)
+{
+    int nrows = g.nc[1] * g.nc[2];
+    k_colsum<<<(g.ncell + 255) / 256, 256, 0, s>>>(g, cs, colsum);
+    k_blk_count<<<(nrows + 63) / 64, 64, 0, s>>>(g, cs, colsum, row_n);
+    launch_scan(row_n, row_base, nrows, scan_scratch, s);
+    k_blk_write<<<(nrows + 63) / 64, 64, 0, s>>>(g, cs, colsum, row_base, i0, i1, c0, c1, cap, flags);
+}
+
+void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
+                      const Geom &g, int n, const int32_t *nblk_p, const int32_t *i0, const int32_t *i1,
+                      const int32_t *c0, const int32_t *c1, uint16_t *nbr, int32_t *cnt, int maxn, int32_t *flags,
+                      hipStream_t s)
+{
+    if (n <= 0) return;
+    int cap = (int)window_block_cap(n, g);
+    if (g.iso)
+        k_vlw_build<true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, i0, i1, c0, c1, nbr,
+                                                    cnt, maxn, flags);
+    else
+        k_vlw_build<false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, i0, i1, c0, c1, nbr,
+                                                     cnt, maxn, flags);
+}
+
+int window_force_blocks() { return kWinGrid; }
+
+template <int NT, bool ISO, bool EN>
+static void win_launch(const ForceArgs &a, const Geom &g, hipStream_t s)
+{
+    int cap = (int)window_block_cap(a.n, g);
+    if (a.container == MD_CONTAINER_VL)
+        k_vlw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, g, a.n, a.w_nblk, cap, a.w_i0, a.w_i1,
+                                                       a.w_c0, a.w_c1, a.w_nbr, a.nbr_count, a.tab, a.pos,
+                                                       (float *)a.force, a.partials, a.flags);
+    else
+        k_lcw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
+                                                       a.w_i0, a.w_i1, a.w_c0, a.w_c1, a.tab, a.pos,
+                                                       (float *)a.force, a.partials, a.flags);
+}
+
+void launch_window_force(const ForceArgs &a, const Geom &g, hipStream_t s)
+{
+    if (a.n <= 0) return;
+    if (g.nt == 1) {
+        if (g.iso) {
+            if (a.energy) win_launch<1, true, true>(a, g, s);
+            else win_launch<1, true, false>(a, g, s);
+        } else {
+            if (a.energy) win_launch<1, false, true>(a, g, s);
+            else win_launch<1, false, false>(a, g, s);
+        }
+    } else {
+        if (g.iso) {
+            if (a.energy) win_launch<2, true, true>(a, g, s);
+            else win_launch<2, true, false>(a, g, s);
+        } else {
+            if (a.energy) win_launch<2, false, true>(a, g, s);
+            else win_launch<2, false, false>(a, g, s);
+        }
+    }
+}
+
+void launch_vlw_decode(const int32_t *cs, const Geom &g, int n, const int32_t *nblk_p, const int32_t *i0,
+                       const int32_t *i1, const int32_t *c0, const int32_t *c1, const uint16_t *nbr,
+                       const int32_t *cnt, int maxr, int32_t *counts, int32_t *rows, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_vlw_decode<<<kWinGrid, 256, 0, s>>>(cs, g, n, nblk_p, (int)window_block_cap(n, g), i0, i1, c0, c1, nbr, cnt,
+                                          maxr, counts, rows);
+}
+
+}  // namespace mdlj
