@@ -57,7 +57,8 @@ extern "C" {
 /* containers (Sec. 2.2.1) */
 #define MD_CONTAINER_LC 0 /* linked cells                                  */
 #define MD_CONTAINER_VL 1 /* Verlet lists with skin, rebuilt every R steps  */
-#define MD_CONTAINER_CL 2 /* cluster-pair lists (8-particle clusters)       */
+#define MD_CONTAINER_CL 2 /* cluster-pair lists (8-particle clusters; FP32,
+                             gather-only)                                   */
 
 /* traversal (Sec. 2.2.2, Table 1: N3L column) */
 #define MD_N3L_OFF 0 /* each pair evaluated from both sides, gather only  */
@@ -90,7 +91,9 @@ typedef struct md_config {
     int32_t container;     /* MD_CONTAINER_*                                   */
     int32_t newton3;       /* MD_N3L_OFF / MD_N3L_ON                           */
     int32_t rebuild_interval; /* R >= 1: rebuild cells and lists every R steps */
-    int32_t max_neighbors; /* Verlet-list row capacity                         */
+    int32_t max_neighbors; /* list row capacity: particles per Verlet row, or
+                              j-clusters per i-cluster for cluster lists;
+                              grown by md_step when a build overflows it      */
     int32_t autotune;      /* MD_TUNE_*; on: md_step selects the configuration */
     int32_t tune_interval; /* steps between tuning phases                      */
     int32_t tune_trial_steps; /* steps each trialled configuration runs        */
@@ -114,7 +117,8 @@ void md_destroy(md_handle *h);
 /* Linked cells (Sec. 2.2.1): bin the particles into cells of side
  * >= csf (r_c,max + skin) stretched to fit the box, by a counting sort, and
  * reorder pos, vel, force, type and ids IN PLACE into cell order (cells in
- * x-fastest linear order; within a cell by ascending ids).  ids carries each
+ * x-fastest linear order; within a cell by ascending ids, or for cluster
+ * lists by the 6-bit Morton code of the position inside the cell, then id).  ids carries each
  * particle's caller-defined identity through every reordering.  vel and force
  * may be NULL (then they are not permuted).  Also stages the positions for
  * the pair kernels and records them as the reference for the skin check. */
@@ -169,11 +173,14 @@ int md_forces_backward(md_handle *h, const double *pos, const int32_t *type,
  *   n_compute_units, skin }.  Synchronises the stream. */
 int md_live_stats(md_handle *h, const double *pos, double *out, void *stream);
 
-/* Copy the current Verlet lists out (Verlet-list container only): counts
- * (DEVICE int32[n]) gets each particle's number of entries, rows (DEVICE
+/* Copy the current lists out (Verlet or cluster-pair lists): counts (DEVICE
+ * int32[n]) gets each particle's number of entries, rows (DEVICE
  * int32[n][max_per_row], row-major) its entries, both in the cell order the
- * arrays are in.  Rows longer than max_per_row are truncated.  For
- * inspection and tests. */
+ * arrays are in.  For cluster lists a particle's entries are all particles of
+ * the j-clusters listed for its cluster, itself excluded: a superset of its
+ * partners within r_c + skin.  Rows longer than max_per_row are truncated
+ * (counts still give the full length).  MD_ERR_INVALID_ARG for linked cells.
+ * For inspection and tests. */
 int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows,
                      int32_t max_per_row, void *stream);
 

@@ -132,7 +132,8 @@ static void free_buffers(md_handle *h)
     void *ptrs[] = {b.cell_id, b.slot, b.perm, b.perm2, b.cell_count, b.cell_start, b.cell_sorted, b.scan_blocks,
                     b.tmp_pos, b.tmp_vel, b.tmp_force, b.tmp_type, b.tmp_ids, b.stage, b.stage_ref,
                     b.nbr, b.nbr_count, b.partials, b.kpart, b.flags, b.tab, b.facc, b.cl_start,
-                    b.cl_count, b.cl_bbox, b.cl_nbr, b.cl_nbr_count, b.snap_pos, b.snap_vel,
+                    b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
+                    b.cl_nbr_count, b.snap_pos, b.snap_vel,
                     b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart, b.w_i0, b.w_i1,
                     b.w_c0, b.w_c1, b.w_rown, b.w_rowb, b.w_nbr};
     for (void *p : ptrs)
@@ -178,6 +179,9 @@ static int ensure_cells(md_handle *h, const Geom &g)
     return MD_OK;
 }
 
+// Containers that keep neighbour lists (Verlet lists, cluster-pair lists).
+static bool has_lists(const md_config &c) { return c.container != MD_CONTAINER_LC; }
+
 static int ensure_list(md_handle *h, int64_t maxn)
 {
     if (maxn <= h->b.nbr_cap && h->b.nbr) return MD_OK;
@@ -211,6 +215,8 @@ static int validate_config(const md_config *c)
     if (c->newton3 != MD_N3L_OFF && c->newton3 != MD_N3L_ON) return fail(MD_ERR_INVALID_ARG, "bad newton3");
     if (c->container == MD_CONTAINER_CL && c->newton3 != MD_N3L_OFF)
         return fail(MD_ERR_INVALID_ARG, "cluster lists are gather-only (newton3 = MD_N3L_OFF)");
+    if (c->container == MD_CONTAINER_CL && c->precision != MD_FP32)
+        return fail(MD_ERR_INVALID_ARG, "cluster lists run in FP32 (precision = MD_FP32)");
     if (c->rebuild_interval < 1) return fail(MD_ERR_INVALID_ARG, "rebuild_interval must be >= 1");
     if (c->max_neighbors < 1 || c->max_neighbors > 4096) return fail(MD_ERR_INVALID_ARG, "max_neighbors out of range");
     if (c->autotune != MD_TUNE_OFF && c->autotune != MD_TUNE_FULL && c->autotune != MD_TUNE_PREDICTIVE)
@@ -355,7 +361,16 @@ static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, i
     launch_cell_hist(n, pos, g, b.cell_id, b.slot, b.cell_count, b.flags, s);
     launch_scan(b.cell_count, b.cell_start, g.ncell, b.scan_blocks, s);
     launch_scatter(n, b.cell_id, b.slot, b.cell_start, b.perm, s);
-    launch_cell_sort(n, b.cell_start, ids, b.cell_id, b.perm, b.slot, b.cell_sorted, b.perm2, s);
+    if (h->cfg.container == MD_CONTAINER_CL) {
+        // cluster lists order each cell by position (Morton code), then id
+        if (!b.cl_key) {
+            int rc2 = dalloc(&b.cl_key, (size_t)std::max<int64_t>(h->n, 1));
+            if (rc2) return rc2;
+        }
+        launch_cl_sort(n, b.cell_start, pos, ids, b.cell_id, b.perm, g, b.cl_key, b.cell_sorted, b.perm2, s);
+    } else {
+        launch_cell_sort(n, b.cell_start, ids, b.cell_id, b.perm, b.slot, b.cell_sorted, b.perm2, s);
+    }
     launch_gather(n, h->cfg.precision, b.perm2, pos, vel, force, type, ids, b.tmp_pos, b.tmp_vel, b.tmp_force,
                   b.tmp_type, b.tmp_ids, b.cell_id, b.cell_sorted, g, b.stage, b.stage_ref, s);
     if (n > 0) {
@@ -374,7 +389,36 @@ static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, i
 }
 
 namespace mdlj {
-int cluster_build_impl(md_handle *h, const double *pos, hipStream_t s);  // clusters.hip
+// Cluster arrays: clusters <= n/8 + cells; the list rows hold up to
+// max_neighbors j-clusters.
+static int ensure_clusters(md_handle *h)
+{
+    Buffers &b = h->b;
+    int rc;
+    int64_t cap = cluster_cap(h->n, h->g);
+    int64_t maxn = h->cfg.max_neighbors;
+    if (cap > b.cl_cap || maxn > b.cl_list_cap) {
+        void *ptrs[] = {b.cl_start, b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_nbr, b.cl_nbr_count};
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+        b.cl_start = b.cl_count = b.cl_cell = b.cl_nbr = b.cl_nbr_count = nullptr;
+        b.cl_centre = nullptr;
+        b.cl_half = nullptr;
+        if ((rc = dalloc(&b.cl_start, cap)) || (rc = dalloc(&b.cl_count, cap)) || (rc = dalloc(&b.cl_cell, cap)) ||
+            (rc = dalloc(&b.cl_centre, cap)) || (rc = dalloc(&b.cl_half, cap)) ||
+            (rc = dalloc(&b.cl_nbr, (size_t)cap * maxn)) || (rc = dalloc(&b.cl_nbr_count, cap)))
+            return rc;
+        b.cl_cap = cap;
+        b.cl_list_cap = maxn;
+    }
+    if ((int64_t)h->g.ncell + 1 > b.cl_base_cap) {
+        if (b.cl_base) (void)hipFree(b.cl_base);
+        b.cl_base = nullptr;
+        if ((rc = dalloc(&b.cl_base, (size_t)h->g.ncell + 1))) return rc;
+        b.cl_base_cap = (int64_t)h->g.ncell + 1;
+    }
+    return MD_OK;
+}
 }
 
 // FP32 gather-only Verlet lists live in LDS windows (16-bit entries); the
@@ -449,7 +493,13 @@ static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
         launch_vl_build(n, b.stage, b.cell_start, b.cell_sorted, pos, h->g, h->cfg.newton3, b.nbr, b.nbr_count,
                         n, h->cfg.max_neighbors, b.flags, s);
     } else if (h->cfg.container == MD_CONTAINER_CL) {
-        return cluster_build_impl(h, pos, s);
+        int rc = ensure_clusters(h);
+        if (rc) return rc;
+        launch_fill_i32(b.flags + 2, 0, 1, s);
+        // per-cell cluster counts go to the (free after the build) count buffer
+        launch_cluster_build(n, h->g, b.cell_start, b.stage, b.cell_count, b.cl_base, b.scan_blocks, b.cl_start,
+                             b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_nbr, b.cl_nbr_count, b.cl_cap,
+                             h->cfg.max_neighbors, b.flags, s);
     }
     return MD_OK;
 }
@@ -504,8 +554,9 @@ static ForceArgs force_args(md_handle *h, const double *pos, const int32_t *type
     a.cl_count = h->b.cl_count;
     a.cl_nbr = h->b.cl_nbr;
     a.cl_nbr_count = h->b.cl_nbr_count;
-    a.cl_ld = h->b.n_clusters_max;
-    a.n_clusters = h->b.n_clusters_max;
+    a.cl_ld = h->b.cl_cap;
+    a.n_clusters = (int)h->b.cl_cap;
+    a.cl_ncl = h->b.cl_base ? h->b.cl_base + h->g.ncell : nullptr;
     a.tab = h->b.tab;
     a.force = force;
     a.partials = h->b.partials;
@@ -743,7 +794,7 @@ static int run_block(md_handle *h, const StepCtx &c, int s0, int s_end, int *nex
     int v = f[1];
     int first_used = rebuild_first ? s0 + 1 : s0;  // first step whose forces used the checked structure
     bool overflow = (f[0] & MD_FLAG_LIST_OVERFLOW) != 0;
-    if (overflow && rebuild_first && h->cfg.container == MD_CONTAINER_VL && h->cfg.max_neighbors < 4096) {
+    if (overflow && rebuild_first && has_lists(h->cfg) && h->cfg.max_neighbors < 4096) {
         // the lists built at step s0 were truncated: grow them, rebuild the
         // lists from the snapshot (the cells are still valid for it) and redo
         // step s0's forces; the rest of the block is run again
@@ -776,7 +827,7 @@ static int run_block(md_handle *h, const StepCtx &c, int s0, int s_end, int *nex
         h->forced++;
         // the forced rebuild's lists must not be truncated either
         if ((rc = read_flags(h, c.s, f))) return rc;
-        if ((f[0] & MD_FLAG_LIST_OVERFLOW) && h->cfg.container == MD_CONTAINER_VL) {
+        if ((f[0] & MD_FLAG_LIST_OVERFLOW) && has_lists(h->cfg)) {
             h->sticky |= (uint32_t)f[0] & ~MD_FLAG_LIST_OVERFLOW;
             h->cfg.max_neighbors = std::min(4096, std::max(h->cfg.max_neighbors * 3 / 2, f[2] + 16));
             launch_fill_i32(h->b.flags, 0, 1, c.s);
@@ -843,7 +894,7 @@ extern "C" int md_step(md_handle *h, double *pos, void *vel, void *force, int32_
         h->truncated = true;
         launch_fill_i32(h->b.flags, 0, 1, c.s);
     }
-    if (h->truncated && h->cfg.container == MD_CONTAINER_VL) {
+    if (h->truncated && has_lists(h->cfg)) {
         h->cfg.max_neighbors = std::min(4096, std::max(h->cfg.max_neighbors * 3 / 2, f0[2] + 16));
         h->built = false;
         h->truncated = false;
@@ -973,11 +1024,15 @@ extern "C" int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows, in
 {
     int rc = check_handle(h);
     if (rc) return rc;
-    if (h->cfg.container != MD_CONTAINER_VL) return fail(MD_ERR_INVALID_ARG, "not a Verlet-list container");
+    if (h->cfg.container == MD_CONTAINER_LC) return fail(MD_ERR_INVALID_ARG, "linked cells keep no lists");
     if (!h->built) return fail(MD_ERR_NOT_BUILT, "lists not built");
     if (max_per_row < 1 || (h->n > 0 && (!counts || !rows))) return fail(MD_ERR_INVALID_ARG, "bad arguments");
     int n = (int)h->n;
-    if (use_window(h->cfg, h->g)) {
+    if (h->cfg.container == MD_CONTAINER_CL) {
+        const Buffers &b = h->b;
+        launch_cl_rows(n, b.cell_sorted, b.cell_start, b.cl_base, b.cl_start, b.cl_count, b.cl_nbr, b.cl_nbr_count,
+                       b.cl_cap, max_per_row, counts, rows, (hipStream_t)stream);
+    } else if (use_window(h->cfg, h->g)) {
         const Geom &g = h->g;
         launch_vlw_decode(h->b.cell_start, g, n, h->b.w_rowb + (int64_t)g.nc[1] * g.nc[2], h->b.w_i0, h->b.w_i1,
                           h->b.w_c0, h->b.w_c1, h->b.w_nbr, h->b.nbr_count, max_per_row, counts, rows,

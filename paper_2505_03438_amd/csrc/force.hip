@@ -351,6 +351,7 @@ void launch_vl_build(int n, const int4 *stage, const int32_t *cell_start, const 
 int force_blocks(const ForceArgs &a)
 {
     if (a.n <= 0) return 0;
+    if (a.container == MD_CONTAINER_CL) return cluster_force_blocks();
     if (a.window) return window_force_blocks();
     return (a.n + kBlock - 1) / kBlock;
 }
@@ -390,8 +391,6 @@ static void launch_f64(const ForceArgs &a, const Geom &g, hipStream_t s)
         k_vl_f64<EN, N3><<<nb, kBlock, 0, s>>>(a.n, a.nbr, a.nbr_count, a.nbr_ld, a.tab, g, a.pos, a.type,
                                                (double *)a.force, a.partials);
 }
-
-void launch_cluster_force(const ForceArgs &a, const Geom &g, hipStream_t s);
 
 void launch_force(const ForceArgs &a, const Geom &g, hipStream_t s)
 {

@@ -72,10 +72,14 @@ struct Buffers {
     PairTab *tab = nullptr;
     float *facc = nullptr;       // N3L accumulation scratch (unused when gather)
     // clusters
-    int32_t *cl_start = nullptr, *cl_count = nullptr;  // per cluster
-    float *cl_bbox = nullptr;   // [n_clusters][6] lo xyz, hi xyz in u units (wrapped)
+    int32_t *cl_start = nullptr, *cl_count = nullptr, *cl_cell = nullptr;  // per cluster
+    int4 *cl_centre = nullptr;
+    float4 *cl_half = nullptr;
+    int32_t *cl_base = nullptr;  // first cluster of each cell; cl_base[ncell] = clusters
+    int64_t cl_base_cap = 0;
+    uint64_t *cl_key = nullptr;  // in-cell ordering keys
     int32_t *cl_nbr = nullptr, *cl_nbr_count = nullptr;
-    int64_t cl_cap = 0;
+    int64_t cl_cap = 0, cl_list_cap = 0;
     int32_t n_clusters_max = 0;
     // rollback snapshot (md_step)
     double *snap_pos = nullptr;
@@ -143,6 +147,7 @@ struct ForceArgs {
     const int32_t *cl_start, *cl_count, *cl_nbr, *cl_nbr_count;
     int64_t cl_ld;
     int n_clusters;
+    const int32_t *cl_ncl;  // device: number of clusters
     const PairTab *tab;
     void *force;
     double *partials;  // per-block {U, W, n_pairs, 0}
@@ -221,8 +226,18 @@ void launch_adjoint_finish(const double *gpart, int nblocks, const double *lj, i
                            double *grad_lj, hipStream_t s);
 
 // clusters.hip
-void launch_cluster_build(int n, const int32_t *cell_start, const Geom &g, const int4 *stage,
-                          int32_t *cl_start, int32_t *cl_count, float *bbox, int *n_clusters_dev,
-                          hipStream_t s);
+int cluster_force_blocks();
+int64_t cluster_cap(int64_t n, const Geom &g);
+void launch_cl_sort(int n, const int32_t *start, const double *pos, const int32_t *ids, const int32_t *cell_id,
+                    const int32_t *perm, const Geom &g, uint64_t *key, int32_t *cell_of_slot, int32_t *perm_out,
+                    hipStream_t s);
+void launch_cluster_build(int n, const Geom &g, const int32_t *cs, const int4 *st, int32_t *ncl_per_cell,
+                          int32_t *cl_base, int32_t *scan_scratch, int32_t *first, int32_t *cnt, int32_t *cell_of,
+                          int4 *centre, float4 *half, int32_t *list, int32_t *lcnt, int64_t ld, int maxn,
+                          int32_t *flags, hipStream_t s);
+void launch_cluster_force(const ForceArgs &a, const Geom &g, hipStream_t s);
+void launch_cl_rows(int n, const int32_t *cell_sorted, const int32_t *cs, const int32_t *cl_base,
+                    const int32_t *first, const int32_t *cnt, const int32_t *list, const int32_t *lcnt, int64_t ld,
+                    int maxr, int32_t *counts, int32_t *rows, hipStream_t s);
 
 }  // namespace mdlj

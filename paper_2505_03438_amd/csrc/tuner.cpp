@@ -128,6 +128,13 @@ void tuning_space(const md_config &base, std::vector<md_config> &space)
             c.newton3 = n3;
             space.push_back(c);
         }
+        // cluster-pair lists (FP32, gather-only)
+        if (base.precision == MD_FP32) {
+            c.container = MD_CONTAINER_CL;
+            c.csf = 1.0;
+            c.newton3 = MD_N3L_OFF;
+            space.push_back(c);
+        }
     }
 }
 

@@ -29,8 +29,15 @@ def _lib():
 FP32_F, FP64_F = 1e-5, 1e-12
 FP32_E, FP64_E = 1e-6, 1e-12
 
-CONTAINERS = [(0, 0, 1.0), (0, 1, 1.0), (0, 0, 0.5), (0, 1, 0.5), (1, 0, 1.0), (1, 1, 1.0)]
-CNAMES = ["lc", "lc-n3l", "lc-csf.5", "lc-n3l-csf.5", "vl", "vl-n3l"]
+CONTAINERS = [(0, 0, 1.0), (0, 1, 1.0), (0, 0, 0.5), (0, 1, 0.5), (1, 0, 1.0), (1, 1, 1.0), (2, 0, 1.0),
+              (2, 0, 0.5)]
+CNAMES = ["lc", "lc-n3l", "lc-csf.5", "lc-n3l-csf.5", "vl", "vl-n3l", "cl", "cl-csf.5"]
+
+
+def _fp32_only(cont, prec):
+    """Cluster-pair lists run in FP32 only."""
+    if cont[0] == 2 and prec == 1:
+        pytest.skip("cluster lists are FP32-only")
 
 
 def _jittered(ncell, seed, density=0.8, jitter=0.08, shape=None):
@@ -44,6 +51,7 @@ def _jittered(ncell, seed, density=0.8, jitter=0.08, shape=None):
 @pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("cont", CONTAINERS, ids=CNAMES)
 def test_fcc_lattice(orc, prec, cont):
+    _fp32_only(cont, prec)
     d = W.plain_fcc_864()
     pos, box = d["pos"], d["box"]
     F0, U0, W0, P0 = orc.forces(pos, box, orc.single())
@@ -85,6 +93,7 @@ SIZES = [(3, 1), (5, 2), (7, 3), ((6, 7, 8), 4)]
 @pytest.mark.parametrize("cont", CONTAINERS, ids=CNAMES)
 @pytest.mark.parametrize("size", SIZES, ids=["n108", "n500", "n1372", "n1344"])
 def test_forces_match_oracle(orc, prec, cont, size):
+    _fp32_only(cont, prec)
     ncell, seed = size
     pos, box = _jittered(ncell, seed)
     if min(box) < 5.6:
@@ -116,6 +125,8 @@ def test_anisotropic_box_and_two_types(orc, prec):
     p = orc.Params(e, sg, rc2)
     F0, U0, W0, P0 = orc.forces(pos, box, p, types)
     for cont in CONTAINERS:
+        if cont[0] == 2 and prec == 1:
+            continue
         cfg = make_config(n, box, container=cont[0], newton3=cont[1], csf=cont[2], precision=prec,
                           n_types=2, rc2=rc2)
         s = DeviceSystem(cfg, pos, types=types, eps=eps_t, sig=sig_t)
@@ -156,12 +167,14 @@ def test_tiny_and_empty_systems(orc):
     box = np.array([8.0, 8.0, 8.0])
     F0, U0, _, P0 = orc.forces(pos, box, orc.single())
     for cont in CONTAINERS:
-        cfg = make_config(2, box, container=cont[0], newton3=cont[1], csf=cont[2], precision=1)
+        prec = 0 if cont[0] == 2 else 1
+        cfg = make_config(2, box, container=cont[0], newton3=cont[1], csf=cont[2], precision=prec)
         s = DeviceSystem(cfg, pos)
         s.build()
         out = s.forces().cpu().numpy()
         assert int(out[2]) == 1
-        assert np.abs(s.by_id(s.force) - F0).max() <= 1e-12 * np.abs(F0).max()
+        tol = 1e-12 if prec == 1 else FP32_F
+        assert np.abs(s.by_id(s.force) - F0).max() <= tol * np.abs(F0).max()
     # no particles at all
     cfg = make_config(0, box)
     s = DeviceSystem(cfg, np.zeros((3, 0)))
@@ -216,6 +229,7 @@ def _run_nve(orc, prec, cont, nsteps=100, R=10, dt=0.005, energy_every=1, d=None
 
 @pytest.mark.parametrize("cont", CONTAINERS, ids=CNAMES)
 def test_nve_fp64_trajectory(orc, cont):
+    _fp32_only(cont, 1)
     d = W.plain_fcc_864()
     p1, v1, f1, log0 = orc.velocity_verlet(d["pos"], d["vel"], d["box"], orc.single(), 0.005, 100)
     s, log = _run_nve(orc, 1, cont)
@@ -229,13 +243,42 @@ def test_nve_fp64_trajectory(orc, cont):
     assert np.abs(s.by_id(s.vel) - v1).max() < 1e-9
 
 
-def test_nve_fp32_energy_conservation(orc):
-    s, log = _run_nve(orc, 0, (1, 0, 1.0), nsteps=400, R=10)
+@pytest.mark.parametrize("cont", [(1, 0, 1.0), (2, 0, 1.0), (0, 0, 0.5)], ids=["vl", "cl", "lc-csf.5"])
+def test_nve_fp32_energy_conservation(orc, cont):
+    s, log = _run_nve(orc, 0, cont, nsteps=400, R=10)
     u_rc = orc.lj(6.25)[1]
     E = (log[:, 0] - log[:, 3] * u_rc + log[:, 1]) / 864
     assert np.abs(E - E[0]).max() < 5e-3
     slope = np.polyfit(np.arange(len(E)) * 0.005, E, 1)[0]
     assert abs(slope) < 1e-2
+
+
+@pytest.mark.parametrize("csf", [1.0, 0.5])
+def test_cluster_lists_cover_verlet_pairs(orc, csf):
+    """Every pair within r_c + skin at the build is a candidate of the cluster
+    lists, clusters hold at most 8 particles of one cell, and the pair count of
+    the first step equals the oracle's."""
+    pos, box = _jittered((6, 7, 8), 21, jitter=0.1)
+    n = pos.shape[1]
+    cfg = make_config(n, box, container=2, csf=csf)
+    s = DeviceSystem(cfg, pos)
+    s.build()
+    counts, rows = M.md_get_neighbors(s.h, 1024)
+    counts, rows = counts.cpu().numpy(), rows.cpu().numpy()
+    assert counts.max() <= 1024
+    ids = s.ids_np()
+    ref = orc.neighbor_rows(pos, box, (2.5 + 0.3) ** 2, np.arange(n))
+    for k in range(n):
+        got = set(ids[rows[k, :counts[k]]].tolist())
+        assert ids[k] not in got
+        assert set(ref[ids[k]].tolist()) <= got, k
+    # candidates come in whole clusters: the row length is bounded by 8 per
+    # listed cluster, and the list is symmetric at the particle level
+    pairs = set()
+    for k in range(n):
+        for j in ids[rows[k, :counts[k]]]:
+            pairs.add((ids[k], j))
+    assert all((j, i) in pairs for (i, j) in pairs)
 
 
 def test_skin_violation_forces_rebuild(orc):
@@ -252,11 +295,13 @@ def test_skin_violation_forces_rebuild(orc):
         assert np.abs(log[:, 0] - log0[:, 0]).max() <= 1e-10 * np.abs(log0[:, 0]).max()
 
 
-def test_list_overflow_grows(orc):
+@pytest.mark.parametrize("cont", [(1, 0, 20, 78), (2, 0, 4, 20)], ids=["vl", "cl"])
+def test_list_overflow_grows(orc, cont):
     import torch
     d = W.plain_fcc_864()
     n = 864
-    cfg = make_config(n, d["box"], container=1, precision=1, max_neighbors=20)
+    prec = 0 if cont[0] == 2 else 1
+    cfg = make_config(n, d["box"], container=cont[0], precision=prec, max_neighbors=cont[2])
     s = DeviceSystem(cfg, d["pos"], d["vel"])
     s.build()
     s.forces(energy=False)  # truncated lists give wrong forces, and a flag
@@ -267,9 +312,15 @@ def test_list_overflow_grows(orc):
     log = torch.zeros((30, 4), dtype=torch.float64, device="cuda")
     M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, 30, 1, log)
     log = log.cpu().numpy()
-    assert M.md_get_config(s.h).max_neighbors >= 78
-    assert np.array_equal(log[:, 3], log0[:, 3])
-    assert np.abs(log[:, 0] - log0[:, 0]).max() <= 1e-10 * np.abs(log0[:, 0]).max()
+    assert M.md_get_config(s.h).max_neighbors >= cont[3]
+    if prec == 1:
+        assert np.array_equal(log[:, 3], log0[:, 3])
+        assert np.abs(log[:, 0] - log0[:, 0]).max() <= 1e-10 * np.abs(log0[:, 0]).max()
+    else:
+        # FP32 pair arithmetic: the first steps still match the FP64 oracle
+        assert np.array_equal(log[:5, 3], log0[:5, 3])
+        assert np.abs(log[:5, 0] - log0[:5, 0]).max() <= 1e-6 * np.abs(log0[:5, 0]).max()
+    assert not (M.md_status(s.h) & M.MD_FLAG_LIST_OVERFLOW)
 
 
 # ---------------------------------------------------------------- live statistics
@@ -328,7 +379,7 @@ def test_fluid_1m_full_size(orc):
     pos, box = d["pos"], d["box"]
     n = pos.shape[1]
     F0, U0, W0, P0 = orc.forces(pos, box, orc.single(), cells=True)
-    for cont in ((1, 0, 1.0), (0, 0, 1.0)):
+    for cont in ((1, 0, 1.0), (0, 0, 1.0), (2, 0, 1.0)):
         cfg = make_config(n, box, container=cont[0], newton3=cont[1], csf=cont[2])
         s = DeviceSystem(cfg, pos)
         s.build()
