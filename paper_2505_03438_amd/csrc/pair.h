@@ -8,39 +8,42 @@
 namespace mdlj {
 
 // Per-kernel copy of the FP32 pair constants.  With one type every lookup is
-// a scalar; with two types the 2x2 tables are selected per lane.
+// a scalar; with two types the 2x2 tables are selected per lane.  Every
+// index below is a constant (no loops), so that the tables are promoted to
+// registers before any later pass could turn the selects into an indexed
+// load from a stack copy.
 template <int NT>
 struct TabF {
     float lo[NT * NT], hi[NT * NT], sig2[NT * NT], eps24[NT * NT], eps4[NT * NT], eps24w[NT * NT];
     double rc2[NT * NT];
+    __device__ __forceinline__ void load_one(const PairTab *__restrict__ t, int k)
+    {
+        lo[k] = t->rc2_lo[k];
+        hi[k] = t->rc2_hi[k];
+        sig2[k] = t->sig2[k];
+        eps24[k] = t->eps24[k];
+        eps4[k] = t->eps4[k];
+        eps24w[k] = t->eps24w[k];
+        rc2[k] = t->rc2[k];
+    }
     __device__ __forceinline__ void load(const PairTab *__restrict__ t)
     {
-#pragma unroll
-        for (int k = 0; k < NT * NT; k++) {
-            lo[k] = t->rc2_lo[k];
-            hi[k] = t->rc2_hi[k];
-            sig2[k] = t->sig2[k];
-            eps24[k] = t->eps24[k];
-            eps4[k] = t->eps4[k];
-            eps24w[k] = t->eps24w[k];
-            rc2[k] = t->rc2[k];
+        load_one(t, 0);
+        if (NT > 1) {
+            load_one(t, 1);
+            load_one(t, 2);
+            load_one(t, 3);
         }
     }
     __device__ __forceinline__ float pick(const float *v, int ab) const
     {
         if (NT == 1) return v[0];
-        float r = v[0];
-#pragma unroll
-        for (int k = 1; k < NT * NT; k++) r = ab == k ? v[k] : r;
-        return r;
+        return ab == 0 ? v[0] : (ab == 1 ? v[1] : (ab == 2 ? v[2] : v[3]));
     }
     __device__ __forceinline__ double pickd(const double *v, int ab) const
     {
         if (NT == 1) return v[0];
-        double r = v[0];
-#pragma unroll
-        for (int k = 1; k < NT * NT; k++) r = ab == k ? v[k] : r;
-        return r;
+        return ab == 0 ? v[0] : (ab == 1 ? v[1] : (ab == 2 ? v[2] : v[3]));
     }
 };
 
@@ -116,14 +119,16 @@ template <int NT, bool ENERGY>
 __device__ __forceinline__ float lj_f32(float r2, int ab, bool in, const TabF<NT> &t, float &eu, float &ew,
                                         int &np)
 {
-    float ir2 = __builtin_amdgcn_rcpf(r2);
+    // a pair outside the cutoff gets 1/r^2 = 0, which zeroes every term
+    // below without a branch
+    float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.0f;
     float s2 = t.pick(t.sig2, ab) * ir2;
     float q = s2 * s2 * s2;
     float a = q * (2.0f * q - 1.0f);
-    float phi = in ? t.pick(t.eps24, ab) * ir2 * a : 0.0f;
+    float phi = t.pick(t.eps24, ab) * ir2 * a;
     if (ENERGY) {
-        eu += in ? t.pick(t.eps4, ab) * q * (q - 1.0f) : 0.0f;
-        ew += in ? t.pick(t.eps24w, ab) * a : 0.0f;
+        eu += t.pick(t.eps4, ab) * q * (q - 1.0f);
+        ew += t.pick(t.eps24w, ab) * a;
         np += in ? 1 : 0;
     }
     return phi;

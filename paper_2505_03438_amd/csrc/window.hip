@@ -19,7 +19,7 @@
 
 namespace mdlj {
 
-constexpr int kWinMax = 3072;    // LDS window capacity (int4 entries, 48 KB)
+constexpr int kWinMax = 3072;    // LDS window capacity (particles)
 constexpr int kBlkCells = 32;    // maximum cells of a block along x
 constexpr int kMaxRows = 9;      // stencil rows of a reach-1 window (3 x 3)
 constexpr int kMaxCols = kBlkCells + 2;  // window columns of a reach-1 window
@@ -28,6 +28,33 @@ constexpr int kWinGrid = 2048;   // persistent workgroups (multiple of 8)
 
 using Ofs = int (*)[kMaxOfs];
 using COfs = const int (*)[kMaxOfs];
+
+// LDS entry of a window particle: its staged fixed-point coordinates, and its
+// type when there are two.  Twelve bytes for one type keep four workgroups'
+// windows (4 x 36 KB) within a compute unit's LDS.
+template <int NT>
+struct WinEntry {
+    int x, y, z, w;
+    __device__ __forceinline__ void set(const int4 &a)
+    {
+        x = a.x;
+        y = a.y;
+        z = a.z;
+        w = a.w;
+    }
+    __device__ __forceinline__ int4 get() const { return make_int4(x, y, z, w); }
+};
+template <>
+struct WinEntry<1> {
+    int x, y, z;
+    __device__ __forceinline__ void set(const int4 &a)
+    {
+        x = a.x;
+        y = a.y;
+        z = a.z;
+    }
+    __device__ __forceinline__ int4 get() const { return make_int4(x, y, z, 0); }
+};
 
 // ------------------------------------------------------------------ windows
 
@@ -147,7 +174,8 @@ __device__ __forceinline__ int window_global(const Window &w, int p)
 
 // Stage the window into LDS, four loads in flight per thread (named
 // registers: an array here would be placed in scratch memory).
-__device__ __forceinline__ void load_window(const Window &w, const int4 *__restrict__ st, int4 *lds)
+template <int NT>
+__device__ __forceinline__ void load_window(const Window &w, const int4 *__restrict__ st, WinEntry<NT> *lds)
 {
     int W = w.W;
     int k = 0;
@@ -168,10 +196,10 @@ __device__ __forceinline__ void load_window(const Window &w, const int4 *__restr
             k = piece_from(w, k, p3);
             a3 = st[w.pc_start[k] + (p3 - w.pc_win[k])];
         }
-        lds[p0] = a0;
-        if (p1 < W) lds[p1] = a1;
-        if (p2 < W) lds[p2] = a2;
-        if (p3 < W) lds[p3] = a3;
+        lds[p0].set(a0);
+        if (p1 < W) lds[p1].set(a1);
+        if (p2 < W) lds[p2].set(a2);
+        if (p3 < W) lds[p3].set(a3);
     }
 }
 
@@ -312,9 +340,10 @@ __global__ void k_blk_write(const Geom g, const int32_t *__restrict__ cs, const 
 
 // Common head of the windowed kernels: lay out and stage the window of
 // block blk; returns false (uniformly) if it does not fit the tile.
+template <int NT>
 __device__ __forceinline__ bool setup_block(const Geom &g, COfs so, const int32_t *__restrict__ cs,
-                                            const int4 *__restrict__ st, int c0, int c1, Window &w, int4 *win,
-                                            int32_t *flags)
+                                            const int4 *__restrict__ st, int c0, int c1, Window &w,
+                                            WinEntry<NT> *win, int32_t *flags)
 {
     __syncthreads();
     make_window(g, so, cs, c0, c1, w);
@@ -337,8 +366,86 @@ __device__ __forceinline__ int self_position(const Geom &g, const Window &w, con
     return w.col[w.self_row][m] + (i - cs[ci]);
 }
 
+// ------------------------------------------------------------------ traversal helpers
+
+// The cell columns a particle in column x visits, as up to three ranges of
+// window columns [a, b]: one range x-1 .. x+1 unless the columns wrap inside
+// a window that covers the whole x-row (or the row has fewer than three
+// distinct columns); then one range per column.  Identical for every stencil
+// row.
+struct ColRanges {
+    int a0, b0, a1, b1, a2, b2;
+};
+
+__device__ __forceinline__ ColRanges column_ranges(const Geom &g, COfs so, const Window &w, int x)
+{
+    int nx = g.nc[0];
+    int m = x - w.lo;
+    m = m < 0 ? m + nx : m;
+    ColRanges r{0, -1, 0, -1, 0, -1};
+    if (g.nofs[0] == 3 && m >= 1 && m + 1 < w.ncols) {
+        r.a0 = m - 1;
+        r.b0 = m + 1;
+        return r;
+    }
+    auto col = [&](int e) {
+        int xx = x + so[0][e];
+        xx = xx >= nx ? xx - nx : xx;
+        int mm = xx - w.lo;
+        return mm < 0 ? mm + nx : mm;
+    };
+    r.a0 = r.b0 = col(0);
+    if (g.nofs[0] > 1) r.a1 = r.b1 = col(1);
+    if (g.nofs[0] > 2) r.a2 = r.b2 = col(2);
+    return r;
+}
+
+// One candidate pair (i, window position p) of the force traversals, branch
+// free: the FP32 cutoff decision, the pair force added to f and the energy
+// terms.  Returns true if the pair lies inside the guard band of the cutoff;
+// the caller then decides it from the FP64 positions (pair_exact).
+template <int NT, bool ISO, bool ENERGY>
+__device__ __forceinline__ bool pair_fast(const int4 &pi, const int4 &pj, bool valid, const TabF<NT> &t,
+                                          const Geom &g, float &fx, float &fy, float &fz, float &eu, float &ew,
+                                          int &np)
+{
+    float dx, dy, dz;
+    staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+    float r2 = dx * dx + dy * dy + dz * dz;
+    int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
+    float lo = t.pick(t.lo, ab), hi = t.pick(t.hi, ab);
+    bool in = valid && r2 < lo;
+    float phi = lj_f32<NT, ENERGY>(r2, ab, in, t, eu, ew, np);
+    fx += phi * dx;
+    fy += phi * dy;
+    fz += phi * dz;
+    return valid && r2 >= lo && r2 < hi;
+}
+
+// A guard-band pair: added if its FP64 distance is inside the cutoff (only
+// the FP64 distance is a call; the accumulators stay in registers).
+template <int NT, bool ISO, bool ENERGY>
+__device__ __forceinline__ void pair_exact(const int4 &pi, const int4 &pj, int i, int j, const TabF<NT> &t,
+                                        const Geom &g, const double *__restrict__ pos, int n, float &fx, float &fy,
+                                        float &fz, float &eu, float &ew, int &np)
+{
+    int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
+    if (exact_r2(pos, n, i, j, g.L[0], g.L[1], g.L[2]) < t.pickd(t.rc2, ab)) {
+        float dx, dy, dz;
+        staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+        float r2 = dx * dx + dy * dy + dz * dz;
+        float phi = lj_f32<NT, ENERGY>(r2, ab, true, t, eu, ew, np);
+        fx += phi * dx;
+        fy += phi * dy;
+        fz += phi * dz;
+    }
+}
+
 // ------------------------------------------------------------------ linked cells
 
+// Each thread scans the window ranges of its stencil, four candidates at a
+// time (the four LDS reads issued before any arithmetic); guard-band pairs
+// are collected in a bit mask and decided after the batch.
 template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                  const int32_t *__restrict__ cell_sorted, Geom g, int n,
@@ -349,7 +456,7 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
                                                  float *__restrict__ F, double *__restrict__ partials,
                                                  int32_t *__restrict__ flags)
 {
-    __shared__ int4 win[kWinMax];
+    __shared__ WinEntry<NT> win[kWinMax];
     __shared__ Window w;
     __shared__ double sh[16];
     __shared__ int so[3][kMaxOfs];
@@ -361,32 +468,38 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
     size_t N = (size_t)n;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
-        if (!setup_block(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
+        if (!setup_block<NT>(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
         int i = bi0[blk] + threadIdx.x;
         if (i >= bi1[blk]) continue;
         int x;
         int self = self_position(g, w, cs, i, cell_sorted[i], x);
-        int4 pi = win[self];
+        int4 pi = win[self].get();
+        ColRanges cr = column_ranges(g, so, w, x);
         float fx = 0.f, fy = 0.f, fz = 0.f;
         for (int rr = 0; rr < w.nrow; rr++)
-            for (int e = 0; e < g.nofs[0]; e++) {
-                int b, en;
-                stencil_range(g, so, w, x, rr, e, b, en);
-                for (int p = b; p < en; p++) {
-                    if (p == self) continue;
-                    int4 pj = win[p];
-                    float dx, dy, dz;
-                    staged_delta<ISO>(pi, pj, g, dx, dy, dz);
-                    float r2 = dx * dx + dy * dy + dz * dz;
-                    int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
-                    float lo = t.pick(t.lo, ab), hi = t.pick(t.hi, ab);
-                    bool in = r2 < lo;
-                    if (r2 >= lo && r2 < hi)
-                        in = exact_r2(pos, n, i, window_global(w, p), g.L[0], g.L[1], g.L[2]) < t.pickd(t.rc2, ab);
-                    float phi = lj_f32<NT, ENERGY>(r2, ab, in, t, eu, ew, np);
-                    fx += phi * dx;
-                    fy += phi * dy;
-                    fz += phi * dz;
+            for (int sgi = 0; sgi < 3; sgi++) {
+                int ca = sgi == 0 ? cr.a0 : (sgi == 1 ? cr.a1 : cr.a2);
+                int cb = sgi == 0 ? cr.b0 : (sgi == 1 ? cr.b1 : cr.b2);
+                if (cb < ca) continue;
+                int b = w.col[rr][ca], en = w.col[rr][cb + 1];
+                for (int p0 = b; p0 < en; p0 += 4) {
+                    int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
+                    int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
+                    uint32_t amb = 0;
+                    amb |= pair_fast<NT, ISO, ENERGY>(pi, q0, p0 != self, t, g, fx, fy, fz, eu, ew, np) ? 1u : 0u;
+                    amb |= pair_fast<NT, ISO, ENERGY>(pi, q1, p0 + 1 < en && p1 != self, t, g, fx, fy, fz, eu, ew,
+                                                      np) ? 2u : 0u;
+                    amb |= pair_fast<NT, ISO, ENERGY>(pi, q2, p0 + 2 < en && p2 != self, t, g, fx, fy, fz, eu, ew,
+                                                      np) ? 4u : 0u;
+                    amb |= pair_fast<NT, ISO, ENERGY>(pi, q3, p0 + 3 < en && p3 != self, t, g, fx, fy, fz, eu, ew,
+                                                      np) ? 8u : 0u;
+                    while (amb) {
+                        int u = __builtin_ctz(amb);
+                        amb &= amb - 1;
+                        int p = p0 + u;
+                        pair_exact<NT, ISO, ENERGY>(pi, win[p].get(), i, window_global(w, p), t, g, pos, n, fx, fy,
+                                                    fz, eu, ew, np);
+                    }
                 }
             }
         F[i] = fx;
@@ -406,6 +519,46 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
 // List entry c of particle i: nbr[((c / 8) * n + i) * 8 + c % 8].
 __device__ __forceinline__ size_t list_slot(int c, int i, size_t N) { return ((size_t)(c >> 3) * N + i) * 8 + (c & 7); }
 
+// Pending chunk of eight 16-bit entries of the list being built.
+struct Chunk {
+    uint64_t lo = 0, hi = 0;
+    __device__ __forceinline__ void put(int e, uint32_t p)
+    {
+        uint64_t v = (uint64_t)p << (16 * (e & 3));
+        if (e < 4)
+            lo |= v;
+        else
+            hi |= v;
+    }
+    __device__ __forceinline__ uint4 word() const
+    {
+        return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+    }
+};
+
+// Append window position p to the list of particle i (c entries so far);
+// every completed chunk is written with one 16-byte store.
+__device__ __forceinline__ void list_append(uint32_t p, int &c, Chunk &ck, uint4 *__restrict__ row, size_t N,
+                                            int maxn)
+{
+    ck.put(c & 7, p);
+    c++;
+    if ((c & 7) == 0) {
+        if (c <= maxn) row[(size_t)((c >> 3) - 1) * N] = ck.word();
+        ck.lo = ck.hi = 0;
+    }
+}
+
+template <bool ISO>
+__device__ __forceinline__ bool build_fast(const int4 &pi, const int4 &pj, bool valid, const Geom &g, bool &amb)
+{
+    float dx, dy, dz;
+    staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+    float r2 = dx * dx + dy * dy + dz * dz;
+    amb = valid && r2 >= g.rl2_lo && r2 < g.rl2_hi;
+    return valid && r2 < g.rl2_lo;
+}
+
 template <bool ISO>
 __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                    const int32_t *__restrict__ cell_sorted,
@@ -416,7 +569,7 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
                                                    uint16_t *__restrict__ nbr, int32_t *__restrict__ cnt, int maxn,
                                                    int32_t *__restrict__ flags)
 {
-    __shared__ int4 win[kWinMax];
+    __shared__ WinEntry<1> win[kWinMax];
     __shared__ Window w;
     __shared__ int so[3][kMaxOfs];
     load_offsets(g, so);
@@ -424,31 +577,42 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
     int cmax = 0;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
-        if (!setup_block(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
+        if (!setup_block<1>(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
         int i = bi0[blk] + threadIdx.x;
         if (i >= bi1[blk]) continue;
         int x;
         int self = self_position(g, w, cs, i, cell_sorted[i], x);
-        int4 pi = win[self];
+        int4 pi = win[self].get();
+        ColRanges cr = column_ranges(g, so, w, x);
+        uint4 *row = (uint4 *)nbr + i;
         int c = 0;
+        Chunk ck;
         for (int rr = 0; rr < w.nrow; rr++)
-            for (int e = 0; e < g.nofs[0]; e++) {
-                int b, en;
-                stencil_range(g, so, w, x, rr, e, b, en);
-                for (int p = b; p < en; p++) {
-                    if (p == self) continue;
-                    float dx, dy, dz;
-                    staged_delta<ISO>(pi, win[p], g, dx, dy, dz);
-                    float r2 = dx * dx + dy * dy + dz * dz;
-                    bool in = r2 < g.rl2_lo;
-                    if (r2 >= g.rl2_lo && r2 < g.rl2_hi)
-                        in = exact_r2(pos, n, i, window_global(w, p), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                    if (in) {
-                        if (c < maxn) nbr[list_slot(c, i, N)] = (uint16_t)p;
-                        c++;
-                    }
+            for (int sgi = 0; sgi < 3; sgi++) {
+                int ca = sgi == 0 ? cr.a0 : (sgi == 1 ? cr.a1 : cr.a2);
+                int cb = sgi == 0 ? cr.b0 : (sgi == 1 ? cr.b1 : cr.b2);
+                if (cb < ca) continue;
+                int b = w.col[rr][ca], en = w.col[rr][cb + 1];
+                for (int p0 = b; p0 < en; p0 += 4) {
+                    int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
+                    int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
+                    bool a0, a1, a2, a3;
+                    bool i0 = build_fast<ISO>(pi, q0, p0 != self, g, a0);
+                    bool i1 = build_fast<ISO>(pi, q1, p0 + 1 < en && p1 != self, g, a1);
+                    bool i2 = build_fast<ISO>(pi, q2, p0 + 2 < en && p2 != self, g, a2);
+                    bool i3 = build_fast<ISO>(pi, q3, p0 + 3 < en && p3 != self, g, a3);
+                    // rare: guard-band pairs decided from the FP64 positions
+                    if (a0) i0 = exact_r2(pos, n, i, window_global(w, p0), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                    if (a1) i1 = exact_r2(pos, n, i, window_global(w, p1), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                    if (a2) i2 = exact_r2(pos, n, i, window_global(w, p2), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                    if (a3) i3 = exact_r2(pos, n, i, window_global(w, p3), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                    if (i0) list_append((uint32_t)p0, c, ck, row, N, maxn);
+                    if (i1) list_append((uint32_t)p1, c, ck, row, N, maxn);
+                    if (i2) list_append((uint32_t)p2, c, ck, row, N, maxn);
+                    if (i3) list_append((uint32_t)p3, c, ck, row, N, maxn);
                 }
             }
+        if ((c & 7) && c < maxn) row[(size_t)(c >> 3) * N] = ck.word();
         if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
         cmax = max(cmax, c);
         cnt[i] = c < maxn ? c : maxn;
@@ -456,6 +620,8 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
     if (cmax > 0) atomicMax(&flags[2], cmax);
 }
 
+// Each thread walks its list in chunks of eight entries; the next chunk's
+// load is in flight while the current one is computed.
 template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs, Geom g,
                                                  int n, const int32_t *__restrict__ nblk_p, int cap,
@@ -466,7 +632,7 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
                                                  float *__restrict__ F, double *__restrict__ partials,
                                                  int32_t *__restrict__ flags)
 {
-    __shared__ int4 win[kWinMax];
+    __shared__ WinEntry<NT> win[kWinMax];
     __shared__ Window w;
     __shared__ double sh[16];
     __shared__ int so[3][kMaxOfs];
@@ -476,57 +642,38 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
     float eu = 0.f, ew = 0.f;
     int np = 0;
     size_t N = (size_t)n;
-    const uint4 *chunks = (const uint4 *)nbr;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
-        if (!setup_block(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
+        if (!setup_block<NT>(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
         int i = bi0[blk] + threadIdx.x;
         if (i >= bi1[blk]) continue;
         int4 pi = st[i];
         int c = cnt[i];
         int nch = (c + 7) >> 3;
         float fx = 0.f, fy = 0.f, fz = 0.f;
-        uint4 cur = nch > 0 ? chunks[i] : make_uint4(0, 0, 0, 0);
+        // chunk ch of particle i is row[ch * n]; the prefetch index is clamped
+        // so that every load is an in-bounds global load
+        const uint4 *row = (const uint4 *)nbr + i;
+        uint4 cur = row[0];
         for (int ch = 0; ch < nch; ch++) {
-            uint4 nxt = ch + 1 < nch ? chunks[(size_t)(ch + 1) * N + i] : cur;
+            uint4 nxt = row[(size_t)min(ch + 1, nch - 1) * N];
             int valid = min(8, c - ch * 8);
-            uint32_t amb = 0;  // entries inside the guard band, decided below
+            int pp[8] = {(int)(cur.x & 0xffff), (int)(cur.x >> 16), (int)(cur.y & 0xffff), (int)(cur.y >> 16),
+                         (int)(cur.z & 0xffff), (int)(cur.z >> 16), (int)(cur.w & 0xffff), (int)(cur.w >> 16)};
+            uint32_t amb = 0;
 #pragma unroll
             for (int u = 0; u < 8; u++) {
-                uint32_t word = u < 2 ? cur.x : (u < 4 ? cur.y : (u < 6 ? cur.z : cur.w));
-                int p = (word >> ((u & 1) * 16)) & 0xffff;
-                if (u >= valid) p = 0;
-                int4 pj = win[p];
-                float dx, dy, dz;
-                staged_delta<ISO>(pi, pj, g, dx, dy, dz);
-                float r2 = dx * dx + dy * dy + dz * dz;
-                int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
-                float lo = t.pick(t.lo, ab), hi = t.pick(t.hi, ab);
-                bool in = r2 < lo && u < valid;
-                amb |= (r2 >= lo && r2 < hi && u < valid) ? 1u << u : 0u;
-                float phi = lj_f32<NT, ENERGY>(r2, ab, in, t, eu, ew, np);
-                fx += phi * dx;
-                fy += phi * dy;
-                fz += phi * dz;
+                int4 pj = win[pp[u]].get();
+                amb |= pair_fast<NT, ISO, ENERGY>(pi, pj, u < valid, t, g, fx, fy, fz, eu, ew, np) ? 1u << u : 0u;
             }
-            // rare: pairs within the guard band of the cutoff are decided
-            // from the FP64 positions, and added when inside
+            // rare: pairs within the guard band of the cutoff
             while (amb) {
                 int u = __builtin_ctz(amb);
                 amb &= amb - 1;
                 uint32_t word = u < 2 ? cur.x : (u < 4 ? cur.y : (u < 6 ? cur.z : cur.w));
                 int p = (word >> ((u & 1) * 16)) & 0xffff;
-                int4 pj = win[p];
-                int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
-                if (exact_r2(pos, n, i, window_global(w, p), g.L[0], g.L[1], g.L[2]) < t.pickd(t.rc2, ab)) {
-                    float dx, dy, dz;
-                    staged_delta<ISO>(pi, pj, g, dx, dy, dz);
-                    float r2 = dx * dx + dy * dy + dz * dz;
-                    float phi = lj_f32<NT, ENERGY>(r2, ab, true, t, eu, ew, np);
-                    fx += phi * dx;
-                    fy += phi * dy;
-                    fz += phi * dz;
-                }
+                pair_exact<NT, ISO, ENERGY>(pi, win[p].get(), i, window_global(w, p), t, g, pos, n, fx, fy, fz, eu,
+                                            ew, np);
             }
             cur = nxt;
         }
