@@ -421,12 +421,15 @@ static int ensure_clusters(md_handle *h)
 }
 }
 
-// FP32 gather-only Verlet lists live in LDS windows (16-bit entries); the
-// Newton's-third-law half lists and the FP64 path use global 32-bit lists.
+// FP32 linked cells and Verlet lists run over LDS windows (Verlet lists as
+// 16-bit window positions): full windows gather-only, half windows with
+// Newton's third law.  The FP64 path, cell grids with a reach above one cell
+// and half traversals of grids with fewer than three cells per dimension use
+// the global kernels (32-bit lists).
 static bool use_window(const md_config &c, const Geom &g)
 {
     return (c.container == MD_CONTAINER_VL || c.container == MD_CONTAINER_LC) && c.precision == MD_FP32 &&
-           c.newton3 == MD_N3L_OFF && window_geometry_ok(g);
+           window_geometry_ok(g, c.newton3 == MD_N3L_ON);
 }
 
 static int ensure_window(md_handle *h, int64_t maxn)
@@ -470,7 +473,7 @@ static int build_blocks(md_handle *h, hipStream_t s)
     // the per-cell counts are no longer needed once the cells are built: the
     // same buffer holds the window column sums of the packer
     launch_blocks(h->g, b.cell_start, b.cell_count, b.w_rown, b.w_rowb, b.scan_blocks, b.w_i0, b.w_i1, b.w_c0,
-                  b.w_c1, (int)b.w_cap, b.flags, s);
+                  b.w_c1, (int)b.w_cap, b.flags, h->cfg.newton3 == MD_N3L_ON, s);
     return MD_OK;
 }
 
@@ -485,7 +488,8 @@ static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
         int nrows = g.nc[1] * g.nc[2];
         launch_fill_i32(b.flags + 2, 0, 1, s);
         launch_vlw_build(b.stage, b.cell_start, b.cell_sorted, pos, g, n, b.w_rowb + nrows, b.w_i0, b.w_i1, b.w_c0,
-                         b.w_c1, b.w_nbr, b.nbr_count, h->cfg.max_neighbors, b.flags, s);
+                         b.w_c1, b.w_nbr, b.nbr_count, h->cfg.max_neighbors, b.flags, h->cfg.newton3 == MD_N3L_ON,
+                         s);
     } else if (h->cfg.container == MD_CONTAINER_VL) {
         int rc = ensure_list(h, h->cfg.max_neighbors);
         if (rc) return rc;
@@ -1036,7 +1040,7 @@ extern "C" int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows, in
         const Geom &g = h->g;
         launch_vlw_decode(h->b.cell_start, g, n, h->b.w_rowb + (int64_t)g.nc[1] * g.nc[2], h->b.w_i0, h->b.w_i1,
                           h->b.w_c0, h->b.w_c1, h->b.w_nbr, h->b.nbr_count, max_per_row, counts, rows,
-                          (hipStream_t)stream);
+                          h->cfg.newton3 == MD_N3L_ON, (hipStream_t)stream);
     } else if (n > 0) {
         k_copy_rows<<<(n + kBlock - 1) / kBlock, kBlock, 0, (hipStream_t)stream>>>(
             n, h->b.nbr, h->b.nbr_count, h->n, max_per_row, counts, rows);

@@ -165,16 +165,18 @@ int64_t window_block_cap(int64_t n, const Geom &g);
 int window_force_blocks();
 void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *row_n, int32_t *row_base,
                    int32_t *scan_scratch, int32_t *i0, int32_t *i1, int32_t *c0, int32_t *c1, int cap,
-                   int32_t *flags, hipStream_t s);
+                   int32_t *flags, bool half, hipStream_t s);
 void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
                       const Geom &g, int n, const int32_t *nblk_p, const int32_t *i0, const int32_t *i1,
                       const int32_t *c0, const int32_t *c1, uint16_t *nbr, int32_t *cnt, int maxn, int32_t *flags,
-                      hipStream_t s);
+                      bool half, hipStream_t s);
 void launch_window_force(const ForceArgs &a, const Geom &g, hipStream_t s);
-bool window_geometry_ok(const Geom &g);
+// Windowed traversals need a reach of one cell; the half windows of the
+// Newton's-third-law traversals need three distinct cells per dimension.
+bool window_geometry_ok(const Geom &g, bool half);
 void launch_vlw_decode(const int32_t *cs, const Geom &g, int n, const int32_t *nblk_p, const int32_t *i0,
                        const int32_t *i1, const int32_t *c0, const int32_t *c1, const uint16_t *nbr,
-                       const int32_t *cnt, int maxr, int32_t *counts, int32_t *rows, hipStream_t s);
+                       const int32_t *cnt, int maxr, int32_t *counts, int32_t *rows, bool half, hipStream_t s);
 void launch_vl_build(int n, const int4 *stage, const int32_t *cell_start, const int32_t *cell_sorted,
                      const double *pos, const Geom &g, int half, int32_t *nbr, int32_t *cnt,
                      int64_t ld, int maxn, int32_t *flags, hipStream_t s);

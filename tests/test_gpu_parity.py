@@ -185,11 +185,15 @@ def test_tiny_and_empty_systems(orc):
 
 # ---------------------------------------------------------------- Verlet sets
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
 @pytest.mark.parametrize("half", [0, 1])
-def test_verlet_sets_bit_exact(orc, half):
+def test_verlet_sets_bit_exact(orc, half, prec):
+    """Full lists equal the oracle's rows within r_c + skin.  Half lists (Newton's
+    third law) hold every such pair exactly once, in the row of one of its two
+    particles."""
     pos, box = _jittered(6, 8, jitter=0.1)
     n = pos.shape[1]
-    cfg = make_config(n, box, container=1, newton3=half)
+    cfg = make_config(n, box, container=1, newton3=half, precision=prec)
     s = DeviceSystem(cfg, pos)
     s.build()
     counts, rows = M.md_get_neighbors(s.h, 256)
@@ -198,16 +202,19 @@ def test_verlet_sets_bit_exact(orc, half):
     ids = s.ids_np()
     rl2 = (2.5 + 0.3) ** 2
     ref = orc.neighbor_rows(pos, box, rl2, np.arange(n))
+    if not half:
+        for k in range(n):
+            got = np.sort(ids[rows[k, :counts[k]]])
+            assert np.array_equal(got, ref[ids[k]]), k
+        return
+    seen = {}
     for k in range(n):
-        i = ids[k]
-        got = np.sort(ids[rows[k, :counts[k]]])
-        want = ref[i]
-        if half:
-            # half list: j kept iff its sorted position is after k
-            pos_of = np.empty(n, np.int64)
-            pos_of[ids] = np.arange(n)
-            want = np.sort(want[pos_of[want] > k])
-        assert np.array_equal(got, want), k
+        for j in ids[rows[k, :counts[k]]]:
+            key = (min(ids[k], j), max(ids[k], j))
+            assert key not in seen, key  # once only
+            seen[key] = 1
+    want = {(i, j) for i in range(n) for j in ref[i] if i < j}
+    assert set(seen) == want
 
 
 # ---------------------------------------------------------------- integration
