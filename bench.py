@@ -121,43 +121,74 @@ def run(M, d, kind, steps, warmup, probe_steps=50):
     return res
 
 
-def cpu_baseline(d, target_s=12.0):
+def force_kernel_name(c):
+    """Name of the force kernel a configuration runs (FP32; the windowed
+    kernels serve cell grids with a reach of one cell)."""
+    if c["container"] == 2:
+        return "k_cl_f32"
+    windowed = c["csf"] >= 1.0
+    if c["container"] == 1:
+        return ("k_vlwh_f32" if c["newton3"] else "k_vlw_f32") if windowed else "k_vl_f32"
+    return ("k_lcwh_f32" if c["newton3"] else "k_lcw_f32") if windowed else "k_lc_f32"
+
+
+def cpu_baseline(d, target_s=10.0, brute_s=2.0):
+    """The FP64 oracle on the host cores: whole-system cell-list force
+    evaluations of the same workload, repeated for about target_s seconds;
+    and, for context, brute-force rows (every row scans all particles) for
+    about brute_s seconds."""
     import numpy as np
     from oracle import oracle as orc
     pos, box = d["pos"], d["box"]
     n = pos.shape[1]
     p = orc.single()
+    k, pairs = 0, 0.0
+    t0 = time.perf_counter()
+    while True:
+        _, _, _, npairs = orc.forces(pos, box, p, cells=True)
+        k += 1
+        pairs += float(npairs)
+        t = time.perf_counter() - t0
+        if t >= target_s:
+            break
     rng = np.random.default_rng(7)
-    m = 128
-    t0 = time.perf_counter()
-    _, cnt = orc.forces_rows(pos, box, p, rng.choice(n, m, replace=False))
-    t = time.perf_counter() - t0
-    m2 = int(min(n, max(m, m * target_s / max(t, 1e-3))))
-    rows = rng.choice(n, m2, replace=False)
-    t0 = time.perf_counter()
-    _, cnt = orc.forces_rows(pos, box, p, rows)
-    t = time.perf_counter() - t0
-    # each row sums the pairs of one particle; a whole-system evaluation sees
-    # every unordered pair twice
-    pairs = float(cnt.sum()) / 2.0
+    m = 64
+    t1 = time.perf_counter()
+    orc.forces_rows(pos, box, p, rng.choice(n, m, replace=False))
+    tb = time.perf_counter() - t1
+    m2 = int(min(n, max(m, m * brute_s / max(tb, 1e-3))))
+    t1 = time.perf_counter()
+    orc.forces_rows(pos, box, p, rng.choice(n, m2, replace=False))
+    tb = time.perf_counter() - t1
     return {"value": pairs / t, "unit": "pair-interactions/s", "cores": orc.num_threads(),
             "kind": "oracle",
-            "sample": "brute-force FP64 force rows of %d of %d particles (every row scans all %d), "
-                      "%.1f s on %s" % (m2, n, n, t, cpu_model()),
-            "pair_checks_per_s": float(m2) * (n - 1) / t}
+            "sample": "%d whole-system FP64 cell-list force evaluations of the %d-particle fluid, %.1f s on %s"
+                      % (k, n, t, cpu_model()),
+            "brute_force_pair_checks_per_s": float(m2) * (n - 1) / tb,
+            "brute_force_sample": "%d FP64 brute-force rows (each scans all %d particles), %.1f s" % (m2, n, tb)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 1000 for the fluid, "
+                    "2000 for the droplet and the slab)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--extra", default="", help="comma-separated extra fixed configs to time, "
                     "e.g. fixed:vl:1:0:5 (container:csf:n3l:R)")
     ap.add_argument("--ncell", type=int, default=64, help="FCC cells per side (64 -> 1,048,576 particles)")
+    ap.add_argument("--workload", default="fluid", choices=["fluid", "droplet", "slab"],
+                    help="fluid: the 1M homogeneous fluid (the benchmark line); droplet / slab: the 2M "
+                         "inhomogeneous systems (autotuner re-selection, measured for reference)")
+    ap.add_argument("--probe", default="", help="time only this configuration (e.g. fixed:vl:1:0:5) and print "
+                    "its result; for profiler runs")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="run a plain device-to-device copy of MIB MiB ten times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 1000 if args.workload == "fluid" else 2000
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
               file=sys.stderr)
@@ -167,9 +198,31 @@ def main():
     from paper_2505_03438_amd import workloads as W
     M.lib()
     assert torch.cuda.is_available(), "no GPU"
-    d = W.homogeneous_fluid(ncell=args.ncell)
+    if args.copy_probe:
+        x = torch.empty(args.copy_probe * 262144, dtype=torch.float32, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(10):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe, "launches": 10}), flush=True)
+        return
+    if args.workload == "fluid":
+        d = W.homogeneous_fluid(ncell=args.ncell)
+        wname = "lj-fluid-%d" % d["pos"].shape[1]
+    elif args.workload == "droplet":
+        d = W.droplet()
+        wname = "lj-droplet-%d" % d["pos"].shape[1]
+    else:
+        d = W.slab()
+        wname = "lj-slab-%d" % d["pos"].shape[1]
     n = d["pos"].shape[1]
-    log("workload: %d particles, L = %.4f" % (n, d["box"][0]))
+    log("workload: %s, box %s" % (wname, d["box"]))
+    if args.probe:
+        r = run(M, d, args.probe, args.steps, args.warmup)
+        log("%s: %.3f ms/step, force %.3f ms" % (args.probe, r["ms_per_step"], r["force_kernel_ms"]))
+        print(json.dumps({"probe": args.probe, "workload": wname, "result": r}), flush=True)
+        return
     auto = run(M, d, "auto", args.steps, args.warmup)
     log("autotuned: %.3f ms/step, %.3e pairs/s, config %s" % (auto["ms_per_step"], auto["pairs_per_s"],
                                                              auto["final_config"]))
@@ -184,7 +237,7 @@ def main():
                                                              extra[kind]["pairs_per_s"],
                                                              extra[kind]["force_kernel_ms"]))
     achieved = FLOPS_PER_PAIR * auto["pairs_per_step"] / (auto["force_kernel_ms"] * 1e-3)
-    kname = {0: "k_lc_f32", 1: "k_vl_f32", 2: "k_cluster_f32"}[auto["final_config"]["container"]]
+    kname = force_kernel_name(auto["final_config"])
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32, "traffic": None, "kernel": kname,
             "kernel_ms": auto["force_kernel_ms"],
@@ -194,7 +247,9 @@ def main():
         cpu = cpu_baseline(d)
         log("cpu oracle: %.3e pairs/s on %d threads" % (cpu["value"], cpu["cores"]))
     res = {
-        "metric": "LJ pair-interactions/sec and MD steps/sec, 1M-particle fluid, autotuned vs plain",
+        "metric": "LJ pair-interactions/sec and MD steps/sec, 1M-particle fluid, autotuned vs plain"
+                  if args.workload == "fluid" else
+                  "LJ pair-interactions/sec and MD steps/sec, 2M-particle %s, autotuned vs plain" % args.workload,
         "value": auto["pairs_per_s"],
         "unit": "pair-interactions/s",
         "n_gpus": 1,
@@ -207,9 +262,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "lj-fluid-%d" % n, "n": n, "density": 0.8, "T": 1.0, "rc": 2.5,
-                   "skin": 0.3, "dt": 0.005, "positions": "f64", "pair_arithmetic": "f32",
-                   "strategy": "predictive", "parallelism": "single-gpu"},
+        "config": {"workload": wname, "n": n, "density": 0.8 if args.workload != "slab" else 0.75,
+                   "T": float(d.get("T", 1.0)), "rc": 2.5, "skin": 0.3, "dt": 0.005, "positions": "f64",
+                   "pair_arithmetic": "f32", "strategy": "predictive", "parallelism": "single-gpu"},
         "autotuned": auto,
         "plain": plain,
         "fixed_configs": extra or None,

@@ -152,7 +152,10 @@ def slab(n: int = 2_000_000, rho_l: float = 0.75, rho_v: float = 0.02, T: float 
     liq[2] += Lx
     n_liq = liq.shape[1]
     n_vap = n - n_liq
-    av = (1.0 / rho_v) ** (1.0 / 3.0)
+    # vapour: a random subset of a grid twice as fine as the mean spacing
+    # (the liquid lattice, fitted to whole cells, may hold slightly fewer
+    # particles than rho_l Lx^3, and the vapour takes the rest)
+    av = 0.5 * (1.0 / rho_v) ** (1.0 / 3.0)
     nvx = int(math.floor(Lx / av))
     avx = Lx / nvx
     nvz = int(math.floor(Lx / avx))

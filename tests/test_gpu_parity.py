@@ -405,3 +405,38 @@ def test_fluid_1m_full_size(orc):
             for i, want in zip(sample, ref):
                 k = pos_of[i]
                 assert np.array_equal(np.sort(ids[rows[k, :counts[k]]]), want)
+
+
+# ---------------------------------------------------------------- autograd
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_autograd_function_force_matching(orc, prec):
+    """LJForces under torch.autograd: the gradient of the force-matching loss
+    with respect to positions and the four (eps, sigma) equals the oracle's
+    analytic gradient (itself pinned to central differences)."""
+    import torch
+    from paper_2505_03438_amd.autograd import lj_forces
+    d = W.binary_mixture(ncell=6, seed=13)
+    pos, box, types = d["pos"], d["box"], d["types"]
+    n = pos.shape[1]
+    theta0 = np.array(d["eps"] + d["sig"])
+    e0, s0 = orc.mix(d["eps"], d["sig"])
+    rc2 = (2.5 * s0) ** 2
+    _, target, _, _ = orc.force_matching(pos, box, types, theta0, rc2, np.zeros((3, n)))
+    theta = W.perturb_params(theta0, seed=5)
+    L0, _, gx, gt = orc.force_matching(pos, box, types, theta, rc2, target)
+    cfg = make_config(n, box, container=0, precision=prec, n_types=2, rc2=rc2)
+    s = DeviceSystem(cfg, pos, types=types, eps=list(theta[:2]), sig=list(theta[2:]))
+    s.build()
+    ids = s.ids_np()
+    x = s.pos.clone().requires_grad_(True)
+    lj = s.lj.clone().requires_grad_(True)
+    F = lj_forces(s.h, x, s.type, lj)
+    tgt = torch.tensor(target[:, ids], device="cuda")
+    loss = ((F.to(torch.float64) - tgt) ** 2).sum() / (3 * n)
+    loss.backward()
+    torch.cuda.synchronize()
+    tol_l, tol_x, tol_t = (1e-12, 1e-12, 1e-12) if prec == 1 else (1e-3, 1e-4, 1e-5)
+    assert abs(loss.item() - L0) <= tol_l * abs(L0)
+    assert rel_l2(s.by_id(x.grad), gx) <= tol_x
+    assert rel_l2(lj.grad.cpu().numpy(), gt) <= tol_t
