@@ -27,6 +27,35 @@ FLOPS_PER_PAIR = 26  # FP32 flops per interacting unordered pair (d 3, r2 5, 1/r
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (published)
 PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
 
+# HBM traffic of the Verlet-list force kernel (k_vlw_f32, 1M fluid, CSF 1,
+# gather-only), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE,
+# KiB per dispatch, averaged over the run's dispatches), each scaled by what
+# the counter reads for a plain 512 MiB device copy (FETCH_SIZE reads half the
+# bytes the copy moves: factor 2.0; WRITE_SIZE reads them exactly: 1.0).
+# Valid only for the kernel sources they were taken on (sha256 prefix of
+# window.hip, pair.h, md_internal.h); otherwise traffic is reported as null.
+VL_TRAFFIC = {"kernel": "k_vlw_f32", "sources_sha256": "fefb0cfa1d40853c",
+              "fetch_kib": 108114.1, "write_kib": 12318.5, "fetch_factor": 2.0, "write_factor": 1.0}
+
+
+def force_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2505_03438_amd", "csrc")
+    for f in ("window.hip", "pair.h", "md_internal.h"):
+        with open(os.path.join(base, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kname):
+    """HBM bytes per launch of the force kernel from the counter runs, or
+    None if they do not cover this kernel as it is now."""
+    t = VL_TRAFFIC
+    if kname != t["kernel"] or force_sources_sha() != t["sources_sha256"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -238,8 +267,11 @@ def main():
                                                              extra[kind]["force_kernel_ms"]))
     achieved = FLOPS_PER_PAIR * auto["pairs_per_step"] / (auto["force_kernel_ms"] * 1e-3)
     kname = force_kernel_name(auto["final_config"])
+    traffic = measured_traffic(kname)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32, "traffic": None, "kernel": kname,
+            "frac": achieved / PEAK_FP32, "traffic": traffic, "kernel": kname,
+            "traffic_unit": "bytes per launch (HBM, counters)",
+            "hbm_GBps_at_kernel_time": (traffic / (auto["force_kernel_ms"] * 1e-3) / 1e9) if traffic else None,
             "kernel_ms": auto["force_kernel_ms"],
             "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED}
     cpu = None

@@ -752,6 +752,9 @@ static int snapshot(md_handle *h, const StepCtx &c, bool restore, bool with_forc
         MD_HIP(cp(c.pos, b.snap_pos, 3 * n * 8));
         MD_HIP(cp(c.vel, b.snap_vel, 3 * n * rs));
         if (with_force) MD_HIP(cp(c.force, b.snap_force, 3 * n * rs));
+        // the FP32 kernels and the list builds read the staged copy of the
+        // positions: stage the restored ones
+        launch_stage((int)n, c.pos, c.type, h->g, b.stage, c.s);
     }
     return MD_OK;
 }

@@ -686,6 +686,9 @@ extern "C" int md_batch_step(md_batch *b, double *pos, void *vel, void *force, i
             if (n > 0) {
                 MD_HIP(hipMemcpyAsync(pos, b->snap_pos, 24 * n, hipMemcpyDeviceToDevice, s));
                 MD_HIP(hipMemcpyAsync(vel, b->snap_vel, 3 * rs * n, hipMemcpyDeviceToDevice, s));
+                // the FP32 force reads the staged copy of the positions: stage
+                // the restored ones
+                k_bstage<<<bblocks((int64_t)n), 256, 0, s>>>((int)n, pos, type, b->sys_of, b->sys, b->stage);
             }
             batch_forces(b, pos, force, false, s);
             for (int k = 1; k < v; k++) {

@@ -302,6 +302,25 @@ def test_skin_violation_forces_rebuild(orc):
         assert np.abs(log[:, 0] - log0[:, 0]).max() <= 1e-10 * np.abs(log0[:, 0]).max()
 
 
+def test_skin_violation_replay_fp32(orc):
+    """FP32 pairs with replays after skin violations: the trajectory stays on
+    the FP64 oracle's within FP32 rounding (a replay that used stale staged
+    coordinates would leave it by orders of magnitude)."""
+    d = W.plain_fcc_864()
+    nsteps = 60
+    p1, v1, _, log0 = orc.velocity_verlet(d["pos"], d["vel"], d["box"], orc.single(), 0.005, nsteps)
+    for cont in ((1, 0, 1.0), (0, 0, 1.0), (2, 0, 1.0), (1, 1, 1.0)):
+        s, log = _run_nve(orc, 0, cont, nsteps=nsteps, R=200)
+        cnt = M.md_get_counters(s.h)
+        assert cnt["forced_rebuilds"] >= 1, cont
+        x = s.by_id(s.pos)
+        dx = x - p1
+        dx -= d["box"][:, None] * np.rint(dx / d["box"][:, None])
+        assert np.abs(dx).max() < 1e-5, cont
+        assert np.abs(s.by_id(s.vel) - v1).max() < 1e-3, cont
+        assert np.array_equal(log[:20, 3], log0[:20, 3]), cont
+
+
 @pytest.mark.parametrize("cont", [(1, 0, 20, 78), (2, 0, 4, 20)], ids=["vl", "cl"])
 def test_list_overflow_grows(orc, cont):
     import torch
