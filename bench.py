@@ -93,7 +93,12 @@ def make_cfg(M, n, box, kind, steps):
         c.container = M.MD_CONTAINER_LC
         c.rebuild_interval = 10
         c.autotune = M.MD_TUNE_PREDICTIVE
-        c.tune_interval = max(1, steps // 4)
+        # two tuning phases (at steps 0 and steps/2): a phase trials every
+        # configuration for tune_trial_steps steps, so shorter intervals would
+        # spend most of a 1000-step run in trials (with four phases the
+        # retrial gap of a quarter of the run is one phase, and every phase
+        # trials the whole space)
+        c.tune_interval = max(1, steps // 2)
         c.tune_trial_steps = 10
         c.total_steps_hint = steps
     return c

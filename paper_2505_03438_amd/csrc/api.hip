@@ -75,6 +75,13 @@ int make_geom(const md_config &c, double csf, Geom &g)
     g.ry = (float)(c.box[1] / c.box[0]);
     g.rz = (float)(c.box[2] / c.box[0]);
     g.iso = (c.box[0] == c.box[1] && c.box[1] == c.box[2]) ? 1 : 0;
+    // y-rows per windowed block: about 256 particles per block at the mean
+    // density, in blocks about four times longer (in x) than high (in y)
+    double ppc = (double)std::max<int64_t>(c.n, 1) / (double)ncell;
+    int band = (int)floor(sqrt(256.0 / ppc / 4.0));
+    band = std::max(1, std::min(band, kWinBlkRows));
+    band = std::min(band, std::max(1, g.nc[1] - 2 * g.reach[1]));
+    g.wband = band;
     double u = c.box[0] / 4294967296.0;
     g.rl2_lo = (float)(g.rl2 / (u * u) * (1.0 - kBand));
     g.rl2_hi = (float)(g.rl2 / (u * u) * (1.0 + kBand));
@@ -134,8 +141,8 @@ static void free_buffers(md_handle *h)
                     b.nbr, b.nbr_count, b.partials, b.kpart, b.flags, b.tab, b.facc, b.cl_start,
                     b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
                     b.cl_nbr_count, b.snap_pos, b.snap_vel,
-                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart, b.w_i0, b.w_i1,
-                    b.w_c0, b.w_c1, b.w_rown, b.w_rowb, b.w_nbr};
+                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart,
+                    b.w_blk, b.w_rown, b.w_rowb, b.w_nbr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (b.host_flags) (void)hipHostFree(b.host_flags);
@@ -438,11 +445,9 @@ static int ensure_window(md_handle *h, int64_t maxn)
     int rc;
     int64_t cap = window_block_cap(h->n, h->g);
     if (cap > b.w_cap) {
-        for (int32_t **p : {&b.w_i0, &b.w_i1, &b.w_c0, &b.w_c1}) {
-            if (*p) (void)hipFree(*p);
-            *p = nullptr;
-            if ((rc = dalloc(p, cap))) return rc;
-        }
+        if (b.w_blk) (void)hipFree(b.w_blk);
+        b.w_blk = nullptr;
+        if ((rc = dalloc(&b.w_blk, cap))) return rc;
         b.w_cap = cap;
     }
     int64_t rows = (int64_t)h->g.nc[1] * h->g.nc[2] + 1;
@@ -472,8 +477,8 @@ static int build_blocks(md_handle *h, hipStream_t s)
     if (rc) return rc;
     // the per-cell counts are no longer needed once the cells are built: the
     // same buffer holds the window column sums of the packer
-    launch_blocks(h->g, b.cell_start, b.cell_count, b.w_rown, b.w_rowb, b.scan_blocks, b.w_i0, b.w_i1, b.w_c0,
-                  b.w_c1, (int)b.w_cap, b.flags, h->cfg.newton3 == MD_N3L_ON, s);
+    launch_blocks(h->g, b.cell_start, b.cell_count, b.w_rown, b.w_rowb, b.scan_blocks, b.w_blk, (int)b.w_cap,
+                  b.flags, h->cfg.newton3 == MD_N3L_ON, s);
     return MD_OK;
 }
 
@@ -485,11 +490,9 @@ static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
         int rc = ensure_window(h, h->cfg.max_neighbors);
         if (rc) return rc;
         const Geom &g = h->g;
-        int nrows = g.nc[1] * g.nc[2];
         launch_fill_i32(b.flags + 2, 0, 1, s);
-        launch_vlw_build(b.stage, b.cell_start, b.cell_sorted, pos, g, n, b.w_rowb + nrows, b.w_i0, b.w_i1, b.w_c0,
-                         b.w_c1, b.w_nbr, b.nbr_count, h->cfg.max_neighbors, b.flags, h->cfg.newton3 == MD_N3L_ON,
-                         s);
+        launch_vlw_build(b.stage, b.cell_start, b.cell_sorted, pos, g, n, b.w_rowb + window_nbands(g), b.w_blk,
+                         b.w_nbr, b.nbr_count, h->cfg.max_neighbors, b.flags, h->cfg.newton3 == MD_N3L_ON, s);
     } else if (h->cfg.container == MD_CONTAINER_VL) {
         int rc = ensure_list(h, h->cfg.max_neighbors);
         if (rc) return rc;
@@ -567,11 +570,8 @@ static ForceArgs force_args(md_handle *h, const double *pos, const int32_t *type
     a.flags = h->b.flags;
     a.window = use_window(h->cfg, h->g);
     if (a.window) {
-        a.w_nblk = h->b.w_rowb + (int64_t)h->g.nc[1] * h->g.nc[2];
-        a.w_i0 = h->b.w_i0;
-        a.w_i1 = h->b.w_i1;
-        a.w_c0 = h->b.w_c0;
-        a.w_c1 = h->b.w_c1;
+        a.w_nblk = h->b.w_rowb + window_nbands(h->g);
+        a.w_blk = h->b.w_blk;
         a.w_nbr = h->b.w_nbr;
     }
     return a;
@@ -1041,9 +1041,9 @@ extern "C" int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows, in
                        b.cl_cap, max_per_row, counts, rows, (hipStream_t)stream);
     } else if (use_window(h->cfg, h->g)) {
         const Geom &g = h->g;
-        launch_vlw_decode(h->b.cell_start, g, n, h->b.w_rowb + (int64_t)g.nc[1] * g.nc[2], h->b.w_i0, h->b.w_i1,
-                          h->b.w_c0, h->b.w_c1, h->b.w_nbr, h->b.nbr_count, max_per_row, counts, rows,
-                          h->cfg.newton3 == MD_N3L_ON, (hipStream_t)stream);
+        launch_vlw_decode(h->b.cell_start, h->b.cell_sorted, g, n, h->b.w_rowb + window_nbands(g), h->b.w_blk,
+                          h->b.w_nbr, h->b.nbr_count, max_per_row, counts, rows, h->cfg.newton3 == MD_N3L_ON,
+                          (hipStream_t)stream);
     } else if (n > 0) {
         k_copy_rows<<<(n + kBlock - 1) / kBlock, kBlock, 0, (hipStream_t)stream>>>(
             n, h->b.nbr, h->b.nbr_count, h->n, max_per_row, counts, rows);

@@ -22,6 +22,7 @@ namespace mdlj {
 constexpr double kBand = 1.0 / 524288.0;
 
 constexpr int kMaxOfs = 5;  // neighbour cell offsets per dimension (reach <= 2)
+constexpr int kWinBlkRows = 4;  // maximum y-rows of a block of the windowed traversals
 
 // Per-type-pair constants, computed on the device from the per-type
 // parameters (Lorentz-Berthelot) so that parameters may live in device memory
@@ -53,6 +54,7 @@ struct Geom {
     float disp2;      // (skin/2)^2 (1 - 1e-4) in u^2: skin check threshold
     int nt;           // number of types
     int reach[3];     // stencil reach in cells per dimension
+    int wband;        // y-rows per block of the windowed traversals
 };
 
 // Device buffers and state of one handle.
@@ -87,7 +89,7 @@ struct Buffers {
     int32_t *snap_type = nullptr, *snap_ids = nullptr;
     int4 *snap_stage = nullptr;
     // Verlet lists over LDS windows (FP32 gather-only)
-    int32_t *w_i0 = nullptr, *w_i1 = nullptr, *w_c0 = nullptr, *w_c1 = nullptr;
+    int4 *w_blk = nullptr;  // per block: first cell, last cell, particle range (or -1, -1)
     int32_t *w_rown = nullptr, *w_rowb = nullptr;
     uint16_t *w_nbr = nullptr;
     int64_t w_cap = 0, w_rows_cap = 0, w_nbr_cap = 0;
@@ -154,7 +156,8 @@ struct ForceArgs {
     int32_t *flags;
     // window lists
     bool window;
-    const int32_t *w_nblk, *w_i0, *w_i1, *w_c0, *w_c1;
+    const int32_t *w_nblk;
+    const int4 *w_blk;
     const uint16_t *w_nbr;
 };
 int force_blocks(const ForceArgs &a);  // number of partial slots written when energy
@@ -162,21 +165,20 @@ void launch_force(const ForceArgs &a, const Geom &g, hipStream_t s);
 
 // window.hip
 int64_t window_block_cap(int64_t n, const Geom &g);
+int window_nbands(const Geom &g);
 int window_force_blocks();
-void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *row_n, int32_t *row_base,
-                   int32_t *scan_scratch, int32_t *i0, int32_t *i1, int32_t *c0, int32_t *c1, int cap,
-                   int32_t *flags, bool half, hipStream_t s);
+void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *band_n, int32_t *band_base,
+                   int32_t *scan_scratch, int4 *blocks, int cap, int32_t *flags, bool half, hipStream_t s);
 void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
-                      const Geom &g, int n, const int32_t *nblk_p, const int32_t *i0, const int32_t *i1,
-                      const int32_t *c0, const int32_t *c1, uint16_t *nbr, int32_t *cnt, int maxn, int32_t *flags,
-                      bool half, hipStream_t s);
+                      const Geom &g, int n, const int32_t *nblk_p, const int4 *blocks, uint16_t *nbr, int32_t *cnt,
+                      int maxn, int32_t *flags, bool half, hipStream_t s);
 void launch_window_force(const ForceArgs &a, const Geom &g, hipStream_t s);
-// Windowed traversals need a reach of one cell; the half windows of the
-// Newton's-third-law traversals need three distinct cells per dimension.
+// Windowed traversals need the same reach (1 or 2 cells) in every
+// dimension and 2 reach + 1 distinct cells per dimension.
 bool window_geometry_ok(const Geom &g, bool half);
-void launch_vlw_decode(const int32_t *cs, const Geom &g, int n, const int32_t *nblk_p, const int32_t *i0,
-                       const int32_t *i1, const int32_t *c0, const int32_t *c1, const uint16_t *nbr,
-                       const int32_t *cnt, int maxr, int32_t *counts, int32_t *rows, bool half, hipStream_t s);
+void launch_vlw_decode(const int32_t *cs, const int32_t *cell_sorted, const Geom &g, int n, const int32_t *nblk_p,
+                       const int4 *blocks, const uint16_t *nbr, const int32_t *cnt, int maxr, int32_t *counts,
+                       int32_t *rows, bool half, hipStream_t s);
 void launch_vl_build(int n, const int4 *stage, const int32_t *cell_start, const int32_t *cell_sorted,
                      const double *pos, const Geom &g, int half, int32_t *nbr, int32_t *cnt,
                      int64_t ld, int maxn, int32_t *flags, hipStream_t s);

@@ -1,17 +1,21 @@
-// Pair traversals over LDS windows (FP32, gather-only).
+// Pair traversals over LDS windows (FP32).
 //
-// Particles are in linked-cell order (cells x-fastest, within a cell by id).
-// A block is a run of consecutive cells of one x-row holding at most 256
-// particles (one workgroup, one thread per particle).  Its window is the
-// union of its cells' stencils: for every neighbouring (y, z) row the
-// contiguous cell columns [x_first - 1, x_last + 1] (two particle ranges, or
-// pieces, when they wrap around the periodic box).  The block packer bounds
-// every window to the LDS tile.  A workgroup stages the window once, then:
-//   - linked cells: each thread scans its own stencil cells inside the
-//     window (the GPU analogue of the C01 traversal: no write conflicts);
+// Particles are in linked-cell order (cells x-fastest).  A block is a
+// rectangle of cells in one z-layer: up to four consecutive y-rows (more rows
+// when cells hold few particles) times a run of consecutive x-columns, with
+// at most 256 particles (one workgroup, one thread per particle).  Its window
+// is the union of its cells' stencils for a reach of r = 1 or 2 cells: the
+// (y, z) rows y0 - r .. y1 + r of layers z - r .. z + r, each over the cell
+// columns [x_first - r, x_last + r] (two particle ranges, or pieces, when the
+// columns wrap around the periodic box).  The block packer bounds every
+// window to the LDS tile.  A workgroup stages the window once, then:
+//   - linked cells: each thread scans its own stencil inside the window (the
+//     GPU analogue of the C01 traversal: no write conflicts);
 //   - Verlet lists: each thread walks its list of 16-bit window positions,
 //     stored in chunks of eight (one 16-byte load per chunk, the next chunk
-//     in flight while the current one is computed).
+//     in flight while the current one is computed);
+//   - with Newton's third law, a half window holds only the forward part of
+//     the stencils (see row_of) and the j-side forces go to LDS.
 // Blocks of neighbouring cells share most of their windows, so the blocks
 // are dealt to the eight XCDs in contiguous chunks (workgroup w runs on XCD
 // w mod 8) to keep the shared window data in one L2.
@@ -19,22 +23,18 @@
 
 namespace mdlj {
 
-constexpr int kWinMax = 3072;    // LDS window capacity (particles)
-constexpr int kBlkCells = 32;    // maximum cells of a block along x
-constexpr int kMaxRows = 9;      // stencil rows of a reach-1 window (3 x 3)
-constexpr int kMaxCols = kBlkCells + 2;  // window columns of a reach-1 window
-constexpr int kLoadPer = (kWinMax + 255) / 256;
-constexpr int kWinGrid = 2048;   // persistent workgroups (multiple of 8)
-constexpr int kHalfRows = 5;     // rows of a half window (four forward rows, then the own row)
-constexpr int kHalfOwn = 4;      // the own row of a half window
-constexpr int kWinMaxHalf = 2048;  // LDS capacity of a half window (positions and j-side forces)
+constexpr int kWinMax = 2880;      // LDS window capacity (particles), full windows
+constexpr int kWinMaxHalf = 2048;  // half windows (positions and j-side forces)
+constexpr int kBlkCells = 32;      // maximum cells of a block along x
+constexpr int kMaxReach = 2;
+constexpr int kMaxRows = (2 * kMaxReach + 1) * (kWinBlkRows + 2 * kMaxReach);  // window rows
+constexpr int kMaxCols = kBlkCells + 2 * kMaxReach;                            // window columns
+constexpr int kWinGrid = 2048;     // persistent workgroups (multiple of 8)
 
-using Ofs = int (*)[kMaxOfs];
 using COfs = const int (*)[kMaxOfs];
 
 // LDS entry of a window particle: its staged fixed-point coordinates, and its
-// type when there are two.  Twelve bytes for one type keep four workgroups'
-// windows (4 x 36 KB) within a compute unit's LDS.
+// type when there are two (12 or 16 bytes).
 template <int NT>
 struct WinEntry {
     int x, y, z, w;
@@ -61,84 +61,133 @@ struct WinEntry<1> {
 
 // ------------------------------------------------------------------ windows
 
-// Columns [lo, hi] of the window of a block spanning xa..xb (hi < lo when it
-// wraps); returns the number of columns.
-__device__ __forceinline__ int window_columns(const Geom &g, int xa, int xb, int &lo, int &hi)
+// Block rectangle from its first and last cells.
+struct Rect {
+    int xa, xb, y0, y1, z;
+};
+
+__device__ __forceinline__ Rect rect_of(const Geom &g, int c0, int c1)
+{
+    int nx = g.nc[0], ny = g.nc[1];
+    Rect r;
+    r.xa = c0 % nx;
+    r.y0 = (c0 / nx) % ny;
+    r.z = c0 / (nx * ny);
+    r.xb = c1 % nx;
+    r.y1 = (c1 / nx) % ny;
+    return r;
+}
+
+// Columns [lo, ...] of the window of a block spanning xa..xb with reach r:
+// ncols columns starting at lo, or the whole row (lo = 0, ncols = nx) when
+// that is not longer.
+__device__ __forceinline__ int window_columns(const Geom &g, int r, int xa, int xb, int &lo)
 {
     int nx = g.nc[0];
-    if (xb - xa + 3 >= nx) {
+    if (xb - xa + 1 + 2 * r >= nx) {
         lo = 0;
-        hi = nx - 1;
         return nx;
     }
-    lo = xa == 0 ? nx - 1 : xa - 1;
-    hi = xb + 1 == nx ? 0 : xb + 1;
-    return xb - xa + 3;
+    lo = xa - r;
+    lo = lo < 0 ? lo + nx : lo;
+    return xb - xa + 1 + 2 * r;
 }
 
-// Linear id of the x = 0 cell of stencil row rr around row (cy, cz).  A full
-// window holds the 3 x 3 stencil rows (fewer when a small periodic grid
-// repeats a row); a half window, for the traversals with Newton's third law,
-// holds the four forward rows (z + 1 with y - 1, y, y + 1, then z with y + 1)
-// and the own row last.  With the forward columns of the own row this is half
-// of the 26 neighbour cells: every pair of distinct cells is seen from exactly
-// one of its two cells (this needs at least three cells in every dimension).
-template <bool HALF>
-__device__ __forceinline__ int row_cell_of(const Geom &g, COfs so, int cy, int cz, int rr)
+// Rows of a window for a block of nyb y-rows, reach r.  Row rr maps to the
+// layer offset dz and y-row offset dy (relative to y0) of the cells it holds:
+//   full window: layers z - r .. z + r, each with y-rows y0 - r .. y1 + r;
+//   half window: layers z + 1 .. z + r with y-rows y0 - r .. y1 + r, then
+//     layer z with y-rows y0 .. y1 + r (the own rows first).
+// A particle in block row k (y = y0 + k) meets, in a half window, the rows
+// of layers z + 1 .. z + r at y - r .. y + r, the rows y + 1 .. y + r of its
+// own layer, and in its own row the columns x + 1 .. x + r and the particles
+// after it in its own cell: half of the (2r + 1)^3 - 1 neighbour cells, so
+// that every pair of distinct cells is seen from exactly one of its two cells
+// (with at least 2r + 1 cells per dimension).
+__device__ __forceinline__ int window_nrow(int r, int nyb, bool half)
 {
-    int zz, yy;
-    if (HALF) {
-        int dz = rr < 3 ? 1 : 0;
-        int dy = rr < 3 ? rr - 1 : (rr == 3 ? 1 : 0);
-        zz = cz + dz;
-        zz = zz >= g.nc[2] ? zz - g.nc[2] : zz;
-        yy = cy + dy;
-        yy = yy < 0 ? yy + g.nc[1] : (yy >= g.nc[1] ? yy - g.nc[1] : yy);
-    } else {
-        int a = rr / g.nofs[1], b = rr - a * g.nofs[1];
-        zz = cz + so[2][a];
-        zz = zz >= g.nc[2] ? zz - g.nc[2] : zz;
-        yy = cy + so[1][b];
-        yy = yy >= g.nc[1] ? yy - g.nc[1] : yy;
-    }
-    return (zz * g.nc[1] + yy) * g.nc[0];
+    int span = nyb + 2 * r;
+    return half ? r * span + nyb + r : (2 * r + 1) * span;
 }
 
-// Window layout in LDS.  Column m of stencil row rr is cell column
+__device__ __forceinline__ void row_of(int r, int nyb, bool half, int rr, int &dz, int &dy)
+{
+    int span = nyb + 2 * r;
+    if (!half) {
+        dz = rr / span - r;
+        dy = rr % span - r;
+    } else if (rr < r * span) {
+        dz = rr / span + 1;
+        dy = rr % span - r;
+    } else {
+        dz = 0;
+        dy = rr - r * span;
+    }
+}
+
+// Window row of layer offset dz, y-row offset dy (relative to y0).
+__device__ __forceinline__ int row_index(int r, int nyb, bool half, int dz, int dy)
+{
+    int span = nyb + 2 * r;
+    if (!half) return (dz + r) * span + dy + r;
+    return dz > 0 ? (dz - 1) * span + dy + r : r * span + dy;
+}
+
+__device__ __forceinline__ int wrap_dim(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Window layout in LDS.  Column m of window row rr is cell column
 // (lo + m) mod nx; its particles occupy window positions
 // [col[rr][m], col[rr][m + 1]).  Piece k (two per row, the second empty
 // unless the columns wrap) holds particles [pc_start[k], ...) at window
-// positions [pc_win[k], pc_win[k + 1]).
+// positions [pc_win[k], pc_win[k + 1]).  The block's own particles are, per
+// block row k, [ba[k], ba[k] + bpref[k + 1] - bpref[k]), threads
+// bpref[k] .. bpref[k + 1] - 1.
 struct Window {
-    int nrow, ncols, lo, self_row, W;
+    int nrow, ncols, lo, W, nyb, r, npart;
+    Rect rc;
+    int ba[kWinBlkRows], bpref[kWinBlkRows + 1];
     int pc_start[2 * kMaxRows];
     int pc_win[2 * kMaxRows + 1];
-    int col[kMaxRows][kMaxCols + 1];
+    uint16_t col[kMaxRows][kMaxCols + 1];
 };
 
-// Lay out the (full or half) window of the block with cells c0..c1 (one
-// row).  All threads take part; ends with a barrier.
-template <bool HALF>
-__device__ void make_window(const Geom &g, COfs so, const int32_t *__restrict__ cs, int c0, int c1, Window &w)
+// Lay out the (full or half) window of block blk = (first cell, last cell,
+// first particle, end particle; the particle range is -1 for blocks of whole
+// cells).  The column table is filled only when COLS.  All threads take
+// part; ends with a barrier.
+template <bool HALF, bool COLS = true>
+__device__ void make_window(const Geom &g, const int32_t *__restrict__ cs, int4 blk, Window &w)
 {
-    int nx = g.nc[0];
-    int xa = c0 % nx, xb = c1 % nx;
-    int r = c0 / nx;
-    int cy = r % g.nc[1], cz = r / g.nc[1];
-    int lo, hi;
-    int ncols = window_columns(g, xa, xb, lo, hi);
-    int nrow = HALF ? kHalfRows : g.nofs[1] * g.nofs[2];
+    int nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
+    int r = g.reach[0];
+    Rect rc = rect_of(g, blk.x, blk.y);
+    int nyb = rc.y1 - rc.y0 + 1;
+    int lo;
+    int ncols = window_columns(g, r, rc.xa, rc.xb, lo);
+    int nrow = window_nrow(r, nyb, HALF);
+    bool wrap = lo + ncols > nx;
+    int x1a = wrap ? nx - 1 : lo + ncols - 1;  // last column of the first piece
     int t = threadIdx.x;
-    bool wrap = hi < lo;
-    int x1a = wrap ? nx - 1 : hi;
     if (t < nrow) {
-        int rb = row_cell_of<HALF>(g, so, cy, cz, t);
+        int dz, dy;
+        row_of(r, nyb, HALF, t, dz, dy);
+        int rb = (wrap_dim(rc.z + dz, nz) * ny + wrap_dim(rc.y0 + dy, ny)) * nx;
         int s0 = cs[rb + lo], e0 = cs[rb + x1a + 1];
-        int s1 = cs[rb], e1 = wrap ? cs[rb + hi + 1] : s1;
+        int s1 = cs[rb], e1 = wrap ? cs[rb + lo + ncols - nx] : s1;
         w.pc_start[2 * t] = s0;
         w.pc_start[2 * t + 1] = s1;
         w.pc_win[2 * t] = e0 - s0;  // lengths for now
         w.pc_win[2 * t + 1] = e1 - s1;
+    } else if (t >= 64 && t < 64 + nyb) {
+        int k = t - 64;
+        if (blk.z >= 0) {  // a particle range (blocks of one row)
+            w.ba[0] = blk.z;
+            w.bpref[1] = blk.w - blk.z;
+        } else {
+            int rb = (rc.z * ny + rc.y0 + k) * nx;
+            w.ba[k] = cs[rb + rc.xa];
+            w.bpref[k + 1] = cs[rb + rc.xb + 1] - cs[rb + rc.xa];  // counts for now
+        }
     }
     __syncthreads();
     if (t == 0) {
@@ -153,18 +202,19 @@ __device__ void make_window(const Geom &g, COfs so, const int32_t *__restrict__ 
         w.nrow = nrow;
         w.ncols = ncols;
         w.lo = lo;
-        if (HALF) {
-            w.self_row = kHalfOwn;
-        } else {
-            int a0 = 0, b0 = 0;
-            for (int a = 0; a < g.nofs[2]; a++)
-                if (so[2][a] == 0) a0 = a;
-            for (int b = 0; b < g.nofs[1]; b++)
-                if (so[1][b] == 0) b0 = b;
-            w.self_row = a0 * g.nofs[1] + b0;
+        w.nyb = nyb;
+        w.r = r;
+        w.rc = rc;
+        int np = 0;
+        w.bpref[0] = 0;
+        for (int k = 0; k < nyb; k++) {
+            np += w.bpref[k + 1];
+            w.bpref[k + 1] = np;
         }
+        w.npart = np;
     }
     __syncthreads();
+    if (!COLS) return;
     int ncol0 = x1a - lo + 1;  // columns in the first piece
     for (int e = t; e < nrow * (ncols + 1); e += blockDim.x) {
         int rr = e / (ncols + 1), m = e - rr * (ncols + 1);
@@ -172,13 +222,15 @@ __device__ void make_window(const Geom &g, COfs so, const int32_t *__restrict__ 
         if (m == ncols) {
             v = w.pc_win[2 * rr + 2];
         } else {
-            int rb = row_cell_of<HALF>(g, so, cy, cz, rr);
+            int dz, dy;
+            row_of(r, nyb, HALF, rr, dz, dy);
+            int rb = (wrap_dim(rc.z + dz, nz) * ny + wrap_dim(rc.y0 + dy, ny)) * nx;
             if (m < ncol0)
                 v = w.pc_win[2 * rr] + cs[rb + lo + m] - w.pc_start[2 * rr];
             else
                 v = w.pc_win[2 * rr + 1] + cs[rb + m - ncol0] - w.pc_start[2 * rr + 1];
         }
-        w.col[rr][m] = v;
+        w.col[rr][m] = (uint16_t)v;
     }
     __syncthreads();
 }
@@ -242,139 +294,221 @@ struct BlockIter {
     }
 };
 
-// Window range of the cell column x + (e-th x offset) in stencil row rr.
-__device__ __forceinline__ void stencil_range(const Geom &g, COfs so, const Window &w, int x, int rr, int e, int &b,
-                                              int &en)
+// The particle of this thread in the block: its index i, block row k and
+// cell column x; false if the thread has none.
+__device__ __forceinline__ bool my_particle(const Geom &g, const Window &w, const int32_t *__restrict__ cell_sorted,
+                                            int &i, int &k, int &x)
+{
+    int t = threadIdx.x;
+    if (t >= w.npart) return false;
+    k = 0;
+    while (k + 1 < w.nyb && w.bpref[k + 1] <= t) k++;
+    i = w.ba[k] + (t - w.bpref[k]);
+    x = cell_sorted[i] % g.nc[0];
+    return true;
+}
+
+// Window column of cell column x.
+__device__ __forceinline__ int column_of(const Geom &g, const Window &w, int x)
+{
+    int m = x - w.lo;
+    return m < 0 ? m + g.nc[0] : m;
+}
+
+// Window position of particle i (in block row k, cell column x) itself.
+template <bool HALF>
+__device__ __forceinline__ int self_position(const Window &w, const int32_t *__restrict__ cs, int i, int k,
+                                             int m, int cell)
+{
+    int own = row_index(w.r, w.nyb, HALF, 0, k);
+    return w.col[own][m] + (i - cs[cell]);
+}
+
+// The window columns of cell columns x + a .. x + b (a <= b, |a|, |b| <= r)
+// as up to two contiguous ranges [a0, b0], [a1, b1] (b < a: empty): one
+// range unless they wrap inside a window that covers the whole x-row.
+struct ColRanges {
+    int a0, b0, a1, b1;
+};
+
+__device__ __forceinline__ ColRanges column_ranges(const Geom &g, const Window &w, int x, int a, int b)
 {
     int nx = g.nc[0];
-    int xx = x + so[0][e];
-    xx = xx >= nx ? xx - nx : xx;
-    int m = xx - w.lo;
-    m = m < 0 ? m + nx : m;
-    b = w.col[rr][m];
-    en = w.col[rr][m + 1];
+    ColRanges cr{0, -1, 0, -1};
+    if (w.ncols < nx) {
+        int m = column_of(g, w, x);
+        cr.a0 = m + a;
+        cr.b0 = m + b;
+        return cr;
+    }
+    int lo = x + a, hi = x + b;  // whole row: lo = 0, column m = cell column
+    if (lo >= nx) {
+        lo -= nx;
+        hi -= nx;
+    } else if (hi < 0) {
+        lo += nx;
+        hi += nx;
+    }
+    if (lo >= 0 && hi < nx) {
+        cr.a0 = lo;
+        cr.b0 = hi;
+    } else if (lo < 0) {
+        cr.a0 = 0;
+        cr.b0 = hi;
+        cr.a1 = lo + nx;
+        cr.b1 = nx - 1;
+    } else {
+        cr.a0 = lo;
+        cr.b0 = nx - 1;
+        cr.a1 = 0;
+        cr.b1 = hi - nx;
+    }
+    return cr;
 }
 
 // ------------------------------------------------------------------ block partition
 
-// Particles in the stencil rows (full or half window) at column x of each
-// cell: the window of a block spanning columns xa..xb is the sum over its
-// window columns.
+// Particles of the window rows of a block band at column x: the window of a
+// block spanning columns xa..xb of band (z, y0 .. y1) is the sum over its
+// window columns.  Band bi of layer z covers y-rows bi * band .. ; colsum is
+// [layer][band][x].
 template <bool HALF>
 __global__ void k_colsum(Geom g, const int32_t *__restrict__ cs, int32_t *__restrict__ colsum)
 {
-    __shared__ int so[3][kMaxOfs];
-    load_offsets(g, so);
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.ncell) return;
-    int nx = g.nc[0];
-    int x = c % nx, r = c / nx;
-    int cy = r % g.nc[1], cz = r / g.nc[1];
-    int nrow = HALF ? kHalfRows : g.nofs[1] * g.nofs[2];
+    int nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
+    int band = g.wband, nby = (ny + band - 1) / band;
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nz * nby * nx) return;
+    int x = e % nx, t = e / nx;
+    int bi = t % nby, z = t / nby;
+    int r = g.reach[0];
+    int y0 = bi * band, nyb = min(band, ny - y0);
+    int nrow = window_nrow(r, nyb, HALF);
     int s = 0;
     for (int rr = 0; rr < nrow; rr++) {
-        int cell = row_cell_of<HALF>(g, so, cy, cz, rr) + x;
+        int dz, dy;
+        row_of(r, nyb, HALF, rr, dz, dy);
+        int cell = (wrap_dim(z + dz, nz) * ny + wrap_dim(y0 + dy, ny)) * nx + x;
         s += cs[cell + 1] - cs[cell];
     }
-    colsum[c] = s;
+    colsum[e] = s;
 }
 
-// Greedy packing of one x-row: a block starts at a non-empty cell and grows
-// while it holds <= 256 particles, spans at most kBlkCells columns and its
-// window fits the LDS tile (wmax positions).  emit == false only counts.  A
-// single cell of more than 256 particles, or whose window alone exceeds the
-// tile, cannot be held: flags[3] reports it.
-__device__ int pack_row(int row, const Geom &g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
-                        int base, int32_t *i0, int32_t *i1, int32_t *c0, int32_t *c1, bool emit, int cap,
-                        int32_t *flags, int wmax)
+// Greedy packing of one band, by one wavefront: the band's column data is
+// staged in LDS, then lane 0 cuts the band into blocks.  A block grows while
+// it holds <= 256 particles, spans at most kBlkCells columns and its window
+// fits the LDS tile (wmax positions).  Bands of one row are cut at particle
+// granularity (a block may start and end inside a cell, so that most blocks
+// hold exactly 256 particles and fill four wavefronts); bands of several rows
+// are cut at whole columns.  emit == false only counts.  A single column
+// whose window cannot be held reports flags[3].
+constexpr int kPackMaxX = 4096;
+
+__device__ int pack_band(int e, const Geom &g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
+                         int base, int4 *blocks, bool emit, int cap, int32_t *flags, int wmax, int *scol, int *snum,
+                         int *sst)
 {
-    int nx = g.nc[0];
-    int rb = row * nx;
-    int rowsum = 0;
-    for (int x = 0; x < nx; x++) rowsum += colsum[rb + x];
-    auto col = [&](int k) { return colsum[rb + (k < 0 ? k + nx : (k >= nx ? k - nx : k))]; };
-    // window of a block spanning xa..xb: the column sums of xa-1 .. xb+1
-    // (the whole row once the columns cover it); extended one column at a
-    // time as a block grows
-    auto window_of = [&](int xa, int xb) {
-        if (xb - xa + 3 >= nx) return rowsum;
-        int s = 0;
-        for (int k = xa - 1; k <= xb + 1; k++) s += col(k);
-        return s;
-    };
-    int nb = 0;
-    int bs = -1, bp = 0, bx0 = 0, bxl = 0, bw = 0;  // open block: first particle, particles, x range, window
-    auto close = [&]() {
-        if (bs >= 0 && bp > 0) {
-            if (emit && base + nb < cap) {
-                i0[base + nb] = bs;
-                i1[base + nb] = bs + bp;
-                c0[base + nb] = rb + bx0;
-                c1[base + nb] = rb + bxl;
-            }
-            nb++;
+    int nx = g.nc[0], ny = g.nc[1];
+    int band = g.wband, nby = (ny + band - 1) / band;
+    int bi = e % nby, z = e / nby;
+    int y0 = bi * band, y1 = min(ny, y0 + band) - 1;
+    int r = g.reach[0];
+    bool one_row = y0 == y1;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+        scol[x] = colsum[(size_t)e * nx + x];
+        int m = 0;
+        for (int y = y0; y <= y1; y++) {
+            int c = (z * ny + y) * nx + x;
+            m += cs[c + 1] - cs[c];
         }
-        bs = -1;
-        bp = 0;
-    };
-    for (int x = 0; x < nx; x++) {
-        int s = cs[rb + x], e = cs[rb + x + 1];
-        int m = e - s;
-        if (m == 0) continue;
-        if (bs >= 0) {
-            // window of [bx0, x] from that of [bx0, bxl]: add columns bxl+2 .. x+1
-            int w2;
-            if (x - bx0 + 3 >= nx) {
-                w2 = rowsum;
-            } else {
-                w2 = bw;
-                for (int k = bxl + 2; k <= x + 1; k++) w2 += col(k);
-            }
-            if (bp + m > 256 || x - bx0 >= kBlkCells || w2 > wmax) close();
-            else bw = w2;
-        }
-        if (bs < 0) {
-            bs = s;
-            bx0 = x;
-            bw = window_of(x, x);
-            if (emit && (m > 256 || bw > wmax)) atomicOr(&flags[3], 1);
-        }
-        bp += m;
-        bxl = x;
+        snum[x] = m;
+        sst[x] = cs[(z * ny + y0) * nx + x];
     }
-    close();
-    (void)bw;
+    __syncthreads();
+    int nb = 0;
+    if (threadIdx.x == 0) {
+        int rowsum = 0;
+        for (int x = 0; x < nx; x++) rowsum += scol[x];
+        auto col = [&](int k) { return scol[k < 0 ? k + nx : (k >= nx ? k - nx : k)]; };
+        auto window_of = [&](int xa, int xb) {
+            if (xb - xa + 1 + 2 * r >= nx) return rowsum;
+            int s = 0;
+            for (int k = xa - r; k <= xb + r; k++) s += col(k);
+            return s;
+        };
+        int bs = -1, bp = 0, bx0 = 0, bxl = 0, bw = 0;  // open block: first particle, particles, x range, window
+        auto close = [&]() {
+            if (bs >= 0 && bp > 0) {
+                if (emit && base + nb < cap)
+                    blocks[base + nb] = make_int4((z * ny + y0) * nx + bx0, (z * ny + y1) * nx + bxl,
+                                                  one_row ? bs : -1, one_row ? bs + bp : -1);
+                nb++;
+            }
+            bs = -1;
+            bp = 0;
+        };
+        for (int x = 0; x < nx; x++) {
+            int m = snum[x];
+            int off = 0;  // particles of column x already in blocks
+            while (off < m) {
+                if (bs >= 0 && x > bxl) {
+                    // extend the window from [bx0, bxl] to [bx0, x]: columns bxl + r + 1 .. x + r
+                    int w2;
+                    if (x - bx0 + 1 + 2 * r >= nx) {
+                        w2 = rowsum;
+                    } else {
+                        w2 = bw;
+                        for (int k = bxl + r + 1; k <= x + r; k++) w2 += col(k);
+                    }
+                    bool fits = x - bx0 < kBlkCells && w2 <= wmax && (one_row || bp + m <= 256);
+                    if (fits) {
+                        bw = w2;
+                        bxl = x;
+                    } else {
+                        close();
+                    }
+                }
+                if (bs < 0) {
+                    bs = sst[x] + off;
+                    bx0 = bxl = x;
+                    bw = window_of(x, x);
+                    if (emit && (bw > wmax || (!one_row && m > 256))) atomicOr(&flags[3], 1);
+                }
+                int take = one_row ? min(m - off, 256 - bp) : m;
+                bp += take;
+                off += take;
+                if (one_row && bp == 256) close();
+            }
+        }
+        close();
+    }
     return nb;
 }
 
 __global__ void k_blk_count(const Geom g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
-                            int32_t *__restrict__ row_n, int wmax)
+                            int32_t *__restrict__ band_n, int wmax)
 {
-    int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= g.nc[1] * g.nc[2]) return;
-    row_n[row] = pack_row(row, g, cs, colsum, 0, nullptr, nullptr, nullptr, nullptr, false, 0, nullptr, wmax);
+    __shared__ int scol[kPackMaxX], snum[kPackMaxX], sst[kPackMaxX];
+    int nb = pack_band(blockIdx.x, g, cs, colsum, 0, nullptr, false, 0, nullptr, wmax, scol, snum, sst);
+    if (threadIdx.x == 0) band_n[blockIdx.x] = nb;
 }
 
 __global__ void k_blk_write(const Geom g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
-                            const int32_t *__restrict__ row_base, int32_t *i0, int32_t *i1, int32_t *c0, int32_t *c1,
-                            int cap, int32_t *flags, int wmax)
+                            const int32_t *__restrict__ band_base, int4 *blocks, int cap, int32_t *flags, int wmax)
 {
-    int row = blockIdx.x * blockDim.x + threadIdx.x;
-    int nrows = g.nc[1] * g.nc[2];
-    if (row >= nrows) return;
-    pack_row(row, g, cs, colsum, row_base[row], i0, i1, c0, c1, true, cap, flags, wmax);
+    __shared__ int scol[kPackMaxX], snum[kPackMaxX], sst[kPackMaxX];
+    pack_band(blockIdx.x, g, cs, colsum, band_base[blockIdx.x], blocks, true, cap, flags, wmax, scol, snum, sst);
 }
 
-// Common head of the windowed kernels: lay out and stage the window of
-// block blk; returns false (uniformly) if it does not fit the tile.
-template <int NT, bool HALF = false>
-__device__ __forceinline__ bool setup_block(const Geom &g, COfs so, const int32_t *__restrict__ cs,
-                                            const int4 *__restrict__ st, int c0, int c1, Window &w,
-                                            WinEntry<NT> *win, int32_t *flags)
+// Common head of the windowed kernels: lay out and stage the window of a
+// block; false (uniformly) if it does not fit the tile.
+template <int NT, bool HALF = false, bool COLS = true>
+__device__ __forceinline__ bool setup_block(const Geom &g, const int32_t *__restrict__ cs, const int4 *__restrict__ st,
+                                            int4 blk, Window &w, WinEntry<NT> *win, int32_t *flags)
 {
     __syncthreads();
-    make_window<HALF>(g, so, cs, c0, c1, w);
-    if (w.W > (HALF ? kWinMaxHalf : kWinMax)) {  // the packer never makes such blocks; never overrun the tile
+    make_window<HALF, COLS>(g, cs, blk, w);
+    if (w.W > (HALF ? kWinMaxHalf : kWinMax) || w.npart > 256) {  // never made by the packer
         if (threadIdx.x == 0) atomicOr(&flags[3], 2);
         return false;
     }
@@ -383,51 +517,35 @@ __device__ __forceinline__ bool setup_block(const Geom &g, COfs so, const int32_
     return true;
 }
 
-// Window position of particle i (in cell ci) itself.
-__device__ __forceinline__ int self_position(const Geom &g, const Window &w, const int32_t *__restrict__ cs, int i,
-                                             int ci, int &x)
+// Every candidate range of window positions of the particle in block row k,
+// cell column x (window position self): the full stencil, or its forward
+// half (see row_of).  fn(b, en) is called per contiguous range [b, en).
+template <bool HALF, typename Fn>
+__device__ __forceinline__ void stencil_ranges(const Geom &g, const Window &w, int k, int x, int self, Fn &&fn)
 {
-    x = ci % g.nc[0];
-    int m = x - w.lo;
-    m = m < 0 ? m + g.nc[0] : m;
-    return w.col[w.self_row][m] + (i - cs[ci]);
-}
-
-// ------------------------------------------------------------------ traversal helpers
-
-// The cell columns a particle in column x visits, as up to three ranges of
-// window columns [a, b]: one range x-1 .. x+1 unless the columns wrap inside
-// a window that covers the whole x-row (or the row has fewer than three
-// distinct columns); then one range per column.  Identical for every stencil
-// row.
-struct ColRanges {
-    int a0, b0, a1, b1, a2, b2;
-};
-
-__device__ __forceinline__ ColRanges column_ranges(const Geom &g, COfs so, const Window &w, int x)
-{
-    int nx = g.nc[0];
-    int m = x - w.lo;
-    m = m < 0 ? m + nx : m;
-    ColRanges r{0, -1, 0, -1, 0, -1};
-    if (g.nofs[0] == 3 && m >= 1 && m + 1 < w.ncols) {
-        r.a0 = m - 1;
-        r.b0 = m + 1;
-        return r;
-    }
-    auto col = [&](int e) {
-        int xx = x + so[0][e];
-        xx = xx >= nx ? xx - nx : xx;
-        int mm = xx - w.lo;
-        return mm < 0 ? mm + nx : mm;
+    int r = w.r, nyb = w.nyb;
+    ColRanges cr = column_ranges(g, w, x, -r, r);
+    auto row = [&](int rr) {
+        fn((int)w.col[rr][cr.a0], (int)w.col[rr][cr.b0 + 1]);
+        if (cr.b1 >= cr.a1) fn((int)w.col[rr][cr.a1], (int)w.col[rr][cr.b1 + 1]);
     };
-    r.a0 = r.b0 = col(0);
-    if (g.nofs[0] > 1) r.a1 = r.b1 = col(1);
-    if (g.nofs[0] > 2) r.a2 = r.b2 = col(2);
-    return r;
+    if (!HALF) {
+        for (int dz = -r; dz <= r; dz++)
+            for (int dy = -r; dy <= r; dy++) row(row_index(r, nyb, false, dz, k + dy));
+    } else {
+        for (int dz = 1; dz <= r; dz++)
+            for (int dy = -r; dy <= r; dy++) row(row_index(r, nyb, true, dz, k + dy));
+        for (int dy = 1; dy <= r; dy++) row(row_index(r, nyb, true, 0, k + dy));
+        int own = row_index(r, nyb, true, 0, k);
+        int m = column_of(g, w, x);
+        fn(self + 1, (int)w.col[own][m + 1]);
+        ColRanges cf = column_ranges(g, w, x, 1, r);
+        fn((int)w.col[own][cf.a0], (int)w.col[own][cf.b0 + 1]);
+        if (cf.b1 >= cf.a1) fn((int)w.col[own][cf.a1], (int)w.col[own][cf.b1 + 1]);
+    }
 }
 
-// One candidate pair (i, window position p) of the force traversals, branch
+// One candidate pair (i, window position p) of the gather traversals, branch
 // free: the FP32 cutoff decision, the pair force added to f and the energy
 // terms.  Returns true if the pair lies inside the guard band of the cutoff;
 // the caller then decides it from the FP64 positions (pair_exact).
@@ -453,8 +571,8 @@ __device__ __forceinline__ bool pair_fast(const int4 &pi, const int4 &pj, bool v
 // the FP64 distance is a call; the accumulators stay in registers).
 template <int NT, bool ISO, bool ENERGY>
 __device__ __forceinline__ void pair_exact(const int4 &pi, const int4 &pj, int i, int j, const TabF<NT> &t,
-                                        const Geom &g, const double *__restrict__ pos, int n, float &fx, float &fy,
-                                        float &fz, float &eu, float &ew, int &np)
+                                           const Geom &g, const double *__restrict__ pos, int n, float &fx,
+                                           float &fy, float &fz, float &eu, float &ew, int &np)
 {
     int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
     if (exact_r2(pos, n, i, j, g.L[0], g.L[1], g.L[2]) < t.pickd(t.rc2, ab)) {
@@ -477,8 +595,7 @@ template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                  const int32_t *__restrict__ cell_sorted, Geom g, int n,
                                                  const int32_t *__restrict__ nblk_p, int cap,
-                                                 const int32_t *__restrict__ bi0, const int32_t *__restrict__ bi1,
-                                                 const int32_t *__restrict__ bc0, const int32_t *__restrict__ bc1,
+                                                 const int4 *__restrict__ blocks,
                                                  const PairTab *__restrict__ tabp, const double *__restrict__ pos,
                                                  float *__restrict__ F, double *__restrict__ partials,
                                                  int32_t *__restrict__ flags)
@@ -486,8 +603,6 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
     __shared__ WinEntry<NT> win[kWinMax];
     __shared__ Window w;
     __shared__ double sh[16];
-    __shared__ int so[3][kMaxOfs];
-    load_offsets(g, so);
     TabF<NT> t;
     t.load(tabp);
     float eu = 0.f, ew = 0.f;
@@ -495,40 +610,33 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
     size_t N = (size_t)n;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
-        if (!setup_block<NT>(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
-        int i = bi0[blk] + threadIdx.x;
-        if (i >= bi1[blk]) continue;
-        int x;
-        int self = self_position(g, w, cs, i, cell_sorted[i], x);
+        if (!setup_block<NT>(g, cs, st, blocks[blk], w, win, flags)) continue;
+        int i, k, x;
+        if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
+        int self = self_position<false>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
         int4 pi = win[self].get();
-        ColRanges cr = column_ranges(g, so, w, x);
         float fx = 0.f, fy = 0.f, fz = 0.f;
-        for (int rr = 0; rr < w.nrow; rr++)
-            for (int sgi = 0; sgi < 3; sgi++) {
-                int ca = sgi == 0 ? cr.a0 : (sgi == 1 ? cr.a1 : cr.a2);
-                int cb = sgi == 0 ? cr.b0 : (sgi == 1 ? cr.b1 : cr.b2);
-                if (cb < ca) continue;
-                int b = w.col[rr][ca], en = w.col[rr][cb + 1];
-                for (int p0 = b; p0 < en; p0 += 4) {
-                    int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
-                    int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
-                    uint32_t amb = 0;
-                    amb |= pair_fast<NT, ISO, ENERGY>(pi, q0, p0 != self, t, g, fx, fy, fz, eu, ew, np) ? 1u : 0u;
-                    amb |= pair_fast<NT, ISO, ENERGY>(pi, q1, p0 + 1 < en && p1 != self, t, g, fx, fy, fz, eu, ew,
-                                                      np) ? 2u : 0u;
-                    amb |= pair_fast<NT, ISO, ENERGY>(pi, q2, p0 + 2 < en && p2 != self, t, g, fx, fy, fz, eu, ew,
-                                                      np) ? 4u : 0u;
-                    amb |= pair_fast<NT, ISO, ENERGY>(pi, q3, p0 + 3 < en && p3 != self, t, g, fx, fy, fz, eu, ew,
-                                                      np) ? 8u : 0u;
-                    while (amb) {
-                        int u = __builtin_ctz(amb);
-                        amb &= amb - 1;
-                        int p = p0 + u;
-                        pair_exact<NT, ISO, ENERGY>(pi, win[p].get(), i, window_global(w, p), t, g, pos, n, fx, fy,
-                                                    fz, eu, ew, np);
-                    }
+        stencil_ranges<false>(g, w, k, x, self, [&](int b, int en) {
+            for (int p0 = b; p0 < en; p0 += 4) {
+                int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
+                int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
+                uint32_t amb = 0;
+                amb |= pair_fast<NT, ISO, ENERGY>(pi, q0, p0 != self, t, g, fx, fy, fz, eu, ew, np) ? 1u : 0u;
+                amb |= pair_fast<NT, ISO, ENERGY>(pi, q1, p0 + 1 < en && p1 != self, t, g, fx, fy, fz, eu, ew, np)
+                           ? 2u : 0u;
+                amb |= pair_fast<NT, ISO, ENERGY>(pi, q2, p0 + 2 < en && p2 != self, t, g, fx, fy, fz, eu, ew, np)
+                           ? 4u : 0u;
+                amb |= pair_fast<NT, ISO, ENERGY>(pi, q3, p0 + 3 < en && p3 != self, t, g, fx, fy, fz, eu, ew, np)
+                           ? 8u : 0u;
+                while (amb) {
+                    int u = __builtin_ctz(amb);
+                    amb &= amb - 1;
+                    int p = p0 + u;
+                    pair_exact<NT, ISO, ENERGY>(pi, win[p].get(), i, window_global(w, p), t, g, pos, n, fx, fy, fz,
+                                                eu, ew, np);
                 }
             }
+        });
         F[i] = fx;
         F[N + i] = fy;
         F[2 * N + i] = fz;
@@ -586,59 +694,51 @@ __device__ __forceinline__ bool build_fast(const int4 &pi, const int4 &pj, bool 
     return valid && r2 < g.rl2_lo;
 }
 
-template <bool ISO>
+// Verlet lists (full windows: every pair within r_c + skin from both sides;
+// half windows: each pair once, in the forward half of the stencil).
+template <bool ISO, bool HALF>
 __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                    const int32_t *__restrict__ cell_sorted,
                                                    const double *__restrict__ pos, Geom g, int n,
                                                    const int32_t *__restrict__ nblk_p, int cap,
-                                                   const int32_t *__restrict__ bi0, const int32_t *__restrict__ bi1,
-                                                   const int32_t *__restrict__ bc0, const int32_t *__restrict__ bc1,
+                                                   const int4 *__restrict__ blocks,
                                                    uint16_t *__restrict__ nbr, int32_t *__restrict__ cnt, int maxn,
                                                    int32_t *__restrict__ flags)
 {
-    __shared__ WinEntry<1> win[kWinMax];
+    __shared__ WinEntry<1> win[HALF ? kWinMaxHalf : kWinMax];
     __shared__ Window w;
-    __shared__ int so[3][kMaxOfs];
-    load_offsets(g, so);
     size_t N = (size_t)n;
     int cmax = 0;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
-        if (!setup_block<1>(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
-        int i = bi0[blk] + threadIdx.x;
-        if (i >= bi1[blk]) continue;
-        int x;
-        int self = self_position(g, w, cs, i, cell_sorted[i], x);
+        if (!setup_block<1, HALF>(g, cs, st, blocks[blk], w, win, flags)) continue;
+        int i, k, x;
+        if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
+        int self = self_position<HALF>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
         int4 pi = win[self].get();
-        ColRanges cr = column_ranges(g, so, w, x);
         uint4 *row = (uint4 *)nbr + i;
         int c = 0;
         Chunk ck;
-        for (int rr = 0; rr < w.nrow; rr++)
-            for (int sgi = 0; sgi < 3; sgi++) {
-                int ca = sgi == 0 ? cr.a0 : (sgi == 1 ? cr.a1 : cr.a2);
-                int cb = sgi == 0 ? cr.b0 : (sgi == 1 ? cr.b1 : cr.b2);
-                if (cb < ca) continue;
-                int b = w.col[rr][ca], en = w.col[rr][cb + 1];
-                for (int p0 = b; p0 < en; p0 += 4) {
-                    int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
-                    int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
-                    bool a0, a1, a2, a3;
-                    bool i0 = build_fast<ISO>(pi, q0, p0 != self, g, a0);
-                    bool i1 = build_fast<ISO>(pi, q1, p0 + 1 < en && p1 != self, g, a1);
-                    bool i2 = build_fast<ISO>(pi, q2, p0 + 2 < en && p2 != self, g, a2);
-                    bool i3 = build_fast<ISO>(pi, q3, p0 + 3 < en && p3 != self, g, a3);
-                    // rare: guard-band pairs decided from the FP64 positions
-                    if (a0) i0 = exact_r2(pos, n, i, window_global(w, p0), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                    if (a1) i1 = exact_r2(pos, n, i, window_global(w, p1), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                    if (a2) i2 = exact_r2(pos, n, i, window_global(w, p2), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                    if (a3) i3 = exact_r2(pos, n, i, window_global(w, p3), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                    if (i0) list_append((uint32_t)p0, c, ck, row, N, maxn);
-                    if (i1) list_append((uint32_t)p1, c, ck, row, N, maxn);
-                    if (i2) list_append((uint32_t)p2, c, ck, row, N, maxn);
-                    if (i3) list_append((uint32_t)p3, c, ck, row, N, maxn);
-                }
+        stencil_ranges<HALF>(g, w, k, x, self, [&](int b, int en) {
+            for (int p0 = b; p0 < en; p0 += 4) {
+                int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
+                int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
+                bool a0, a1, a2, a3;
+                bool i0 = build_fast<ISO>(pi, q0, p0 != self, g, a0);
+                bool i1 = build_fast<ISO>(pi, q1, p0 + 1 < en && p1 != self, g, a1);
+                bool i2 = build_fast<ISO>(pi, q2, p0 + 2 < en && p2 != self, g, a2);
+                bool i3 = build_fast<ISO>(pi, q3, p0 + 3 < en && p3 != self, g, a3);
+                // rare: guard-band pairs decided from the FP64 positions
+                if (a0) i0 = exact_r2(pos, n, i, window_global(w, p0), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                if (a1) i1 = exact_r2(pos, n, i, window_global(w, p1), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                if (a2) i2 = exact_r2(pos, n, i, window_global(w, p2), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                if (a3) i3 = exact_r2(pos, n, i, window_global(w, p3), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                if (i0) list_append((uint32_t)p0, c, ck, row, N, maxn);
+                if (i1) list_append((uint32_t)p1, c, ck, row, N, maxn);
+                if (i2) list_append((uint32_t)p2, c, ck, row, N, maxn);
+                if (i3) list_append((uint32_t)p3, c, ck, row, N, maxn);
             }
+        });
         if ((c & 7) && c < maxn) row[(size_t)(c >> 3) * N] = ck.word();
         if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
         cmax = max(cmax, c);
@@ -650,10 +750,10 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
 // Each thread walks its list in chunks of eight entries; the next chunk's
 // load is in flight while the current one is computed.
 template <int NT, bool ISO, bool ENERGY>
-__global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs, Geom g,
-                                                 int n, const int32_t *__restrict__ nblk_p, int cap,
-                                                 const int32_t *__restrict__ bi0, const int32_t *__restrict__ bi1,
-                                                 const int32_t *__restrict__ bc0, const int32_t *__restrict__ bc1,
+__global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
+                                                 const int32_t *__restrict__ cell_sorted, Geom g, int n,
+                                                 const int32_t *__restrict__ nblk_p, int cap,
+                                                 const int4 *__restrict__ blocks,
                                                  const uint16_t *__restrict__ nbr, const int32_t *__restrict__ cnt,
                                                  const PairTab *__restrict__ tabp, const double *__restrict__ pos,
                                                  float *__restrict__ F, double *__restrict__ partials,
@@ -662,8 +762,6 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
     __shared__ WinEntry<NT> win[kWinMax];
     __shared__ Window w;
     __shared__ double sh[16];
-    __shared__ int so[3][kMaxOfs];
-    load_offsets(g, so);
     TabF<NT> t;
     t.load(tabp);
     float eu = 0.f, ew = 0.f;
@@ -671,9 +769,10 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
     size_t N = (size_t)n;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
-        if (!setup_block<NT>(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
-        int i = bi0[blk] + threadIdx.x;
-        if (i >= bi1[blk]) continue;
+        // the list holds window positions: only the window's pieces are needed
+        if (!setup_block<NT, false, false>(g, cs, st, blocks[blk], w, win, flags)) continue;
+        int i, k, x;
+        if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
         int4 pi = st[i];
         int c = cnt[i];
         int nch = (c + 7) >> 3;
@@ -719,26 +818,24 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
 // ------------------------------------------------------------------ Newton's third law (half windows)
 
 // Each pair once: a thread takes the pairs of its particle with the forward
-// rows of the half window and, in its own row, with the particles after it
-// in its cell and those of the next cell.  The j-side forces accumulate in
-// LDS (one float per component and window position, LDS atomics); after the
-// block every nonzero entry is added to the global force with one atomic per
-// component, where consecutive positions of a piece are consecutive
+// half of its stencil (stencil_ranges<true>).  The j-side forces accumulate
+// in LDS (one float per component and window position, LDS atomics); after
+// the block every nonzero entry is added to the global force with one atomic
+// per component, where consecutive positions of a piece are consecutive
 // particles, so that a wavefront's atomics are coalesced.
 struct HalfAcc {
     float x[kWinMaxHalf], y[kWinMaxHalf], z[kWinMaxHalf];
 };
 
-// Head of the half-window kernels: window laid out and staged, accumulators
-// cleared; false (uniformly) if the window does not fit.
+// Head of the half-window force kernels: window laid out and staged,
+// accumulators cleared; false (uniformly) if the window does not fit.
 template <int NT>
-__device__ __forceinline__ bool setup_half(const Geom &g, COfs so, const int32_t *__restrict__ cs,
-                                           const int4 *__restrict__ st, int c0, int c1, Window &w,
-                                           WinEntry<NT> *win, HalfAcc &acc, int32_t *flags)
+__device__ __forceinline__ bool setup_half(const Geom &g, const int32_t *__restrict__ cs, const int4 *__restrict__ st,
+                                           int4 blk, Window &w, WinEntry<NT> *win, HalfAcc &acc, int32_t *flags)
 {
     __syncthreads();
-    make_window<true>(g, so, cs, c0, c1, w);
-    if (w.W > kWinMaxHalf) {  // the packer never makes such blocks; never overrun the tile
+    make_window<true>(g, cs, blk, w);
+    if (w.W > kWinMaxHalf || w.npart > 256) {  // never made by the packer
         if (threadIdx.x == 0) atomicOr(&flags[3], 2);
         return false;
     }
@@ -813,67 +910,11 @@ __device__ __forceinline__ void pair_exact_n3l(const int4 &pi, const int4 &pj, i
     }
 }
 
-// The candidate window ranges of a particle in a half window: the forward
-// rows over its three columns (as in the full traversal), then in the own
-// row the positions after its own (self + 1 to the end of its cell) and the
-// cell of column x + 1, merged when the two are adjacent in the window.
-struct HalfOwn {
-    int b0, e0, b1, e1;
-};
-
-__device__ __forceinline__ HalfOwn half_own(const Geom &g, const Window &w, int self, int x)
-{
-    int nx = g.nc[0];
-    int m = x - w.lo;
-    m = m < 0 ? m + nx : m;
-    int x1 = x + 1 == nx ? 0 : x + 1;
-    int m1 = x1 - w.lo;
-    m1 = m1 < 0 ? m1 + nx : m1;
-    HalfOwn r;
-    if (m1 == m + 1) {
-        r.b0 = self + 1;
-        r.e0 = w.col[kHalfOwn][m + 2];
-        r.b1 = r.e1 = 0;
-    } else {
-        r.b0 = self + 1;
-        r.e0 = w.col[kHalfOwn][m + 1];
-        r.b1 = w.col[kHalfOwn][m1];
-        r.e1 = w.col[kHalfOwn][m1 + 1];
-    }
-    return r;
-}
-
-// All pairs of particle i with window positions [b, en), four at a time.
-template <int NT, bool ISO, bool ENERGY>
-__device__ __forceinline__ void range_n3l(int b, int en, const int4 &pi, int i, const WinEntry<NT> *win,
-                                          const Window &w, const TabF<NT> &t, const Geom &g,
-                                          const double *__restrict__ pos, int n, HalfAcc &acc, float &fx, float &fy,
-                                          float &fz, float &eu, float &ew, int &np)
-{
-    for (int p0 = b; p0 < en; p0 += 4) {
-        int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
-        int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
-        uint32_t amb = 0;
-        amb |= pair_n3l<NT, ISO, ENERGY>(pi, q0, p0, true, t, g, acc, fx, fy, fz, eu, ew, np) ? 1u : 0u;
-        amb |= pair_n3l<NT, ISO, ENERGY>(pi, q1, p1, p0 + 1 < en, t, g, acc, fx, fy, fz, eu, ew, np) ? 2u : 0u;
-        amb |= pair_n3l<NT, ISO, ENERGY>(pi, q2, p2, p0 + 2 < en, t, g, acc, fx, fy, fz, eu, ew, np) ? 4u : 0u;
-        amb |= pair_n3l<NT, ISO, ENERGY>(pi, q3, p3, p0 + 3 < en, t, g, acc, fx, fy, fz, eu, ew, np) ? 8u : 0u;
-        while (amb) {
-            int u = __builtin_ctz(amb);
-            amb &= amb - 1;
-            int p = p0 + u;
-            pair_exact_n3l<NT, ISO, ENERGY>(pi, win[p].get(), p, i, window_global(w, p), t, g, pos, n, acc, fx, fy,
-                                            fz, eu, ew, np);
-        }
-    }
-}
-
 template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(256) void k_lcwh_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                   const int32_t *__restrict__ cell_sorted, Geom g, int n,
                                                   const int32_t *__restrict__ nblk_p, int cap,
-                                                  const int32_t *__restrict__ bi0, const int32_t *__restrict__ bi1,
-                                                  const int32_t *__restrict__ bc0, const int32_t *__restrict__ bc1,
+                                                  const int4 *__restrict__ blocks,
                                                   const PairTab *__restrict__ tabp, const double *__restrict__ pos,
                                                   float *__restrict__ F, double *__restrict__ partials,
                                                   int32_t *__restrict__ flags)
@@ -882,8 +923,6 @@ __global__ __launch_bounds__(256) void k_lcwh_f32(const int4 *__restrict__ st, c
     __shared__ HalfAcc acc;
     __shared__ Window w;
     __shared__ double sh[16];
-    __shared__ int so[3][kMaxOfs];
-    load_offsets(g, so);
     TabF<NT> t;
     t.load(tabp);
     float eu = 0.f, ew = 0.f;
@@ -891,25 +930,33 @@ __global__ __launch_bounds__(256) void k_lcwh_f32(const int4 *__restrict__ st, c
     size_t N = (size_t)n;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
-        if (!setup_half<NT>(g, so, cs, st, bc0[blk], bc1[blk], w, win, acc, flags)) continue;
-        int i = bi0[blk] + threadIdx.x;
-        if (i < bi1[blk]) {
-            int x;
-            int self = self_position(g, w, cs, i, cell_sorted[i], x);
+        if (!setup_half<NT>(g, cs, st, blocks[blk], w, win, acc, flags)) continue;
+        int i, k, x;
+        if (my_particle(g, w, cell_sorted, i, k, x)) {
+            int self = self_position<true>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
             int4 pi = win[self].get();
-            ColRanges cr = column_ranges(g, so, w, x);
             float fx = 0.f, fy = 0.f, fz = 0.f;
-            for (int rr = 0; rr < kHalfOwn; rr++)
-                for (int sgi = 0; sgi < 3; sgi++) {
-                    int ca = sgi == 0 ? cr.a0 : (sgi == 1 ? cr.a1 : cr.a2);
-                    int cb = sgi == 0 ? cr.b0 : (sgi == 1 ? cr.b1 : cr.b2);
-                    if (cb < ca) continue;
-                    range_n3l<NT, ISO, ENERGY>(w.col[rr][ca], w.col[rr][cb + 1], pi, i, win, w, t, g, pos, n, acc,
-                                               fx, fy, fz, eu, ew, np);
+            stencil_ranges<true>(g, w, k, x, self, [&](int b, int en) {
+                for (int p0 = b; p0 < en; p0 += 4) {
+                    int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
+                    int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
+                    uint32_t amb = 0;
+                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q0, p0, true, t, g, acc, fx, fy, fz, eu, ew, np) ? 1u : 0u;
+                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q1, p1, p0 + 1 < en, t, g, acc, fx, fy, fz, eu, ew, np)
+                               ? 2u : 0u;
+                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q2, p2, p0 + 2 < en, t, g, acc, fx, fy, fz, eu, ew, np)
+                               ? 4u : 0u;
+                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q3, p3, p0 + 3 < en, t, g, acc, fx, fy, fz, eu, ew, np)
+                               ? 8u : 0u;
+                    while (amb) {
+                        int u = __builtin_ctz(amb);
+                        amb &= amb - 1;
+                        int p = p0 + u;
+                        pair_exact_n3l<NT, ISO, ENERGY>(pi, win[p].get(), p, i, window_global(w, p), t, g, pos, n,
+                                                        acc, fx, fy, fz, eu, ew, np);
+                    }
                 }
-            HalfOwn ow = half_own(g, w, self, x);
-            range_n3l<NT, ISO, ENERGY>(ow.b0, ow.e0, pi, i, win, w, t, g, pos, n, acc, fx, fy, fz, eu, ew, np);
-            range_n3l<NT, ISO, ENERGY>(ow.b1, ow.e1, pi, i, win, w, t, g, pos, n, acc, fx, fy, fz, eu, ew, np);
+            });
             atomicAdd(&acc.x[self], fx);
             atomicAdd(&acc.y[self], fy);
             atomicAdd(&acc.z[self], fz);
@@ -924,83 +971,11 @@ __global__ __launch_bounds__(256) void k_lcwh_f32(const int4 *__restrict__ st, c
     }
 }
 
-// Half Verlet lists: the candidates of the half traversal within r_c + skin.
-template <bool ISO>
-__device__ __forceinline__ void range_build(int b, int en, const int4 &pi, int i, const WinEntry<1> *win,
-                                            const Window &w, const Geom &g, const double *__restrict__ pos, int n,
-                                            int &c, Chunk &ck, uint4 *__restrict__ row, size_t N, int maxn)
-{
-    for (int p0 = b; p0 < en; p0 += 4) {
-        int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
-        int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
-        bool a0, a1, a2, a3;
-        bool i0 = build_fast<ISO>(pi, q0, true, g, a0);
-        bool i1 = build_fast<ISO>(pi, q1, p0 + 1 < en, g, a1);
-        bool i2 = build_fast<ISO>(pi, q2, p0 + 2 < en, g, a2);
-        bool i3 = build_fast<ISO>(pi, q3, p0 + 3 < en, g, a3);
-        if (a0) i0 = exact_r2(pos, n, i, window_global(w, p0), g.L[0], g.L[1], g.L[2]) < g.rl2;
-        if (a1) i1 = exact_r2(pos, n, i, window_global(w, p1), g.L[0], g.L[1], g.L[2]) < g.rl2;
-        if (a2) i2 = exact_r2(pos, n, i, window_global(w, p2), g.L[0], g.L[1], g.L[2]) < g.rl2;
-        if (a3) i3 = exact_r2(pos, n, i, window_global(w, p3), g.L[0], g.L[1], g.L[2]) < g.rl2;
-        if (i0) list_append((uint32_t)p0, c, ck, row, N, maxn);
-        if (i1) list_append((uint32_t)p1, c, ck, row, N, maxn);
-        if (i2) list_append((uint32_t)p2, c, ck, row, N, maxn);
-        if (i3) list_append((uint32_t)p3, c, ck, row, N, maxn);
-    }
-}
-
-template <bool ISO>
-__global__ __launch_bounds__(256) void k_vlwh_build(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
-                                                    const int32_t *__restrict__ cell_sorted,
-                                                    const double *__restrict__ pos, Geom g, int n,
-                                                    const int32_t *__restrict__ nblk_p, int cap,
-                                                    const int32_t *__restrict__ bi0, const int32_t *__restrict__ bi1,
-                                                    const int32_t *__restrict__ bc0, const int32_t *__restrict__ bc1,
-                                                    uint16_t *__restrict__ nbr, int32_t *__restrict__ cnt, int maxn,
-                                                    int32_t *__restrict__ flags)
-{
-    __shared__ WinEntry<1> win[kWinMaxHalf];
-    __shared__ Window w;
-    __shared__ int so[3][kMaxOfs];
-    load_offsets(g, so);
-    size_t N = (size_t)n;
-    int cmax = 0;
-    for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
-        int blk = it.blk;
-        if (!setup_block<1, true>(g, so, cs, st, bc0[blk], bc1[blk], w, win, flags)) continue;
-        int i = bi0[blk] + threadIdx.x;
-        if (i >= bi1[blk]) continue;
-        int x;
-        int self = self_position(g, w, cs, i, cell_sorted[i], x);
-        int4 pi = win[self].get();
-        ColRanges cr = column_ranges(g, so, w, x);
-        uint4 *row = (uint4 *)nbr + i;
-        int c = 0;
-        Chunk ck;
-        for (int rr = 0; rr < kHalfOwn; rr++)
-            for (int sgi = 0; sgi < 3; sgi++) {
-                int ca = sgi == 0 ? cr.a0 : (sgi == 1 ? cr.a1 : cr.a2);
-                int cb = sgi == 0 ? cr.b0 : (sgi == 1 ? cr.b1 : cr.b2);
-                if (cb < ca) continue;
-                range_build<ISO>(w.col[rr][ca], w.col[rr][cb + 1], pi, i, win, w, g, pos, n, c, ck, row, N, maxn);
-            }
-        HalfOwn ow = half_own(g, w, self, x);
-        range_build<ISO>(ow.b0, ow.e0, pi, i, win, w, g, pos, n, c, ck, row, N, maxn);
-        range_build<ISO>(ow.b1, ow.e1, pi, i, win, w, g, pos, n, c, ck, row, N, maxn);
-        if ((c & 7) && c < maxn) row[(size_t)(c >> 3) * N] = ck.word();
-        if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
-        cmax = max(cmax, c);
-        cnt[i] = c < maxn ? c : maxn;
-    }
-    if (cmax > 0) atomicMax(&flags[2], cmax);
-}
-
 template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(256) void k_vlwh_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                   const int32_t *__restrict__ cell_sorted, Geom g, int n,
                                                   const int32_t *__restrict__ nblk_p, int cap,
-                                                  const int32_t *__restrict__ bi0, const int32_t *__restrict__ bi1,
-                                                  const int32_t *__restrict__ bc0, const int32_t *__restrict__ bc1,
+                                                  const int4 *__restrict__ blocks,
                                                   const uint16_t *__restrict__ nbr, const int32_t *__restrict__ cnt,
                                                   const PairTab *__restrict__ tabp, const double *__restrict__ pos,
                                                   float *__restrict__ F, double *__restrict__ partials,
@@ -1010,8 +985,6 @@ __global__ __launch_bounds__(256) void k_vlwh_f32(const int4 *__restrict__ st, c
     __shared__ HalfAcc acc;
     __shared__ Window w;
     __shared__ double sh[16];
-    __shared__ int so[3][kMaxOfs];
-    load_offsets(g, so);
     TabF<NT> t;
     t.load(tabp);
     float eu = 0.f, ew = 0.f;
@@ -1019,11 +992,10 @@ __global__ __launch_bounds__(256) void k_vlwh_f32(const int4 *__restrict__ st, c
     size_t N = (size_t)n;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
-        if (!setup_half<NT>(g, so, cs, st, bc0[blk], bc1[blk], w, win, acc, flags)) continue;
-        int i = bi0[blk] + threadIdx.x;
-        if (i < bi1[blk]) {
-            int x;
-            int self = self_position(g, w, cs, i, cell_sorted[i], x);
+        if (!setup_half<NT>(g, cs, st, blocks[blk], w, win, acc, flags)) continue;
+        int i, k, x;
+        if (my_particle(g, w, cell_sorted, i, k, x)) {
+            int self = self_position<true>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
             int4 pi = win[self].get();
             int c = cnt[i];
             int nch = (c + 7) >> 3;
@@ -1069,77 +1041,79 @@ __global__ __launch_bounds__(256) void k_vlwh_f32(const int4 *__restrict__ st, c
 
 // Decode the window lists back to global indices (inspection).
 template <bool HALF>
-__global__ void k_vlw_decode(const int32_t *__restrict__ cs, Geom g, int n, const int32_t *__restrict__ nblk_p, int cap,
-                             const int32_t *__restrict__ bi0, const int32_t *__restrict__ bi1,
-                             const int32_t *__restrict__ bc0, const int32_t *__restrict__ bc1,
-                             const uint16_t *__restrict__ nbr, const int32_t *__restrict__ cnt, int maxr,
-                             int32_t *__restrict__ counts, int32_t *__restrict__ rows)
+__global__ void k_vlw_decode(const int32_t *__restrict__ cs, const int32_t *__restrict__ cell_sorted, Geom g, int n,
+                             const int32_t *__restrict__ nblk_p, int cap, const int4 *__restrict__ blocks,
+                             const uint16_t *__restrict__ nbr,
+                             const int32_t *__restrict__ cnt, int maxr, int32_t *__restrict__ counts,
+                             int32_t *__restrict__ rows)
 {
     __shared__ Window w;
-    __shared__ int so[3][kMaxOfs];
-    load_offsets(g, so);
     size_t N = (size_t)n;
     int nblk = min(*nblk_p, cap);
     for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         __syncthreads();
-        make_window<HALF>(g, so, cs, bc0[blk], bc1[blk], w);
-        int i = bi0[blk] + threadIdx.x;
-        if (i >= bi1[blk]) continue;
+        make_window<HALF, false>(g, cs, blocks[blk], w);
+        int i, k, x;
+        if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
         int c = cnt[i];
         counts[i] = c;
-        for (int k = 0; k < c && k < maxr; k++) rows[(size_t)i * maxr + k] = window_global(w, nbr[list_slot(k, i, N)]);
+        for (int e = 0; e < c && e < maxr; e++) rows[(size_t)i * maxr + e] = window_global(w, nbr[list_slot(e, i, N)]);
     }
 }
 
 // ------------------------------------------------------------------ host side
 
-int64_t window_block_cap(int64_t n, const Geom &g) { return n + (int64_t)g.nc[1] * g.nc[2] + 16; }
+int window_nbands(const Geom &g) { return g.nc[2] * ((g.nc[1] + g.wband - 1) / g.wband); }
+
+int64_t window_block_cap(int64_t n, const Geom &g) { return n + (int64_t)window_nbands(g) + 16; }
 
 bool window_geometry_ok(const Geom &g, bool half)
 {
-    bool ok = g.reach[0] == 1 && g.reach[1] == 1 && g.reach[2] == 1 && g.nofs[1] * g.nofs[2] <= kMaxRows;
-    if (half) ok = ok && g.nofs[0] == 3 && g.nofs[1] == 3 && g.nofs[2] == 3;
-    return ok;
+    (void)half;
+    int r = g.reach[0];
+    if (r < 1 || r > kMaxReach || g.reach[1] != r || g.reach[2] != r) return false;
+    for (int d = 0; d < 3; d++)
+        if (g.nofs[d] != 2 * r + 1) return false;  // every stencil cell distinct
+    return g.wband >= 1 && g.wband <= kWinBlkRows && g.nc[1] >= g.wband + 2 * r && g.nc[0] <= kPackMaxX;
 }
 
-void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *row_n, int32_t *row_base,
-                   int32_t *scan_scratch, int32_t *i0, int32_t *i1, int32_t *c0, int32_t *c1, int cap,
-                   int32_t *flags, bool half, hipStream_t s)
+void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *band_n, int32_t *band_base,
+                   int32_t *scan_scratch, int4 *blocks, int cap, int32_t *flags, bool half, hipStream_t s)
 {
-    int nrows = g.nc[1] * g.nc[2];
+    int nb = window_nbands(g);
     int wmax = half ? kWinMaxHalf : kWinMax;
+    int ncol = nb * g.nc[0];
     if (half)
-        k_colsum<true><<<(g.ncell + 255) / 256, 256, 0, s>>>(g, cs, colsum);
+        k_colsum<true><<<(ncol + 255) / 256, 256, 0, s>>>(g, cs, colsum);
     else
-        k_colsum<false><<<(g.ncell + 255) / 256, 256, 0, s>>>(g, cs, colsum);
-    k_blk_count<<<(nrows + 63) / 64, 64, 0, s>>>(g, cs, colsum, row_n, wmax);
-    launch_scan(row_n, row_base, nrows, scan_scratch, s);
-    k_blk_write<<<(nrows + 63) / 64, 64, 0, s>>>(g, cs, colsum, row_base, i0, i1, c0, c1, cap, flags, wmax);
+        k_colsum<false><<<(ncol + 255) / 256, 256, 0, s>>>(g, cs, colsum);
+    k_blk_count<<<nb, 64, 0, s>>>(g, cs, colsum, band_n, wmax);
+    launch_scan(band_n, band_base, nb, scan_scratch, s);
+    k_blk_write<<<nb, 64, 0, s>>>(g, cs, colsum, band_base, blocks, cap, flags, wmax);
 }
 
 // maxn is rounded up to whole chunks of eight (the list holds them).
 void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
-                      const Geom &g, int n, const int32_t *nblk_p, const int32_t *i0, const int32_t *i1,
-                      const int32_t *c0, const int32_t *c1, uint16_t *nbr, int32_t *cnt, int maxn, int32_t *flags,
-                      bool half, hipStream_t s)
+                      const Geom &g, int n, const int32_t *nblk_p, const int4 *blocks,
+                      uint16_t *nbr, int32_t *cnt, int maxn, int32_t *flags, bool half, hipStream_t s)
 {
     if (n <= 0) return;
     int cap = (int)window_block_cap(n, g);
     maxn = (maxn + 7) & ~7;
     if (half) {
         if (g.iso)
-            k_vlwh_build<true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, i0, i1, c0, c1,
-                                                         nbr, cnt, maxn, flags);
+            k_vlw_build<true, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
+                                                              nbr, cnt, maxn, flags);
         else
-            k_vlwh_build<false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, i0, i1, c0,
-                                                          c1, nbr, cnt, maxn, flags);
+            k_vlw_build<false, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
+                                                               nbr, cnt, maxn, flags);
     } else {
         if (g.iso)
-            k_vlw_build<true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, i0, i1, c0, c1,
-                                                        nbr, cnt, maxn, flags);
+            k_vlw_build<true, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
+                                                               nbr, cnt, maxn, flags);
         else
-            k_vlw_build<false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, i0, i1, c0, c1,
-                                                         nbr, cnt, maxn, flags);
+            k_vlw_build<false, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
+                                                                nbr, cnt, maxn, flags);
     }
 }
 
@@ -1152,20 +1126,20 @@ static void win_launch(const ForceArgs &a, const Geom &g, hipStream_t s)
     bool vl = a.container == MD_CONTAINER_VL;
     if (a.newton3 && vl)
         k_vlwh_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
-                                                        a.w_i0, a.w_i1, a.w_c0, a.w_c1, a.w_nbr, a.nbr_count, a.tab,
-                                                        a.pos, (float *)a.force, a.partials, a.flags);
+                                                        a.w_blk, a.w_nbr, a.nbr_count, a.tab, a.pos,
+                                                        (float *)a.force, a.partials, a.flags);
     else if (a.newton3)
         k_lcwh_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
-                                                        a.w_i0, a.w_i1, a.w_c0, a.w_c1, a.tab, a.pos,
-                                                        (float *)a.force, a.partials, a.flags);
+                                                        a.w_blk, a.tab, a.pos, (float *)a.force, a.partials,
+                                                        a.flags);
     else if (vl)
-        k_vlw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, g, a.n, a.w_nblk, cap, a.w_i0, a.w_i1,
-                                                       a.w_c0, a.w_c1, a.w_nbr, a.nbr_count, a.tab, a.pos,
+        k_vlw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
+                                                       a.w_blk, a.w_nbr, a.nbr_count, a.tab, a.pos,
                                                        (float *)a.force, a.partials, a.flags);
     else
         k_lcw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
-                                                       a.w_i0, a.w_i1, a.w_c0, a.w_c1, a.tab, a.pos,
-                                                       (float *)a.force, a.partials, a.flags);
+                                                       a.w_blk, a.tab, a.pos, (float *)a.force, a.partials,
+                                                       a.flags);
 }
 
 void launch_window_force(const ForceArgs &a, const Geom &g, hipStream_t s)
@@ -1190,18 +1164,18 @@ void launch_window_force(const ForceArgs &a, const Geom &g, hipStream_t s)
     }
 }
 
-void launch_vlw_decode(const int32_t *cs, const Geom &g, int n, const int32_t *nblk_p, const int32_t *i0,
-                       const int32_t *i1, const int32_t *c0, const int32_t *c1, const uint16_t *nbr,
-                       const int32_t *cnt, int maxr, int32_t *counts, int32_t *rows, bool half, hipStream_t s)
+void launch_vlw_decode(const int32_t *cs, const int32_t *cell_sorted, const Geom &g, int n, const int32_t *nblk_p,
+                       const int4 *blocks, const uint16_t *nbr, const int32_t *cnt, int maxr,
+                       int32_t *counts, int32_t *rows, bool half, hipStream_t s)
 {
     if (n <= 0) return;
     int cap = (int)window_block_cap(n, g);
     if (half)
-        k_vlw_decode<true><<<kWinGrid, 256, 0, s>>>(cs, g, n, nblk_p, cap, i0, i1, c0, c1, nbr, cnt, maxr, counts,
-                                                    rows);
+        k_vlw_decode<true><<<kWinGrid, 256, 0, s>>>(cs, cell_sorted, g, n, nblk_p, cap, blocks, nbr, cnt, maxr,
+                                                    counts, rows);
     else
-        k_vlw_decode<false><<<kWinGrid, 256, 0, s>>>(cs, g, n, nblk_p, cap, i0, i1, c0, c1, nbr, cnt, maxr, counts,
-                                                     rows);
+        k_vlw_decode<false><<<kWinGrid, 256, 0, s>>>(cs, cell_sorted, g, n, nblk_p, cap, blocks, nbr, cnt, maxr,
+                                                     counts, rows);
 }
 
 }  // namespace mdlj

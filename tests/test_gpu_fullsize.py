@@ -26,7 +26,7 @@ def _lib():
 
 
 # containers the autotuner chooses between on these inputs
-CONTS = [(1, 0, 1.0), (1, 1, 1.0), (0, 0, 1.0), (0, 1, 1.0), (0, 0, 0.5), (2, 0, 1.0)]
+CONTS = [(1, 0, 1.0), (1, 1, 1.0), (0, 0, 1.0), (0, 1, 1.0), (0, 0, 0.5), (0, 1, 0.5), (1, 0, 0.5), (2, 0, 1.0)]
 
 
 @pytest.mark.parametrize("kind", ["droplet", "slab"])

@@ -29,9 +29,9 @@ def _lib():
 FP32_F, FP64_F = 1e-5, 1e-12
 FP32_E, FP64_E = 1e-6, 1e-12
 
-CONTAINERS = [(0, 0, 1.0), (0, 1, 1.0), (0, 0, 0.5), (0, 1, 0.5), (1, 0, 1.0), (1, 1, 1.0), (2, 0, 1.0),
-              (2, 0, 0.5)]
-CNAMES = ["lc", "lc-n3l", "lc-csf.5", "lc-n3l-csf.5", "vl", "vl-n3l", "cl", "cl-csf.5"]
+CONTAINERS = [(0, 0, 1.0), (0, 1, 1.0), (0, 0, 0.5), (0, 1, 0.5), (1, 0, 1.0), (1, 1, 1.0), (1, 0, 0.5),
+              (1, 1, 0.5), (2, 0, 1.0), (2, 0, 0.5)]
+CNAMES = ["lc", "lc-n3l", "lc-csf.5", "lc-n3l-csf.5", "vl", "vl-n3l", "vl-csf.5", "vl-n3l-csf.5", "cl", "cl-csf.5"]
 
 
 def _fp32_only(cont, prec):
@@ -185,15 +185,16 @@ def test_tiny_and_empty_systems(orc):
 
 # ---------------------------------------------------------------- Verlet sets
 
+@pytest.mark.parametrize("csf", [1.0, 0.5])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "fp64"])
 @pytest.mark.parametrize("half", [0, 1])
-def test_verlet_sets_bit_exact(orc, half, prec):
+def test_verlet_sets_bit_exact(orc, half, prec, csf):
     """Full lists equal the oracle's rows within r_c + skin.  Half lists (Newton's
     third law) hold every such pair exactly once, in the row of one of its two
     particles."""
     pos, box = _jittered(6, 8, jitter=0.1)
     n = pos.shape[1]
-    cfg = make_config(n, box, container=1, newton3=half, precision=prec)
+    cfg = make_config(n, box, container=1, newton3=half, precision=prec, csf=csf)
     s = DeviceSystem(cfg, pos)
     s.build()
     counts, rows = M.md_get_neighbors(s.h, 256)
@@ -405,7 +406,7 @@ def test_fluid_1m_full_size(orc):
     pos, box = d["pos"], d["box"]
     n = pos.shape[1]
     F0, U0, W0, P0 = orc.forces(pos, box, orc.single(), cells=True)
-    for cont in ((1, 0, 1.0), (0, 0, 1.0), (2, 0, 1.0)):
+    for cont in ((1, 0, 1.0), (0, 0, 1.0), (2, 0, 1.0), (1, 0, 0.5), (1, 1, 0.5), (0, 1, 0.5)):
         cfg = make_config(n, box, container=cont[0], newton3=cont[1], csf=cont[2])
         s = DeviceSystem(cfg, pos)
         s.build()
@@ -413,7 +414,7 @@ def test_fluid_1m_full_size(orc):
         assert int(out[2]) == P0
         assert rel_l2(s.by_id(s.force), F0) <= FP32_F
         assert abs(out[0] - U0) <= FP32_E * abs(U0)
-        if cont[0] == 1:
+        if cont[0] == 1 and cont[1] == 0:
             counts, rows = M.md_get_neighbors(s.h, 160)
             counts, rows = counts.cpu().numpy(), rows.cpu().numpy()
             ids = s.ids_np()
