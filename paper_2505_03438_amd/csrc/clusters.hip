@@ -182,7 +182,10 @@ __global__ void k_cl_pairs(const int32_t *__restrict__ ncl_p, const int32_t *__r
     }
 }
 
-// One wavefront per i-cluster, lane (ii, jj); gather-only.
+// One wavefront per i-cluster, lane (ii, jj); gather-only.  The cluster
+// indices are wavefront-uniform (scalar loads); the j-cluster of the next
+// list entry, and its staged positions, are loaded while the current one is
+// computed.
 template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(256) void k_cl_f32(int n, const int32_t *__restrict__ ncl_p,
                                                 const int32_t *__restrict__ first, const int32_t *__restrict__ cnt,
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(256) void k_cl_f32(int n, const int32_t *__restrict
     t.load(tabp);
     int lane = threadIdx.x & 63;
     int ii = lane & 7, jj = lane >> 3;
-    int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     int nwaves = (gridDim.x * blockDim.x) >> 6;
     int ncl = *ncl_p;
     float eu = 0.f, ew = 0.f;
@@ -210,25 +213,35 @@ __global__ __launch_bounds__(256) void k_cl_f32(int n, const int32_t *__restrict
         int4 pi = st[i];
         float fx = 0.f, fy = 0.f, fz = 0.f;
         int m = lcnt[ci];
-        for (int k = 0; k < m; k++) {
-            int cj = list[(size_t)k * ld + ci];
+        if (m > 0) {
+            // entry k: cluster cj with first particle fj and count nj; pj is
+            // this lane's j particle
+            int cj = list[ci];
             int fj = first[cj], nj = cnt[cj];
-            bool vj = jj < nj;
-            int j = fj + (vj ? jj : 0);
-            int4 pj = st[j];
-            bool valid = vi && vj && i != j;
-            float dx, dy, dz;
-            staged_delta<ISO>(pi, pj, g, dx, dy, dz);
-            float r2 = dx * dx + dy * dy + dz * dz;
-            int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
-            float lo = t.pick(t.lo, ab), hi = t.pick(t.hi, ab);
-            bool in = valid && r2 < lo;
-            if (valid && r2 >= lo && r2 < hi) in = exact_r2(pos, n, i, j, g.L[0], g.L[1], g.L[2]) < t.pickd(t.rc2, ab);
-            if (!valid) r2 = 1.0f;  // keep the reciprocal finite on idle lanes
-            float phi = lj_f32<NT, ENERGY>(r2, ab, in, t, eu, ew, np);
-            fx += phi * dx;
-            fy += phi * dy;
-            fz += phi * dz;
+            int4 pj = st[fj + (jj < nj ? jj : 0)];
+            for (int k = 0; k < m; k++) {
+                int kn = min(k + 1, m - 1);
+                int cjn = list[(size_t)kn * ld + ci];
+                int fjn = first[cjn], njn = cnt[cjn];
+                int4 pjn = st[fjn + (jj < njn ? jj : 0)];
+                int j = fj + (jj < nj ? jj : 0);
+                bool valid = vi && jj < nj && i != j;
+                float dx, dy, dz;
+                staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+                float r2 = dx * dx + dy * dy + dz * dz;
+                int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
+                float lo = t.pick(t.lo, ab), hi = t.pick(t.hi, ab);
+                bool in = valid && r2 < lo;
+                if (valid && r2 >= lo && r2 < hi)
+                    in = exact_r2(pos, n, i, j, g.L[0], g.L[1], g.L[2]) < t.pickd(t.rc2, ab);
+                float phi = lj_f32<NT, ENERGY>(r2, ab, in, t, eu, ew, np);
+                fx += phi * dx;
+                fy += phi * dy;
+                fz += phi * dz;
+                fj = fjn;
+                nj = njn;
+                pj = pjn;
+            }
         }
         // sum the eight j-slots of every i-particle
         for (int off = 8; off < 64; off <<= 1) {
