@@ -138,7 +138,7 @@ static void free_buffers(md_handle *h)
     Buffers &b = h->b;
     void *ptrs[] = {b.cell_id, b.slot, b.perm, b.perm2, b.cell_count, b.cell_start, b.cell_sorted, b.scan_blocks,
                     b.tmp_pos, b.tmp_vel, b.tmp_force, b.tmp_type, b.tmp_ids, b.stage, b.stage_ref,
-                    b.nbr, b.nbr_count, b.partials, b.kpart, b.flags, b.tab, b.facc, b.cl_start,
+                    b.nbr, b.nbr_count, b.partials, b.kpart, b.flags, b.tab, b.cl_start,
                     b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
                     b.cl_nbr_count, b.snap_pos, b.snap_vel,
                     b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart,
@@ -459,16 +459,6 @@ static int ensure_window(md_handle *h, int64_t maxn)
         }
         b.w_rows_cap = rows;
     }
-    if (h->cfg.newton3 == MD_N3L_ON && b.facc_n < h->n) {
-        // per-XCD force copies of the half-window traversals, kept zero
-        // between force passes
-        if (b.facc) (void)hipFree(b.facc);
-        b.facc = nullptr;
-        size_t cnt = (size_t)kXcdCopies * 3 * (size_t)std::max<int64_t>(h->n, 1);
-        if ((rc = dalloc(&b.facc, cnt))) return rc;
-        MD_HIP(hipMemset(b.facc, 0, cnt * sizeof(float)));
-        b.facc_n = h->n;
-    }
     if (h->cfg.container == MD_CONTAINER_VL && (maxn > b.w_nbr_cap || !b.w_nbr)) {
         if (b.w_nbr) (void)hipFree(b.w_nbr);
         b.w_nbr = nullptr;
@@ -582,7 +572,6 @@ static ForceArgs force_args(md_handle *h, const double *pos, const int32_t *type
     if (a.window) {
         a.w_nblk = h->b.w_rowb + window_nbands(h->g);
         a.w_blk = h->b.w_blk;
-        a.facc = h->b.facc;
         a.w_nbr = h->b.w_nbr;
     }
     return a;

@@ -72,10 +72,6 @@ struct Buffers {
     double *kpart = nullptr;     // [kMaxPartials]
     int32_t *flags = nullptr;    // device [4]: sticky bits, first skin step, spare
     PairTab *tab = nullptr;
-    // per-XCD force copies of the windowed Newton's-third-law traversals
-    // [kXcdCopies][3][n] (zero between force passes)
-    float *facc = nullptr;
-    int64_t facc_n = 0;
     // clusters
     int32_t *cl_start = nullptr, *cl_count = nullptr, *cl_cell = nullptr;  // per cluster
     int4 *cl_centre = nullptr;
@@ -102,7 +98,6 @@ struct Buffers {
 };
 
 constexpr int kBlock = 256;
-constexpr int kXcdCopies = 8;  // XCDs of the MI355X
 constexpr int kMaxPartials = 65536;  // per-block reduction slots
 
 // Set the thread-local error string; returns code.
@@ -162,7 +157,6 @@ struct ForceArgs {
     bool window;
     const int32_t *w_nblk;
     const int4 *w_blk;
-    float *facc;  // per-XCD force copies (half-window traversals)
     const uint16_t *w_nbr;
 };
 int force_blocks(const ForceArgs &a);  // number of partial slots written when energy

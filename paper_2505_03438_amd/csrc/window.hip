@@ -849,40 +849,23 @@ __device__ __forceinline__ bool setup_half(const Geom &g, const int32_t *__restr
     return true;
 }
 
-// XCD (accelerator complex die) that runs the calling wavefront.
-__device__ __forceinline__ int xcd_id() { return (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & (kXcdCopies - 1)); }
-
-// Add the block's accumulators to the force copy of this XCD.  All blocks
-// that add to one copy run on one XCD and share its L2, so the atomics are
-// performed in that L2 (workgroup scope: no bypass to memory); the copies are
-// summed by k_xcd_reduce after the kernel.
-__device__ __forceinline__ void flush_half(const HalfAcc &acc, const Window &w, float *__restrict__ facc, size_t N)
+// Add the block's accumulators to the global forces: one atomic per
+// component and nonzero window position; consecutive positions of a piece
+// are consecutive particles, so a wavefront's atomics are coalesced.  (The
+// device-wide float atomics are performed at the memory side; per-XCD
+// copies of the forces with L2-scope atomics were measured no faster.)
+__device__ __forceinline__ void flush_half(const HalfAcc &acc, const Window &w, float *__restrict__ F, size_t N)
 {
     __syncthreads();
-    float *Fx = facc + (size_t)xcd_id() * 3 * N;
     int k = 0;
     for (int p = threadIdx.x; p < w.W; p += blockDim.x) {
         k = piece_from(w, k, p);
         int j = w.pc_start[k] + (p - w.pc_win[k]);
         float vx = acc.x[p], vy = acc.y[p], vz = acc.z[p];
-        if (vx != 0.f) __hip_atomic_fetch_add(&Fx[j], vx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (vy != 0.f) __hip_atomic_fetch_add(&Fx[N + j], vy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (vz != 0.f) __hip_atomic_fetch_add(&Fx[2 * N + j], vz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (vx != 0.f) atomicAdd(&F[j], vx);
+        if (vy != 0.f) atomicAdd(&F[N + j], vy);
+        if (vz != 0.f) atomicAdd(&F[2 * N + j], vz);
     }
-}
-
-// F = sum of the XCD copies; the copies are left zero for the next pass.
-__global__ void k_xcd_reduce(int64_t m, float *__restrict__ facc, float *__restrict__ F)
-{
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    float s = 0.f;
-#pragma unroll
-    for (int c = 0; c < kXcdCopies; c++) {
-        s += facc[(size_t)c * m + k];
-        facc[(size_t)c * m + k] = 0.f;
-    }
-    F[k] = s;
 }
 
 // One candidate pair with Newton's third law: the i-side force in registers,
@@ -938,7 +921,7 @@ __global__ __launch_bounds__(256) void k_lcwh_f32(const int4 *__restrict__ st, c
                                                   const int32_t *__restrict__ nblk_p, int cap,
                                                   const int4 *__restrict__ blocks,
                                                   const PairTab *__restrict__ tabp, const double *__restrict__ pos,
-                                                  float *__restrict__ facc, double *__restrict__ partials,
+                                                  float *__restrict__ F, double *__restrict__ partials,
                                                   int32_t *__restrict__ flags)
 {
     __shared__ WinEntry<NT> win[kWinMaxHalf];
@@ -983,7 +966,7 @@ __global__ __launch_bounds__(256) void k_lcwh_f32(const int4 *__restrict__ st, c
             atomicAdd(&acc.y[self], fy);
             atomicAdd(&acc.z[self], fz);
         }
-        flush_half(acc, w, facc, N);
+        flush_half(acc, w, F, N);
     }
     if (ENERGY) {
         double v[4] = {(double)eu, (double)ew, (double)np, 0.0};
@@ -1000,7 +983,7 @@ __global__ __launch_bounds__(256) void k_vlwh_f32(const int4 *__restrict__ st, c
                                                   const int4 *__restrict__ blocks,
                                                   const uint16_t *__restrict__ nbr, const int32_t *__restrict__ cnt,
                                                   const PairTab *__restrict__ tabp, const double *__restrict__ pos,
-                                                  float *__restrict__ facc, double *__restrict__ partials,
+                                                  float *__restrict__ F, double *__restrict__ partials,
                                                   int32_t *__restrict__ flags)
 {
     __shared__ WinEntry<NT> win[kWinMaxHalf];
@@ -1051,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_vlwh_f32(const int4 *__restrict__ st, c
             atomicAdd(&acc.y[self], fy);
             atomicAdd(&acc.z[self], fz);
         }
-        flush_half(acc, w, facc, N);
+        flush_half(acc, w, F, N);
     }
     if (ENERGY) {
         double v[4] = {(double)eu, (double)ew, (double)np, 0.0};
@@ -1147,16 +1130,14 @@ static void win_launch(const ForceArgs &a, const Geom &g, hipStream_t s)
     int cap = (int)window_block_cap(a.n, g);
     bool vl = a.container == MD_CONTAINER_VL;
     if (a.newton3) {
-        // each pair once into the per-XCD copies, then F = their sum
         if (vl)
             k_vlwh_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk,
-                                                            cap, a.w_blk, a.w_nbr, a.nbr_count, a.tab, a.pos, a.facc,
-                                                            a.partials, a.flags);
+                                                            cap, a.w_blk, a.w_nbr, a.nbr_count, a.tab, a.pos,
+                                                            (float *)a.force, a.partials, a.flags);
         else
             k_lcwh_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk,
-                                                            cap, a.w_blk, a.tab, a.pos, a.facc, a.partials, a.flags);
-        int64_t m = 3 * (int64_t)a.n;
-        k_xcd_reduce<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(m, a.facc, (float *)a.force);
+                                                            cap, a.w_blk, a.tab, a.pos, (float *)a.force, a.partials,
+                                                            a.flags);
     } else if (vl) {
         k_vlw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
                                                        a.w_blk, a.w_nbr, a.nbr_count, a.tab, a.pos,
