@@ -129,6 +129,8 @@ struct md_handle {
     bool energy_gather = true;    // the last energy partials saw each pair twice
     bool replay_no_log = false;   // the next block replays: its first step's log entry is done
     int64_t next_phase = 0;       // step index of the next tuning phase
+    double rate[4] = {0, 0, 0, 0};  // recent largest displacements per step (fixed-point units)
+    int rate_pos = 0;
 };
 
 static size_t real_size(const md_config &c) { return c.precision == MD_FP64 ? 8 : 4; }
@@ -138,7 +140,7 @@ static void free_buffers(md_handle *h)
     Buffers &b = h->b;
     void *ptrs[] = {b.cell_id, b.slot, b.perm, b.perm2, b.cell_count, b.cell_start, b.cell_sorted, b.scan_blocks,
                     b.tmp_pos, b.tmp_vel, b.tmp_force, b.tmp_type, b.tmp_ids, b.stage, b.stage_ref,
-                    b.nbr, b.nbr_count, b.partials, b.kpart, b.flags, b.tab, b.cl_start,
+                    b.nbr, b.nbr_count, b.partials, b.kpart, b.dpart, b.flags, b.tab, b.cl_start,
                     b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
                     b.cl_nbr_count, b.snap_pos, b.snap_vel,
                     b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart,
@@ -298,18 +300,19 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
     ALLOC(dalloc(&b.nbr_count, n));
     ALLOC(dalloc(&b.partials, (size_t)kMaxPartials * 4));
     ALLOC(dalloc(&b.kpart, (size_t)kMaxPartials));
+    ALLOC(dalloc(&b.dpart, (size_t)kMaxPartials));
     ALLOC(dalloc(&b.gpart, (size_t)kMaxPartials * 8));
-    ALLOC(dalloc(&b.flags, 4));
+    ALLOC(dalloc(&b.flags, 8));
     ALLOC(dalloc(&b.tab, 1));
     ALLOC(ensure_cells(h, g));
 #undef ALLOC
-    if (hipHostMalloc((void **)&b.host_flags, 4 * sizeof(uint32_t), 0) != hipSuccess) {
+    if (hipHostMalloc((void **)&b.host_flags, 8 * sizeof(uint32_t), 0) != hipSuccess) {
         free_buffers(h);
         delete h;
         return fail(MD_ERR_HIP, "hipHostMalloc failed");
     }
-    (void)hipMemset(b.flags, 0, 4 * sizeof(int32_t));
-    int32_t init[4] = {0, INT32_MAX, 0, 0};
+    (void)hipMemset(b.flags, 0, 8 * sizeof(int32_t));
+    int32_t init[8] = {0, INT32_MAX, 0, 0, 0, 0, 0, 0};
     (void)hipMemcpy(b.flags, init, sizeof(init), hipMemcpyHostToDevice);
     (void)hipEventCreate(&h->ev0);
     (void)hipEventCreate(&h->ev1);
@@ -620,7 +623,8 @@ struct StepCtx {
     hipStream_t s;
 };
 
-static IntegrateArgs integ_args(md_handle *h, const StepCtx &c, int kick_prev, int start, int energy, int step)
+static IntegrateArgs integ_args(md_handle *h, const StepCtx &c, int kick_prev, int start, int energy, int step,
+                                bool track = false)
 {
     IntegrateArgs a;
     memset(&a, 0, sizeof(a));
@@ -641,6 +645,7 @@ static IntegrateArgs integ_args(md_handle *h, const StepCtx &c, int kick_prev, i
     a.stage_ref = h->b.stage_ref;
     a.flags = h->b.flags;
     a.kpart = h->b.kpart;
+    a.dpart = track ? h->b.dpart : nullptr;
     return a;
 }
 
@@ -689,10 +694,10 @@ static int snapshot(md_handle *h, const StepCtx &c, bool restore, bool with_forc
 static int step_forces(md_handle *h, const StepCtx &c, int s);
 
 static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, bool log_prev_ok = true,
-                    bool snap_after_rebuild = false)
+                    bool snap_after_rebuild = false, bool track = false)
 {
     bool log_prev = s > 0 && logs_step(c, s - 1) && log_prev_ok;
-    launch_integrate(integ_args(h, c, s > 0, 1, log_prev, s), h->g, c.s);
+    launch_integrate(integ_args(h, c, s > 0, 1, log_prev, s, track), h->g, c.s);
     if (log_prev) {
         ForceArgs fa = force_args(h, c.pos, c.type, c.force, true);
         launch_log_entry(h->b.partials, force_blocks(fa), h->energy_gather, h->b.kpart,
@@ -760,18 +765,45 @@ static int snapshot(md_handle *h, const StepCtx &c, bool restore, bool with_forc
 }
 
 // Read the device flags (synchronises the stream).
-static int read_flags(md_handle *h, hipStream_t s, int32_t out[3])
+static int read_flags(md_handle *h, hipStream_t s, int32_t out[4])
 {
-    MD_HIP(hipMemcpyAsync(h->b.host_flags, h->b.flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MD_HIP(hipMemcpyAsync(h->b.host_flags, h->b.flags, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     MD_HIP(hipStreamSynchronize(s));
     out[0] = (int32_t)h->b.host_flags[0];
     out[1] = (int32_t)h->b.host_flags[1];
     out[2] = (int32_t)h->b.host_flags[2];
+    out[3] = (int32_t)h->b.host_flags[4];  // squared displacement since the build (float bits)
     timing_collect(h);
     if (h->b.host_flags[3])
         return fail(MD_ERR_INVALID_ARG, "a cell neighbourhood exceeds the windowed traversal's LDS tile "
                                         "(density far above liquid); use MD_N3L_ON or csf 0.5");
     return MD_OK;
+}
+
+// Largest displacement per step, from the largest squared displacement
+// since the last build (d2bits: float bits, fixed-point units) after h->age
+// steps; particles move ballistically between builds, so it grows linearly.
+static void update_motion(md_handle *h, int32_t d2bits)
+{
+    float d2;
+    memcpy(&d2, &d2bits, sizeof(d2));
+    if (!(d2 > 0.f) || h->age < 1) return;
+    h->rate[h->rate_pos++ & 3] = sqrt((double)d2) / (double)h->age;
+}
+
+// Rebuild interval derived by the autotuner.  A structure built at step s
+// serves the forces of steps s .. s + R - 1, after 0 .. R - 1 drifts: R is
+// the most steps that keep the fastest recent particle's displacement after
+// R - 1 drifts within 95 % of skin/2 (the skin check and the replay still
+// guard every step).  The base interval until motion has been measured.
+static int derived_interval(const md_handle *h)
+{
+    double r = 0.0;
+    for (double v : h->rate) r = std::max(r, v);
+    if (!(h->cfg.skin > 0.0)) return 1;
+    if (r <= 0.0) return h->base.rebuild_interval;
+    double R = floor(0.95 * sqrt((double)h->g.disp2) / r) + 1.0;
+    return (int)std::max(1.0, std::min(R, 100.0));
 }
 
 // Run one block of steps starting at s0: a rebuild can only happen at the
@@ -794,10 +826,14 @@ static int run_block(md_handle *h, const StepCtx &c, int s0, int s_end, int *nex
     // of the block); otherwise before step s0, forces included.
     if (!rebuild_first && (rc = snapshot(h, c, false, true))) return rc;
     launch_fill_i32(h->b.flags + 1, INT32_MAX, 1, c.s);
+    // the autotuner tracks the motion at the block's last step
+    bool track = h->tuner != nullptr;
     for (int st = s0; st <= last; st++)
-        if ((rc = one_step(h, c, st, false, true, rebuild_first && st == s0))) return rc;
-    int32_t f[3];
+        if ((rc = one_step(h, c, st, false, true, rebuild_first && st == s0, track && st == last))) return rc;
+    if (track) launch_dmax_reduce(h->b.dpart, integrate_blocks((int)h->n), h->b.flags, c.s);
+    int32_t f[4];
     if ((rc = read_flags(h, c.s, f))) return rc;
+    if (track) update_motion(h, f[3]);
     int v = f[1];
     int first_used = rebuild_first ? s0 + 1 : s0;  // first step whose forces used the checked structure
     bool overflow = (f[0] & MD_FLAG_LIST_OVERFLOW) != 0;
@@ -869,6 +905,7 @@ static int run_steps(md_handle *h, const StepCtx &c, int s0, int s1)
     int s = s0;
     h->replay_no_log = false;
     while (s < s1) {
+        if (h->tuner) h->cfg.rebuild_interval = derived_interval(h);
         int next = s;
         int rc = run_block(h, c, s, s1, &next);
         if (rc) return rc;
@@ -894,7 +931,7 @@ extern "C" int md_step(md_handle *h, double *pos, void *vel, void *force, int32_
     launch_prepare_tab(lj, h->cfg.rc2, h->g, h->b.tab, c.s);
     // lists truncated since the last look (a build before this call overflowed):
     // grow them, rebuild and recompute the entry forces
-    int32_t f0[3];
+    int32_t f0[4];
     if ((rc = read_flags(h, c.s, f0))) return rc;
     if (f0[0] & MD_FLAG_LIST_OVERFLOW) {
         h->sticky |= (uint32_t)f0[0];
@@ -907,7 +944,7 @@ extern "C" int md_step(md_handle *h, double *pos, void *vel, void *force, int32_
         h->truncated = false;
         if ((rc = rebuild(h, c))) return rc;
         if ((rc = forces_impl(h, c.pos, c.type, c.force, false, c.s))) return rc;
-        int32_t f1[3];
+        int32_t f1[4];
         if ((rc = read_flags(h, c.s, f1))) return rc;
         if (f1[0] & MD_FLAG_LIST_OVERFLOW) h->truncated = true;
         if (h->truncated) return fail(MD_ERR_LIST_OVERFLOW, "neighbour rows exceed max_neighbors after growth");
@@ -1141,7 +1178,8 @@ int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
     int s = s0, last_k = -1, rc;
     for (int k = 0; k < (int)trial.size(); k++) {
         if (!trial[k]) continue;
-        const md_config &kc = h->space[k];
+        md_config kc = h->space[k];
+        kc.rebuild_interval = derived_interval(h);
         if ((rc = apply_config(h, kc))) return rc;
         MD_HIP(hipEventRecord(h->ev0, c.s));
         if ((rc = run_steps(h, c, s, s + 1))) return rc;

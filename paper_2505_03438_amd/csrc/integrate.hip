@@ -32,6 +32,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntegrateArgs a, Geom g)
     __shared__ double sh[4 * kBlock / 64];
     int i = blockIdx.x * kBlock + threadIdx.x;
     double ke = 0.0;
+    float dmax = 0.f;  // squared displacement since the last build
     if (i < a.n) {
         size_t N = (size_t)a.n;
         real *v = (real *)a.vel;
@@ -74,10 +75,25 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntegrateArgs a, Geom g)
                 atomicMin(&a.flags[1], a.step_index);
             }
             if (!(x == x && y == y && z == z)) atomicOr(&a.flags[0], (int)MD_FLAG_NONFINITE);
+            dmax = d2;
         }
         v[i] = vx;
         v[N + i] = vy;
         v[2 * N + i] = vz;
+    }
+    if (a.start && a.dpart) {
+        // largest squared displacement since the last build, per block: the
+        // rate of motion from which the autotuner derives the rebuild
+        // interval (reduced by k_dmax_reduce)
+        __shared__ float wm[kBlock / 64];
+        for (int off = 32; off > 0; off >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, off, 64));
+        if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = dmax;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = wm[0];
+            for (int w = 1; w < kBlock / 64; w++) m = fmaxf(m, wm[w]);
+            a.dpart[blockIdx.x] = m;
+        }
     }
     if (a.energy && a.kick_prev) {
         double s4[4] = {ke, 0.0, 0.0, 0.0};
@@ -128,6 +144,26 @@ void launch_log_entry(const double *fpart, int fblocks, int gather, const double
                       double *out4, hipStream_t s)
 {
     k_log_entry<<<1, kBlock, 0, s>>>(fpart, fblocks, gather, kpart, kblocks, out4);
+}
+
+__global__ void k_dmax_reduce(const float *__restrict__ dpart, int nb, int32_t *__restrict__ flags)
+{
+    __shared__ float wm[kBlock / 64];
+    float m = 0.f;
+    for (int b = threadIdx.x; b < nb; b += kBlock) m = fmaxf(m, dpart[b]);
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; w++) m = fmaxf(m, wm[w]);
+        m = fmaxf(m, wm[0]);
+        flags[4] = __float_as_int(m);
+    }
+}
+
+void launch_dmax_reduce(const float *dpart, int nblocks, int32_t *flags, hipStream_t s)
+{
+    k_dmax_reduce<<<1, kBlock, 0, s>>>(dpart, nblocks, flags);
 }
 
 // Zero a buffer with a kernel (not a memset node, so it can sit in a graph).

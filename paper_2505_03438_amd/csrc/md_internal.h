@@ -70,6 +70,7 @@ struct Buffers {
     int64_t nbr_cap = 0;  // entries per row allocated
     double *partials = nullptr;  // [kMaxPartials][4]
     double *kpart = nullptr;     // [kMaxPartials]
+    float *dpart = nullptr;      // [kMaxPartials] per-block displacement maxima
     int32_t *flags = nullptr;    // device [4]: sticky bits, first skin step, spare
     PairTab *tab = nullptr;
     // clusters
@@ -202,11 +203,14 @@ struct IntegrateArgs {
     const int4 *stage_ref;
     int32_t *flags;
     double *kpart;
+    float *dpart;  // if not null: per-block largest squared displacement since the build
 };
 int integrate_blocks(int n);
 void launch_integrate(const IntegrateArgs &a, const Geom &g, hipStream_t s);
 void launch_log_entry(const double *fpart, int fblocks, int gather, const double *kpart,
                       int kblocks, double *out4, hipStream_t s);
+// flags[4] = the bits of the largest of the nblocks per-block maxima.
+void launch_dmax_reduce(const float *dpart, int nblocks, int32_t *flags, hipStream_t s);
 
 // adjoint.hip
 struct AdjointArgs {

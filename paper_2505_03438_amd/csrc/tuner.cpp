@@ -108,33 +108,29 @@ int Tuner::end_phase()
 void tuning_space(const md_config &base, std::vector<md_config> &space)
 {
     space.clear();
-    const int Rs[3] = {4, 6, 10};
-    for (int r = 0; r < 3; r++) {
-        md_config c = base;
-        c.rebuild_interval = Rs[r];
-        c.autotune = MD_TUNE_OFF;
-        // linked cells, CSF 1 and 0.5, gather-only and N3L
-        for (double csf : {1.0, 0.5})
-            for (int n3 : {MD_N3L_OFF, MD_N3L_ON}) {
-                c.container = MD_CONTAINER_LC;
-                c.csf = csf;
-                c.newton3 = n3;
-                space.push_back(c);
-            }
-        // Verlet lists (built from CSF-1 cells)
+    md_config c = base;
+    c.autotune = MD_TUNE_OFF;
+    // linked cells, CSF 1 and 0.5, gather-only and N3L
+    for (double csf : {1.0, 0.5})
         for (int n3 : {MD_N3L_OFF, MD_N3L_ON}) {
-            c.container = MD_CONTAINER_VL;
-            c.csf = 1.0;
+            c.container = MD_CONTAINER_LC;
+            c.csf = csf;
             c.newton3 = n3;
             space.push_back(c);
         }
-        // cluster-pair lists (FP32, gather-only)
-        if (base.precision == MD_FP32) {
-            c.container = MD_CONTAINER_CL;
-            c.csf = 1.0;
-            c.newton3 = MD_N3L_OFF;
-            space.push_back(c);
-        }
+    // Verlet lists (built from CSF-1 cells)
+    for (int n3 : {MD_N3L_OFF, MD_N3L_ON}) {
+        c.container = MD_CONTAINER_VL;
+        c.csf = 1.0;
+        c.newton3 = n3;
+        space.push_back(c);
+    }
+    // cluster-pair lists (FP32, gather-only)
+    if (base.precision == MD_FP32) {
+        c.container = MD_CONTAINER_CL;
+        c.csf = 1.0;
+        c.newton3 = MD_N3L_OFF;
+        space.push_back(c);
     }
 }
 

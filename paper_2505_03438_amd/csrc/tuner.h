@@ -41,8 +41,9 @@ private:
 
 // The GPU configuration space the autotuner explores for a base config:
 // linked cells (CSF 1 and 0.5) and Verlet lists, gather-only or with
-// Newton's third law, cluster lists (gather-only), rebuild intervals
-// {4, 6, 10}.
+// Newton's third law, and cluster lists (gather-only, FP32).  The rebuild
+// interval is not a trial dimension: it is derived from the measured
+// particle motion (the most steps that keep displacements within the skin).
 void tuning_space(const md_config &base, std::vector<md_config> &space);
 
 }  // namespace mdlj

@@ -460,3 +460,64 @@ def test_autograd_function_force_matching(orc, prec):
     assert abs(loss.item() - L0) <= tol_l * abs(L0)
     assert rel_l2(s.by_id(x.grad), gx) <= tol_x
     assert rel_l2(lj.grad.cpu().numpy(), gt) <= tol_t
+
+
+# ---------------------------------------------------------------- autotuned runs
+
+@pytest.mark.parametrize("strategy", [1, 2], ids=["full", "predictive"])
+def test_autotuned_fp64_trajectory(orc, strategy):
+    """md_step with the run-time configuration selection: every trial step
+    advances the simulation, so the trajectory (pair counts, energies,
+    positions) equals the oracle's whatever configurations are chosen."""
+    import torch
+    d = W.plain_fcc_864()
+    nsteps = 150
+    p1, v1, _, log0 = orc.velocity_verlet(d["pos"], d["vel"], d["box"], orc.single(), 0.005, nsteps)
+    n = 864
+    cfg = make_config(n, d["box"], container=0, precision=1, R=10)
+    cfg.autotune = strategy
+    cfg.tune_interval = 40
+    cfg.tune_trial_steps = 3
+    cfg.total_steps_hint = nsteps
+    s = DeviceSystem(cfg, d["pos"], d["vel"])
+    s.build()
+    s.forces(energy=False)
+    log = torch.zeros((nsteps, 4), dtype=torch.float64, device="cuda")
+    M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, nsteps, 1, log)
+    torch.cuda.synchronize()
+    log = log.cpu().numpy()
+    cnt = M.md_get_counters(s.h)
+    assert cnt["tuning_phases"] >= 3
+    assert cnt["trials"] >= 6 * 2  # the first two phases trial every configuration
+    assert 1 <= M.md_get_config(s.h).rebuild_interval <= 100
+    assert np.array_equal(log[:, 3], log0[:, 3])
+    for k in (0, 1, 2):
+        assert np.abs(log[:, k] - log0[:, k]).max() <= 1e-10 * np.abs(log0[:, k]).max()
+    dx = s.by_id(s.pos) - p1
+    dx -= d["box"][:, None] * np.rint(dx / d["box"][:, None])
+    assert np.abs(dx).max() < 1e-9
+
+
+def test_autotuned_fp32_energy_conservation(orc):
+    """FP32 autotuned run over all seven configurations (cluster lists
+    included): the total energy stays conserved across configuration
+    switches."""
+    import torch
+    d = W.plain_fcc_864()
+    nsteps = 400
+    cfg = make_config(864, d["box"], container=0, precision=0, R=10)
+    cfg.autotune = 2
+    cfg.tune_interval = 100
+    cfg.tune_trial_steps = 4
+    cfg.total_steps_hint = nsteps
+    s = DeviceSystem(cfg, d["pos"], d["vel"])
+    s.build()
+    s.forces(energy=False)
+    log = torch.zeros((nsteps, 4), dtype=torch.float64, device="cuda")
+    M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, nsteps, 1, log)
+    torch.cuda.synchronize()
+    log = log.cpu().numpy()
+    assert M.md_get_counters(s.h)["trials"] >= 14
+    u_rc = orc.lj(6.25)[1]
+    E = (log[:, 0] - log[:, 3] * u_rc + log[:, 1]) / 864
+    assert np.abs(E - E[0]).max() < 5e-3
