@@ -654,21 +654,21 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
 // List entry c of particle i: nbr[((c / 8) * n + i) * 8 + c % 8].
 __device__ __forceinline__ size_t list_slot(int c, int i, size_t N) { return ((size_t)(c >> 3) * N + i) * 8 + (c & 7); }
 
-// Pending chunk of eight 16-bit entries of the list being built.
+// Pending chunk of the list being built: a 128-bit shift register of eight
+// 16-bit entries (each append shifts the register down by one entry and
+// puts the new entry on top; after eight appends entry 0 is in the low half
+// of word x, entry 7 in the high half of word w, as the force kernels read
+// them).
 struct Chunk {
-    uint64_t lo = 0, hi = 0;
-    __device__ __forceinline__ void put(int e, uint32_t p)
+    uint32_t x = 0, y = 0, z = 0, w = 0;
+    __device__ __forceinline__ void push(uint32_t p)
     {
-        uint64_t v = (uint64_t)p << (16 * (e & 3));
-        if (e < 4)
-            lo |= v;
-        else
-            hi |= v;
+        x = __builtin_amdgcn_alignbit(y, x, 16);
+        y = __builtin_amdgcn_alignbit(z, y, 16);
+        z = __builtin_amdgcn_alignbit(w, z, 16);
+        w = __builtin_amdgcn_alignbit(p, w, 16);
     }
-    __device__ __forceinline__ uint4 word() const
-    {
-        return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
-    }
+    __device__ __forceinline__ uint4 word() const { return make_uint4(x, y, z, w); }
 };
 
 // Append window position p to the list of particle i (c entries so far);
@@ -676,14 +676,21 @@ struct Chunk {
 __device__ __forceinline__ void list_append(uint32_t p, int &c, Chunk &ck, uint4 *__restrict__ row, size_t N,
                                             int maxn)
 {
-    ck.put(c & 7, p);
+    ck.push(p);
     c++;
-    if ((c & 7) == 0) {
-        if (c <= maxn) row[(size_t)((c >> 3) - 1) * N] = ck.word();
-        ck.lo = ck.hi = 0;
-    }
+    if ((c & 7) == 0 && c <= maxn) row[(size_t)((c >> 3) - 1) * N] = ck.word();
 }
 
+// Write the last, partial chunk (its entries shifted down to the bottom).
+__device__ __forceinline__ void list_finish(int c, Chunk &ck, uint4 *__restrict__ row, size_t N, int maxn)
+{
+    if ((c & 7) == 0 || c >= maxn) return;
+    for (int e = c & 7; e < 8; e++) ck.push(0u);
+    row[(size_t)(c >> 3) * N] = ck.word();
+}
+
+// Verlet-list candidate test: true if r2 < (r_c + skin)^2 outside the guard
+// band; amb if inside the band (decided by the caller in FP64).
 template <bool ISO>
 __device__ __forceinline__ bool build_fast(const int4 &pi, const int4 &pj, bool valid, const Geom &g, bool &amb)
 {
@@ -695,7 +702,9 @@ __device__ __forceinline__ bool build_fast(const int4 &pi, const int4 &pj, bool 
 }
 
 // Verlet lists (full windows: every pair within r_c + skin from both sides;
-// half windows: each pair once, in the forward half of the stencil).
+// half windows: each pair once, in the forward half of the stencil).  Each
+// range of candidates is tested 32 positions at a time into a bit mask (four
+// LDS reads in flight), then the set bits are appended.
 template <bool ISO, bool HALF>
 __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                    const int32_t *__restrict__ cell_sorted,
@@ -720,26 +729,33 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
         int c = 0;
         Chunk ck;
         stencil_ranges<HALF>(g, w, k, x, self, [&](int b, int en) {
-            for (int p0 = b; p0 < en; p0 += 4) {
-                int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
-                int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
-                bool a0, a1, a2, a3;
-                bool i0 = build_fast<ISO>(pi, q0, p0 != self, g, a0);
-                bool i1 = build_fast<ISO>(pi, q1, p0 + 1 < en && p1 != self, g, a1);
-                bool i2 = build_fast<ISO>(pi, q2, p0 + 2 < en && p2 != self, g, a2);
-                bool i3 = build_fast<ISO>(pi, q3, p0 + 3 < en && p3 != self, g, a3);
-                // rare: guard-band pairs decided from the FP64 positions
-                if (a0) i0 = exact_r2(pos, n, i, window_global(w, p0), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                if (a1) i1 = exact_r2(pos, n, i, window_global(w, p1), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                if (a2) i2 = exact_r2(pos, n, i, window_global(w, p2), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                if (a3) i3 = exact_r2(pos, n, i, window_global(w, p3), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                if (i0) list_append((uint32_t)p0, c, ck, row, N, maxn);
-                if (i1) list_append((uint32_t)p1, c, ck, row, N, maxn);
-                if (i2) list_append((uint32_t)p2, c, ck, row, N, maxn);
-                if (i3) list_append((uint32_t)p3, c, ck, row, N, maxn);
+            for (int base = b; base < en; base += 32) {
+                int e32 = min(en, base + 32);
+                uint32_t mask = 0;
+                for (int p0 = base; p0 < e32; p0 += 4) {
+                    int p1 = min(p0 + 1, e32 - 1), p2 = min(p0 + 2, e32 - 1), p3 = min(p0 + 3, e32 - 1);
+                    int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
+                    bool a0, a1, a2, a3;
+                    bool i0 = build_fast<ISO>(pi, q0, p0 != self, g, a0);
+                    bool i1 = build_fast<ISO>(pi, q1, p0 + 1 < e32 && p1 != self, g, a1);
+                    bool i2 = build_fast<ISO>(pi, q2, p0 + 2 < e32 && p2 != self, g, a2);
+                    bool i3 = build_fast<ISO>(pi, q3, p0 + 3 < e32 && p3 != self, g, a3);
+                    // rare: guard-band pairs decided from the FP64 positions
+                    if (a0) i0 = exact_r2(pos, n, i, window_global(w, p0), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                    if (a1) i1 = exact_r2(pos, n, i, window_global(w, p1), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                    if (a2) i2 = exact_r2(pos, n, i, window_global(w, p2), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                    if (a3) i3 = exact_r2(pos, n, i, window_global(w, p3), g.L[0], g.L[1], g.L[2]) < g.rl2;
+                    uint32_t nib = (i0 ? 1u : 0u) | (i1 ? 2u : 0u) | (i2 ? 4u : 0u) | (i3 ? 8u : 0u);
+                    mask |= nib << (p0 - base);
+                }
+                while (mask) {
+                    int u = __builtin_ctz(mask);
+                    mask &= mask - 1;
+                    list_append((uint32_t)(base + u), c, ck, row, N, maxn);
+                }
             }
         });
-        if ((c & 7) && c < maxn) row[(size_t)(c >> 3) * N] = ck.word();
+        list_finish(c, ck, row, N, maxn);
         if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
         cmax = max(cmax, c);
         cnt[i] = c < maxn ? c : maxn;
