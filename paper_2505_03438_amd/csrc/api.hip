@@ -680,9 +680,12 @@ static void timing_collect(md_handle *h)
     h->tnext = 0;
 }
 
-static int rebuild(md_handle *h, const StepCtx &c)
+// Cells and lists for the current positions.  with_force = false inside a
+// step, after the drift: the forces of the previous step have been used by
+// both kicks and are about to be recomputed, so they are not reordered.
+static int rebuild(md_handle *h, const StepCtx &c, bool with_force = true)
 {
-    int rc = build_cells_impl(h, c.pos, c.vel, c.force, c.type, c.ids, c.s);
+    int rc = build_cells_impl(h, c.pos, c.vel, with_force ? c.force : nullptr, c.type, c.ids, c.s);
     if (rc) return rc;
     return build_lists_impl(h, c.pos, c.s);
 }
@@ -707,7 +710,7 @@ static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, b
     if (force_rebuild || h->age >= h->cfg.rebuild_interval) {
         hipEvent_t e0 = timing_event(h), e1 = nullptr;
         if (e0) MD_HIP(hipEventRecord(e0, c.s));
-        int rc = rebuild(h, c);
+        int rc = rebuild(h, c, false);
         if (rc) return rc;
         if (e0 && (e1 = timing_event(h))) {
             MD_HIP(hipEventRecord(e1, c.s));

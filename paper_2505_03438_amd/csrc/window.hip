@@ -485,10 +485,12 @@ __device__ int pack_band(int e, const Geom &g, const int32_t *__restrict__ cs, c
     return nb;
 }
 
+// The three per-column LDS arrays of the packer are sized at launch: 3 nx ints.
 __global__ void k_blk_count(const Geom g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
                             int32_t *__restrict__ band_n, int wmax)
 {
-    __shared__ int scol[kPackMaxX], snum[kPackMaxX], sst[kPackMaxX];
+    extern __shared__ int pack_lds[];
+    int *scol = pack_lds, *snum = pack_lds + g.nc[0], *sst = pack_lds + 2 * g.nc[0];
     int nb = pack_band(blockIdx.x, g, cs, colsum, 0, nullptr, false, 0, nullptr, wmax, scol, snum, sst);
     if (threadIdx.x == 0) band_n[blockIdx.x] = nb;
 }
@@ -496,7 +498,8 @@ __global__ void k_blk_count(const Geom g, const int32_t *__restrict__ cs, const 
 __global__ void k_blk_write(const Geom g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
                             const int32_t *__restrict__ band_base, int4 *blocks, int cap, int32_t *flags, int wmax)
 {
-    __shared__ int scol[kPackMaxX], snum[kPackMaxX], sst[kPackMaxX];
+    extern __shared__ int pack_lds[];
+    int *scol = pack_lds, *snum = pack_lds + g.nc[0], *sst = pack_lds + 2 * g.nc[0];
     pack_band(blockIdx.x, g, cs, colsum, band_base[blockIdx.x], blocks, true, cap, flags, wmax, scol, snum, sst);
 }
 
@@ -763,8 +766,69 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
     if (cmax > 0) atomicMax(&flags[2], cmax);
 }
 
+// One entry of the gather Verlet-list force.  As pair_fast, except that with
+// one type the factor 24 eps is applied once per particle after the sum
+// (FOLD), and the guard band is tested with one unsigned compare of the
+// float bits (r2 >= 0, so the bit patterns order as the values).  Returns
+// true for a guard-band pair.
+template <int NT, bool ISO, bool ENERGY>
+__device__ __forceinline__ bool vl_entry(const int4 &pi, const int4 &pj, bool valid, const TabF<NT> &t,
+                                         const Geom &g, float &fx, float &fy, float &fz, float &eu, float &ew,
+                                         int &np)
+{
+    float dx, dy, dz;
+    staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+    float r2 = dx * dx + dy * dy + dz * dz;
+    int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
+    float lo = t.pick(t.lo, ab), hi = t.pick(t.hi, ab);
+    bool in = valid && r2 < lo;
+    float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.0f;
+    float s2 = t.pick(t.sig2, ab) * ir2;
+    float q = s2 * s2 * s2;
+    float a = q * (2.0f * q - 1.0f);
+    float phi = NT == 1 ? ir2 * a : t.pick(t.eps24, ab) * ir2 * a;
+    if (ENERGY) {
+        eu += t.pick(t.eps4, ab) * q * (q - 1.0f);
+        ew += t.pick(t.eps24w, ab) * a;
+        np += in ? 1 : 0;
+    }
+    fx += phi * dx;
+    fy += phi * dy;
+    fz += phi * dz;
+    uint32_t lob = __float_as_uint(lo);
+    return valid && __float_as_uint(r2) - lob < __float_as_uint(hi) - lob;
+}
+
+// Guard-band entry, decided from the FP64 positions (same folding).
+template <int NT, bool ISO, bool ENERGY>
+__device__ __forceinline__ void vl_exact(const int4 &pi, const int4 &pj, int i, int j, const TabF<NT> &t,
+                                         const Geom &g, const double *__restrict__ pos, int n, float &fx, float &fy,
+                                         float &fz, float &eu, float &ew, int &np)
+{
+    int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
+    if (exact_r2(pos, n, i, j, g.L[0], g.L[1], g.L[2]) < t.pickd(t.rc2, ab)) {
+        float dx, dy, dz;
+        staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+        float r2 = dx * dx + dy * dy + dz * dz;
+        float ir2 = __builtin_amdgcn_rcpf(r2);
+        float s2 = t.pick(t.sig2, ab) * ir2;
+        float q = s2 * s2 * s2;
+        float a = q * (2.0f * q - 1.0f);
+        float phi = NT == 1 ? ir2 * a : t.pick(t.eps24, ab) * ir2 * a;
+        if (ENERGY) {
+            eu += t.pick(t.eps4, ab) * q * (q - 1.0f);
+            ew += t.pick(t.eps24w, ab) * a;
+            np += 1;
+        }
+        fx += phi * dx;
+        fy += phi * dy;
+        fz += phi * dz;
+    }
+}
+
 // Each thread walks its list in chunks of eight entries; the next chunk's
-// load is in flight while the current one is computed.
+// load is in flight while the current one is computed.  A chunk with an
+// entry in the guard band (rare) is walked again for those entries.
 template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                  const int32_t *__restrict__ cell_sorted, Geom g, int n,
@@ -802,22 +866,32 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
             int valid = min(8, c - ch * 8);
             int pp[8] = {(int)(cur.x & 0xffff), (int)(cur.x >> 16), (int)(cur.y & 0xffff), (int)(cur.y >> 16),
                          (int)(cur.z & 0xffff), (int)(cur.z >> 16), (int)(cur.w & 0xffff), (int)(cur.w >> 16)};
-            uint32_t amb = 0;
+            bool amb = false;
 #pragma unroll
             for (int u = 0; u < 8; u++) {
                 int4 pj = win[pp[u]].get();
-                amb |= pair_fast<NT, ISO, ENERGY>(pi, pj, u < valid, t, g, fx, fy, fz, eu, ew, np) ? 1u << u : 0u;
+                amb |= vl_entry<NT, ISO, ENERGY>(pi, pj, u < valid, t, g, fx, fy, fz, eu, ew, np);
             }
-            // rare: pairs within the guard band of the cutoff
-            while (amb) {
-                int u = __builtin_ctz(amb);
-                amb &= amb - 1;
-                uint32_t word = u < 2 ? cur.x : (u < 4 ? cur.y : (u < 6 ? cur.z : cur.w));
-                int p = (word >> ((u & 1) * 16)) & 0xffff;
-                pair_exact<NT, ISO, ENERGY>(pi, win[p].get(), i, window_global(w, p), t, g, pos, n, fx, fy, fz, eu,
-                                            ew, np);
+            if (amb) {
+                for (int u = 0; u < valid; u++) {
+                    int p = pp[u];
+                    int4 pj = win[p].get();
+                    float dx, dy, dz;
+                    staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+                    float r2 = dx * dx + dy * dy + dz * dz;
+                    int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
+                    if (r2 >= t.pick(t.lo, ab) && r2 < t.pick(t.hi, ab))
+                        vl_exact<NT, ISO, ENERGY>(pi, pj, i, window_global(w, p), t, g, pos, n, fx, fy, fz, eu, ew,
+                                                  np);
+                }
             }
             cur = nxt;
+        }
+        if (NT == 1) {
+            float e24 = t.eps24[0];
+            fx *= e24;
+            fy *= e24;
+            fz *= e24;
         }
         F[i] = fx;
         F[N + i] = fy;
@@ -1108,9 +1182,10 @@ void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *b
         k_colsum<true><<<(ncol + 255) / 256, 256, 0, s>>>(g, cs, colsum);
     else
         k_colsum<false><<<(ncol + 255) / 256, 256, 0, s>>>(g, cs, colsum);
-    k_blk_count<<<nb, 64, 0, s>>>(g, cs, colsum, band_n, wmax);
+    size_t lds = 3 * (size_t)g.nc[0] * sizeof(int);  // <= 48 KB (nc[0] <= kPackMaxX)
+    k_blk_count<<<nb, 64, lds, s>>>(g, cs, colsum, band_n, wmax);
     launch_scan(band_n, band_base, nb, scan_scratch, s);
-    k_blk_write<<<nb, 64, 0, s>>>(g, cs, colsum, band_base, blocks, cap, flags, wmax);
+    k_blk_write<<<nb, 64, lds, s>>>(g, cs, colsum, band_base, blocks, cap, flags, wmax);
 }
 
 // maxn is rounded up to whole chunks of eight (the list holds them).
