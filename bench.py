@@ -34,8 +34,8 @@ PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no 
 # bytes the copy moves: factor 2.0; WRITE_SIZE reads them exactly: 1.0).
 # Valid only for the kernel sources they were taken on (sha256 prefix of
 # window.hip, pair.h, md_internal.h); otherwise traffic is reported as null.
-VL_TRAFFIC = {"kernel": "k_vlw_f32", "sources_sha256": "fefb0cfa1d40853c",
-              "fetch_kib": 108114.1, "write_kib": 12318.5, "fetch_factor": 2.0, "write_factor": 1.0}
+VL_TRAFFIC = {"kernel": "k_vlw_f32", "sources_sha256": "5c554c98554148f6",
+              "fetch_kib": 107809.1, "write_kib": 12379.5, "fetch_factor": 2.0, "write_factor": 1.0}
 
 
 def force_sources_sha():
@@ -155,15 +155,15 @@ def run(M, d, kind, steps, warmup, probe_steps=50):
     return res
 
 
-def force_kernel_name(c):
-    """Name of the force kernel a configuration runs (FP32; the windowed
-    kernels serve cell grids with a reach of one cell)."""
-    if c["container"] == 2:
+def force_kernel_name(c, family):
+    """Name of the FP32 force kernel a configuration runs; family is the
+    library's report (0 one cell row per thread, 1 LDS cell windows, 2
+    cluster pairs)."""
+    if family == 2:
         return "k_cl_f32"
-    windowed = c["csf"] >= 1.0
     if c["container"] == 1:
-        return ("k_vlwh_f32" if c["newton3"] else "k_vlw_f32") if windowed else "k_vl_f32"
-    return ("k_lcwh_f32" if c["newton3"] else "k_lcw_f32") if windowed else "k_lc_f32"
+        return ("k_vlwh_f32" if c["newton3"] else "k_vlw_f32") if family == 1 else "k_vl_f32"
+    return ("k_lcwh_f32" if c["newton3"] else "k_lcw_f32") if family == 1 else "k_lc_f32"
 
 
 def cpu_baseline(d, target_s=10.0, brute_s=2.0):
@@ -271,7 +271,7 @@ def main():
                                                              extra[kind]["pairs_per_s"],
                                                              extra[kind]["force_kernel_ms"]))
     achieved = FLOPS_PER_PAIR * auto["pairs_per_step"] / (auto["force_kernel_ms"] * 1e-3)
-    kname = force_kernel_name(auto["final_config"])
+    kname = force_kernel_name(auto["final_config"], auto["counters"]["force_family"])
     traffic = measured_traffic(kname)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32, "traffic": traffic, "kernel": kname,

@@ -191,9 +191,13 @@ int md_status(md_handle *h, uint32_t *flags);
 /* Configuration the handle currently uses (after tuning decisions). */
 int md_get_config(md_handle *h, md_config *cfg);
 
-/* Counters since md_create: out (HOST int64[6]) = { rebuilds,
+/* Counters since md_create: out (HOST int64[7]) = { rebuilds,
  * forced_rebuilds (skin exceeded), tuning_phases, trials, current config
- * index in the tuning space, neighbour-list entries at the last build }. */
+ * index in the tuning space, entries of the current neighbour lists
+ * (particle entries of Verlet lists, cluster-pair entries of cluster lists,
+ * 0 for linked cells; reading them waits for the device), force-kernel family of the current configuration (0 one cell row per
+ * thread, 1 LDS cell windows, 2 cluster pairs; valid after the first
+ * step) }. */
 int md_get_counters(md_handle *h, int64_t *out);
 
 /* Kernel-class timing of md_step with HIP events recorded on the caller's

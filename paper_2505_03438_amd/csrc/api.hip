@@ -1114,15 +1114,44 @@ extern "C" int md_get_config(md_handle *h, md_config *cfg)
     return MD_OK;
 }
 
+// Entries of the current neighbour lists: particle entries (Verlet lists)
+// or cluster-pair entries (cluster lists); 0 for linked cells.  Waits for
+// the device.
+static int list_entries(md_handle *h, int64_t *entries)
+{
+    *entries = 0;
+    const Buffers &b = h->b;
+    if (!h->built || !has_lists(h->cfg)) return MD_OK;
+    int32_t m = (int32_t)h->n;
+    const int32_t *cnt = b.nbr_count;
+    if (h->cfg.container == MD_CONTAINER_CL) {
+        if (!b.cl_base || !b.cl_nbr_count) return MD_OK;
+        MD_HIP(hipDeviceSynchronize());
+        MD_HIP(hipMemcpy(&m, b.cl_base + h->g.ncell, sizeof(int32_t), hipMemcpyDeviceToHost));
+        cnt = b.cl_nbr_count;
+    }
+    if (!cnt || m <= 0) return MD_OK;
+    std::vector<int32_t> host((size_t)m);
+    MD_HIP(hipDeviceSynchronize());
+    MD_HIP(hipMemcpy(host.data(), cnt, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost));
+    int64_t sum = 0;
+    for (int32_t c : host) sum += c;
+    *entries = sum;
+    return MD_OK;
+}
+
 extern "C" int md_get_counters(md_handle *h, int64_t *out)
 {
     if (!h || !out) return fail(MD_ERR_INVALID_ARG, "NULL argument");
+    int rc = list_entries(h, &h->list_entries);
+    if (rc) return rc;
     out[0] = h->rebuilds;
     out[1] = h->forced;
     out[2] = h->phases;
     out[3] = h->trials;
     out[4] = h->config_index;
     out[5] = h->list_entries;
+    out[6] = h->cfg.container == MD_CONTAINER_CL ? 2 : use_window(h->cfg, h->g) ? 1 : 0;
     return MD_OK;
 }
 

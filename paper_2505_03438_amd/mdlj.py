@@ -257,9 +257,10 @@ def md_get_config(h: Handle) -> md_config:
 
 
 def md_get_counters(h: Handle):
-    out = (ctypes.c_int64 * 6)()
+    out = (ctypes.c_int64 * 7)()
     _check(lib().md_get_counters(h.ptr, out), "md_get_counters")
-    keys = ("rebuilds", "forced_rebuilds", "tuning_phases", "trials", "config_index", "list_entries")
+    keys = ("rebuilds", "forced_rebuilds", "tuning_phases", "trials", "config_index", "list_entries",
+            "force_family")
     return dict(zip(keys, list(out)))
 
 

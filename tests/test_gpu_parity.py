@@ -203,6 +203,9 @@ def test_verlet_sets_bit_exact(orc, half, prec, csf):
     ids = s.ids_np()
     rl2 = (2.5 + 0.3) ** 2
     ref = orc.neighbor_rows(pos, box, rl2, np.arange(n))
+    cnt = M.md_get_counters(s.h)
+    assert cnt["list_entries"] == int(counts.sum())
+    assert cnt["force_family"] in ((0,) if prec == 1 else (0, 1))  # FP64 has no windowed kernels
     if not half:
         for k in range(n):
             got = np.sort(ids[rows[k, :counts[k]]])
@@ -274,6 +277,10 @@ def test_cluster_lists_cover_verlet_pairs(orc, csf):
     counts, rows = M.md_get_neighbors(s.h, 1024)
     counts, rows = counts.cpu().numpy(), rows.cpu().numpy()
     assert counts.max() <= 1024
+    cnt = M.md_get_counters(s.h)
+    assert cnt["force_family"] == 2
+    ncl_min = -(-n // 8)  # at least this many clusters of at most 8
+    assert ncl_min <= cnt["list_entries"] and cnt["list_entries"] * 8 >= int(counts.sum()) // 8
     ids = s.ids_np()
     ref = orc.neighbor_rows(pos, box, (2.5 + 0.3) ** 2, np.arange(n))
     for k in range(n):
