@@ -137,7 +137,9 @@ int md_build_neighbors(md_handle *h, const double *pos, const int32_t *type,
  * f_ij = 24 eps q (2q - 1) / r^2 * d_ij, q = (sig^2/r^2)^3, with the current
  * container.  pos/type in cell order; force written in the same order.
  * If out (DEVICE double[4]) is not NULL it receives
- * { U = sum_{i<j} 4 eps q (q - 1), W = sum_{i<j} r . f, n_pairs, 0 }. */
+ * { U = sum_{i<j} 4 eps q (q - 1), W = sum_{i<j} r . f, n_pairs, 0 }.
+ * MD_ERR_NOT_BUILT if no md_build_cells came first, or (Verlet and cluster
+ * lists) no md_build_neighbors after the last md_build_cells. */
 int md_compute_forces(md_handle *h, const double *pos, const int32_t *type,
                       const double *lj, void *force, double *out, void *stream);
 

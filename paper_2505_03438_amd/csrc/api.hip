@@ -106,6 +106,7 @@ struct md_handle {
     int64_t ncell_cap = 0;   // allocated cell-array entries
     int64_t scan_cap = 0;
     bool built = false;      // cells (and lists) valid for the staged positions
+    bool lists = false;      // neighbour lists built since the last cell build
     int age = 0;             // integrator steps since the last build
     int64_t rebuilds = 0, forced = 0, phases = 0, trials = 0, list_entries = 0;
     int32_t config_index = -1;
@@ -144,7 +145,7 @@ static void free_buffers(md_handle *h)
                     b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
                     b.cl_nbr_count, b.snap_pos, b.snap_vel,
                     b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart,
-                    b.w_blk, b.w_rown, b.w_rowb, b.w_nbr};
+                    b.w_blk, b.w_perm, b.w_rown, b.w_rowb, b.w_nbr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (b.host_flags) (void)hipHostFree(b.host_flags);
@@ -394,6 +395,7 @@ static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, i
     h->rebuilds++;
     h->age = 0;
     h->built = true;
+    h->lists = false;
     if (use_window(h->cfg, h->g)) return build_blocks(h, s);
     return MD_OK;
 }
@@ -449,8 +451,11 @@ static int ensure_window(md_handle *h, int64_t maxn)
     int64_t cap = window_block_cap(h->n, h->g);
     if (cap > b.w_cap) {
         if (b.w_blk) (void)hipFree(b.w_blk);
+        if (b.w_perm) (void)hipFree(b.w_perm);
         b.w_blk = nullptr;
-        if ((rc = dalloc(&b.w_blk, cap))) return rc;
+        b.w_perm = nullptr;
+        b.w_cap = 0;
+        if ((rc = dalloc(&b.w_blk, cap)) || (rc = dalloc(&b.w_perm, (size_t)cap * 256))) return rc;
         b.w_cap = cap;
     }
     int64_t rows = (int64_t)h->g.nc[1] * h->g.nc[2] + 1;
@@ -495,7 +500,8 @@ static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
         const Geom &g = h->g;
         launch_fill_i32(b.flags + 2, 0, 1, s);
         launch_vlw_build(b.stage, b.cell_start, b.cell_sorted, pos, g, n, b.w_rowb + window_nbands(g), b.w_blk,
-                         b.w_nbr, b.nbr_count, h->cfg.max_neighbors, b.flags, h->cfg.newton3 == MD_N3L_ON, s);
+                         b.w_nbr, b.nbr_count, b.w_perm, h->cfg.max_neighbors, b.flags, h->cfg.newton3 == MD_N3L_ON,
+                         s);
     } else if (h->cfg.container == MD_CONTAINER_VL) {
         int rc = ensure_list(h, h->cfg.max_neighbors);
         if (rc) return rc;
@@ -511,6 +517,7 @@ static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
                              b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_nbr, b.cl_nbr_count, b.cl_cap,
                              h->cfg.max_neighbors, b.flags, s);
     }
+    h->lists = true;
     return MD_OK;
 }
 
@@ -575,6 +582,7 @@ static ForceArgs force_args(md_handle *h, const double *pos, const int32_t *type
     if (a.window) {
         a.w_nblk = h->b.w_rowb + window_nbands(h->g);
         a.w_blk = h->b.w_blk;
+        a.w_perm = h->b.w_perm;
         a.w_nbr = h->b.w_nbr;
     }
     return a;
@@ -599,6 +607,8 @@ extern "C" int md_compute_forces(md_handle *h, const double *pos, const int32_t 
     if ((rc = check_particles(h, pos, type))) return rc;
     if (!lj || (h->n > 0 && !force)) return fail(MD_ERR_INVALID_ARG, "lj and force must not be NULL");
     if (!h->built) return fail(MD_ERR_NOT_BUILT, "md_build_cells (and md_build_neighbors) must be called first");
+    if (has_lists(h->cfg) && !h->lists)
+        return fail(MD_ERR_NOT_BUILT, "md_build_neighbors must be called after md_build_cells");
     hipStream_t s = (hipStream_t)stream;
     launch_prepare_tab(lj, h->cfg.rc2, h->g, h->b.tab, s);
     launch_stage((int)h->n, pos, type, h->g, h->b.stage, s);
@@ -1072,7 +1082,7 @@ extern "C" int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows, in
     int rc = check_handle(h);
     if (rc) return rc;
     if (h->cfg.container == MD_CONTAINER_LC) return fail(MD_ERR_INVALID_ARG, "linked cells keep no lists");
-    if (!h->built) return fail(MD_ERR_NOT_BUILT, "lists not built");
+    if (!h->built || !h->lists) return fail(MD_ERR_NOT_BUILT, "lists not built");
     if (max_per_row < 1 || (h->n > 0 && (!counts || !rows))) return fail(MD_ERR_INVALID_ARG, "bad arguments");
     int n = (int)h->n;
     if (h->cfg.container == MD_CONTAINER_CL) {
@@ -1121,7 +1131,7 @@ static int list_entries(md_handle *h, int64_t *entries)
 {
     *entries = 0;
     const Buffers &b = h->b;
-    if (!h->built || !has_lists(h->cfg)) return MD_OK;
+    if (!h->built || !h->lists || !has_lists(h->cfg)) return MD_OK;
     int32_t m = (int32_t)h->n;
     const int32_t *cnt = b.nbr_count;
     if (h->cfg.container == MD_CONTAINER_CL) {

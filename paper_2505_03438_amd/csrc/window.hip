@@ -294,12 +294,12 @@ struct BlockIter {
     }
 };
 
-// The particle of this thread in the block: its index i, block row k and
-// cell column x; false if the thread has none.
+// Particle t of the block (default: this thread's): its index i, block row
+// k and cell column x; false if the block has no particle t.
 __device__ __forceinline__ bool my_particle(const Geom &g, const Window &w, const int32_t *__restrict__ cell_sorted,
-                                            int &i, int &k, int &x)
+                                            int &i, int &k, int &x, int t = -1)
 {
-    int t = threadIdx.x;
+    if (t < 0) t = threadIdx.x;
     if (t >= w.npart) return false;
     k = 0;
     while (k + 1 < w.nyb && w.bpref[k + 1] <= t) k++;
@@ -692,76 +692,140 @@ __device__ __forceinline__ void list_finish(int c, Chunk &ck, uint4 *__restrict_
     row[(size_t)(c >> 3) * N] = ck.word();
 }
 
-// Verlet-list candidate test: true if r2 < (r_c + skin)^2 outside the guard
-// band; amb if inside the band (decided by the caller in FP64).
+// Guard band of the list radius as centre and half width, the half width
+// widened so that every r2 in [rl2_lo, rl2_hi) passes |r2 - mid| <= hw: the
+// band is 2^-18 of rl2 wide, the rounding of mid moves it by at most 2^-24
+// of rl2 (3 % of the half width), and r2 - mid is exact near the band.
+struct Band {
+    float mid, hw;
+    __device__ __forceinline__ explicit Band(const Geom &g)
+        : mid(0.5f * (g.rl2_lo + g.rl2_hi)), hw(0.5f * (g.rl2_hi - g.rl2_lo) * 1.125f)
+    {
+    }
+};
+
+// One batch of Verlet-list candidates: window positions q[0 .. m-1], m <= 32,
+// tested against the list radius in FP32.  Returns the mask of those with
+// r2 below the upper edge of the guard band (candidate u at bit m - 1 - u:
+// each test shifts the mask up and adds its outcome); amb is set if one of
+// them may lie inside the band (the nearest r2 to its centre is within the
+// widened half width; the caller then decides those from the FP64
+// positions).  Reads whole groups of four, up to three positions past the
+// batch (the window arrays are padded for them); their bits are dropped.
 template <bool ISO>
-__device__ __forceinline__ bool build_fast(const int4 &pi, const int4 &pj, bool valid, const Geom &g, bool &amb)
+__device__ __forceinline__ uint32_t build_batch(const int4 &pi, const WinEntry<1> *__restrict__ q, int m,
+                                                const Geom &g, const Band &band, bool &amb)
 {
-    float dx, dy, dz;
-    staged_delta<ISO>(pi, pj, g, dx, dy, dz);
-    float r2 = dx * dx + dy * dy + dz * dz;
-    amb = valid && r2 >= g.rl2_lo && r2 < g.rl2_hi;
-    return valid && r2 < g.rl2_lo;
+    uint32_t mask = 0;
+    float near = 3.0e38f;
+    int nb = 0;
+    auto test = [&](const WinEntry<1> &e) {
+        float dx, dy, dz;
+        staged_delta<ISO>(pi, e.get(), g, dx, dy, dz);
+        float r2 = dx * dx + dy * dy + dz * dz;
+        mask = mask + mask + (r2 < g.rl2_hi ? 1u : 0u);
+        near = fminf(near, fabsf(r2 - band.mid));
+    };
+    for (; nb < m; nb += 4) {
+        test(q[nb]);
+        test(q[nb + 1]);
+        test(q[nb + 2]);
+        test(q[nb + 3]);
+    }
+    // the candidates read past the batch may raise amb: a harmless slow path
+    amb = near <= band.hw;
+    return mask >> (nb - m);
+}
+
+// Order of the block's particles by chunk count, longest list first (counts
+// of kRankBins - 1 chunks and more share the last bin): slot r of perm gets
+// the block index of the particle of rank r.  The force kernel deals the
+// slots to its threads in order, so each wavefront walks lists of similar
+// length and waits less for its longest one.  Called by every thread.
+constexpr int kRankBins = 64;
+
+__device__ __forceinline__ void rank_by_chunks(bool mine, int c, int npart, int *bins, int *from,
+                                               uint8_t *__restrict__ perm)
+{
+    int key = min((c + 7) >> 3, kRankBins - 1);
+    for (int b = threadIdx.x; b < kRankBins; b += blockDim.x) bins[b] = 0;
+    __syncthreads();
+    int at = mine ? atomicAdd(&bins[key], 1) : 0;
+    __syncthreads();
+    // from[b]: particles in the bins above b (the longer lists)
+    for (int b = threadIdx.x; b < kRankBins; b += blockDim.x) {
+        int sum = 0;
+        for (int u = b + 1; u < kRankBins; u++) sum += bins[u];
+        from[b] = sum;
+    }
+    __syncthreads();
+    if (mine && threadIdx.x < npart) perm[from[key] + at] = (uint8_t)threadIdx.x;
 }
 
 // Verlet lists (full windows: every pair within r_c + skin from both sides;
 // half windows: each pair once, in the forward half of the stencil).  Each
-// range of candidates is tested 32 positions at a time into a bit mask (four
-// LDS reads in flight), then the set bits are appended.
+// range of candidates is tested 32 positions at a time into a bit mask, then
+// the set bits are appended in window order.
 template <bool ISO, bool HALF>
 __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                    const int32_t *__restrict__ cell_sorted,
                                                    const double *__restrict__ pos, Geom g, int n,
                                                    const int32_t *__restrict__ nblk_p, int cap,
                                                    const int4 *__restrict__ blocks,
-                                                   uint16_t *__restrict__ nbr, int32_t *__restrict__ cnt, int maxn,
-                                                   int32_t *__restrict__ flags)
+                                                   uint16_t *__restrict__ nbr, int32_t *__restrict__ cnt,
+                                                   uint8_t *__restrict__ perm, int maxn, int32_t *__restrict__ flags)
 {
-    __shared__ WinEntry<1> win[HALF ? kWinMaxHalf : kWinMax];
+    __shared__ WinEntry<1> win[(HALF ? kWinMaxHalf : kWinMax) + 4];  // + the reads past a batch
     __shared__ Window w;
+    __shared__ int bins[kRankBins], from[kRankBins];
     size_t N = (size_t)n;
     int cmax = 0;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
         if (!setup_block<1, HALF>(g, cs, st, blocks[blk], w, win, flags)) continue;
         int i, k, x;
-        if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
-        int self = self_position<HALF>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
-        int4 pi = win[self].get();
-        uint4 *row = (uint4 *)nbr + i;
+        bool mine = my_particle(g, w, cell_sorted, i, k, x);
         int c = 0;
-        Chunk ck;
-        stencil_ranges<HALF>(g, w, k, x, self, [&](int b, int en) {
-            for (int base = b; base < en; base += 32) {
-                int e32 = min(en, base + 32);
-                uint32_t mask = 0;
-                for (int p0 = base; p0 < e32; p0 += 4) {
-                    int p1 = min(p0 + 1, e32 - 1), p2 = min(p0 + 2, e32 - 1), p3 = min(p0 + 3, e32 - 1);
-                    int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
-                    bool a0, a1, a2, a3;
-                    bool i0 = build_fast<ISO>(pi, q0, p0 != self, g, a0);
-                    bool i1 = build_fast<ISO>(pi, q1, p0 + 1 < e32 && p1 != self, g, a1);
-                    bool i2 = build_fast<ISO>(pi, q2, p0 + 2 < e32 && p2 != self, g, a2);
-                    bool i3 = build_fast<ISO>(pi, q3, p0 + 3 < e32 && p3 != self, g, a3);
-                    // rare: guard-band pairs decided from the FP64 positions
-                    if (a0) i0 = exact_r2(pos, n, i, window_global(w, p0), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                    if (a1) i1 = exact_r2(pos, n, i, window_global(w, p1), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                    if (a2) i2 = exact_r2(pos, n, i, window_global(w, p2), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                    if (a3) i3 = exact_r2(pos, n, i, window_global(w, p3), g.L[0], g.L[1], g.L[2]) < g.rl2;
-                    uint32_t nib = (i0 ? 1u : 0u) | (i1 ? 2u : 0u) | (i2 ? 4u : 0u) | (i3 ? 8u : 0u);
-                    mask |= nib << (p0 - base);
+        if (mine) {
+            int self = self_position<HALF>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
+            int4 pi = win[self].get();
+            uint4 *row = (uint4 *)nbr + i;
+            Chunk ck;
+            const Band band(g);
+            stencil_ranges<HALF>(g, w, k, x, self, [&](int b, int en) {
+                for (int base = b; base < en; base += 32) {
+                    int m = min(32, en - base);
+                    bool amb;
+                    uint32_t mask = build_batch<ISO>(pi, win + base, m, g, band, amb);
+                    unsigned us = (unsigned)(self - base);
+                    if (us < (unsigned)m) mask &= ~(1u << (m - 1 - us));
+                    if (amb) {
+                        // rare: guard-band candidates decided from the FP64 positions
+                        for (uint32_t t = mask; t;) {
+                            int h = 31 - __builtin_clz(t);
+                            t ^= 1u << h;
+                            int p = base + m - 1 - h;
+                            float dx, dy, dz;
+                            staged_delta<ISO>(pi, win[p].get(), g, dx, dy, dz);
+                            float r2 = dx * dx + dy * dy + dz * dz;
+                            if (r2 >= g.rl2_lo &&
+                                !(exact_r2(pos, n, i, window_global(w, p), g.L[0], g.L[1], g.L[2]) < g.rl2))
+                                mask ^= 1u << h;
+                        }
+                    }
+                    while (mask) {
+                        int h = 31 - __builtin_clz(mask);
+                        mask ^= 1u << h;
+                        list_append((uint32_t)(base + m - 1 - h), c, ck, row, N, maxn);
+                    }
                 }
-                while (mask) {
-                    int u = __builtin_ctz(mask);
-                    mask &= mask - 1;
-                    list_append((uint32_t)(base + u), c, ck, row, N, maxn);
-                }
-            }
-        });
-        list_finish(c, ck, row, N, maxn);
-        if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
-        cmax = max(cmax, c);
-        cnt[i] = c < maxn ? c : maxn;
+            });
+            list_finish(c, ck, row, N, maxn);
+            if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
+            cmax = max(cmax, c);
+            cnt[i] = c < maxn ? c : maxn;
+        }
+        if (!HALF) rank_by_chunks(mine, min(c, maxn), w.npart, bins, from, perm + (size_t)blk * 256);
     }
     if (cmax > 0) atomicMax(&flags[2], cmax);
 }
@@ -835,9 +899,9 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
                                                  const int32_t *__restrict__ nblk_p, int cap,
                                                  const int4 *__restrict__ blocks,
                                                  const uint16_t *__restrict__ nbr, const int32_t *__restrict__ cnt,
-                                                 const PairTab *__restrict__ tabp, const double *__restrict__ pos,
-                                                 float *__restrict__ F, double *__restrict__ partials,
-                                                 int32_t *__restrict__ flags)
+                                                 const uint8_t *__restrict__ perm, const PairTab *__restrict__ tabp,
+                                                 const double *__restrict__ pos, float *__restrict__ F,
+                                                 double *__restrict__ partials, int32_t *__restrict__ flags)
 {
     __shared__ WinEntry<NT> win[kWinMax];
     __shared__ Window w;
@@ -851,8 +915,10 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
         int blk = it.blk;
         // the list holds window positions: only the window's pieces are needed
         if (!setup_block<NT, false, false>(g, cs, st, blocks[blk], w, win, flags)) continue;
+        if ((int)threadIdx.x >= w.npart) continue;
+        // the particles in order of list length (ranked by the list build)
         int i, k, x;
-        if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
+        if (!my_particle(g, w, cell_sorted, i, k, x, perm[(size_t)blk * 256 + threadIdx.x])) continue;
         int4 pi = st[i];
         int c = cnt[i];
         int nch = (c + 7) >> 3;
@@ -1188,10 +1254,12 @@ void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *b
     k_blk_write<<<nb, 64, lds, s>>>(g, cs, colsum, band_base, blocks, cap, flags, wmax);
 }
 
-// maxn is rounded up to whole chunks of eight (the list holds them).
+// maxn is rounded up to whole chunks of eight (the list holds them).  perm
+// (256 slots per block) receives the order of the full lists' particles by
+// length.
 void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
-                      const Geom &g, int n, const int32_t *nblk_p, const int4 *blocks,
-                      uint16_t *nbr, int32_t *cnt, int maxn, int32_t *flags, bool half, hipStream_t s)
+                      const Geom &g, int n, const int32_t *nblk_p, const int4 *blocks, uint16_t *nbr, int32_t *cnt,
+                      uint8_t *perm, int maxn, int32_t *flags, bool half, hipStream_t s)
 {
     if (n <= 0) return;
     int cap = (int)window_block_cap(n, g);
@@ -1199,17 +1267,17 @@ void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sor
     if (half) {
         if (g.iso)
             k_vlw_build<true, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                              nbr, cnt, maxn, flags);
+                                                              nbr, cnt, perm, maxn, flags);
         else
             k_vlw_build<false, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                               nbr, cnt, maxn, flags);
+                                                               nbr, cnt, perm, maxn, flags);
     } else {
         if (g.iso)
             k_vlw_build<true, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                               nbr, cnt, maxn, flags);
+                                                               nbr, cnt, perm, maxn, flags);
         else
             k_vlw_build<false, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                                nbr, cnt, maxn, flags);
+                                                                nbr, cnt, perm, maxn, flags);
     }
 }
 
@@ -1231,7 +1299,7 @@ static void win_launch(const ForceArgs &a, const Geom &g, hipStream_t s)
                                                             a.flags);
     } else if (vl) {
         k_vlw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
-                                                       a.w_blk, a.w_nbr, a.nbr_count, a.tab, a.pos,
+                                                       a.w_blk, a.w_nbr, a.nbr_count, a.w_perm, a.tab, a.pos,
                                                        (float *)a.force, a.partials, a.flags);
     } else {
         k_lcw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,

@@ -183,6 +183,24 @@ def test_tiny_and_empty_systems(orc):
     assert list(out) == [0.0, 0.0, 0.0, 0.0]
 
 
+def test_forces_need_lists_after_cell_build(orc):
+    """A cell build reorders the particles: list containers refuse to compute
+    forces until the lists are built again (no stale or unbuilt lists)."""
+    pos, box = _jittered(6, 8, jitter=0.1)
+    n = pos.shape[1]
+    for cont in (1, 2):
+        cfg = make_config(n, box, container=cont, precision=0)
+        s = DeviceSystem(cfg, pos)
+        M.md_build_cells(s.h, s.pos, s.vel, s.force, s.type, s.ids)
+        with pytest.raises(RuntimeError, match="md_build_neighbors"):
+            s.forces()
+        M.md_build_neighbors(s.h, s.pos, s.type)
+        s.forces()
+        M.md_build_cells(s.h, s.pos, s.vel, s.force, s.type, s.ids)
+        with pytest.raises(RuntimeError, match="md_build_neighbors"):
+            s.forces()
+
+
 # ---------------------------------------------------------------- Verlet sets
 
 @pytest.mark.parametrize("csf", [1.0, 0.5])
