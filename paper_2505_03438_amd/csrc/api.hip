@@ -470,7 +470,9 @@ static int ensure_window(md_handle *h, int64_t maxn)
     if (h->cfg.container == MD_CONTAINER_VL && (maxn > b.w_nbr_cap || !b.w_nbr)) {
         if (b.w_nbr) (void)hipFree(b.w_nbr);
         b.w_nbr = nullptr;
-        int64_t rows8 = (maxn + 7) / 8 * 8;  // entries are stored in chunks of eight
+        // entries are stored in chunks of eight, plus one chunk row that the
+        // force kernels' prefetch may read past a full list
+        int64_t rows8 = (maxn + 7) / 8 * 8 + 8;
         if ((rc = dalloc(&b.w_nbr, (size_t)rows8 * (size_t)std::max<int64_t>(h->n, 1)))) return rc;
         b.w_nbr_cap = maxn;
     }

@@ -503,9 +503,22 @@ __global__ void k_blk_write(const Geom g, const int32_t *__restrict__ cs, const 
     pack_band(blockIdx.x, g, cs, colsum, band_base[blockIdx.x], blocks, true, cap, flags, wmax, scol, snum, sst);
 }
 
+// A staged position at least r_c + skin from every particle of the block
+// (blk: its descriptor): half the box away in z from the centre of the
+// block's z layer of cells.  The particles of the block lie within half a
+// cell of that centre, and a box holds at least three cells per dimension,
+// so every one of them is at least a cell side (>= r_c + skin) from it.
+__device__ __forceinline__ int4 far_entry(const Geom &g, int4 blk)
+{
+    int zc = blk.x / (g.nc[0] * g.nc[1]);
+    uint32_t centre = (uint32_t)((((uint64_t)(2 * zc + 1)) << 31) / (uint64_t)g.nc[2]);
+    return make_int4(0, 0, (int)(centre + 0x80000000u), 0);
+}
+
 // Common head of the windowed kernels: lay out and stage the window of a
-// block; false (uniformly) if it does not fit the tile.
-template <int NT, bool HALF = false, bool COLS = true>
+// block; false (uniformly) if it does not fit the tile.  FAR: also stage
+// far_entry at position kWinMax (the padding of the full Verlet lists).
+template <int NT, bool HALF = false, bool COLS = true, bool FAR = false>
 __device__ __forceinline__ bool setup_block(const Geom &g, const int32_t *__restrict__ cs, const int4 *__restrict__ st,
                                             int4 blk, Window &w, WinEntry<NT> *win, int32_t *flags)
 {
@@ -516,6 +529,7 @@ __device__ __forceinline__ bool setup_block(const Geom &g, const int32_t *__rest
         return false;
     }
     load_window(w, st, win);
+    if (FAR && threadIdx.x == 0) win[kWinMax].set(far_entry(g, blk));
     __syncthreads();
     return true;
 }
@@ -684,11 +698,13 @@ __device__ __forceinline__ void list_append(uint32_t p, int &c, Chunk &ck, uint4
     if ((c & 7) == 0 && c <= maxn) row[(size_t)((c >> 3) - 1) * N] = ck.word();
 }
 
-// Write the last, partial chunk (its entries shifted down to the bottom).
-__device__ __forceinline__ void list_finish(int c, Chunk &ck, uint4 *__restrict__ row, size_t N, int maxn)
+// Write the last, partial chunk (its entries shifted down to the bottom,
+// the rest filled with pad).
+__device__ __forceinline__ void list_finish(int c, Chunk &ck, uint4 *__restrict__ row, size_t N, int maxn,
+                                            uint32_t pad)
 {
     if ((c & 7) == 0 || c >= maxn) return;
-    for (int e = c & 7; e < 8; e++) ck.push(0u);
+    for (int e = c & 7; e < 8; e++) ck.push(pad);
     row[(size_t)(c >> 3) * N] = ck.word();
 }
 
@@ -765,7 +781,10 @@ __device__ __forceinline__ void rank_by_chunks(bool mine, int c, int npart, int 
 // Verlet lists (full windows: every pair within r_c + skin from both sides;
 // half windows: each pair once, in the forward half of the stencil).  Each
 // range of candidates is tested 32 positions at a time into a bit mask, then
-// the set bits are appended in window order.
+// the set bits are appended in window order.  Full lists hold LDS byte
+// offsets (window position times esz, the size of the force kernel's window
+// entry) and pad their last chunk with the offset of the far entry; half
+// lists hold window positions (esz 1) padded with 0.
 template <bool ISO, bool HALF>
 __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                    const int32_t *__restrict__ cell_sorted,
@@ -773,7 +792,8 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
                                                    const int32_t *__restrict__ nblk_p, int cap,
                                                    const int4 *__restrict__ blocks,
                                                    uint16_t *__restrict__ nbr, int32_t *__restrict__ cnt,
-                                                   uint8_t *__restrict__ perm, int maxn, int32_t *__restrict__ flags)
+                                                   uint8_t *__restrict__ perm, int maxn, int esz,
+                                                   int32_t *__restrict__ flags)
 {
     __shared__ WinEntry<1> win[(HALF ? kWinMaxHalf : kWinMax) + 4];  // + the reads past a batch
     __shared__ Window w;
@@ -816,11 +836,11 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
                     while (mask) {
                         int h = 31 - __builtin_clz(mask);
                         mask ^= 1u << h;
-                        list_append((uint32_t)(base + m - 1 - h), c, ck, row, N, maxn);
+                        list_append((uint32_t)((base + m - 1 - h) * esz), c, ck, row, N, maxn);
                     }
                 }
             });
-            list_finish(c, ck, row, N, maxn);
+            list_finish(c, ck, row, N, maxn, HALF ? 0u : (uint32_t)(kWinMax * esz));
             if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
             cmax = max(cmax, c);
             cnt[i] = c < maxn ? c : maxn;
@@ -890,9 +910,44 @@ __device__ __forceinline__ void vl_exact(const int4 &pi, const int4 &pj, int i, 
     }
 }
 
-// Each thread walks its list in chunks of eight entries; the next chunk's
-// load is in flight while the current one is computed.  A chunk with an
-// entry in the guard band (rare) is walked again for those entries.
+// One list entry of the gather force, branch free: the window entry at LDS
+// byte offset off.  With one type the guard band is tracked through near,
+// the smallest |r2 - centre| seen; otherwise through amb.
+template <int NT, bool ISO, bool ENERGY>
+__device__ __forceinline__ void vl_step(const int4 &pi, const WinEntry<NT> *__restrict__ win, uint32_t off,
+                                        const TabF<NT> &t, const Geom &g, float mid, float &near, bool &amb,
+                                        float &fx, float &fy, float &fz, float &eu, float &ew, int &np)
+{
+    const WinEntry<NT> &e = *(const WinEntry<NT> *)((const char *)win + off);
+    if (NT == 1) {
+        float dx, dy, dz;
+        staged_delta<ISO>(pi, e.get(), g, dx, dy, dz);
+        float r2 = dx * dx + dy * dy + dz * dz;
+        bool in = r2 < t.lo[0];
+        float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.0f;
+        float s2 = t.sig2[0] * ir2;
+        float q = s2 * s2 * s2;
+        float a = q * (2.0f * q - 1.0f);
+        float phi = ir2 * a;
+        if (ENERGY) {
+            eu += t.eps4[0] * q * (q - 1.0f);
+            ew += t.eps24w[0] * a;
+            np += in ? 1 : 0;
+        }
+        fx += phi * dx;
+        fy += phi * dy;
+        fz += phi * dz;
+        near = fminf(near, fabsf(r2 - mid));
+    } else {
+        amb |= vl_entry<NT, ISO, ENERGY>(pi, e.get(), true, t, g, fx, fy, fz, eu, ew, np);
+    }
+}
+
+// Each thread walks its list in chunks of eight entries (the lists hold LDS
+// byte offsets; the last chunk is padded with the far entry, whose pairs
+// never interact); the next chunk's load is in flight while the current one
+// is computed.  A chunk with an entry that may lie in the guard band (rare)
+// is walked again for those entries.
 template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                  const int32_t *__restrict__ cell_sorted, Geom g, int n,
@@ -903,18 +958,20 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
                                                  const double *__restrict__ pos, float *__restrict__ F,
                                                  double *__restrict__ partials, int32_t *__restrict__ flags)
 {
-    __shared__ WinEntry<NT> win[kWinMax];
+    __shared__ WinEntry<NT> win[kWinMax + 1];  // + the far entry
     __shared__ Window w;
     __shared__ double sh[16];
     TabF<NT> t;
     t.load(tabp);
+    // guard band of the cutoff as centre and widened half width (one type)
+    const float mid = 0.5f * (t.lo[0] + t.hi[0]), hw = 0.5f * (t.hi[0] - t.lo[0]) * 1.125f;
     float eu = 0.f, ew = 0.f;
     int np = 0;
     size_t N = (size_t)n;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
         // the list holds window positions: only the window's pieces are needed
-        if (!setup_block<NT, false, false>(g, cs, st, blocks[blk], w, win, flags)) continue;
+        if (!setup_block<NT, false, false, true>(g, cs, st, blocks[blk], w, win, flags)) continue;
         if ((int)threadIdx.x >= w.npart) continue;
         // the particles in order of list length (ranked by the list build)
         int i, k, x;
@@ -923,24 +980,26 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
         int c = cnt[i];
         int nch = (c + 7) >> 3;
         float fx = 0.f, fy = 0.f, fz = 0.f;
-        // chunk ch of particle i is row[ch * n]; the prefetch index is clamped
-        // so that every load is an in-bounds global load
+        // chunk ch of particle i is row[ch * n]; the list has one chunk row
+        // more than it can fill, so the prefetch past the last chunk is an
+        // in-bounds load
         const uint4 *row = (const uint4 *)nbr + i;
-        uint4 cur = row[0];
+        uint4 cur = *row;
         for (int ch = 0; ch < nch; ch++) {
-            uint4 nxt = row[(size_t)min(ch + 1, nch - 1) * N];
-            int valid = min(8, c - ch * 8);
-            int pp[8] = {(int)(cur.x & 0xffff), (int)(cur.x >> 16), (int)(cur.y & 0xffff), (int)(cur.y >> 16),
-                         (int)(cur.z & 0xffff), (int)(cur.z >> 16), (int)(cur.w & 0xffff), (int)(cur.w >> 16)};
+            row += N;
+            uint4 nxt = *row;
+            uint32_t off[8] = {cur.x & 0xffff, cur.x >> 16, cur.y & 0xffff, cur.y >> 16,
+                               cur.z & 0xffff, cur.z >> 16, cur.w & 0xffff, cur.w >> 16};
+            float near = 3.0e38f;
             bool amb = false;
 #pragma unroll
-            for (int u = 0; u < 8; u++) {
-                int4 pj = win[pp[u]].get();
-                amb |= vl_entry<NT, ISO, ENERGY>(pi, pj, u < valid, t, g, fx, fy, fz, eu, ew, np);
-            }
+            for (int u = 0; u < 8; u++)
+                vl_step<NT, ISO, ENERGY>(pi, win, off[u], t, g, mid, near, amb, fx, fy, fz, eu, ew, np);
+            if (NT == 1) amb = near <= hw;
             if (amb) {
-                for (int u = 0; u < valid; u++) {
-                    int p = pp[u];
+                // the far entries of the padding are never in the band
+                for (int u = 0; u < 8; u++) {
+                    int p = (int)(off[u] / sizeof(WinEntry<NT>));
                     int4 pj = win[p].get();
                     float dx, dy, dz;
                     staged_delta<ISO>(pi, pj, g, dx, dy, dz);
@@ -1205,7 +1264,7 @@ template <bool HALF>
 __global__ void k_vlw_decode(const int32_t *__restrict__ cs, const int32_t *__restrict__ cell_sorted, Geom g, int n,
                              const int32_t *__restrict__ nblk_p, int cap, const int4 *__restrict__ blocks,
                              const uint16_t *__restrict__ nbr,
-                             const int32_t *__restrict__ cnt, int maxr, int32_t *__restrict__ counts,
+                             const int32_t *__restrict__ cnt, int maxr, int esz, int32_t *__restrict__ counts,
                              int32_t *__restrict__ rows)
 {
     __shared__ Window w;
@@ -1218,7 +1277,8 @@ __global__ void k_vlw_decode(const int32_t *__restrict__ cs, const int32_t *__re
         if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
         int c = cnt[i];
         counts[i] = c;
-        for (int e = 0; e < c && e < maxr; e++) rows[(size_t)i * maxr + e] = window_global(w, nbr[list_slot(e, i, N)]);
+        for (int e = 0; e < c && e < maxr; e++)
+            rows[(size_t)i * maxr + e] = window_global(w, (int)nbr[list_slot(e, i, N)] / esz);
     }
 }
 
@@ -1254,6 +1314,10 @@ void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *b
     k_blk_write<<<nb, 64, lds, s>>>(g, cs, colsum, band_base, blocks, cap, flags, wmax);
 }
 
+// Size of the force kernels' LDS window entry (positions, plus the type when
+// there are several).
+static int window_entry_size(const Geom &g) { return g.nt == 1 ? (int)sizeof(WinEntry<1>) : (int)sizeof(WinEntry<2>); }
+
 // maxn is rounded up to whole chunks of eight (the list holds them).  perm
 // (256 slots per block) receives the order of the full lists' particles by
 // length.
@@ -1264,20 +1328,21 @@ void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sor
     if (n <= 0) return;
     int cap = (int)window_block_cap(n, g);
     maxn = (maxn + 7) & ~7;
+    int esz = half ? 1 : window_entry_size(g);
     if (half) {
         if (g.iso)
             k_vlw_build<true, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                              nbr, cnt, perm, maxn, flags);
+                                                              nbr, cnt, perm, maxn, esz, flags);
         else
             k_vlw_build<false, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                               nbr, cnt, perm, maxn, flags);
+                                                               nbr, cnt, perm, maxn, esz, flags);
     } else {
         if (g.iso)
             k_vlw_build<true, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                               nbr, cnt, perm, maxn, flags);
+                                                               nbr, cnt, perm, maxn, esz, flags);
         else
             k_vlw_build<false, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                                nbr, cnt, perm, maxn, flags);
+                                                                nbr, cnt, perm, maxn, esz, flags);
     }
 }
 
@@ -1338,10 +1403,10 @@ void launch_vlw_decode(const int32_t *cs, const int32_t *cell_sorted, const Geom
     int cap = (int)window_block_cap(n, g);
     if (half)
         k_vlw_decode<true><<<kWinGrid, 256, 0, s>>>(cs, cell_sorted, g, n, nblk_p, cap, blocks, nbr, cnt, maxr,
-                                                    counts, rows);
+                                                    1, counts, rows);
     else
         k_vlw_decode<false><<<kWinGrid, 256, 0, s>>>(cs, cell_sorted, g, n, nblk_p, cap, blocks, nbr, cnt, maxr,
-                                                     counts, rows);
+                                                     window_entry_size(g), counts, rows);
 }
 
 }  // namespace mdlj
