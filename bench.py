@@ -254,7 +254,8 @@ def main():
     log("workload: %s, box %s" % (wname, d["box"]))
     if args.probe:
         r = run(M, d, args.probe, args.steps, args.warmup)
-        log("%s: %.3f ms/step, force %.3f ms" % (args.probe, r["ms_per_step"], r["force_kernel_ms"]))
+        log("%s: %.3f ms/step, force %.3f ms, build %s ms" % (args.probe, r["ms_per_step"], r["force_kernel_ms"],
+                                                               "%.3f" % r["build_ms"] if r["build_ms"] else "-"))
         print(json.dumps({"probe": args.probe, "workload": wname, "result": r}), flush=True)
         return
     auto = run(M, d, "auto", args.steps, args.warmup)
