@@ -27,15 +27,20 @@ FLOPS_PER_PAIR = 26  # FP32 flops per interacting unordered pair (d 3, r2 5, 1/r
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (published)
 PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
 
-# HBM traffic of the Verlet-list force kernel (k_vlw_f32, 1M fluid, CSF 1,
-# gather-only), from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE,
-# KiB per dispatch, averaged over the run's dispatches), each scaled by what
-# the counter reads for a plain 512 MiB device copy (FETCH_SIZE reads half the
-# bytes the copy moves: factor 2.0; WRITE_SIZE reads them exactly: 1.0).
-# Valid only for the kernel sources they were taken on (sha256 prefix of
-# window.hip, pair.h, md_internal.h); otherwise traffic is reported as null.
-VL_TRAFFIC = {"kernel": "k_vlw_f32", "sources_sha256": "5c554c98554148f6",
-              "fetch_kib": 107809.1, "write_kib": 12379.5, "fetch_factor": 2.0, "write_factor": 1.0}
+# Counters of the Verlet-list force kernel (k_vlw_f32, 1M fluid, CSF 1,
+# gather-only), from rocprofv3 --pmc runs, averaged over the run's dispatches:
+# HBM traffic from FETCH_SIZE and WRITE_SIZE (KiB per dispatch; separate
+# runs), each scaled by what the counter reads for a plain 512 MiB device
+# copy (FETCH_SIZE reads half the bytes the copy moves: factor 2.0;
+# WRITE_SIZE reads them exactly: 1.0); FP32 work from SQ_INSTS_VALU_FLOPS_FP32
+# (per dispatch, in wavefront instructions weighted by flops per lane, so 64
+# lanes' flops each).  Valid only for the kernel sources they were taken on
+# (sha256 prefix of window.hip, pair.h, md_internal.h); otherwise reported as
+# null.
+VL_COUNTERS = {"kernel": "k_vlw_f32",
+               "traffic_sha256": "5c554c98554148f6", "fetch_kib": 107809.1, "write_kib": 12379.5,
+               "fetch_factor": 2.0, "write_factor": 1.0,
+               "flops_sha256": None, "valu_flops_fp32_wave": None}
 
 
 def force_sources_sha():
@@ -51,10 +56,19 @@ def force_sources_sha():
 def measured_traffic(kname):
     """HBM bytes per launch of the force kernel from the counter runs, or
     None if they do not cover this kernel as it is now."""
-    t = VL_TRAFFIC
-    if kname != t["kernel"] or force_sources_sha() != t["sources_sha256"]:
+    t = VL_COUNTERS
+    if kname != t["kernel"] or force_sources_sha() != t["traffic_sha256"]:
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+
+
+def measured_flops(kname):
+    """FP32 flops issued per launch of the force kernel (every lane of every
+    VALU instruction, idle lanes of divergent loops included), or None."""
+    t = VL_COUNTERS
+    if kname != t["kernel"] or not t["valu_flops_fp32_wave"] or force_sources_sha() != t["flops_sha256"]:
+        return None
+    return 64.0 * t["valu_flops_fp32_wave"]
 
 
 def log(*a):
@@ -153,6 +167,48 @@ def run(M, d, kind, steps, warmup, probe_steps=50):
                energy_per_particle_first_last=[float(E[0] / n), float(E[-1] / n)] if len(E) else None)
     h.close()
     return res
+
+
+def measured_peaks():
+    """Ceilings measured on this device: the FP32 FMA rate of a kernel built
+    like the library (libmdprobe.so, packed FP32 disabled) and the bandwidth
+    of a 512 MiB device-to-device copy, both timed with events on torch's
+    current stream (the stream they are launched on)."""
+    import ctypes
+    import torch
+    here = os.path.dirname(os.path.abspath(__file__))
+    L = ctypes.CDLL(os.path.join(here, "paper_2505_03438_amd", "libmdprobe.so"))
+    L.mdprobe_fma_f32.restype = ctypes.c_int
+    L.mdprobe_fma_f32.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    L.mdprobe_fma_f32_flops.restype = ctypes.c_int64
+    L.mdprobe_fma_f32_flops.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    wgs, iters = 4096, 4096
+    out = torch.empty(wgs * 256, dtype=torch.float32, device="cuda")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = None
+    for _ in range(5):
+        e0.record()
+        if L.mdprobe_fma_f32(wgs, iters, ctypes.c_void_p(out.data_ptr()), st) != 0:
+            raise RuntimeError("mdprobe_fma_f32 failed")
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    fma_tflops = L.mdprobe_fma_f32_flops(wgs, iters) / (best * 1e-3) / 1e12
+    x = torch.empty(512 * 262144, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    best = None
+    for _ in range(5):
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    copy_gbps = 2 * x.numel() * 4 / (best * 1e-3) / 1e9
+    return {"fp32_fma_TFLOPs_nonpacked": fma_tflops, "copy_GBps_read_plus_write": copy_gbps,
+            "how": "best of 5: 4096 x 256 threads x 8 chains x 4096 dependent FMAs; 512 MiB device copy"}
 
 
 def force_kernel_name(c, family):
@@ -280,6 +336,16 @@ def main():
             "hbm_GBps_at_kernel_time": (traffic / (auto["force_kernel_ms"] * 1e-3) / 1e9) if traffic else None,
             "kernel_ms": auto["force_kernel_ms"],
             "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED}
+    issued = measured_flops(kname)
+    roof["valu_fp32_issued"] = ({"flops_per_launch": issued,
+                                 "TFLOPs": issued / (auto["force_kernel_ms"] * 1e-3) / 1e12,
+                                 "frac": issued / (auto["force_kernel_ms"] * 1e-3) / PEAK_FP32,
+                                 "source": "SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes (rocprofv3 --pmc)"}
+                                if issued else None)
+    try:
+        roof["measured_peaks"] = measured_peaks()
+    except (OSError, RuntimeError) as e:
+        roof["measured_peaks"] = {"error": str(e)}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(d)

@@ -130,3 +130,25 @@ def test_tuner_rejects_bad_use(M):
         tu.report(7, 1.0)
     with pytest.raises(RuntimeError):
         tu.report(tr[0], float("nan"))
+
+
+def test_probe_library_exports_its_header():
+    """The measurement probe (libmdprobe.so) exports what include/mdprobe.h
+    declares and counts its work without a device."""
+    import ctypes
+    from paper_2505_03438_amd import build
+    if not os.path.exists(build.PROBE_LIB):
+        build.build(verbose=False)
+    txt = open(os.path.join(ROOT, "include", "mdprobe.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = sorted(set(re.findall(r"\b(mdprobe_[a-z0-9_]+)\s*\(", txt)))
+    assert names == ["mdprobe_fma_f32", "mdprobe_fma_f32_flops"]
+    L = ctypes.CDLL(build.PROBE_LIB)
+    for name in names:
+        assert hasattr(L, name), name
+    L.mdprobe_fma_f32_flops.restype = ctypes.c_int64
+    L.mdprobe_fma_f32_flops.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    assert L.mdprobe_fma_f32_flops(4096, 4096) == 4096 * 256 * 4096 * 8 * 2
+    L.mdprobe_fma_f32.restype = ctypes.c_int
+    L.mdprobe_fma_f32.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    assert L.mdprobe_fma_f32(0, 1, None, None) == -1
