@@ -359,8 +359,18 @@ static int check_handle(md_handle *h)
 static bool use_window(const md_config &c, const Geom &g);
 static int build_blocks(md_handle *h, hipStream_t s);
 
+// Where the particle arrays of a time-stepping call currently live.  Inside
+// md_step a cell build does not copy the reordered arrays back: the current
+// arrays and the build's output buffers trade places (cur points at the
+// caller's or the handle's buffers; md_step copies back once at its end).
+struct CurArrays {
+    double **pos;
+    void **vel, **force;
+    int32_t **type, **ids;
+};
+
 static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, int32_t *type, int32_t *ids,
-                            hipStream_t s)
+                            hipStream_t s, const CurArrays *cur = nullptr)
 {
     const Geom &g = h->g;
     Buffers &b = h->b;
@@ -371,8 +381,8 @@ static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, i
     launch_fill_i32(b.cell_count, 0, g.ncell, s);
     launch_cell_hist(n, pos, g, b.cell_id, b.slot, b.cell_count, b.flags, s);
     launch_scan(b.cell_count, b.cell_start, g.ncell, b.scan_blocks, s);
-    launch_scatter(n, b.cell_id, b.slot, b.cell_start, b.perm, s);
     if (h->cfg.container == MD_CONTAINER_CL) {
+        launch_scatter(n, b.cell_id, b.slot, b.cell_start, b.perm, s);
         // cluster lists order each cell by position (Morton code), then id
         if (!b.cl_key) {
             int rc2 = dalloc(&b.cl_key, (size_t)std::max<int64_t>(h->n, 1));
@@ -380,11 +390,20 @@ static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, i
         }
         launch_cl_sort(n, b.cell_start, pos, ids, b.cell_id, b.perm, g, b.cl_key, b.cell_sorted, b.perm2, s);
     } else {
-        launch_cell_sort(n, b.cell_start, ids, b.cell_id, b.perm, b.slot, b.cell_sorted, b.perm2, s);
+        // the keys go to the gather's id buffer, written again by the gather
+        launch_scatter_sort(n, b.cell_id, b.slot, b.cell_start, ids, b.perm, b.tmp_ids, b.cell_sorted, b.perm2, s);
     }
     launch_gather(n, h->cfg.precision, b.perm2, pos, vel, force, type, ids, b.tmp_pos, b.tmp_vel, b.tmp_force,
                   b.tmp_type, b.tmp_ids, b.cell_id, b.cell_sorted, g, b.stage, b.stage_ref, s);
-    if (n > 0) {
+    if (cur) {
+        // the gathered buffers become the current arrays, the old ones the
+        // next build's output buffers (forces only if they were gathered)
+        std::swap(*cur->pos, b.tmp_pos);
+        if (vel) std::swap(*cur->vel, b.tmp_vel);
+        if (force) std::swap(*cur->force, b.tmp_force);
+        std::swap(*cur->type, b.tmp_type);
+        std::swap(*cur->ids, b.tmp_ids);
+    } else if (n > 0) {
         MD_HIP(hipMemcpyAsync(pos, b.tmp_pos, 3 * (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
         if (vel) MD_HIP(hipMemcpyAsync(vel, b.tmp_vel, 3 * (size_t)n * rs, hipMemcpyDeviceToDevice, s));
         if (force) MD_HIP(hipMemcpyAsync(force, b.tmp_force, 3 * (size_t)n * rs, hipMemcpyDeviceToDevice, s));
@@ -628,9 +647,11 @@ extern "C" int md_compute_forces(md_handle *h, const double *pos, const int32_t 
 // ------------------------------------------------------------------ time stepping
 
 struct StepCtx {
-    double *pos;
-    void *vel, *force;
-    int32_t *type, *ids;
+    // the current particle arrays: the caller's, or after a cell build the
+    // handle's buffers (see CurArrays); shared by every function of the call
+    mutable double *pos;
+    mutable void *vel, *force;
+    mutable int32_t *type, *ids;
     const double *inv_mass, *lj;
     double dt;
     int32_t nsteps, energy_every;
@@ -700,7 +721,8 @@ static void timing_collect(md_handle *h)
 // both kicks and are about to be recomputed, so they are not reordered.
 static int rebuild(md_handle *h, const StepCtx &c, bool with_force = true)
 {
-    int rc = build_cells_impl(h, c.pos, c.vel, with_force ? c.force : nullptr, c.type, c.ids, c.s);
+    CurArrays cur{&c.pos, &c.vel, &c.force, &c.type, &c.ids};
+    int rc = build_cells_impl(h, c.pos, c.vel, with_force ? c.force : nullptr, c.type, c.ids, c.s, &cur);
     if (rc) return rc;
     return build_lists_impl(h, c.pos, c.s);
 }
@@ -946,6 +968,31 @@ extern "C" int md_step(md_handle *h, double *pos, void *vel, void *force, int32_
     if (energy_every < 0) return fail(MD_ERR_INVALID_ARG, "energy_every must be >= 0");
     if (nsteps == 0) return MD_OK;
     StepCtx c{pos, vel, force, type, ids, inv_mass, lj, dt, nsteps, energy_every, log, (hipStream_t)stream};
+    // on every return: arrays that live in the handle's buffers are copied
+    // to the caller's, and those buffers go back to the handle
+    struct Restore {
+        md_handle *h;
+        const StepCtx &c;
+        double *pos;
+        void *vel, *force;
+        int32_t *type, *ids;
+        ~Restore()
+        {
+            Buffers &b = h->b;
+            size_t n = (size_t)h->n, rs = real_size(h->cfg);
+            auto back = [&](auto *&cur, auto *&spare, auto *mine, size_t bytes) {
+                if (cur == mine) return;
+                if (n > 0) (void)hipMemcpyAsync(mine, cur, bytes, hipMemcpyDeviceToDevice, c.s);
+                spare = cur;
+                cur = mine;
+            };
+            back(c.pos, b.tmp_pos, pos, 3 * n * sizeof(double));
+            back(c.vel, b.tmp_vel, vel, 3 * n * rs);
+            back(c.force, b.tmp_force, force, 3 * n * rs);
+            back(c.type, b.tmp_type, type, n * sizeof(int32_t));
+            back(c.ids, b.tmp_ids, ids, n * sizeof(int32_t));
+        }
+    } restore{h, c, pos, vel, force, type, ids};
     launch_prepare_tab(lj, h->cfg.rc2, h->g, h->b.tab, c.s);
     // lists truncated since the last look (a build before this call overflowed):
     // grow them, rebuild and recompute the entry forces

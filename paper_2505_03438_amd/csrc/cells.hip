@@ -171,10 +171,24 @@ __global__ void k_scan_blocks(int32_t *__restrict__ totals, int nb)
     }
 }
 
+// Per-block scan plus the block's offset: offs[blockIdx.x] if offs is given
+// (scanned block totals), else the sum of the totals of the blocks before
+// this one (at most kScanTile of them; none for a single block).
 __global__ void k_scan_final(const int32_t *__restrict__ in, int64_t n, const int32_t *__restrict__ offs,
-                             int32_t *__restrict__ out)
+                             const int32_t *__restrict__ totals, int32_t *__restrict__ out)
 {
     __shared__ int sh[kBlock];
+    int off;
+    if (offs) {
+        off = offs[blockIdx.x];
+    } else {
+        int part = 0;
+        for (int b = threadIdx.x; b < (int)blockIdx.x; b += blockDim.x) part += totals[b];
+        int tot;
+        int ex0 = block_exclusive_scan(part, sh, tot);
+        (void)ex0;
+        off = tot;
+    }
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int v[kScanItems];
     int s = 0;
@@ -183,7 +197,7 @@ __global__ void k_scan_final(const int32_t *__restrict__ in, int64_t n, const in
         s += v[k];
     }
     int total;
-    int ex = block_exclusive_scan(s, sh, total) + offs[blockIdx.x];
+    int ex = block_exclusive_scan(s, sh, total) + off;
     for (int k = 0; k < kScanItems; k++) {
         if (base + k < n) out[base + k] = ex;
         ex += v[k];
@@ -208,7 +222,15 @@ void launch_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch, h
     }
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     int32_t *totals = scratch;
+    if (nb == 1) {  // one tile: a single pass
+        k_scan_final<<<1, kBlock, 0, s>>>(in, n, nullptr, totals, out);
+        return;
+    }
     k_scan_totals<<<(unsigned)nb, kBlock, 0, s>>>(in, n, totals);
+    if (nb <= 64) {  // each block sums the few totals before it
+        k_scan_final<<<(unsigned)nb, kBlock, 0, s>>>(in, n, nullptr, totals, out);
+        return;
+    }
     const int32_t *offs = totals;
     if (nb <= kScanTile) {
         k_scan_blocks<<<1, kBlock, 0, s>>>(totals, (int)nb);
@@ -217,7 +239,7 @@ void launch_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch, h
         launch_scan(totals, scanned, nb, scanned + nb + 1, s);
         offs = scanned;
     }
-    k_scan_final<<<(unsigned)nb, kBlock, 0, s>>>(in, n, offs, out);
+    k_scan_final<<<(unsigned)nb, kBlock, 0, s>>>(in, n, offs, nullptr, out);
 }
 
 // ------------------------------------------------------------------ K3: scatter + order
@@ -265,6 +287,35 @@ __global__ void k_cell_rank(int n, const int32_t *__restrict__ start, const int3
     int r = 0;
     for (int m = b; m < e; m++) r += key[m] < kk ? 1 : 0;
     perm_out[b + r] = perm[k];
+}
+
+// Scatter fused with the key gather of the in-cell ordering: slot p of the
+// cell order gets particle i, its id as key and its cell.  key must not alias
+// slot (slot[i] is read while other threads write key[p]).
+__global__ void k_scatter_keys(int n, const int32_t *__restrict__ cell_id, const int32_t *__restrict__ slot,
+                               const int32_t *__restrict__ start, const int32_t *__restrict__ ids,
+                               int32_t *__restrict__ perm, int32_t *__restrict__ key,
+                               int32_t *__restrict__ cell_of_slot)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = cell_id[i];
+    int p = start[c] + slot[i];
+    perm[p] = i;
+    key[p] = ids[i];
+    cell_of_slot[p] = c;
+}
+
+// Counting-sort scatter and in-cell ordering by id in two launches:
+// perm_out[k] = particle in cell-order slot k (perm and key are scratch).
+void launch_scatter_sort(int n, const int32_t *cell_id, const int32_t *slot, const int32_t *start,
+                         const int32_t *ids, int32_t *perm, int32_t *key, int32_t *cell_of_slot, int32_t *perm_out,
+                         hipStream_t s)
+{
+    if (n <= 0) return;
+    int nb = (n + kBlock - 1) / kBlock;
+    k_scatter_keys<<<nb, kBlock, 0, s>>>(n, cell_id, slot, start, ids, perm, key, cell_of_slot);
+    k_cell_rank<<<nb, kBlock, 0, s>>>(n, start, key, cell_of_slot, perm, perm_out);
 }
 
 void launch_cell_sort(int n, const int32_t *start, const int32_t *ids, const int32_t *cell_id, const int32_t *perm,

@@ -122,6 +122,9 @@ int64_t scan_scratch_size(int64_t n);
 void launch_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch, hipStream_t s);
 void launch_scatter(int n, const int32_t *cell_id, const int32_t *slot, const int32_t *start,
                     int32_t *perm, hipStream_t s);
+void launch_scatter_sort(int n, const int32_t *cell_id, const int32_t *slot, const int32_t *start,
+                         const int32_t *ids, int32_t *perm, int32_t *key, int32_t *cell_of_slot, int32_t *perm_out,
+                         hipStream_t s);
 void launch_cell_sort(int n, const int32_t *start, const int32_t *ids, const int32_t *cell_id, const int32_t *perm,
                       int32_t *key, int32_t *cell_of_slot, int32_t *perm_out, hipStream_t s);
 void launch_gather(int n, int precision, const int32_t *perm, const double *pos, const void *vel,
