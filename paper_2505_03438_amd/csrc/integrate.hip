@@ -25,7 +25,9 @@ __device__ __forceinline__ uint32_t quantise_i(double x, double S)
     return (uint32_t)q;
 }
 
-template <typename real, bool ISO>
+// ONE_TYPE: a single particle type, so the type array is not read and the
+// staged type field (0, written by the cell build) is left as it is.
+template <typename real, bool ISO, bool ONE_TYPE>
 __global__ __launch_bounds__(kBlock) void k_integrate(IntegrateArgs a, Geom g)
 {
 #pragma clang fp contract(off)
@@ -37,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntegrateArgs a, Geom g)
         size_t N = (size_t)a.n;
         real *v = (real *)a.vel;
         const real *F = (const real *)a.force;
-        int t = a.type[i];
+        int t = ONE_TYPE ? 0 : a.type[i];
         double im = a.inv_mass[t];
         real c = (real)(a.hdt * im);  // (dt/2) / m, as in v += (dt/2) (1/m) F
         real vx = v[i], vy = v[N + i], vz = v[2 * N + i];
@@ -64,7 +66,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntegrateArgs a, Geom g)
             q.y = (int)quantise_i(y, g.S[1]);
             q.z = (int)quantise_i(z, g.S[2]);
             q.w = t;
-            a.stage[i] = q;
+            if (ONE_TYPE)
+                *(int3 *)&a.stage[i] = make_int3(q.x, q.y, q.z);
+            else
+                a.stage[i] = q;
             // skin check: displacement since the last build, minimum image
             int4 r = a.stage_ref[i];
             float dx, dy, dz;
@@ -108,12 +113,23 @@ void launch_integrate(const IntegrateArgs &a, const Geom &g, hipStream_t s)
 {
     if (a.n <= 0) return;
     int nb = integrate_blocks(a.n);
+    bool one = g.nt == 1;
     if (a.precision == MD_FP64) {
-        if (g.iso) k_integrate<double, true><<<nb, kBlock, 0, s>>>(a, g);
-        else k_integrate<double, false><<<nb, kBlock, 0, s>>>(a, g);
+        if (g.iso) {
+            if (one) k_integrate<double, true, true><<<nb, kBlock, 0, s>>>(a, g);
+            else k_integrate<double, true, false><<<nb, kBlock, 0, s>>>(a, g);
+        } else {
+            if (one) k_integrate<double, false, true><<<nb, kBlock, 0, s>>>(a, g);
+            else k_integrate<double, false, false><<<nb, kBlock, 0, s>>>(a, g);
+        }
     } else {
-        if (g.iso) k_integrate<float, true><<<nb, kBlock, 0, s>>>(a, g);
-        else k_integrate<float, false><<<nb, kBlock, 0, s>>>(a, g);
+        if (g.iso) {
+            if (one) k_integrate<float, true, true><<<nb, kBlock, 0, s>>>(a, g);
+            else k_integrate<float, true, false><<<nb, kBlock, 0, s>>>(a, g);
+        } else {
+            if (one) k_integrate<float, false, true><<<nb, kBlock, 0, s>>>(a, g);
+            else k_integrate<float, false, false><<<nb, kBlock, 0, s>>>(a, g);
+        }
     }
 }
 

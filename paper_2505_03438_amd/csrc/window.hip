@@ -1156,22 +1156,31 @@ __global__ __launch_bounds__(256) void k_lcwh_f32(const int4 *__restrict__ st, c
             int self = self_position<true>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
             int4 pi = win[self].get();
             float fx = 0.f, fy = 0.f, fz = 0.f;
+            // each thread walks a range from its own starting point (the
+            // threads of a cell share their ranges): the j-side LDS atomics
+            // of a wavefront then hit different positions instead of the
+            // same one
             stencil_ranges<true>(g, w, k, x, self, [&](int b, int en) {
-                for (int p0 = b; p0 < en; p0 += 4) {
-                    int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
+                int len = en - b;
+                if (len <= 0) return;
+                int o = (int)(threadIdx.x % (unsigned)len);
+                auto at = [&](int q) { return b + (q >= len ? q - len : q); };
+                for (int t0 = 0; t0 < len; t0 += 4) {
+                    int p0 = at(o + t0), p1 = at(o + min(t0 + 1, len - 1)), p2 = at(o + min(t0 + 2, len - 1)),
+                        p3 = at(o + min(t0 + 3, len - 1));
                     int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
                     uint32_t amb = 0;
                     amb |= pair_n3l<NT, ISO, ENERGY>(pi, q0, p0, true, t, g, acc, fx, fy, fz, eu, ew, np) ? 1u : 0u;
-                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q1, p1, p0 + 1 < en, t, g, acc, fx, fy, fz, eu, ew, np)
+                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q1, p1, t0 + 1 < len, t, g, acc, fx, fy, fz, eu, ew, np)
                                ? 2u : 0u;
-                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q2, p2, p0 + 2 < en, t, g, acc, fx, fy, fz, eu, ew, np)
+                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q2, p2, t0 + 2 < len, t, g, acc, fx, fy, fz, eu, ew, np)
                                ? 4u : 0u;
-                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q3, p3, p0 + 3 < en, t, g, acc, fx, fy, fz, eu, ew, np)
+                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q3, p3, t0 + 3 < len, t, g, acc, fx, fy, fz, eu, ew, np)
                                ? 8u : 0u;
                     while (amb) {
                         int u = __builtin_ctz(amb);
                         amb &= amb - 1;
-                        int p = p0 + u;
+                        int p = u == 0 ? p0 : (u == 1 ? p1 : (u == 2 ? p2 : p3));
                         pair_exact_n3l<NT, ISO, ENERGY>(pi, win[p].get(), p, i, window_global(w, p), t, g, pos, n,
                                                         acc, fx, fy, fz, eu, ew, np);
                     }
