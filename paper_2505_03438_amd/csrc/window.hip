@@ -605,9 +605,44 @@ __device__ __forceinline__ void pair_exact(const int4 &pi, const int4 &pj, int i
 
 // ------------------------------------------------------------------ linked cells
 
-// Each thread scans the window ranges of its stencil, four candidates at a
-// time (the four LDS reads issued before any arithmetic); guard-band pairs
-// are collected in a bit mask and decided after the batch.
+// Cutoff prefilter of the linked-cell traversals: window positions q[0 ..
+// m-1], m <= 32, tested against the largest upper guard-band edge of the
+// cutoffs; returns the mask of the candidates below it (candidate u at bit
+// m - 1 - u).  Reads whole groups of four, up to three positions past the
+// batch (the window arrays are padded for them); their bits are dropped.
+template <int NT, bool ISO>
+__device__ __forceinline__ uint32_t cut_batch(const int4 &pi, const WinEntry<NT> *__restrict__ q, int m,
+                                              const Geom &g, float hi)
+{
+    uint32_t mask = 0;
+    int nb = 0;
+    auto test = [&](const WinEntry<NT> &e) {
+        float dx, dy, dz;
+        staged_delta<ISO>(pi, e.get(), g, dx, dy, dz);
+        float r2 = dx * dx + dy * dy + dz * dz;
+        mask = mask + mask + (r2 < hi ? 1u : 0u);
+    };
+    for (; nb < m; nb += 4) {
+        test(q[nb]);
+        test(q[nb + 1]);
+        test(q[nb + 2]);
+        test(q[nb + 3]);
+    }
+    return mask >> (nb - m);
+}
+
+template <int NT>
+__device__ __forceinline__ float max_hi(const TabF<NT> &t)
+{
+    float h = t.hi[0];
+    for (int k = 1; k < NT * NT; k++) h = fmaxf(h, t.hi[k]);
+    return h;
+}
+
+// Each thread scans the window ranges of its stencil 32 candidates at a
+// time: a cheap distance test gives the mask of those that may interact,
+// and only they are evaluated (guard-band pairs decided from the FP64
+// positions).
 template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                  const int32_t *__restrict__ cell_sorted, Geom g, int n,
@@ -617,11 +652,12 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
                                                  float *__restrict__ F, double *__restrict__ partials,
                                                  int32_t *__restrict__ flags)
 {
-    __shared__ WinEntry<NT> win[kWinMax];
+    __shared__ WinEntry<NT> win[kWinMax + 4];  // + the reads past a batch
     __shared__ Window w;
     __shared__ double sh[16];
     TabF<NT> t;
     t.load(tabp);
+    const float hi = max_hi(t);
     float eu = 0.f, ew = 0.f;
     int np = 0;
     size_t N = (size_t)n;
@@ -634,23 +670,19 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
         int4 pi = win[self].get();
         float fx = 0.f, fy = 0.f, fz = 0.f;
         stencil_ranges<false>(g, w, k, x, self, [&](int b, int en) {
-            for (int p0 = b; p0 < en; p0 += 4) {
-                int p1 = min(p0 + 1, en - 1), p2 = min(p0 + 2, en - 1), p3 = min(p0 + 3, en - 1);
-                int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
-                uint32_t amb = 0;
-                amb |= pair_fast<NT, ISO, ENERGY>(pi, q0, p0 != self, t, g, fx, fy, fz, eu, ew, np) ? 1u : 0u;
-                amb |= pair_fast<NT, ISO, ENERGY>(pi, q1, p0 + 1 < en && p1 != self, t, g, fx, fy, fz, eu, ew, np)
-                           ? 2u : 0u;
-                amb |= pair_fast<NT, ISO, ENERGY>(pi, q2, p0 + 2 < en && p2 != self, t, g, fx, fy, fz, eu, ew, np)
-                           ? 4u : 0u;
-                amb |= pair_fast<NT, ISO, ENERGY>(pi, q3, p0 + 3 < en && p3 != self, t, g, fx, fy, fz, eu, ew, np)
-                           ? 8u : 0u;
-                while (amb) {
-                    int u = __builtin_ctz(amb);
-                    amb &= amb - 1;
-                    int p = p0 + u;
-                    pair_exact<NT, ISO, ENERGY>(pi, win[p].get(), i, window_global(w, p), t, g, pos, n, fx, fy, fz,
-                                                eu, ew, np);
+            for (int base = b; base < en; base += 32) {
+                int m = min(32, en - base);
+                uint32_t mask = cut_batch<NT, ISO>(pi, win + base, m, g, hi);
+                unsigned us = (unsigned)(self - base);
+                if (us < (unsigned)m) mask &= ~(1u << (m - 1 - us));
+                while (mask) {
+                    int h = 31 - __builtin_clz(mask);
+                    mask ^= 1u << h;
+                    int p = base + m - 1 - h;
+                    int4 pj = win[p].get();
+                    if (pair_fast<NT, ISO, ENERGY>(pi, pj, true, t, g, fx, fy, fz, eu, ew, np))
+                        pair_exact<NT, ISO, ENERGY>(pi, pj, i, window_global(w, p), t, g, pos, n, fx, fy, fz, eu,
+                                                    ew, np);
                 }
             }
         });
@@ -1169,12 +1201,13 @@ __global__ __launch_bounds__(256) void k_lcwh_f32(const int4 *__restrict__ st, c
                                                   float *__restrict__ F, double *__restrict__ partials,
                                                   int32_t *__restrict__ flags)
 {
-    __shared__ WinEntry<NT> win[kWinMaxHalf];
+    __shared__ WinEntry<NT> win[kWinMaxHalf + 4];  // + the reads past a batch
     __shared__ HalfAcc acc;
     __shared__ Window w;
     __shared__ double sh[16];
     TabF<NT> t;
     t.load(tabp);
+    const float hi = max_hi(t);
     float eu = 0.f, ew = 0.f;
     int np = 0;
     size_t N = (size_t)n;
@@ -1186,33 +1219,18 @@ __global__ __launch_bounds__(256) void k_lcwh_f32(const int4 *__restrict__ st, c
             int self = self_position<true>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
             int4 pi = win[self].get();
             float fx = 0.f, fy = 0.f, fz = 0.f;
-            // each thread walks a range from its own starting point (the
-            // threads of a cell share their ranges): the j-side LDS atomics
-            // of a wavefront then hit different positions instead of the
-            // same one
             stencil_ranges<true>(g, w, k, x, self, [&](int b, int en) {
-                int len = en - b;
-                if (len <= 0) return;
-                int o = (int)(threadIdx.x % (unsigned)len);
-                auto at = [&](int q) { return b + (q >= len ? q - len : q); };
-                for (int t0 = 0; t0 < len; t0 += 4) {
-                    int p0 = at(o + t0), p1 = at(o + min(t0 + 1, len - 1)), p2 = at(o + min(t0 + 2, len - 1)),
-                        p3 = at(o + min(t0 + 3, len - 1));
-                    int4 q0 = win[p0].get(), q1 = win[p1].get(), q2 = win[p2].get(), q3 = win[p3].get();
-                    uint32_t amb = 0;
-                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q0, p0, true, t, g, acc, fx, fy, fz, eu, ew, np) ? 1u : 0u;
-                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q1, p1, t0 + 1 < len, t, g, acc, fx, fy, fz, eu, ew, np)
-                               ? 2u : 0u;
-                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q2, p2, t0 + 2 < len, t, g, acc, fx, fy, fz, eu, ew, np)
-                               ? 4u : 0u;
-                    amb |= pair_n3l<NT, ISO, ENERGY>(pi, q3, p3, t0 + 3 < len, t, g, acc, fx, fy, fz, eu, ew, np)
-                               ? 8u : 0u;
-                    while (amb) {
-                        int u = __builtin_ctz(amb);
-                        amb &= amb - 1;
-                        int p = u == 0 ? p0 : (u == 1 ? p1 : (u == 2 ? p2 : p3));
-                        pair_exact_n3l<NT, ISO, ENERGY>(pi, win[p].get(), p, i, window_global(w, p), t, g, pos, n,
-                                                        acc, fx, fy, fz, eu, ew, np);
+                for (int base = b; base < en; base += 32) {
+                    int m = min(32, en - base);
+                    uint32_t mask = cut_batch<NT, ISO>(pi, win + base, m, g, hi);
+                    while (mask) {
+                        int h = 31 - __builtin_clz(mask);
+                        mask ^= 1u << h;
+                        int p = base + m - 1 - h;
+                        int4 pj = win[p].get();
+                        if (pair_n3l<NT, ISO, ENERGY>(pi, pj, p, true, t, g, acc, fx, fy, fz, eu, ew, np))
+                            pair_exact_n3l<NT, ISO, ENERGY>(pi, pj, p, i, window_global(w, p), t, g, pos, n, acc, fx,
+                                                            fy, fz, eu, ew, np);
                     }
                 }
             });
