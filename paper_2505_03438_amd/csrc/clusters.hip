@@ -182,10 +182,11 @@ __global__ void k_cl_pairs(const int32_t *__restrict__ ncl_p, const int32_t *__r
     }
 }
 
-// One wavefront per i-cluster, lane (ii, jj); gather-only.  The cluster
-// indices are wavefront-uniform (scalar loads); the j-cluster of the next
-// list entry, and its staged positions, are loaded while the current one is
-// computed.
+// One wavefront per i-cluster, lane (ii, jj); gather-only.  The list is
+// read 64 entries at a time, one entry per lane, together with each entry's
+// j-cluster first particle and count; the loop over the entries then takes
+// them from those lanes (wavefront-uniform), and the staged positions of
+// the next entry's j-cluster are loaded while the current one is computed.
 template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(256) void k_cl_f32(int n, const int32_t *__restrict__ ncl_p,
                                                 const int32_t *__restrict__ first, const int32_t *__restrict__ cnt,
@@ -212,17 +213,18 @@ __global__ __launch_bounds__(256) void k_cl_f32(int n, const int32_t *__restrict
         int i = fi + (vi ? ii : 0);
         int4 pi = st[i];
         float fx = 0.f, fy = 0.f, fz = 0.f;
-        int m = lcnt[ci];
-        if (m > 0) {
-            // entry k: cluster cj with first particle fj and count nj; pj is
-            // this lane's j particle
-            int cj = list[ci];
-            int fj = first[cj], nj = cnt[cj];
+        int m = __builtin_amdgcn_readfirstlane(lcnt[ci]);
+        for (int k0 = 0; k0 < m; k0 += 64) {
+            int mm = min(64, m - k0);
+            // lane e holds entry k0 + e: its j-cluster's first particle and count
+            int cjl = lane < mm ? list[(size_t)(k0 + lane) * ld + ci] : 0;
+            int fjl = lane < mm ? first[cjl] : 0;
+            int njl = lane < mm ? cnt[cjl] : 0;
+            int fj = __builtin_amdgcn_readlane(fjl, 0), nj = __builtin_amdgcn_readlane(njl, 0);
             int4 pj = st[fj + (jj < nj ? jj : 0)];
-            for (int k = 0; k < m; k++) {
-                int kn = min(k + 1, m - 1);
-                int cjn = list[(size_t)kn * ld + ci];
-                int fjn = first[cjn], njn = cnt[cjn];
+            for (int e = 0; e < mm; e++) {
+                int en = min(e + 1, mm - 1);
+                int fjn = __builtin_amdgcn_readlane(fjl, en), njn = __builtin_amdgcn_readlane(njl, en);
                 int4 pjn = st[fjn + (jj < njn ? jj : 0)];
                 int j = fj + (jj < nj ? jj : 0);
                 bool valid = vi && jj < nj && i != j;
