@@ -38,9 +38,9 @@ PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no 
 # (sha256 prefix of window.hip, pair.h, md_internal.h); otherwise reported as
 # null.
 VL_COUNTERS = {"kernel": "k_vlw_f32",
-               "traffic_sha256": "5c554c98554148f6", "fetch_kib": 107809.1, "write_kib": 12379.5,
+               "traffic_sha256": "6dc9cd9c41c6162d", "fetch_kib": 126201.6, "write_kib": 12773.6,
                "fetch_factor": 2.0, "write_factor": 1.0,
-               "flops_sha256": None, "valu_flops_fp32_wave": None}
+               "flops_sha256": "6dc9cd9c41c6162d", "valu_flops_fp32_wave": 27020949.9}
 
 
 def force_sources_sha():

@@ -145,7 +145,7 @@ static void free_buffers(md_handle *h)
                     b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
                     b.cl_nbr_count, b.snap_pos, b.snap_vel,
                     b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart,
-                    b.w_blk, b.w_blk_raw, b.w_perm, b.w_rown, b.w_rowb, b.w_nbr};
+                    b.w_blk, b.w_perm, b.w_rown, b.w_rowb, b.w_nbr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (b.host_flags) (void)hipHostFree(b.host_flags);
@@ -470,14 +470,11 @@ static int ensure_window(md_handle *h, int64_t maxn)
     int64_t cap = window_block_cap(h->n, h->g);
     if (cap > b.w_cap) {
         if (b.w_blk) (void)hipFree(b.w_blk);
-        if (b.w_blk_raw) (void)hipFree(b.w_blk_raw);
         if (b.w_perm) (void)hipFree(b.w_perm);
-        b.w_blk = b.w_blk_raw = nullptr;
+        b.w_blk = nullptr;
         b.w_perm = nullptr;
         b.w_cap = 0;
-        if ((rc = dalloc(&b.w_blk, cap)) || (rc = dalloc(&b.w_blk_raw, cap)) ||
-            (rc = dalloc(&b.w_perm, (size_t)cap * 256)))
-            return rc;
+        if ((rc = dalloc(&b.w_blk, cap)) || (rc = dalloc(&b.w_perm, (size_t)cap * 256))) return rc;
         b.w_cap = cap;
     }
     int64_t rows = (int64_t)h->g.nc[1] * h->g.nc[2] + 1;
@@ -509,8 +506,8 @@ static int build_blocks(md_handle *h, hipStream_t s)
     if (rc) return rc;
     // the per-cell counts are no longer needed once the cells are built: the
     // same buffer holds the window column sums of the packer
-    launch_blocks(h->g, b.cell_start, b.cell_count, b.w_rown, b.w_rowb, b.scan_blocks, b.w_blk_raw, b.w_blk,
-                  (int)b.w_cap, b.flags, h->cfg.newton3 == MD_N3L_ON, s);
+    launch_blocks(h->g, b.cell_start, b.cell_count, b.w_rown, b.w_rowb, b.scan_blocks, b.w_blk, (int)b.w_cap,
+                  b.flags, h->cfg.newton3 == MD_N3L_ON, s);
     return MD_OK;
 }
 

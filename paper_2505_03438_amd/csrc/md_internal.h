@@ -90,7 +90,6 @@ struct Buffers {
     int4 *snap_stage = nullptr;
     // Verlet lists over LDS windows (FP32 gather-only)
     int4 *w_blk = nullptr;  // per block: first cell, last cell, particle range (or -1, -1)
-    int4 *w_blk_raw = nullptr;  // the same in packer order (w_blk: sorted by size per XCD chunk)
     uint8_t *w_perm = nullptr;  // per block, 256 slots: particles by list length, longest first
     int32_t *w_rown = nullptr, *w_rowb = nullptr;
     uint16_t *w_nbr = nullptr;
@@ -174,7 +173,7 @@ int64_t window_block_cap(int64_t n, const Geom &g);
 int window_nbands(const Geom &g);
 int window_force_blocks();
 void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *band_n, int32_t *band_base,
-                   int32_t *scan_scratch, int4 *raw, int4 *blocks, int cap, int32_t *flags, bool half, hipStream_t s);
+                   int32_t *scan_scratch, int4 *blocks, int cap, int32_t *flags, bool half, hipStream_t s);
 void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
                       const Geom &g, int n, const int32_t *nblk_p, const int4 *blocks, uint16_t *nbr, int32_t *cnt,
                       uint8_t *perm, int maxn, int32_t *flags, bool half, hipStream_t s);

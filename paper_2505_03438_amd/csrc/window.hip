@@ -1351,69 +1351,11 @@ bool window_geometry_ok(const Geom &g, bool half)
     return g.wband >= 1 && g.wband <= kWinBlkRows && g.nc[1] >= g.wband + 2 * r && g.nc[0] <= kPackMaxX;
 }
 
-// Particles of a block (descriptor blk).
-__device__ __forceinline__ int block_npart(const Geom &g, const int32_t *__restrict__ cs, int4 blk)
-{
-    if (blk.z >= 0) return blk.w - blk.z;
-    Rect r = rect_of(g, blk.x, blk.y);
-    int nx = g.nc[0], ny = g.nc[1], np = 0;
-    for (int y = r.y0; y <= r.y1; y++) {
-        int row = (r.z * ny + y) * nx;
-        np += cs[row + r.xb + 1] - cs[row + r.xa];
-    }
-    return np;
-}
-
-// Order of the blocks within each XCD's contiguous chunk (the split of
-// BlockIter): by particle count, largest first, ties by packer order.  The
-// persistent workgroups take the chunk's blocks round robin, so the large
-// blocks start first and the small ones fill the end of the launch.  A chunk
-// of more than kSortMax blocks keeps the packer order.
-constexpr int kSortMax = 4096;
-
-__global__ __launch_bounds__(1024) void k_blk_sort(const Geom g, const int32_t *__restrict__ cs,
-                                                   const int32_t *__restrict__ nblk_p, int cap,
-                                                   const int4 *__restrict__ raw, int4 *__restrict__ out)
-{
-    __shared__ uint32_t key[kSortMax];
-    int nblk = min(*nblk_p, cap);
-    int chunk = (nblk + 7) / 8;
-    int b0 = blockIdx.x * chunk;
-    int m = min(nblk, b0 + chunk) - b0;
-    if (m <= 0) return;
-    if (m > kSortMax) {
-        for (int k = threadIdx.x; k < m; k += blockDim.x) out[b0 + k] = raw[b0 + k];
-        return;
-    }
-    int P = 1;
-    while (P < m) P <<= 1;
-    // key: (256 - particles) above the 12-bit chunk index; padding sorts last
-    for (int k = threadIdx.x; k < P; k += blockDim.x)
-        key[k] = k < m ? ((uint32_t)(256 - min(block_npart(g, cs, raw[b0 + k]), 256)) << 12) | (uint32_t)k
-                       : 0xffffffffu;
-    __syncthreads();
-    // bitonic sort, ascending
-    for (int size = 2; size <= P; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < P / 2; t += blockDim.x) {
-                int lo = 2 * t - (t & (stride - 1)), hi = lo + stride;
-                bool up = (lo & size) == 0;
-                uint32_t a = key[lo], b = key[hi];
-                if ((a > b) == up) {
-                    key[lo] = b;
-                    key[hi] = a;
-                }
-            }
-            __syncthreads();
-        }
-    for (int k = threadIdx.x; k < m; k += blockDim.x) out[b0 + k] = raw[b0 + (int)(key[k] & 0xfffu)];
-}
-
 // Blocks of the windowed kernels: column sums, per-band block counts, their
-// scan, the descriptors in packer order (raw), then each XCD chunk sorted by
-// size into blocks.
+// scan, then the descriptors.  (Ordering each XCD's blocks by size, largest
+// first, was measured to gain nothing and cost a launch per build.)
 void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *band_n, int32_t *band_base,
-                   int32_t *scan_scratch, int4 *raw, int4 *blocks, int cap, int32_t *flags, bool half, hipStream_t s)
+                   int32_t *scan_scratch, int4 *blocks, int cap, int32_t *flags, bool half, hipStream_t s)
 {
     int nb = window_nbands(g);
     int wmax = half ? kWinMaxHalf : kWinMax;
@@ -1425,8 +1367,7 @@ void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *b
     size_t lds = 3 * (size_t)g.nc[0] * sizeof(int);  // <= 48 KB (nc[0] <= kPackMaxX)
     k_blk_count<<<nb, 64, lds, s>>>(g, cs, colsum, band_n, wmax);
     launch_scan(band_n, band_base, nb, scan_scratch, s);
-    k_blk_write<<<nb, 64, lds, s>>>(g, cs, colsum, band_base, raw, cap, flags, wmax);
-    k_blk_sort<<<8, 1024, 0, s>>>(g, cs, band_base + nb, cap, raw, blocks);
+    k_blk_write<<<nb, 64, lds, s>>>(g, cs, colsum, band_base, blocks, cap, flags, wmax);
 }
 
 // Size of the force kernels' LDS window entry (positions, plus the type when
