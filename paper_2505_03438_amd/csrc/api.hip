@@ -145,7 +145,7 @@ static void free_buffers(md_handle *h)
                     b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
                     b.cl_nbr_count, b.snap_pos, b.snap_vel,
                     b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart,
-                    b.w_blk, b.w_perm, b.w_rown, b.w_rowb, b.w_nbr};
+                    b.w_blk, b.w_rown, b.w_rowb, b.w_nbr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (b.host_flags) (void)hipHostFree(b.host_flags);
@@ -470,11 +470,9 @@ static int ensure_window(md_handle *h, int64_t maxn)
     int64_t cap = window_block_cap(h->n, h->g);
     if (cap > b.w_cap) {
         if (b.w_blk) (void)hipFree(b.w_blk);
-        if (b.w_perm) (void)hipFree(b.w_perm);
         b.w_blk = nullptr;
-        b.w_perm = nullptr;
         b.w_cap = 0;
-        if ((rc = dalloc(&b.w_blk, cap)) || (rc = dalloc(&b.w_perm, (size_t)cap * 256))) return rc;
+        if ((rc = dalloc(&b.w_blk, cap))) return rc;
         b.w_cap = cap;
     }
     int64_t rows = (int64_t)h->g.nc[1] * h->g.nc[2] + 1;
@@ -521,8 +519,7 @@ static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
         const Geom &g = h->g;
         launch_fill_i32(b.flags + 2, 0, 1, s);
         launch_vlw_build(b.stage, b.cell_start, b.cell_sorted, pos, g, n, b.w_rowb + window_nbands(g), b.w_blk,
-                         b.w_nbr, b.nbr_count, b.w_perm, h->cfg.max_neighbors, b.flags, h->cfg.newton3 == MD_N3L_ON,
-                         s);
+                         b.w_nbr, b.nbr_count, h->cfg.max_neighbors, b.flags, h->cfg.newton3 == MD_N3L_ON, s);
     } else if (h->cfg.container == MD_CONTAINER_VL) {
         int rc = ensure_list(h, h->cfg.max_neighbors);
         if (rc) return rc;
@@ -603,7 +600,6 @@ static ForceArgs force_args(md_handle *h, const double *pos, const int32_t *type
     if (a.window) {
         a.w_nblk = h->b.w_rowb + window_nbands(h->g);
         a.w_blk = h->b.w_blk;
-        a.w_perm = h->b.w_perm;
         a.w_nbr = h->b.w_nbr;
     }
     return a;

@@ -90,7 +90,6 @@ struct Buffers {
     int4 *snap_stage = nullptr;
     // Verlet lists over LDS windows (FP32 gather-only)
     int4 *w_blk = nullptr;  // per block: first cell, last cell, particle range (or -1, -1)
-    uint8_t *w_perm = nullptr;  // per block, 256 slots: particles by list length, longest first
     int32_t *w_rown = nullptr, *w_rowb = nullptr;
     uint16_t *w_nbr = nullptr;
     int64_t w_cap = 0, w_rows_cap = 0, w_nbr_cap = 0;
@@ -162,7 +161,6 @@ struct ForceArgs {
     bool window;
     const int32_t *w_nblk;
     const int4 *w_blk;
-    const uint8_t *w_perm;
     const uint16_t *w_nbr;
 };
 int force_blocks(const ForceArgs &a);  // number of partial slots written when energy
@@ -176,7 +174,7 @@ void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *b
                    int32_t *scan_scratch, int4 *blocks, int cap, int32_t *flags, bool half, hipStream_t s);
 void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
                       const Geom &g, int n, const int32_t *nblk_p, const int4 *blocks, uint16_t *nbr, int32_t *cnt,
-                      uint8_t *perm, int maxn, int32_t *flags, bool half, hipStream_t s);
+                      int maxn, int32_t *flags, bool half, hipStream_t s);
 void launch_window_force(const ForceArgs &a, const Geom &g, hipStream_t s);
 // Windowed traversals need the same reach (1 or 2 cells) in every
 // dimension and 2 reach + 1 distinct cells per dimension.

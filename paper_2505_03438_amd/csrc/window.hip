@@ -294,12 +294,12 @@ struct BlockIter {
     }
 };
 
-// Particle t of the block (default: this thread's): its index i, block row
-// k and cell column x; false if the block has no particle t.
+// The particle of this thread in the block: its index i, block row k and
+// cell column x; false if the thread has none.
 __device__ __forceinline__ bool my_particle(const Geom &g, const Window &w, const int32_t *__restrict__ cell_sorted,
-                                            int &i, int &k, int &x, int t = -1)
+                                            int &i, int &k, int &x)
 {
-    if (t < 0) t = threadIdx.x;
+    int t = threadIdx.x;
     if (t >= w.npart) return false;
     k = 0;
     while (k + 1 < w.nyb && w.bpref[k + 1] <= t) k++;
@@ -785,31 +785,6 @@ __device__ __forceinline__ uint32_t build_batch(const int4 &pi, const WinEntry<1
     return mask >> (nb - m);
 }
 
-// Order of the block's particles by chunk count, longest list first (counts
-// of kRankBins - 1 chunks and more share the last bin): slot r of perm gets
-// the block index of the particle of rank r.  The force kernel deals the
-// slots to its threads in order, so each wavefront walks lists of similar
-// length and waits less for its longest one.  Called by every thread.
-constexpr int kRankBins = 64;
-
-__device__ __forceinline__ void rank_by_chunks(bool mine, int c, int npart, int *bins, int *from,
-                                               uint8_t *__restrict__ perm)
-{
-    int key = min((c + 7) >> 3, kRankBins - 1);
-    for (int b = threadIdx.x; b < kRankBins; b += blockDim.x) bins[b] = 0;
-    __syncthreads();
-    int at = mine ? atomicAdd(&bins[key], 1) : 0;
-    __syncthreads();
-    // from[b]: particles in the bins above b (the longer lists)
-    for (int b = threadIdx.x; b < kRankBins; b += blockDim.x) {
-        int sum = 0;
-        for (int u = b + 1; u < kRankBins; u++) sum += bins[u];
-        from[b] = sum;
-    }
-    __syncthreads();
-    if (mine && threadIdx.x < npart) perm[from[key] + at] = (uint8_t)threadIdx.x;
-}
-
 // Verlet lists (full windows: every pair within r_c + skin from both sides;
 // half windows: each pair once, in the forward half of the stencil).  Each
 // range of candidates is tested 32 positions at a time into a bit mask, then
@@ -823,13 +798,11 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
                                                    const double *__restrict__ pos, Geom g, int n,
                                                    const int32_t *__restrict__ nblk_p, int cap,
                                                    const int4 *__restrict__ blocks,
-                                                   uint16_t *__restrict__ nbr, int32_t *__restrict__ cnt,
-                                                   uint8_t *__restrict__ perm, int maxn, int esz,
-                                                   int32_t *__restrict__ flags)
+                                                   uint16_t *__restrict__ nbr, int32_t *__restrict__ cnt, int maxn,
+                                                   int esz, int32_t *__restrict__ flags)
 {
     __shared__ WinEntry<1> win[(HALF ? kWinMaxHalf : kWinMax) + 4];  // + the reads past a batch
     __shared__ Window w;
-    __shared__ int bins[kRankBins], from[kRankBins];
     size_t N = (size_t)n;
     int cmax = 0;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
@@ -877,7 +850,6 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
             cmax = max(cmax, c);
             cnt[i] = c < maxn ? c : maxn;
         }
-        if (!HALF) rank_by_chunks(mine, min(c, maxn), w.npart, bins, from, perm + (size_t)blk * 256);
     }
     if (cmax > 0) atomicMax(&flags[2], cmax);
 }
@@ -986,9 +958,9 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
                                                  const int32_t *__restrict__ nblk_p, int cap,
                                                  const int4 *__restrict__ blocks,
                                                  const uint16_t *__restrict__ nbr, const int32_t *__restrict__ cnt,
-                                                 const uint8_t *__restrict__ perm, const PairTab *__restrict__ tabp,
-                                                 const double *__restrict__ pos, float *__restrict__ F,
-                                                 double *__restrict__ partials, int32_t *__restrict__ flags)
+                                                 const PairTab *__restrict__ tabp, const double *__restrict__ pos,
+                                                 float *__restrict__ F, double *__restrict__ partials,
+                                                 int32_t *__restrict__ flags)
 {
     __shared__ WinEntry<NT> win[kWinMax + 1];  // + the far entry
     __shared__ Window w;
@@ -1004,10 +976,8 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
         int blk = it.blk;
         // the list holds window positions: only the window's pieces are needed
         if (!setup_block<NT, false, false, true>(g, cs, st, blocks[blk], w, win, flags)) continue;
-        if ((int)threadIdx.x >= w.npart) continue;
-        // the particles in order of list length (ranked by the list build)
         int i, k, x;
-        if (!my_particle(g, w, cell_sorted, i, k, x, perm[(size_t)blk * 256 + threadIdx.x])) continue;
+        if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
         int4 pi = st[i];
         int c = cnt[i];
         int nch = (c + 7) >> 3;
@@ -1374,12 +1344,10 @@ void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *b
 // there are several).
 static int window_entry_size(const Geom &g) { return g.nt == 1 ? (int)sizeof(WinEntry<1>) : (int)sizeof(WinEntry<2>); }
 
-// maxn is rounded up to whole chunks of eight (the list holds them).  perm
-// (256 slots per block) receives the order of the full lists' particles by
-// length.
+// maxn is rounded up to whole chunks of eight (the list holds them).
 void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
                       const Geom &g, int n, const int32_t *nblk_p, const int4 *blocks, uint16_t *nbr, int32_t *cnt,
-                      uint8_t *perm, int maxn, int32_t *flags, bool half, hipStream_t s)
+                      int maxn, int32_t *flags, bool half, hipStream_t s)
 {
     if (n <= 0) return;
     int cap = (int)window_block_cap(n, g);
@@ -1388,17 +1356,17 @@ void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sor
     if (half) {
         if (g.iso)
             k_vlw_build<true, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                              nbr, cnt, perm, maxn, esz, flags);
+                                                              nbr, cnt, maxn, esz, flags);
         else
             k_vlw_build<false, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                               nbr, cnt, perm, maxn, esz, flags);
+                                                               nbr, cnt, maxn, esz, flags);
     } else {
         if (g.iso)
             k_vlw_build<true, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                               nbr, cnt, perm, maxn, esz, flags);
+                                                               nbr, cnt, maxn, esz, flags);
         else
             k_vlw_build<false, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                                nbr, cnt, perm, maxn, esz, flags);
+                                                                nbr, cnt, maxn, esz, flags);
     }
 }
 
@@ -1420,7 +1388,7 @@ static void win_launch(const ForceArgs &a, const Geom &g, hipStream_t s)
                                                             a.flags);
     } else if (vl) {
         k_vlw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
-                                                       a.w_blk, a.w_nbr, a.nbr_count, a.w_perm, a.tab, a.pos,
+                                                       a.w_blk, a.w_nbr, a.nbr_count, a.tab, a.pos,
                                                        (float *)a.force, a.partials, a.flags);
     } else {
         k_lcw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
