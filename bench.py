@@ -35,7 +35,7 @@ PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no 
 # WRITE_SIZE reads them exactly: 1.0); FP32 work from SQ_INSTS_VALU_FLOPS_FP32
 # (per dispatch, in wavefront instructions weighted by flops per lane, so 64
 # lanes' flops each).  Valid only for the kernel sources they were taken on
-# (sha256 prefix of window.hip, pair.h, md_internal.h); otherwise reported as
+# (sha256 prefix of window.hip, pair.h, md_internal.h, verlet.h); otherwise reported as
 # null.
 VL_COUNTERS = {"kernel": "k_vlw_f32",
                "traffic_sha256": "6dc9cd9c41c6162d", "fetch_kib": 126201.6, "write_kib": 12773.6,
@@ -47,7 +47,7 @@ def force_sources_sha():
     import hashlib
     h = hashlib.sha256()
     base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2505_03438_amd", "csrc")
-    for f in ("window.hip", "pair.h", "md_internal.h"):
+    for f in ("window.hip", "pair.h", "md_internal.h", "verlet.h"):
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -132,6 +132,11 @@ struct md_handle {
     int64_t next_phase = 0;       // step index of the next tuning phase
     double rate[4] = {0, 0, 0, 0};  // recent largest displacements per step (fixed-point units)
     int rate_pos = 0;
+    // fused integrator: the step whose start (first half kick, drift, stage,
+    // skin check) the last force pass already did (-1: none), and how many
+    // per-workgroup kinetic-energy and displacement partials were written last
+    int started = -1;
+    int kpart_blocks = 0, dpart_blocks = 0;
 };
 
 static size_t real_size(const md_config &c) { return c.precision == MD_FP64 ? 8 : 4; }
@@ -144,7 +149,7 @@ static void free_buffers(md_handle *h)
                     b.nbr, b.nbr_count, b.partials, b.kpart, b.dpart, b.flags, b.tab, b.cl_start,
                     b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
                     b.cl_nbr_count, b.snap_pos, b.snap_vel,
-                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart,
+                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart, b.pos_alt, b.stage_alt,
                     b.w_blk, b.w_rown, b.w_rowb, b.w_nbr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -724,17 +729,25 @@ static int rebuild(md_handle *h, const StepCtx &c, bool with_force = true)
 // suppressed, its log entry), start step s (kick, drift, stage, skin check),
 // rebuild when the structure is due (or when force_rebuild), then forces.
 static int snapshot(md_handle *h, const StepCtx &c, bool restore, bool with_force);
-static int step_forces(md_handle *h, const StepCtx &c, int s);
+static int step_forces(md_handle *h, const StepCtx &c, int s, bool fuse = false, bool track_next = false);
 
 static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, bool log_prev_ok = true,
-                    bool snap_after_rebuild = false, bool track = false)
+                    bool snap_after_rebuild = false, bool track = false, bool fuse = false, bool track_next = false)
 {
     bool log_prev = s > 0 && logs_step(c, s - 1) && log_prev_ok;
-    launch_integrate(integ_args(h, c, s > 0, 1, log_prev, s, track), h->g, c.s);
+    if (h->started == s) {
+        // the previous force pass has done the integration (the kinetic
+        // energy and displacement partials included)
+        h->started = -1;
+    } else {
+        launch_integrate(integ_args(h, c, s > 0, 1, log_prev, s, track), h->g, c.s);
+        h->kpart_blocks = integrate_blocks((int)h->n);
+        if (track) h->dpart_blocks = integrate_blocks((int)h->n);
+    }
     if (log_prev) {
         ForceArgs fa = force_args(h, c.pos, c.type, c.force, true);
-        launch_log_entry(h->b.partials, force_blocks(fa), h->energy_gather, h->b.kpart,
-                         integrate_blocks((int)h->n), c.log + 4 * (s / c.energy_every - 1), c.s);
+        launch_log_entry(h->b.partials, force_blocks(fa), h->energy_gather, h->b.kpart, h->kpart_blocks,
+                         c.log + 4 * (s / c.energy_every - 1), c.s);
     }
     h->age++;
     if (force_rebuild || h->age >= h->cfg.rebuild_interval) {
@@ -748,15 +761,52 @@ static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, b
         }
         if (snap_after_rebuild && (rc = snapshot(h, c, false, false))) return rc;
     }
-    return step_forces(h, c, s);
+    return step_forces(h, c, s, fuse, track_next);
 }
 
 // The force pass of step s (energy partials when step s is logged).
-static int step_forces(md_handle *h, const StepCtx &c, int s)
+// The force pass of step s.  fuse: step s + 1 follows at once (same block,
+// no host decision in between), so with the Verlet-list gather kernel the
+// pass also does step s + 1's integration (second half kick of s, first
+// half kick and drift of s + 1): the positions and stage go to the second
+// buffers, which then become the current ones.  track_next: record the
+// displacement partials of that integration (the autotuner's motion).
+static bool fusable(const md_handle *h)
+{
+    return use_window(h->cfg, h->g) && h->cfg.container == MD_CONTAINER_VL && h->cfg.newton3 == MD_N3L_OFF &&
+           h->lists;
+}
+
+static int step_forces(md_handle *h, const StepCtx &c, int s, bool fuse, bool track_next)
 {
     hipEvent_t e0 = timing_event(h), e1 = nullptr;
     if (e0) MD_HIP(hipEventRecord(e0, c.s));
-    int rc = forces_impl(h, c.pos, c.type, c.force, logs_step(c, s), c.s);
+    int rc;
+    bool energy = logs_step(c, s);
+    if (fuse && fusable(h)) {
+        Buffers &b = h->b;
+        size_t n = (size_t)h->n;
+        if (!b.pos_alt && ((rc = dalloc(&b.pos_alt, 3 * std::max<size_t>(n, 1))) ||
+                           (rc = dalloc(&b.stage_alt, std::max<size_t>(n, 1)))))
+            return rc;
+        ForceArgs a = force_args(h, c.pos, c.type, c.force, energy);
+        if (force_blocks(a) > kMaxPartials) return fail(MD_ERR_INVALID_ARG, "too many particles for the reduction");
+        a.fused = true;
+        a.ia = integ_args(h, c, 1, 1, energy, s + 1, track_next);
+        a.ia.stage = b.stage_alt;
+        a.pos_out = b.pos_alt;
+        a.stage_out = b.stage_alt;
+        launch_force(a, h->g, c.s);
+        if (energy) h->energy_gather = true;
+        std::swap(c.pos, b.pos_alt);
+        std::swap(b.stage, b.stage_alt);
+        h->started = s + 1;
+        h->kpart_blocks = force_blocks(a);
+        if (track_next) h->dpart_blocks = force_blocks(a);
+        rc = MD_OK;
+    } else {
+        rc = forces_impl(h, c.pos, c.type, c.force, energy, c.s);
+    }
     if (e0 && (e1 = timing_event(h))) {
         MD_HIP(hipEventRecord(e1, c.s));
         h->tpend.push_back({e0, e1, 0});
@@ -787,6 +837,7 @@ static int snapshot(md_handle *h, const StepCtx &c, bool restore, bool with_forc
         MD_HIP(cp(b.snap_vel, c.vel, 3 * n * rs));
         if (with_force) MD_HIP(cp(b.snap_force, c.force, 3 * n * rs));
     } else {
+        h->started = -1;
         MD_HIP(cp(c.pos, b.snap_pos, 3 * n * 8));
         MD_HIP(cp(c.vel, b.snap_vel, 3 * n * rs));
         if (with_force) MD_HIP(cp(c.force, b.snap_force, 3 * n * rs));
@@ -861,9 +912,13 @@ static int run_block(md_handle *h, const StepCtx &c, int s0, int s_end, int *nex
     launch_fill_i32(h->b.flags + 1, INT32_MAX, 1, c.s);
     // the autotuner tracks the motion at the block's last step
     bool track = h->tuner != nullptr;
+    // every step but the block's last hands its successor's integration to
+    // its force pass where the configuration allows (fused integrator)
     for (int st = s0; st <= last; st++)
-        if ((rc = one_step(h, c, st, false, true, rebuild_first && st == s0, track && st == last))) return rc;
-    if (track) launch_dmax_reduce(h->b.dpart, integrate_blocks((int)h->n), h->b.flags, c.s);
+        if ((rc = one_step(h, c, st, false, true, rebuild_first && st == s0, track && st == last, st < last,
+                           track && st + 1 == last)))
+            return rc;
+    if (track) launch_dmax_reduce(h->b.dpart, h->dpart_blocks, h->b.flags, c.s);
     int32_t f[4];
     if ((rc = read_flags(h, c.s, f))) return rc;
     if (track) update_motion(h, f[3]);
@@ -979,13 +1034,23 @@ extern "C" int md_step(md_handle *h, double *pos, void *vel, void *force, int32_
                 spare = cur;
                 cur = mine;
             };
-            back(c.pos, b.tmp_pos, pos, 3 * n * sizeof(double));
+            // positions rotate through three buffers (the caller's, the cell
+            // build's output, the fused integrator's second buffer)
+            if (c.pos != pos) {
+                if (n > 0) (void)hipMemcpyAsync(pos, c.pos, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, c.s);
+                if (b.tmp_pos == pos)
+                    b.tmp_pos = c.pos;
+                else if (b.pos_alt == pos)
+                    b.pos_alt = c.pos;
+                c.pos = pos;
+            }
             back(c.vel, b.tmp_vel, vel, 3 * n * rs);
             back(c.force, b.tmp_force, force, 3 * n * rs);
             back(c.type, b.tmp_type, type, n * sizeof(int32_t));
             back(c.ids, b.tmp_ids, ids, n * sizeof(int32_t));
         }
     } restore{h, c, pos, vel, force, type, ids};
+    h->started = -1;
     launch_prepare_tab(lj, h->cfg.rc2, h->g, h->b.tab, c.s);
     // lists truncated since the last look (a build before this call overflowed):
     // grow them, rebuild and recompute the entry forces

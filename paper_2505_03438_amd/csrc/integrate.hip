@@ -3,27 +3,9 @@
 // starts the next step (half kick, drift, wrap, fixed-point staging and the
 // skin check of the rebuild policy), so each time step costs one integrator
 // pass plus the force pass.  Kinetic energy is taken between the two kicks.
-#include "pair.h"
+#include "verlet.h"
 
 namespace mdlj {
-
-__device__ __forceinline__ double wrap_box(double x, double L)
-{
-#pragma clang fp contract(off)
-    if (x >= L)
-        x -= L;
-    else if (x < 0.0)
-        x += L;
-    if (x >= L) x = 0.0;  // x + L may round up to exactly L
-    return x;
-}
-
-__device__ __forceinline__ uint32_t quantise_i(double x, double S)
-{
-    double q = x * S;
-    q = q < 0.0 ? 0.0 : (q > 4294967295.0 ? 4294967295.0 : q);
-    return (uint32_t)q;
-}
 
 // ONE_TYPE: a single particle type, so the type array is not read and the
 // staged type field (0, written by the cell build) is left as it is.
@@ -37,54 +19,11 @@ __global__ __launch_bounds__(kBlock) void k_integrate(IntegrateArgs a, Geom g)
     float dmax = 0.f;  // squared displacement since the last build
     if (i < a.n) {
         size_t N = (size_t)a.n;
-        real *v = (real *)a.vel;
         const real *F = (const real *)a.force;
-        int t = ONE_TYPE ? 0 : a.type[i];
-        double im = a.inv_mass[t];
-        real c = (real)(a.hdt * im);  // (dt/2) / m, as in v += (dt/2) (1/m) F
-        real vx = v[i], vy = v[N + i], vz = v[2 * N + i];
-        real ax = c * F[i], ay = c * F[N + i], az = c * F[2 * N + i];
-        if (a.kick_prev) {
-            vx += ax;
-            vy += ay;
-            vz += az;
-            if (a.energy)
-                ke = 0.5 * ((double)vx * (double)vx + (double)vy * (double)vy + (double)vz * (double)vz) / im;
-        }
-        if (a.start) {
-            vx += ax;
-            vy += ay;
-            vz += az;
-            double x = wrap_box(a.pos[i] + a.dt * (double)vx, g.L[0]);
-            double y = wrap_box(a.pos[N + i] + a.dt * (double)vy, g.L[1]);
-            double z = wrap_box(a.pos[2 * N + i] + a.dt * (double)vz, g.L[2]);
-            a.pos[i] = x;
-            a.pos[N + i] = y;
-            a.pos[2 * N + i] = z;
-            int4 q;
-            q.x = (int)quantise_i(x, g.S[0]);
-            q.y = (int)quantise_i(y, g.S[1]);
-            q.z = (int)quantise_i(z, g.S[2]);
-            q.w = t;
-            if (ONE_TYPE)
-                *(int3 *)&a.stage[i] = make_int3(q.x, q.y, q.z);
-            else
-                a.stage[i] = q;
-            // skin check: displacement since the last build, minimum image
-            int4 r = a.stage_ref[i];
-            float dx, dy, dz;
-            staged_delta<ISO>(q, r, g, dx, dy, dz);
-            float d2 = dx * dx + dy * dy + dz * dz;
-            if (d2 >= g.disp2) {
-                atomicOr(&a.flags[0], (int)MD_FLAG_SKIN_EXCEEDED);
-                atomicMin(&a.flags[1], a.step_index);
-            }
-            if (!(x == x && y == y && z == z)) atomicOr(&a.flags[0], (int)MD_FLAG_NONFINITE);
-            dmax = d2;
-        }
-        v[i] = vx;
-        v[N + i] = vy;
-        v[2 * N + i] = vz;
+        VState<real, ONE_TYPE> p;
+        p.load(a, i, N, a.pos, a.start != 0);
+        verlet_update<real, ISO, ONE_TYPE>(a, g, i, N, p, F[i], F[N + i], F[2 * N + i], a.kick_prev != 0,
+                                           a.start != 0, a.pos, a.stage, ke, dmax);
     }
     if (a.start && a.dpart) {
         // largest squared displacement since the last build, per block: the

@@ -84,6 +84,10 @@ struct Buffers {
     int64_t cl_cap = 0, cl_list_cap = 0;
     int32_t n_clusters_max = 0;
     // rollback snapshot (md_step)
+    // second position and stage buffers of the fused integrator (the force
+    // pass of one step writes the next step's positions beside the current)
+    double *pos_alt = nullptr;
+    int4 *stage_alt = nullptr;
     double *snap_pos = nullptr;
     void *snap_vel = nullptr, *snap_force = nullptr;
     int32_t *snap_type = nullptr, *snap_ids = nullptr;
@@ -137,6 +141,26 @@ void launch_prepare_tab(const double *lj, const double *rc2_host, const Geom &g,
 void launch_bin_counts(int n, const double *pos, const Geom &g, int32_t *count, hipStream_t s);
 
 // force.hip
+struct IntegrateArgs {
+    int n;
+    int precision;
+    double *pos;
+    void *vel;
+    const void *force;
+    const int32_t *type;
+    const double *inv_mass;
+    double hdt, dt;
+    int kick_prev;  // complete the previous step: v += dt/2 F/m (and kinetic energy)
+    int start;      // start a step: v += dt/2 F/m; x += dt v; wrap; stage; skin check
+    int energy;
+    int step_index;
+    int4 *stage;
+    const int4 *stage_ref;
+    int32_t *flags;
+    double *kpart;
+    float *dpart;  // if not null: per-block largest squared displacement since the build
+};
+
 struct ForceArgs {
     int n;
     int precision;
@@ -162,6 +186,13 @@ struct ForceArgs {
     const int32_t *w_nblk;
     const int4 *w_blk;
     const uint16_t *w_nbr;
+    // the Verlet-list gather kernel may also advance each particle right
+    // after its force (second half kick of this step, first half kick and
+    // drift of the next): positions and stage then go to pos_out, stage_out
+    bool fused;
+    IntegrateArgs ia;
+    double *pos_out;
+    int4 *stage_out;
 };
 int force_blocks(const ForceArgs &a);  // number of partial slots written when energy
 void launch_force(const ForceArgs &a, const Geom &g, hipStream_t s);
@@ -189,25 +220,7 @@ void launch_reduce_out(const double *partials, int nblocks, int gather, double *
                        hipStream_t s);
 
 // integrate.hip
-struct IntegrateArgs {
-    int n;
-    int precision;
-    double *pos;
-    void *vel;
-    const void *force;
-    const int32_t *type;
-    const double *inv_mass;
-    double hdt, dt;
-    int kick_prev;  // complete the previous step: v += dt/2 F/m (and kinetic energy)
-    int start;      // start a step: v += dt/2 F/m; x += dt v; wrap; stage; skin check
-    int energy;
-    int step_index;
-    int4 *stage;
-    const int4 *stage_ref;
-    int32_t *flags;
-    double *kpart;
-    float *dpart;  // if not null: per-block largest squared displacement since the build
-};
+
 int integrate_blocks(int n);
 void launch_integrate(const IntegrateArgs &a, const Geom &g, hipStream_t s);
 void launch_log_entry(const double *fpart, int fblocks, int gather, const double *kpart,

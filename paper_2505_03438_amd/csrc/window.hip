@@ -19,7 +19,7 @@
 // Blocks of neighbouring cells share most of their windows, so the blocks
 // are dealt to the eight XCDs in contiguous chunks (workgroup w runs on XCD
 // w mod 8) to keep the shared window data in one L2.
-#include "pair.h"
+#include "verlet.h"
 
 namespace mdlj {
 
@@ -951,8 +951,13 @@ __device__ __forceinline__ void vl_step(const int4 &pi, const WinEntry<NT> *__re
 // byte offsets; the last chunk is padded with the far entry, whose pairs
 // never interact); the next chunk's load is in flight while the current one
 // is computed.  A chunk with an entry that may lie in the guard band (rare)
-// is walked again for those entries.
-template <int NT, bool ISO, bool ENERGY>
+// is walked again for those entries.  FUSED: each thread then advances its
+// particle (verlet_update: this step's second half kick, the next step's
+// first half kick, drift, stage and skin check), reading the positions from
+// pos and writing them to pos_out and stage_out (other blocks still read pos
+// and st); the kinetic energy and the largest displacement go to ia.kpart
+// and ia.dpart per workgroup.
+template <int NT, bool ISO, bool ENERGY, bool FUSED>
 __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                  const int32_t *__restrict__ cell_sorted, Geom g, int n,
                                                  const int32_t *__restrict__ nblk_p, int cap,
@@ -960,7 +965,8 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
                                                  const uint16_t *__restrict__ nbr, const int32_t *__restrict__ cnt,
                                                  const PairTab *__restrict__ tabp, const double *__restrict__ pos,
                                                  float *__restrict__ F, double *__restrict__ partials,
-                                                 int32_t *__restrict__ flags)
+                                                 int32_t *__restrict__ flags, IntegrateArgs ia, double *pos_out,
+                                                 int4 *stage_out)
 {
     __shared__ WinEntry<NT> win[kWinMax + 1];  // + the far entry
     __shared__ Window w;
@@ -971,6 +977,8 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
     const float mid = 0.5f * (t.lo[0] + t.hi[0]), hw = 0.5f * (t.hi[0] - t.lo[0]) * 1.125f;
     float eu = 0.f, ew = 0.f;
     int np = 0;
+    double ke = 0.0;
+    float dmax = 0.f;
     size_t N = (size_t)n;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
@@ -982,6 +990,8 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
         int c = cnt[i];
         int nch = (c + 7) >> 3;
         float fx = 0.f, fy = 0.f, fz = 0.f;
+        VState<float, NT == 1> vs;
+        if (FUSED) vs.load(ia, i, N, pos, true);  // in flight during the force loop
         // chunk ch of particle i is row[ch * n]; the list has one chunk row
         // more than it can fill, so the prefetch past the last chunk is an
         // in-bounds load
@@ -1023,12 +1033,33 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
         F[i] = fx;
         F[N + i] = fy;
         F[2 * N + i] = fz;
+        if (FUSED) {
+            double kei = 0.0;
+            float d2 = 0.f;
+            verlet_update<float, ISO, NT == 1>(ia, g, i, N, vs, fx, fy, fz, true, true, pos_out, stage_out, kei, d2);
+            ke += kei;
+            dmax = fmaxf(dmax, d2);
+        }
     }
     if (ENERGY) {
         double v[4] = {(double)eu, (double)ew, (double)np, 0.0};
         block_sum4(v, sh);
         if (threadIdx.x == 0)
             for (int k = 0; k < 4; k++) partials[blockIdx.x * 4 + k] = v[k];
+    }
+    if (FUSED) {
+        if (ia.energy) {
+            double v[4] = {ke, 0.0, 0.0, 0.0};
+            block_sum4(v, sh);
+            if (threadIdx.x == 0) ia.kpart[blockIdx.x] = v[0];
+        }
+        if (ia.dpart) {
+            __shared__ float wm[256 / 64];
+            for (int off = 32; off > 0; off >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, off, 64));
+            if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = dmax;
+            __syncthreads();
+            if (threadIdx.x == 0) ia.dpart[blockIdx.x] = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+        }
     }
 }
 
@@ -1387,9 +1418,14 @@ static void win_launch(const ForceArgs &a, const Geom &g, hipStream_t s)
                                                             cap, a.w_blk, a.tab, a.pos, (float *)a.force, a.partials,
                                                             a.flags);
     } else if (vl) {
-        k_vlw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
-                                                       a.w_blk, a.w_nbr, a.nbr_count, a.tab, a.pos,
-                                                       (float *)a.force, a.partials, a.flags);
+        if (a.fused)
+            k_vlw_f32<NT, ISO, EN, true><<<kWinGrid, 256, 0, s>>>(
+                a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap, a.w_blk, a.w_nbr, a.nbr_count, a.tab,
+                a.pos, (float *)a.force, a.partials, a.flags, a.ia, a.pos_out, a.stage_out);
+        else
+            k_vlw_f32<NT, ISO, EN, false><<<kWinGrid, 256, 0, s>>>(
+                a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap, a.w_blk, a.w_nbr, a.nbr_count, a.tab,
+                a.pos, (float *)a.force, a.partials, a.flags, a.ia, a.pos_out, a.stage_out);
     } else {
         k_lcw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
                                                        a.w_blk, a.tab, a.pos, (float *)a.force, a.partials,
