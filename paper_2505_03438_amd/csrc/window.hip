@@ -809,47 +809,46 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
         int blk = it.blk;
         if (!setup_block<1, HALF>(g, cs, st, blocks[blk], w, win, flags)) continue;
         int i, k, x;
-        bool mine = my_particle(g, w, cell_sorted, i, k, x);
+        if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
+        int self = self_position<HALF>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
+        int4 pi = win[self].get();
+        uint4 *row = (uint4 *)nbr + i;
         int c = 0;
-        if (mine) {
-            int self = self_position<HALF>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
-            int4 pi = win[self].get();
-            uint4 *row = (uint4 *)nbr + i;
-            Chunk ck;
-            const Band band(g);
-            stencil_ranges<HALF>(g, w, k, x, self, [&](int b, int en) {
-                for (int base = b; base < en; base += 32) {
-                    int m = min(32, en - base);
-                    bool amb;
-                    uint32_t mask = build_batch<ISO>(pi, win + base, m, g, band, amb);
-                    unsigned us = (unsigned)(self - base);
-                    if (us < (unsigned)m) mask &= ~(1u << (m - 1 - us));
-                    if (amb) {
-                        // rare: guard-band candidates decided from the FP64 positions
-                        for (uint32_t t = mask; t;) {
-                            int h = 31 - __builtin_clz(t);
-                            t ^= 1u << h;
-                            int p = base + m - 1 - h;
-                            float dx, dy, dz;
-                            staged_delta<ISO>(pi, win[p].get(), g, dx, dy, dz);
-                            float r2 = dx * dx + dy * dy + dz * dz;
-                            if (r2 >= g.rl2_lo &&
-                                !(exact_r2(pos, n, i, window_global(w, p), g.L[0], g.L[1], g.L[2]) < g.rl2))
-                                mask ^= 1u << h;
-                        }
-                    }
-                    while (mask) {
-                        int h = 31 - __builtin_clz(mask);
-                        mask ^= 1u << h;
-                        list_append((uint32_t)((base + m - 1 - h) * esz), c, ck, row, N, maxn);
+        Chunk ck;
+        const Band band(g);
+        stencil_ranges<HALF>(g, w, k, x, self, [&](int b, int en) {
+            for (int base = b; base < en; base += 32) {
+                int m = min(32, en - base);
+                bool amb;
+                uint32_t mask = build_batch<ISO>(pi, win + base, m, g, band, amb);
+                unsigned us = (unsigned)(self - base);
+                if (us < (unsigned)m) mask &= ~(1u << (m - 1 - us));
+                if (amb) {
+                    // rare: guard-band candidates decided from the FP64 positions
+                    for (uint32_t t = mask; t;) {
+                        int h = 31 - __builtin_clz(t);
+                        t ^= 1u << h;
+                        int p = base + m - 1 - h;
+                        float dx, dy, dz;
+                        staged_delta<ISO>(pi, win[p].get(), g, dx, dy, dz);
+                        float r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 >= g.rl2_lo &&
+                            !(exact_r2(pos, n, i, window_global(w, p), g.L[0], g.L[1], g.L[2]) < g.rl2))
+                            mask ^= 1u << h;
                     }
                 }
-            });
-            list_finish(c, ck, row, N, maxn, HALF ? 0u : (uint32_t)(kWinMax * esz));
-            if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
-            cmax = max(cmax, c);
-            cnt[i] = c < maxn ? c : maxn;
-        }
+                // entries are window positions times esz (< 2^16: a 24-bit product)
+                while (mask) {
+                    int h = 31 - __builtin_clz(mask);
+                    mask ^= 1u << h;
+                    list_append(__umul24((unsigned)(base + m - 1 - h), (unsigned)esz), c, ck, row, N, maxn);
+                }
+            }
+        });
+        list_finish(c, ck, row, N, maxn, HALF ? 0u : (uint32_t)(kWinMax * esz));
+        if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
+        cmax = max(cmax, c);
+        cnt[i] = c < maxn ? c : maxn;
     }
     if (cmax > 0) atomicMax(&flags[2], cmax);
 }

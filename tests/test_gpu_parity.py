@@ -282,6 +282,31 @@ def test_nve_fp32_energy_conservation(orc, cont):
     assert abs(slope) < 1e-2
 
 
+def test_fused_integration_matches_separate_steps(orc):
+    """Within a block of steps the Verlet-list force pass also integrates
+    the next step; a run of single-step calls (each its own block) never
+    does.  Both run the same arithmetic, so the trajectories agree bit for
+    bit."""
+    import torch
+    d = W.plain_fcc_864()
+    out = []
+    for split in (False, True):
+        cfg = make_config(864, d["box"], container=1, precision=0, R=5)
+        s = DeviceSystem(cfg, d["pos"], d["vel"])
+        s.build()
+        s.forces(energy=False)
+        if split:
+            for _ in range(20):
+                M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, 1)
+        else:
+            M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, 20)
+        torch.cuda.synchronize()
+        assert M.md_get_counters(s.h)["forced_rebuilds"] == 0
+        out.append((s.by_id(s.pos), s.by_id(s.vel), s.by_id(s.force)))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("csf", [1.0, 0.5])
 def test_cluster_lists_cover_verlet_pairs(orc, csf):
     """Every pair within r_c + skin at the build is a candidate of the cluster
