@@ -37,10 +37,14 @@ PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no 
 # lanes' flops each).  Valid only for the kernel sources they were taken on
 # (sha256 prefix of window.hip, pair.h, md_internal.h, verlet.h); otherwise reported as
 # null.
-VL_COUNTERS = {"kernel": "k_vlw_f32",
-               "traffic_sha256": "6dc9cd9c41c6162d", "fetch_kib": 126201.6, "write_kib": 12773.6,
+# Counter runs of the Verlet-list gather force kernel (fluid, CSF 1, R 7),
+# per dispatch and per variant: "fused" also integrates each particle for the
+# next step (every step of a rebuild interval but its last), "plain" does not.
+# Valid while the force sources hash to "sha".
+VL_COUNTERS = {"kernel": "k_vlw_f32", "sha": "1e6ff319434eaf59",
                "fetch_factor": 2.0, "write_factor": 1.0,
-               "flops_sha256": "6dc9cd9c41c6162d", "valu_flops_fp32_wave": 27020949.9}
+               "fused": {"fetch_kib": 144715.3, "write_kib": 66148.0, "valu_flops_fp32_wave": 28150547.1},
+               "plain": {"fetch_kib": 116584.2, "write_kib": 12377.9, "valu_flops_fp32_wave": 28004872.5}}
 
 
 def force_sources_sha():
@@ -53,22 +57,35 @@ def force_sources_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kname):
-    """HBM bytes per launch of the force kernel from the counter runs, or
-    None if they do not cover this kernel as it is now."""
+def _variant_mix(R):
+    """Share of the force passes of a rebuild interval of R steps that run the
+    fused variant (all but the interval's last)."""
+    R = max(int(R), 1)
+    return (R - 1) / R
+
+
+def measured_traffic(kname, R):
+    """HBM bytes per launch of the force kernel from the counter runs (the
+    variants weighted as a rebuild interval of R steps runs them), or None if
+    they do not cover this kernel as it is now."""
     t = VL_COUNTERS
-    if kname != t["kernel"] or force_sources_sha() != t["traffic_sha256"]:
+    if kname != t["kernel"] or force_sources_sha() != t["sha"]:
         return None
-    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+    w = _variant_mix(R)
+    by = {k: 1024.0 * (t[k]["fetch_kib"] * t["fetch_factor"] + t[k]["write_kib"] * t["write_factor"])
+          for k in ("fused", "plain")}
+    return w * by["fused"] + (1.0 - w) * by["plain"]
 
 
-def measured_flops(kname):
+def measured_flops(kname, R):
     """FP32 flops issued per launch of the force kernel (every lane of every
-    VALU instruction, idle lanes of divergent loops included), or None."""
+    VALU instruction, idle lanes of divergent loops included; variants
+    weighted as in measured_traffic), or None."""
     t = VL_COUNTERS
-    if kname != t["kernel"] or not t["valu_flops_fp32_wave"] or force_sources_sha() != t["flops_sha256"]:
+    if kname != t["kernel"] or force_sources_sha() != t["sha"]:
         return None
-    return 64.0 * t["valu_flops_fp32_wave"]
+    w = _variant_mix(R)
+    return 64.0 * (w * t["fused"]["valu_flops_fp32_wave"] + (1.0 - w) * t["plain"]["valu_flops_fp32_wave"])
 
 
 def log(*a):
@@ -88,6 +105,8 @@ def cpu_model():
 
 def make_cfg(M, n, box, kind, steps):
     c = M.config_default(n, float(box[0]))
+    for d in range(3):
+        c.box[d] = float(box[d])
     c.precision = M.MD_FP32
     c.skin = 0.3
     c.max_neighbors = 128
@@ -329,14 +348,16 @@ def main():
                                                              extra[kind]["force_kernel_ms"]))
     achieved = FLOPS_PER_PAIR * auto["pairs_per_step"] / (auto["force_kernel_ms"] * 1e-3)
     kname = force_kernel_name(auto["final_config"], auto["counters"]["force_family"])
-    traffic = measured_traffic(kname)
+    R_final = auto["final_config"]["rebuild_interval"]
+    traffic = measured_traffic(kname, R_final)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32, "traffic": traffic, "kernel": kname,
-            "traffic_unit": "bytes per launch (HBM, counters)",
+            "traffic_unit": "bytes per launch (HBM, counters; variants weighted as a rebuild interval of "
+                            "R = %d steps runs them: fused (R - 1)/R, plain 1/R)" % R_final,
             "hbm_GBps_at_kernel_time": (traffic / (auto["force_kernel_ms"] * 1e-3) / 1e9) if traffic else None,
             "kernel_ms": auto["force_kernel_ms"],
             "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED}
-    issued = measured_flops(kname)
+    issued = measured_flops(kname, R_final)
     roof["valu_fp32_issued"] = ({"flops_per_launch": issued,
                                  "TFLOPs": issued / (auto["force_kernel_ms"] * 1e-3) / 1e12,
                                  "frac": issued / (auto["force_kernel_ms"] * 1e-3) / PEAK_FP32,

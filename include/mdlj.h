@@ -121,7 +121,10 @@ void md_destroy(md_handle *h);
  * lists by the 6-bit Morton code of the position inside the cell, then id).  ids carries each
  * particle's caller-defined identity through every reordering.  vel and force
  * may be NULL (then they are not permuted).  Also stages the positions for
- * the pair kernels and records them as the reference for the skin check. */
+ * the pair kernels and records them as the reference for the skin check.
+ * Positions belong in [0, box[d]); one more than a cell outside the box, or
+ * a non-finite one, is binned into an edge cell and sets MD_FLAG_NONFINITE
+ * (this call does not wait to see it; md_step does). */
 int md_build_cells(md_handle *h, double *pos, void *vel, void *force,
                    int32_t *type, int32_t *ids, void *stream);
 
@@ -153,7 +156,10 @@ int md_compute_forces(md_handle *h, const double *pos, const int32_t *type,
  * DEVICE double[n_types].  If energy_every > 0 and log is not NULL (DEVICE
  * double[nsteps / energy_every][4]), after every energy_every-th step it
  * receives { U, K = 1/2 sum m v^2, W, n_pairs }.  Synchronises the stream
- * once per rebuild interval (to read the skin check). */
+ * once per rebuild interval (to read the skin check).  MD_ERR_NONFINITE when
+ * MD_FLAG_NONFINITE is set (by this call or an earlier one, until md_status
+ * clears it); MD_ERR_INVALID_ARG when a cell neighbourhood outgrows the LDS
+ * tile of the windowed kernels. */
 int md_step(md_handle *h, double *pos, void *vel, void *force, int32_t *type,
             int32_t *ids, const double *inv_mass, const double *lj, double dt,
             int32_t nsteps, int32_t energy_every, double *log, void *stream);

@@ -858,9 +858,25 @@ static int read_flags(md_handle *h, hipStream_t s, int32_t out[4])
     out[2] = (int32_t)h->b.host_flags[2];
     out[3] = (int32_t)h->b.host_flags[4];  // squared displacement since the build (float bits)
     timing_collect(h);
-    if (h->b.host_flags[3])
-        return fail(MD_ERR_INVALID_ARG, "a cell neighbourhood exceeds the windowed traversal's LDS tile "
-                                        "(density far above liquid); use MD_N3L_ON or csf 0.5");
+    if (h->b.host_flags[0] & MD_FLAG_NONFINITE) {
+        // checked first: a particle far outside the box is binned into an
+        // edge cell, which can also overfill a window
+        h->sticky |= MD_FLAG_NONFINITE;
+        return fail(MD_ERR_NONFINITE,
+                    "a position outside the box (beyond one cell) or a non-finite position or force appeared; "
+                    "md_status clears the flag");
+    }
+    if (h->b.host_flags[3]) {
+        // 1: the packer met a single cell column whose window exceeds the
+        // tile; 2: a kernel met a block whose window does (never made by the
+        // packer)
+        char msg[200];
+        snprintf(msg, sizeof(msg),
+                 "a cell neighbourhood exceeds the windowed traversal's LDS tile (code %u; density far above "
+                 "liquid); use MD_N3L_ON or csf 0.5",
+                 (unsigned)h->b.host_flags[3]);
+        return fail(MD_ERR_INVALID_ARG, msg);
+    }
     return MD_OK;
 }
 

@@ -152,20 +152,28 @@ def slab(n: int = 2_000_000, rho_l: float = 0.75, rho_v: float = 0.02, T: float 
     liq[2] += Lx
     n_liq = liq.shape[1]
     n_vap = n - n_liq
-    # vapour: a random subset of a grid twice as fine as the mean spacing
-    # (the liquid lattice, fitted to whole cells, may hold slightly fewer
-    # particles than rho_l Lx^3, and the vapour takes the rest)
+    # vapour: a random subset of a grid about twice as fine as the mean
+    # spacing, filling the space between the slab's faces (the liquid
+    # lattice, fitted to whole cells, may hold slightly fewer particles than
+    # rho_l Lx^3, and the vapour takes the rest).  Its layers keep `gap` plus
+    # half a layer step from the outermost liquid layers (z = Lx and z = top),
+    # so that no vapour particle starts inside the repulsive core of a liquid
+    # one.
+    top = Lx + (ncz - 0.5) * ax
+    gap = 1.0
+    hv = Lz - (top - Lx) - 2.0 * gap
     av = 0.5 * (1.0 / rho_v) ** (1.0 / 3.0)
     nvx = int(math.floor(Lx / av))
     avx = Lx / nvx
-    nvz = int(math.floor(Lx / avx))
-    gx, gy, gz = np.meshgrid(np.arange(nvx), np.arange(nvx), np.arange(2 * nvz), indexing="ij")
-    vap = np.stack([gx.ravel(), gy.ravel(), gz.ravel()]).astype(np.float64) * avx + 0.5 * avx
-    vap[2] = np.where(vap[2] >= Lx, vap[2] + Lx + (Lx - nvz * avx), vap[2])
+    nvz = int(math.floor(hv / av))
+    avz = hv / nvz
+    gx, gy, gz = np.meshgrid(np.arange(nvx), np.arange(nvx), np.arange(nvz), indexing="ij")
+    vap = np.stack([(gx.ravel() + 0.5) * avx, (gy.ravel() + 0.5) * avx,
+                    top + gap + (gz.ravel() + 0.5) * avz]).astype(np.float64)
     if vap.shape[1] < n_vap:
         raise ValueError("vapour lattice too small")
     vap = vap[:, rng.choice(vap.shape[1], n_vap, replace=False)]
-    vap = vap + rng.uniform(-0.2 * avx, 0.2 * avx, size=vap.shape)
+    vap = vap + rng.uniform(-0.2, 0.2, size=vap.shape) * np.array([[avx], [avx], [avz]])
     liq = liq + rng.uniform(-jitter * ax, jitter * ax, size=liq.shape)
     pos = np.concatenate([liq, vap], axis=1)
     pos = pos[:, rng.permutation(n)]

@@ -152,3 +152,14 @@ def test_probe_library_exports_its_header():
     L.mdprobe_fma_f32.restype = ctypes.c_int
     L.mdprobe_fma_f32.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
     assert L.mdprobe_fma_f32(0, 1, None, None) == -1
+
+
+def test_bench_config_takes_every_box_side(M):
+    # the slab's box is 1:1:3; a cubic configuration would fold two thirds of
+    # it onto the edge cells
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    for kind in ("auto", "plain", "fixed:vl:1:0:5"):
+        c = bench.make_cfg(M, 1000, [12.0, 13.0, 39.0], kind, 100)
+        assert list(c.box) == [12.0, 13.0, 39.0], kind

@@ -201,6 +201,26 @@ def test_forces_need_lists_after_cell_build(orc):
             s.forces()
 
 
+def test_step_reports_position_outside_box(orc):
+    """A particle placed far outside the box is binned into an edge cell (no
+    access leaves the cell arrays) and flagged: md_step fails with
+    MD_ERR_NONFINITE until md_status clears the flag."""
+    pos, box = _jittered(6, 8, jitter=0.1)
+    n = pos.shape[1]
+    pos = pos.copy()
+    pos[2, 5] = 2.5 * box[2]
+    for cont in (0, 1):
+        cfg = make_config(n, box, container=cont, precision=0)
+        s = DeviceSystem(cfg, pos)
+        s.build()
+        s.forces()
+        with pytest.raises(RuntimeError, match=r"\(-4\).*outside the box"):
+            M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.001, 2)
+        assert M.md_status(s.h) & M.MD_FLAG_NONFINITE
+        assert not (M.md_status(s.h) & M.MD_FLAG_NONFINITE)
+        s.h.close()
+
+
 # ---------------------------------------------------------------- Verlet sets
 
 @pytest.mark.parametrize("csf", [1.0, 0.5])
