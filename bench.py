@@ -122,10 +122,10 @@ def make_cfg(M, n, box, kind, steps):
         c.csf = float(csf)
         c.newton3 = int(n3)
         c.rebuild_interval = int(R)
-    else:  # autotuned, Predictive strategy
+    else:  # autotuned: Predictive strategy ("auto") or Expert rules ("expert")
         c.container = M.MD_CONTAINER_LC
         c.rebuild_interval = 10
-        c.autotune = M.MD_TUNE_PREDICTIVE
+        c.autotune = M.MD_TUNE_EXPERT if kind == "expert" else M.MD_TUNE_PREDICTIVE
         # two tuning phases (at steps 0 and steps/2): a phase trials every
         # configuration for tune_trial_steps steps, so shorter intervals would
         # spend most of a 1000-step run in trials (with four phases the
@@ -285,6 +285,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-expert", action="store_true", help="skip the run under the Expert strategy")
     ap.add_argument("--extra", default="", help="comma-separated extra fixed configs to time, "
                     "e.g. fixed:vl:1:0:5 (container:csf:n3l:R)")
     ap.add_argument("--ncell", type=int, default=64, help="FCC cells per side (64 -> 1,048,576 particles)")
@@ -336,6 +337,11 @@ def main():
     auto = run(M, d, "auto", args.steps, args.warmup)
     log("autotuned: %.3f ms/step, %.3e pairs/s, config %s" % (auto["ms_per_step"], auto["pairs_per_s"],
                                                              auto["final_config"]))
+    expert = None
+    if not args.no_expert:
+        expert = run(M, d, "expert", args.steps, args.warmup)
+        log("expert rules: %.3f ms/step, %.3e pairs/s, config %s, %d trials" % (
+            expert["ms_per_step"], expert["pairs_per_s"], expert["final_config"], expert["counters"]["trials"]))
     plain = None
     if not args.no_plain:
         plain = run(M, d, "plain", args.steps, args.warmup)
@@ -391,6 +397,7 @@ def main():
                    "T": float(d.get("T", 1.0)), "rc": 2.5, "skin": 0.3, "dt": 0.005, "positions": "f64",
                    "pair_arithmetic": "f32", "strategy": "predictive", "parallelism": "single-gpu"},
         "autotuned": auto,
+        "expert_strategy": expert,
         "plain": plain,
         "fixed_configs": extra or None,
         "speedup_vs_plain": (auto["pairs_per_s"] / plain["pairs_per_s"]) if plain else None,

@@ -68,6 +68,13 @@ extern "C" {
 #define MD_TUNE_OFF 0
 #define MD_TUNE_FULL 1
 #define MD_TUNE_PREDICTIVE 2
+#define MD_TUNE_EXPERT 3 /* Sec. 5.2: fuzzy rules over the live statistics  */
+
+/* consequents of the Expert strategy's fuzzy rules: terms of the output
+ * variable "suitability" on [0, 1] (triangles peaking at 0, 0.5 and 1) */
+#define MD_SUIT_BAD 0
+#define MD_SUIT_OKAY 1
+#define MD_SUIT_GOOD 2
 
 /* md_status flag bits */
 #define MD_FLAG_LIST_OVERFLOW 1u  /* a neighbour row exceeded max_neighbors   */
@@ -252,6 +259,53 @@ int md_batch_step(md_batch *b, double *pos, void *vel, void *force,
                   int32_t use_graph, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Scores of the autotuner's trials: scores (HOST double[n]) gets, per
+ * configuration of the tuning space, its last measured score (ms per step:
+ * per-step time plus build time spread over its rebuild interval) or NaN if
+ * it was never trialled; configs (HOST md_config[n], may be NULL) gets the
+ * configurations themselves.  Returns the size of the tuning space (n must be
+ * at least that), or MD_ERR_INVALID_ARG when the handle does not tune.  The
+ * data from which Expert rules are written (Sec. 5.2). */
+int md_get_trial_scores(md_handle *h, double *scores, md_config *configs,
+                        int32_t n);
+
+/* Expert strategy (Sec. 5.2, with the fuzzy logic of Sec. 2.3): a rule
+ *   IF stats[input[0]] IS trap[0] (AND stats[input[1]] IS trap[1])
+ *   THEN suitability(config) IS then
+ * where stats are the live statistics in md_live_stats order and trap[k] =
+ * (a, b, c, d) is a trapezoid membership function: 0 outside (a, d), rising
+ * linearly on [a, b], 1 on [b, c], falling on [c, d]; a = b = -INFINITY or
+ * c = d = INFINITY make shoulders.  input[1] = -1: one antecedent.  config
+ * indexes the tuning space (md_get_trial_scores lists it).  Evaluation:
+ * firing strength = min over the antecedents; each rule clips its output
+ * term at its strength; a configuration's clipped terms are joined by max;
+ * the crisp suitability is the centre of gravity of that set over [0, 1],
+ * or 0 if none of its rules fires.  A tuning phase trials every
+ * configuration whose suitability is within 0.1 of the largest (all of them
+ * if no rule fires at all). */
+typedef struct md_fuzzy_rule {
+    int32_t input[2];
+    double trap[2][4];
+    int32_t config;
+    int32_t then; /* MD_SUIT_* */
+} md_fuzzy_rule;
+
+/* Rules the Expert strategy of this handle uses (copied).  rules NULL or
+ * n_rules 0 restores the built-in rules, which were written from Full Search
+ * scores measured on MI355X and use the mean particles per bin only.
+ * MD_ERR_INVALID_ARG for an input outside 0..7, a config outside the tuning
+ * space, an unknown term or a trapezoid with a > b, b > c, c > d or NaN. */
+int md_set_expert_rules(md_handle *h, const md_fuzzy_rule *rules,
+                        int32_t n_rules);
+
+/* Host only: the crisp suitability (HOST double[n_configs]) of each
+ * configuration under rules (NULL: those built-in rules that name
+ * configurations below n_configs) for the live statistics stats (HOST
+ * double[8]).  Same validation as md_set_expert_rules. */
+int md_expert_suitability(const md_fuzzy_rule *rules, int32_t n_rules,
+                          int32_t n_configs, const double *stats,
+                          double *suitability);
+
 /* Configuration-selection engine, usable on its own with externally measured
  * scores (host only; needs no GPU).  Sec. 2.2.5 Full Search and Sec. 5.1
  * Predictive: trial all in the first two phases; predict each configuration
@@ -259,7 +313,9 @@ int md_batch_step(md_batch *b, double *pos, void *vel, void *force,
  * half its last score); trial those predicted within rel_threshold of the
  * best prediction (inclusive) or not trialled for ceil(total_phases/4)
  * phases; blacklist those measured above blacklist_factor x the phase's best;
- * choose the lowest score (ties: lower index). */
+ * choose the lowest score (ties: lower index).  Sec. 5.2 Expert: trial the
+ * configurations whose suitability (md_tuner_set_suitability, before each
+ * phase) is within 0.1 of the largest; no blacklist. */
 typedef struct md_tuner md_tuner;
 
 int md_tuner_create(int32_t strategy, int32_t n_configs, int32_t total_phases,
@@ -269,6 +325,9 @@ void md_tuner_destroy(md_tuner *t);
 /* Start the next phase; trial[n_configs] (HOST) gets 1 for configurations to
  * trial, 0 otherwise.  Returns the number to trial (>= 0) or an error. */
 int md_tuner_begin_phase(md_tuner *t, int32_t *trial);
+/* Expert strategy: the suitability (HOST double[n_configs], each in [0, 1])
+ * the next begin_phase selects by; all 0 (the default) trials everything. */
+int md_tuner_set_suitability(md_tuner *t, const double *suitability);
 /* Report the measured score (lower is better) of a trialled configuration. */
 int md_tuner_report(md_tuner *t, int32_t config, double score);
 /* Finish the phase: returns the chosen configuration index (>= 0) or an

@@ -124,6 +124,7 @@ struct md_handle {
     // autotuning
     mdlj::Tuner *tuner = nullptr;
     std::vector<md_config> space;
+    std::vector<md_fuzzy_rule> rules;  // Expert strategy
     int64_t steps_done = 0;       // md_step steps since creation
     uint32_t sticky = 0;          // flag bits already read back from the device
     bool truncated = false;       // the current lists overflowed max_neighbors
@@ -140,6 +141,15 @@ struct md_handle {
 };
 
 static size_t real_size(const md_config &c) { return c.precision == MD_FP64 ? 8 : 4; }
+
+// The built-in Expert rules, less those naming configurations outside this
+// handle's tuning space (cluster lists are FP32 only).
+static void set_builtin_rules(md_handle *h)
+{
+    h->rules.clear();
+    for (const md_fuzzy_rule &u : builtin_rules())
+        if (u.config < (int)h->space.size()) h->rules.push_back(u);
+}
 
 static void free_buffers(md_handle *h)
 {
@@ -234,7 +244,8 @@ static int validate_config(const md_config *c)
         return fail(MD_ERR_INVALID_ARG, "cluster lists run in FP32 (precision = MD_FP32)");
     if (c->rebuild_interval < 1) return fail(MD_ERR_INVALID_ARG, "rebuild_interval must be >= 1");
     if (c->max_neighbors < 1 || c->max_neighbors > 4096) return fail(MD_ERR_INVALID_ARG, "max_neighbors out of range");
-    if (c->autotune != MD_TUNE_OFF && c->autotune != MD_TUNE_FULL && c->autotune != MD_TUNE_PREDICTIVE)
+    if (c->autotune != MD_TUNE_OFF && c->autotune != MD_TUNE_FULL && c->autotune != MD_TUNE_PREDICTIVE &&
+        c->autotune != MD_TUNE_EXPERT)
         return fail(MD_ERR_INVALID_ARG, "bad autotune");
     if (c->autotune != MD_TUNE_OFF && (c->tune_interval < 1 || c->tune_trial_steps < 2))
         return fail(MD_ERR_INVALID_ARG, "tune_interval >= 1 and tune_trial_steps >= 2 required");
@@ -327,6 +338,7 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
         tuning_space(*cfg, h->space);
         int total_phases = std::max(1, (int)((cfg->total_steps_hint + cfg->tune_interval - 1) / cfg->tune_interval));
         h->tuner = new Tuner(cfg->autotune, (int)h->space.size(), total_phases, 2.0, 10.0);
+        set_builtin_rules(h);
     }
     if (hipDeviceSynchronize() != hipSuccess) {
         md_destroy(h);
@@ -1148,15 +1160,24 @@ extern "C" int md_forces_backward(md_handle *h, const double *pos, const int32_t
 
 // ------------------------------------------------------------------ statistics, status
 
-extern "C" int md_live_stats(md_handle *h, const double *pos, double *out, void *stream)
+// Live statistics (Sec. 4) over CSF-1 bins.  hist false: only what the
+// counts alone give (mean, bins, compute units, skin; the rest NaN).
+static int live_stats(md_handle *h, const double *pos, double *out, hipStream_t s, bool hist)
 {
-    int rc = check_handle(h);
-    if (rc) return rc;
-    if (!out || (h->n > 0 && !pos)) return fail(MD_ERR_INVALID_ARG, "pos and out must not be NULL");
+    int rc;
     Geom g;
     if ((rc = make_geom(h->cfg, 1.0, g))) return rc;
+    hipDeviceProp_t prop;
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) cus = prop.multiProcessorCount;
+    int64_t nb = (int64_t)g.ncell;
+    out[0] = (double)h->n / (double)nb;
+    out[1] = out[2] = out[3] = out[5] = NAN;
+    out[4] = (double)nb;
+    out[6] = (double)cus;
+    out[7] = h->cfg.skin;
+    if (!hist) return MD_OK;
     if ((rc = ensure_cells(h, g))) return rc;
-    hipStream_t s = (hipStream_t)stream;
     launch_fill_i32(h->b.cell_count, 0, g.ncell, s);
     launch_bin_counts((int)h->n, pos, g, h->b.cell_count, s);
     std::vector<int32_t> cnt(g.ncell);
@@ -1171,24 +1192,43 @@ extern "C" int md_live_stats(md_handle *h, const double *pos, double *out, void 
         mx = std::max<int64_t>(mx, v);
         empty += v == 0;
     }
-    int64_t nb = (int64_t)cnt.size();
     double mean = sum / (double)nb;
     double var = 0.0;
     for (int32_t v : cnt) var += ((double)v - mean) * ((double)v - mean);
     var /= (double)nb;
-    std::sort(cnt.begin(), cnt.end());
-    double med = (nb % 2) ? (double)cnt[nb / 2] : 0.5 * ((double)cnt[nb / 2 - 1] + (double)cnt[nb / 2]);
-    hipDeviceProp_t prop;
-    int cus = 0;
-    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) cus = prop.multiProcessorCount;
+    // median: the middle order statistic(s), found by selection
+    std::nth_element(cnt.begin(), cnt.begin() + nb / 2, cnt.end());
+    double hi = (double)cnt[nb / 2];
+    double med = hi;
+    if (nb % 2 == 0) med = 0.5 * ((double)*std::max_element(cnt.begin(), cnt.begin() + nb / 2) + hi);
     out[0] = mean;
     out[1] = mean > 0.0 ? sqrt(var) / mean : 0.0;
     out[2] = med;
     out[3] = (double)mx;
-    out[4] = (double)nb;
     out[5] = (double)empty;
-    out[6] = (double)cus;
-    out[7] = h->cfg.skin;
+    return MD_OK;
+}
+
+extern "C" int md_live_stats(md_handle *h, const double *pos, double *out, void *stream)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!out || (h->n > 0 && !pos)) return fail(MD_ERR_INVALID_ARG, "pos and out must not be NULL");
+    return live_stats(h, pos, out, (hipStream_t)stream, true);
+}
+
+extern "C" int md_set_expert_rules(md_handle *h, const md_fuzzy_rule *rules, int32_t n_rules)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!h->tuner) return fail(MD_ERR_INVALID_ARG, "the handle does not tune (autotune is MD_TUNE_OFF)");
+    if (!rules || n_rules == 0) {
+        set_builtin_rules(h);
+        return MD_OK;
+    }
+    std::string why = check_rules(rules, n_rules, (int)h->space.size());
+    if (!why.empty()) return fail(MD_ERR_INVALID_ARG, why);
+    h->rules.assign(rules, rules + n_rules);
     return MD_OK;
 }
 
@@ -1291,6 +1331,19 @@ extern "C" int md_get_counters(md_handle *h, int64_t *out)
     return MD_OK;
 }
 
+extern "C" int md_get_trial_scores(md_handle *h, double *scores, md_config *configs, int32_t n)
+{
+    if (!h) return fail(MD_ERR_INVALID_ARG, "NULL handle");
+    int m = (int)h->space.size();
+    if (m == 0) return fail(MD_ERR_INVALID_ARG, "the handle does not tune (autotune is MD_TUNE_OFF)");
+    if (n < m || !scores) return fail(MD_ERR_INVALID_ARG, "scores needs room for " + std::to_string(m) + " entries");
+    for (int k = 0; k < m; k++) {
+        scores[k] = h->tuner->last_score(k);
+        if (configs) configs[k] = h->space[k];
+    }
+    return m;
+}
+
 extern "C" int md_timing(md_handle *h, int32_t enable, double *out)
 {
     int rc = check_handle(h);
@@ -1333,12 +1386,22 @@ int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
 {
     Tuner *t = h->tuner;
     int T = h->base.tune_trial_steps;
-    int live = 0;
+    int rc0, live = 0;
     for (int k = 0; k < t->n(); k++) live += t->blacklisted(k) ? 0 : 1;
     *next = s0;
     if ((int64_t)live * T > (int64_t)(c.nsteps - s0)) {
         h->next_phase = h->steps_done + c.nsteps;
         return MD_OK;
+    }
+    if (h->base.autotune == MD_TUNE_EXPERT) {
+        // Sec. 5.2: the rules read the live statistics of the current
+        // positions (the histogram only if a rule needs more than counts;
+        // every trial starts with a rebuild, so the cell arrays are free)
+        double st[8];
+        if ((rc0 = live_stats(h, c.pos, st, c.s, rules_need_histogram(h->rules)))) return rc0;
+        std::vector<double> suit;
+        expert_suitability(h->rules.data(), (int)h->rules.size(), t->n(), st, suit);
+        t->set_suitability(suit);
     }
     std::vector<int> trial;
     t->begin_phase(trial);

@@ -1,7 +1,10 @@
-// Configuration-selection strategies (host only): Full Search (Sec. 2.2.5)
-// and the Predictive strategy (Sec. 5.1).
+// Configuration-selection strategies (host only): Full Search (Sec. 2.2.5),
+// the Predictive strategy (Sec. 5.1) and the Expert strategy (Sec. 5.2).
 #pragma once
 
+#include <math.h>
+
+#include <string>
 #include <vector>
 
 #include "mdlj.h"
@@ -14,6 +17,9 @@ public:
 
     // Start a phase; fills trial[c] = 1 for configurations to trial.
     int begin_phase(std::vector<int> &trial);
+    // Expert strategy: the suitability of each configuration for the next
+    // phase (all 0: trial everything).
+    void set_suitability(const std::vector<double> &s) { suit_ = s; }
     // Score of a trialled configuration (lower is better).
     bool report(int config, double score);
     // Finish the phase; returns the chosen configuration or -1 if a trialled
@@ -23,6 +29,8 @@ public:
     int n() const { return n_; }
     bool blacklisted(int c) const { return black_[c] != 0; }
     int phase() const { return phase_; }
+    // Last score measured for configuration c (NaN if never trialled).
+    double last_score(int c) const { return hist_[c].empty() ? NAN : hist_[c].back().score; }
 
 private:
     struct Point {
@@ -36,8 +44,25 @@ private:
     int phase_ = -1;
     std::vector<std::vector<Point>> hist_;
     std::vector<char> black_, in_trial_, scored_;
-    std::vector<double> score_;
+    std::vector<double> score_, suit_;
 };
+
+// Expert strategy: margin below the largest suitability within which a
+// configuration is trialled.
+constexpr double kExpertMargin = 0.1;
+
+// Check a rule set against a tuning space of n_configs entries; "" if valid,
+// else the reason.
+std::string check_rules(const md_fuzzy_rule *rules, int n_rules, int n_configs);
+// Crisp suitability of each of n_configs configurations (Sec. 5.2 with the
+// fuzzy logic of Sec. 2.3) for the live statistics stats[8].
+void expert_suitability(const md_fuzzy_rule *rules, int n_rules, int n_configs, const double *stats,
+                        std::vector<double> &suit);
+// The built-in rules (written from Full Search scores on MI355X).
+const std::vector<md_fuzzy_rule> &builtin_rules();
+// Whether a rule set reads statistics that need the bin histogram (relative
+// spread, median, maximum, empty bins) rather than counts alone.
+bool rules_need_histogram(const std::vector<md_fuzzy_rule> &rules);
 
 // The GPU configuration space the autotuner explores for a base config:
 // linked cells (CSF 1 and 0.5) and Verlet lists, gather-only or with

@@ -30,6 +30,10 @@ MD_N3L_ON = 1
 MD_TUNE_OFF = 0
 MD_TUNE_FULL = 1
 MD_TUNE_PREDICTIVE = 2
+MD_TUNE_EXPERT = 3
+MD_SUIT_BAD = 0
+MD_SUIT_OKAY = 1
+MD_SUIT_GOOD = 2
 MD_FLAG_LIST_OVERFLOW = 1
 MD_FLAG_SKIN_EXCEEDED = 2
 MD_FLAG_NONFINITE = 4
@@ -57,6 +61,31 @@ class md_config(ctypes.Structure):
     ]
 
 
+class md_fuzzy_rule(ctypes.Structure):
+    """IF stats[input[0]] IS trap[0] (AND stats[input[1]] IS trap[1]) THEN
+    suitability(config) IS then; input[1] = -1 for one antecedent."""
+    _fields_ = [("input", ctypes.c_int32 * 2), ("trap", (ctypes.c_double * 4) * 2),
+                ("config", ctypes.c_int32), ("then", ctypes.c_int32)]
+
+
+def fuzzy_rules(rules):
+    """ctypes array of md_fuzzy_rule from dicts {"if": [(stat index,
+    (a, b, c, d)), ...] (one or two), "config": c, "then": MD_SUIT_*}."""
+    arr = (md_fuzzy_rule * max(len(rules), 1))()
+    for k, r in enumerate(rules):
+        ants = list(r["if"])
+        if not 1 <= len(ants) <= 2:
+            raise ValueError("a rule has one or two antecedents")
+        arr[k].input[0] = int(ants[0][0])
+        arr[k].input[1] = int(ants[1][0]) if len(ants) == 2 else -1
+        for j, (_, trap) in enumerate(ants):
+            for q in range(4):
+                arr[k].trap[j][q] = float(trap[q])
+        arr[k].config = int(r["config"])
+        arr[k].then = int(r["then"])
+    return arr
+
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -78,6 +107,9 @@ _SIGS = {
     "md_get_config": (_i32, [_vp, ctypes.POINTER(md_config)]),
     "md_get_counters": (_i32, [_vp, _vp]),
     "md_timing": (_i32, [_vp, _i32, _vp]),
+    "md_get_trial_scores": (_i32, [_vp, _vp, _vp, _i32]),
+    "md_set_expert_rules": (_i32, [_vp, _vp, _i32]),
+    "md_expert_suitability": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "md_last_error": (ctypes.c_char_p, []),
     "md_batch_create": (_i32, [ctypes.POINTER(md_config), _i32, _vp, _vp, ctypes.POINTER(_vp)]),
     "md_batch_destroy": (None, [_vp]),
@@ -87,6 +119,7 @@ _SIGS = {
     "md_tuner_create": (_i32, [_i32, _i32, _i32, _d, _d, ctypes.POINTER(_vp)]),
     "md_tuner_destroy": (None, [_vp]),
     "md_tuner_begin_phase": (_i32, [_vp, _vp]),
+    "md_tuner_set_suitability": (_i32, [_vp, _vp]),
     "md_tuner_report": (_i32, [_vp, _i32, _d]),
     "md_tuner_end_phase": (_i32, [_vp]),
     "md_tuner_blacklist": (_i32, [_vp, _vp]),
@@ -264,6 +297,36 @@ def md_get_counters(h: Handle):
     return dict(zip(keys, list(out)))
 
 
+def md_get_trial_scores(h: Handle, n_max: int = 64):
+    """Last trial score (ms per step, NaN if never trialled) and the
+    configuration of every entry of the handle's tuning space."""
+    scores = (ctypes.c_double * n_max)()
+    cfgs = (md_config * n_max)()
+    m = lib().md_get_trial_scores(h.ptr, scores, cfgs, n_max)
+    _check(m if m < 0 else 0, "md_get_trial_scores")
+    return list(scores[:m]), [cfgs[k] for k in range(m)]
+
+
+def md_set_expert_rules(h: Handle, rules=None):
+    """Rules of the Expert strategy (dicts as in fuzzy_rules); None restores
+    the built-in rules."""
+    if not rules:
+        _check(lib().md_set_expert_rules(h.ptr, None, 0), "md_set_expert_rules")
+    else:
+        _check(lib().md_set_expert_rules(h.ptr, fuzzy_rules(rules), len(rules)), "md_set_expert_rules")
+
+
+def md_expert_suitability(stats, n_configs: int = 7, rules=None):
+    """Crisp suitability per configuration (host only); rules None: the
+    built-in rules."""
+    st = (ctypes.c_double * 8)(*[float(v) for v in stats])
+    out = (ctypes.c_double * n_configs)()
+    arr = fuzzy_rules(rules) if rules is not None else None
+    _check(lib().md_expert_suitability(arr, len(rules) if rules is not None else 0, n_configs, st, out),
+           "md_expert_suitability")
+    return list(out)
+
+
 def md_timing(h: Handle, enable: bool, want: bool = True):
     """Start (True) / stop (False) kernel-class timing of md_step; returns
     {force_ms, force_passes, build_ms, builds} accumulated so far."""
@@ -346,6 +409,10 @@ class Tuner:
         arr = (ctypes.c_int32 * self.n)()
         _check(lib().md_tuner_begin_phase(self._t, arr), "md_tuner_begin_phase")
         return [c for c in range(self.n) if arr[c]]
+
+    def set_suitability(self, suit):
+        arr = (ctypes.c_double * self.n)(*[float(v) for v in suit])
+        _check(lib().md_tuner_set_suitability(self._t, arr), "md_tuner_set_suitability")
 
     def report(self, c: int, score: float):
         _check(lib().md_tuner_report(self._t, int(c), float(score)), "md_tuner_report")

@@ -7,7 +7,8 @@ import re
 
 import pytest
 
-from oracle.tuner import FULL_SEARCH, PREDICTIVE, TunerOracle
+from oracle import tuner as orc_tuner
+from oracle.tuner import EXPERT, FULL_SEARCH, PREDICTIVE, TunerOracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -119,6 +120,93 @@ def test_tuner_matches_oracle_on_random_traces(M, strategy):
             for p in range(phases):
                 scores[p][1] = scores[p][0]
         _drive(strategy, n, phases, scores, M)
+
+
+def _random_rules(rng, n_configs):
+    inf = float("inf")
+    rules = []
+    for _ in range(rng.randint(1, 12)):
+        ants = []
+        for _ in range(rng.choice((1, 1, 2))):
+            pts = sorted(rng.uniform(0.0, 10.0) for _ in range(4))
+            if rng.random() < 0.2:
+                pts[0] = pts[1] = -inf
+            if rng.random() < 0.2:
+                pts[2] = pts[3] = inf
+            if rng.random() < 0.1:
+                pts[1] = pts[2]  # triangle
+            ants.append((rng.randrange(8), tuple(pts)))
+        rules.append({"if": ants, "config": rng.randrange(n_configs), "then": rng.randrange(3)})
+    return rules
+
+
+def test_expert_suitability_matches_oracle(M):
+    """The library's exact piecewise-linear centre of gravity against the
+    oracle's fine-grid integral, on random rule sets and statistics."""
+    rng = random.Random(2505)
+    for trial in range(60):
+        n = rng.randint(1, 8)
+        rules = _random_rules(rng, n)
+        stats = [rng.uniform(0.0, 10.0) for _ in range(8)]
+        got = M.md_expert_suitability(stats, n, rules)
+        want = orc_tuner.suitability(rules, stats, n)
+        for c in range(n):
+            assert abs(got[c] - want[c]) < 1e-8, (trial, c, got[c], want[c])
+        assert orc_tuner.expert_trial_set(want) == orc_tuner.expert_trial_set(got) or \
+            any(abs(v - max(want) + 0.1) < 1e-8 for v in want)
+
+
+def test_expert_rules_validated(M):
+    inf = float("inf")
+    ok = {"if": [(0, (-inf, -inf, 2.0, 4.0))], "config": 0, "then": M.MD_SUIT_GOOD}
+    M.md_expert_suitability([1.0] * 8, 1, [ok])
+    for bad in ({"if": [(8, (0, 1, 2, 3))], "config": 0, "then": 0},
+                {"if": [(0, (0, 2, 1, 3))], "config": 0, "then": 0},
+                {"if": [(0, (0, float("nan"), 1, 3))], "config": 0, "then": 0},
+                {"if": [(0, (0, 1, 2, 3))], "config": 1, "then": 0},
+                {"if": [(0, (0, 1, 2, 3))], "config": 0, "then": 3}):
+        with pytest.raises(RuntimeError):
+            M.md_expert_suitability([1.0] * 8, 1, [bad])
+
+
+def test_builtin_expert_rules_select_families(M):
+    """The built-in rules (mean particles per CSF-1 bin only): Verlet lists,
+    gather-only, always; its N3L variant too at medium means; linked and
+    cluster lists never while Verlet lists are suited."""
+    def trials(mean):
+        s = M.md_expert_suitability([mean, 0.2, mean, 2 * mean, 1e5, 0, 256, 0.3], 7)
+        return orc_tuner.expert_trial_set(s)
+    assert trials(0.9) == [4]      # droplet
+    assert trials(17.7) == [4]     # 1M fluid at density 0.8
+    assert trials(6.7) == [4, 5]   # fluid at density 0.3
+    assert trials(5.95) == [4, 5]  # slab
+    s64 = M.md_expert_suitability([17.7, 0.2, 17.7, 40, 1e5, 0, 256, 0.3], 6)  # FP64 space: no cluster lists
+    assert orc_tuner.expert_trial_set(s64) == [4]
+
+
+def test_expert_tuner_matches_oracle(M):
+    rng = random.Random(77)
+    for trial in range(30):
+        n = rng.randint(1, 9)
+        phases = rng.randint(1, 6)
+        lib_t = M.Tuner(EXPERT, n, phases)
+        orc_t = TunerOracle(EXPERT, n, phases)
+        for p in range(phases):
+            suit = [rng.choice((0.0, 1.0 / 6.0, 0.5, 0.75, 0.8, 5.0 / 6.0, rng.random())) for _ in range(n)]
+            if trial % 7 == 0:
+                suit = [0.0] * n
+            lib_t.set_suitability(suit)
+            a = lib_t.begin_phase()
+            b = orc_t.begin_phase(suit)
+            assert a == b, (trial, p, suit, a, b)
+            for c in a:
+                sc = rng.uniform(1.0, 20.0)
+                lib_t.report(c, sc)
+                orc_t.report(c, sc)
+            assert lib_t.end_phase() == orc_t.end_phase()
+            assert lib_t.blacklisted() == []
+    with pytest.raises(RuntimeError):
+        M.Tuner(EXPERT, 2, 2).set_suitability([0.5, 1.5])
 
 
 def test_tuner_rejects_bad_use(M):

@@ -568,6 +568,73 @@ def test_autotuned_fp64_trajectory(orc, strategy):
     assert np.abs(dx).max() < 1e-9
 
 
+INF = float("inf")
+
+
+@pytest.mark.parametrize("rules", ["builtin", "lc_pair", "histogram"])
+def test_expert_strategy_fp64_trajectory(orc, rules):
+    """Expert strategy (fuzzy rules over the live statistics): only the
+    configurations the rules mark as suited are trialled, the fastest of
+    them is kept, and the trajectory equals the oracle's whatever is chosen.
+    "histogram": a rule on the spread of the bin counts, so each phase runs
+    the bin histogram over the cell arrays before its trials rebuild them."""
+    import torch
+    d = W.plain_fcc_864()
+    nsteps = 150
+    p1, v1, _, log0 = orc.velocity_verlet(d["pos"], d["vel"], d["box"], orc.single(), 0.005, nsteps)
+    n = 864
+    cfg = make_config(n, d["box"], container=0, precision=1, R=10)
+    cfg.autotune = M.MD_TUNE_EXPERT
+    cfg.tune_interval = 40
+    cfg.tune_trial_steps = 3
+    cfg.total_steps_hint = nsteps
+    s = DeviceSystem(cfg, d["pos"], d["vel"])
+    every = (0, (-INF, -INF, INF, INF))
+    if rules == "builtin":
+        suited = [4]  # 32 particles per bin: dense, Verlet lists gather-only
+    elif rules == "lc_pair":
+        M.md_set_expert_rules(s.h, [{"if": [every], "config": 0, "then": M.MD_SUIT_GOOD},
+                                    {"if": [every], "config": 2, "then": M.MD_SUIT_GOOD},
+                                    {"if": [every], "config": 4, "then": M.MD_SUIT_OKAY}])
+        suited = [0, 2]
+    else:
+        M.md_set_expert_rules(s.h, [{"if": [(1, (-INF, -INF, 1.0, 2.0)), (3, (0.0, 1.0, 1e9, 2e9))],
+                                     "config": 1, "then": M.MD_SUIT_GOOD}])
+        suited = [1]
+    s.build()
+    s.forces(energy=False)
+    log = torch.zeros((nsteps, 4), dtype=torch.float64, device="cuda")
+    M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, nsteps, 1, log)
+    torch.cuda.synchronize()
+    log = log.cpu().numpy()
+    cnt = M.md_get_counters(s.h)
+    assert cnt["tuning_phases"] == 4
+    assert cnt["trials"] == 4 * len(suited)
+    assert cnt["config_index"] in suited
+    scores, cfgs = M.md_get_trial_scores(s.h)
+    assert len(scores) == 6  # FP64: no cluster lists
+    assert [k for k in range(6) if np.isfinite(scores[k])] == suited
+    assert all(scores[k] > 0.0 for k in suited)
+    assert int(cfgs[4].container) == M.MD_CONTAINER_VL and int(cfgs[4].newton3) == 0
+    assert np.array_equal(log[:, 3], log0[:, 3])
+    for k in (0, 1, 2):
+        assert np.abs(log[:, k] - log0[:, k]).max() <= 1e-10 * np.abs(log0[:, k]).max()
+    dx = s.by_id(s.pos) - p1
+    dx -= d["box"][:, None] * np.rint(dx / d["box"][:, None])
+    assert np.abs(dx).max() < 1e-9
+    s.h.close()
+
+
+def test_expert_rules_rejected_for_untuned_handle(orc):
+    d = W.plain_fcc_864()
+    s = DeviceSystem(make_config(864, d["box"], container=0, precision=1), d["pos"])
+    with pytest.raises(RuntimeError, match="does not tune"):
+        M.md_set_expert_rules(s.h, None)
+    with pytest.raises(RuntimeError, match="does not tune"):
+        M.md_get_trial_scores(s.h)
+    s.h.close()
+
+
 def test_autotuned_fp32_energy_conservation(orc):
     """FP32 autotuned run over all seven configurations (cluster lists
     included): the total energy stays conserved across configuration
