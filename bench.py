@@ -116,16 +116,20 @@ def make_cfg(M, n, box, kind, steps):
         c.newton3 = M.MD_N3L_OFF
         c.rebuild_interval = 10
     elif kind.startswith("fixed:"):
-        # fixed:<container>:<csf>:<n3l>:<R>, e.g. fixed:vl:1:0:5
-        _, cont, csf, n3, R = kind.split(":")
+        # fixed:<container>:<csf>:<n3l>:<R>[:<skin>], e.g. fixed:vl:1:0:5
+        parts = kind.split(":")
+        _, cont, csf, n3, R = parts[:5]
+        if len(parts) > 5:
+            c.skin = float(parts[5])
         c.container = {"lc": M.MD_CONTAINER_LC, "vl": M.MD_CONTAINER_VL, "cl": M.MD_CONTAINER_CL}[cont]
         c.csf = float(csf)
         c.newton3 = int(n3)
         c.rebuild_interval = int(R)
-    else:  # autotuned: Predictive strategy ("auto") or Expert rules ("expert")
+    else:  # autotuned: Predictive strategy ("auto") or Expert rules ("expert"); "+skin": skin tuned too
         c.container = M.MD_CONTAINER_LC
         c.rebuild_interval = 10
-        c.autotune = M.MD_TUNE_EXPERT if kind == "expert" else M.MD_TUNE_PREDICTIVE
+        c.autotune = M.MD_TUNE_EXPERT if kind.startswith("expert") else M.MD_TUNE_PREDICTIVE
+        c.tune_skin = 1 if kind.endswith("+skin") else 0
         # two tuning phases (at steps 0 and steps/2): a phase trials every
         # configuration for tune_trial_steps steps, so shorter intervals would
         # spend most of a 1000-step run in trials (with four phases the
@@ -182,7 +186,8 @@ def run(M, d, kind, steps, warmup, probe_steps=50):
                pairs_per_s=pairs_mean * steps / wall,
                force_kernel_ms=force_ms, build_ms=build_ms, counters=cnt,
                final_config=dict(container=int(cfg_now.container), newton3=int(cfg_now.newton3),
-                                 csf=float(cfg_now.csf), rebuild_interval=int(cfg_now.rebuild_interval)),
+                                 csf=float(cfg_now.csf), rebuild_interval=int(cfg_now.rebuild_interval),
+                                 skin=float(cfg_now.skin)),
                energy_per_particle_first_last=[float(E[0] / n), float(E[-1] / n)] if len(E) else None)
     h.close()
     return res
@@ -286,8 +291,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-expert", action="store_true", help="skip the run under the Expert strategy")
-    ap.add_argument("--extra", default="", help="comma-separated extra fixed configs to time, "
-                    "e.g. fixed:vl:1:0:5 (container:csf:n3l:R)")
+    ap.add_argument("--extra", default="", help="comma-separated extra configs to time, e.g. "
+                    "fixed:vl:1:0:5 (container:csf:n3l:R[:skin]) or auto+skin (Predictive with the skin tuned)")
     ap.add_argument("--ncell", type=int, default=64, help="FCC cells per side (64 -> 1,048,576 particles)")
     ap.add_argument("--workload", default="fluid", choices=["fluid", "droplet", "slab"],
                     help="fluid: the 1M homogeneous fluid (the benchmark line); droplet / slab: the 2M "

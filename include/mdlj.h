@@ -105,6 +105,11 @@ typedef struct md_config {
     int32_t tune_interval; /* steps between tuning phases                      */
     int32_t tune_trial_steps; /* steps each trialled configuration runs        */
     int32_t total_steps_hint; /* expected steps of the run (retrial gap)       */
+    int32_t tune_skin;     /* 1: the tuning space also holds Verlet lists
+                              (gather-only, CSF 1) at 2/3, 4/3 and 5/3 of the
+                              skin, each with its rebuild interval derived
+                              from the motion (a joint skin / R search); 0
+                              (default): the skin stays fixed               */
 } md_config;
 
 /* Fill *cfg with defaults for n particles in a cubic box of side L:

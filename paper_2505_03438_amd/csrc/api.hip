@@ -249,6 +249,7 @@ static int validate_config(const md_config *c)
         return fail(MD_ERR_INVALID_ARG, "bad autotune");
     if (c->autotune != MD_TUNE_OFF && (c->tune_interval < 1 || c->tune_trial_steps < 2))
         return fail(MD_ERR_INVALID_ARG, "tune_interval >= 1 and tune_trial_steps >= 2 required");
+    if (c->tune_skin != 0 && c->tune_skin != 1) return fail(MD_ERR_INVALID_ARG, "tune_skin must be 0 or 1");
     return MD_OK;
 }
 
@@ -336,6 +337,15 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
     (void)hipEventCreate(&h->ev2);
     if (cfg->autotune != MD_TUNE_OFF) {
         tuning_space(*cfg, h->space);
+        // skin variants whose list radius does not fit the box are left out
+        std::vector<md_config> fit;
+        for (const md_config &k : h->space) {
+            Geom gk;
+            std::string keep_err = g_err;
+            if (make_geom(k, k.csf, gk) == MD_OK) fit.push_back(k);
+            g_err = keep_err;
+        }
+        h->space.swap(fit);
         int total_phases = std::max(1, (int)((cfg->total_steps_hint + cfg->tune_interval - 1) / cfg->tune_interval));
         h->tuner = new Tuner(cfg->autotune, (int)h->space.size(), total_phases, 2.0, 10.0);
         set_builtin_rules(h);
@@ -1410,8 +1420,9 @@ int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
     for (int k = 0; k < (int)trial.size(); k++) {
         if (!trial[k]) continue;
         md_config kc = h->space[k];
-        kc.rebuild_interval = derived_interval(h);
         if ((rc = apply_config(h, kc))) return rc;
+        // the interval follows from the motion and this configuration's skin
+        kc.rebuild_interval = h->cfg.rebuild_interval = derived_interval(h);
         MD_HIP(hipEventRecord(h->ev0, c.s));
         if ((rc = run_steps(h, c, s, s + 1))) return rc;
         MD_HIP(hipEventRecord(h->ev1, c.s));

@@ -294,6 +294,16 @@ void tuning_space(const md_config &base, std::vector<md_config> &space)
         c.newton3 = MD_N3L_OFF;
         space.push_back(c);
     }
+    // joint skin / rebuild-interval search: Verlet lists at other skins (a
+    // larger skin buys a longer interval with longer lists)
+    if (base.tune_skin && base.skin > 0.0)
+        for (double f : {2.0 / 3.0, 4.0 / 3.0, 5.0 / 3.0}) {
+            c.container = MD_CONTAINER_VL;
+            c.csf = 1.0;
+            c.newton3 = MD_N3L_OFF;
+            c.skin = base.skin * f;
+            space.push_back(c);
+        }
 }
 
 }  // namespace mdlj

@@ -75,7 +75,8 @@ def full_search(d, trial_steps: int = 10, dt: float = 0.005):
     scores, cfgs = M.md_get_trial_scores(h)
     chosen = M.md_get_counters(h)["config_index"]
     h.close()
-    names = ["%s-csf%g-%s" % (CONTAINER[int(k.container)], float(k.csf), "n3l" if k.newton3 else "gather")
+    names = ["%s-csf%g-%s%s" % (CONTAINER[int(k.container)], float(k.csf), "n3l" if k.newton3 else "gather",
+                                "" if k.skin == cfgs[0].skin else "-skin%.3g" % k.skin)
              for k in cfgs]
     return stats, dict(zip(names, scores)), names[chosen]
 

@@ -58,6 +58,7 @@ class md_config(ctypes.Structure):
         ("tune_interval", ctypes.c_int32),
         ("tune_trial_steps", ctypes.c_int32),
         ("total_steps_hint", ctypes.c_int32),
+        ("tune_skin", ctypes.c_int32),
     ]
 
 

@@ -56,6 +56,10 @@ def _create_rc(M, c):
 
 def test_create_rejects_bad_configs(M):
     c = M.config_default(100, 12.0)
+    assert c.tune_skin == 0
+    c.tune_skin = 2
+    assert _create_rc(M, c) == M.MD_ERR_INVALID_ARG and "tune_skin" in M.md_last_error()
+    c.tune_skin = 0
     c.box[1] = 5.0  # < 2 (r_c + skin)
     assert _create_rc(M, c) == M.MD_ERR_BOX_TOO_SMALL
     assert "box[1]" in M.md_last_error()

@@ -625,6 +625,46 @@ def test_expert_strategy_fp64_trajectory(orc, rules):
     s.h.close()
 
 
+def test_skin_tuning_fp64_trajectory(orc):
+    """Joint skin / rebuild-interval search: the tuning space gains Verlet
+    lists at 2/3, 4/3 and 5/3 of the skin; Full Search trials them all, and
+    the trajectory still equals the oracle's (the skin changes the work, not
+    the forces)."""
+    import torch
+    d = W.plain_fcc_864()
+    nsteps = 120
+    p1, v1, _, log0 = orc.velocity_verlet(d["pos"], d["vel"], d["box"], orc.single(), 0.005, nsteps)
+    cfg = make_config(864, d["box"], container=0, precision=1, R=10)
+    cfg.autotune = M.MD_TUNE_FULL
+    cfg.tune_skin = 1
+    cfg.tune_interval = 60
+    cfg.tune_trial_steps = 3
+    cfg.total_steps_hint = nsteps
+    s = DeviceSystem(cfg, d["pos"], d["vel"])
+    scores, cfgs = M.md_get_trial_scores(s.h)
+    assert len(scores) == 9 and all(np.isnan(scores))
+    assert [round(float(c.skin), 12) for c in cfgs[6:]] == [0.2, 0.4, 0.5]
+    assert all(int(c.container) == M.MD_CONTAINER_VL for c in cfgs[6:])
+    s.build()
+    s.forces(energy=False)
+    log = torch.zeros((nsteps, 4), dtype=torch.float64, device="cuda")
+    M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, nsteps, 1, log)
+    torch.cuda.synchronize()
+    log = log.cpu().numpy()
+    cnt = M.md_get_counters(s.h)
+    assert cnt["tuning_phases"] == 2 and cnt["trials"] == 18
+    scores, _ = M.md_get_trial_scores(s.h)
+    assert all(np.isfinite(scores))
+    assert abs(float(M.md_get_config(s.h).skin) - float(cfgs[cnt["config_index"]].skin)) < 1e-15
+    assert np.array_equal(log[:, 3], log0[:, 3])
+    for k in (0, 1, 2):
+        assert np.abs(log[:, k] - log0[:, k]).max() <= 1e-10 * np.abs(log0[:, k]).max()
+    dx = s.by_id(s.pos) - p1
+    dx -= d["box"][:, None] * np.rint(dx / d["box"][:, None])
+    assert np.abs(dx).max() < 1e-9
+    s.h.close()
+
+
 def test_expert_rules_rejected_for_untuned_handle(orc):
     d = W.plain_fcc_864()
     s = DeviceSystem(make_config(864, d["box"], container=0, precision=1), d["pos"])
