@@ -125,10 +125,11 @@ def make_cfg(M, n, box, kind, steps):
         c.csf = float(csf)
         c.newton3 = int(n3)
         c.rebuild_interval = int(R)
-    else:  # autotuned: Predictive strategy ("auto") or Expert rules ("expert"); "+skin": skin tuned too
+    else:  # autotuned: Predictive ("auto"), Expert rules ("expert"), Random Forest ("forest"); "+skin": skin tuned
         c.container = M.MD_CONTAINER_LC
         c.rebuild_interval = 10
-        c.autotune = M.MD_TUNE_EXPERT if kind.startswith("expert") else M.MD_TUNE_PREDICTIVE
+        c.autotune = (M.MD_TUNE_EXPERT if kind.startswith("expert") else
+                      M.MD_TUNE_RF if kind.startswith("forest") else M.MD_TUNE_PREDICTIVE)
         c.tune_skin = 1 if kind.endswith("+skin") else 0
         # two tuning phases (at steps 0 and steps/2): a phase trials every
         # configuration for tune_trial_steps steps, so shorter intervals would
@@ -290,7 +291,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-expert", action="store_true", help="skip the run under the Expert strategy")
+    ap.add_argument("--no-expert", action="store_true",
+                    help="skip the runs under the Expert and Random Forest strategies")
     ap.add_argument("--extra", default="", help="comma-separated extra configs to time, e.g. "
                     "fixed:vl:1:0:5 (container:csf:n3l:R[:skin]) or auto+skin (Predictive with the skin tuned)")
     ap.add_argument("--ncell", type=int, default=64, help="FCC cells per side (64 -> 1,048,576 particles)")
@@ -347,6 +349,11 @@ def main():
         expert = run(M, d, "expert", args.steps, args.warmup)
         log("expert rules: %.3f ms/step, %.3e pairs/s, config %s, %d trials" % (
             expert["ms_per_step"], expert["pairs_per_s"], expert["final_config"], expert["counters"]["trials"]))
+    forest = None
+    if not args.no_expert:
+        forest = run(M, d, "forest", args.steps, args.warmup)
+        log("random forest: %.3f ms/step, %.3e pairs/s, config %s, %d trials" % (
+            forest["ms_per_step"], forest["pairs_per_s"], forest["final_config"], forest["counters"]["trials"]))
     plain = None
     if not args.no_plain:
         plain = run(M, d, "plain", args.steps, args.warmup)
@@ -403,6 +410,7 @@ def main():
                    "pair_arithmetic": "f32", "strategy": "predictive", "parallelism": "single-gpu"},
         "autotuned": auto,
         "expert_strategy": expert,
+        "random_forest_strategy": forest,
         "plain": plain,
         "fixed_configs": extra or None,
         "speedup_vs_plain": (auto["pairs_per_s"] / plain["pairs_per_s"]) if plain else None,

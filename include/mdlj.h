@@ -69,6 +69,7 @@ extern "C" {
 #define MD_TUNE_FULL 1
 #define MD_TUNE_PREDICTIVE 2
 #define MD_TUNE_EXPERT 3 /* Sec. 5.2: fuzzy rules over the live statistics  */
+#define MD_TUNE_RF 4     /* Sec. 5.3: a random forest over the statistics   */
 
 /* consequents of the Expert strategy's fuzzy rules: terms of the output
  * variable "suitability" on [0, 1] (triangles peaking at 0, 0.5 and 1) */
@@ -311,6 +312,16 @@ int md_expert_suitability(const md_fuzzy_rule *rules, int32_t n_rules,
                           int32_t n_configs, const double *stats,
                           double *suitability);
 
+/* Random Forest strategy (Sec. 5.3), host only: the tuning-space index of
+ * the configuration the built-in forest (100 trees fitted offline to Full
+ * Search trials on MI355X over generative scenarios) predicts for the live
+ * statistics stats (HOST double[8], md_live_stats order): the class with the
+ * largest mean leaf fraction over the trees, features compared in single
+ * precision, ties to the first class, among the classes below n_configs.
+ * A tuning phase under MD_TUNE_RF trials that configuration alone.
+ * MD_ERR_INVALID_ARG for a NaN statistic or if no class fits n_configs. */
+int md_rf_predict(const double *stats, int32_t n_configs);
+
 /* Configuration-selection engine, usable on its own with externally measured
  * scores (host only; needs no GPU).  Sec. 2.2.5 Full Search and Sec. 5.1
  * Predictive: trial all in the first two phases; predict each configuration
@@ -318,9 +329,11 @@ int md_expert_suitability(const md_fuzzy_rule *rules, int32_t n_rules,
  * half its last score); trial those predicted within rel_threshold of the
  * best prediction (inclusive) or not trialled for ceil(total_phases/4)
  * phases; blacklist those measured above blacklist_factor x the phase's best;
- * choose the lowest score (ties: lower index).  Sec. 5.2 Expert: trial the
- * configurations whose suitability (md_tuner_set_suitability, before each
- * phase) is within 0.1 of the largest; no blacklist. */
+ * choose the lowest score (ties: lower index).  Sec. 5.2 Expert (and Sec.
+ * 5.3 Random Forest, with a suitability of 1 for the predicted configuration
+ * and 0 elsewhere): trial the configurations whose suitability
+ * (md_tuner_set_suitability, before each phase) is within 0.1 of the
+ * largest; no blacklist. */
 typedef struct md_tuner md_tuner;
 
 int md_tuner_create(int32_t strategy, int32_t n_configs, int32_t total_phases,

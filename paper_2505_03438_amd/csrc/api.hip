@@ -245,7 +245,7 @@ static int validate_config(const md_config *c)
     if (c->rebuild_interval < 1) return fail(MD_ERR_INVALID_ARG, "rebuild_interval must be >= 1");
     if (c->max_neighbors < 1 || c->max_neighbors > 4096) return fail(MD_ERR_INVALID_ARG, "max_neighbors out of range");
     if (c->autotune != MD_TUNE_OFF && c->autotune != MD_TUNE_FULL && c->autotune != MD_TUNE_PREDICTIVE &&
-        c->autotune != MD_TUNE_EXPERT)
+        c->autotune != MD_TUNE_EXPERT && c->autotune != MD_TUNE_RF)
         return fail(MD_ERR_INVALID_ARG, "bad autotune");
     if (c->autotune != MD_TUNE_OFF && (c->tune_interval < 1 || c->tune_trial_steps < 2))
         return fail(MD_ERR_INVALID_ARG, "tune_interval >= 1 and tune_trial_steps >= 2 required");
@@ -1411,6 +1411,16 @@ int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
         if ((rc0 = live_stats(h, c.pos, st, c.s, rules_need_histogram(h->rules)))) return rc0;
         std::vector<double> suit;
         expert_suitability(h->rules.data(), (int)h->rules.size(), t->n(), st, suit);
+        t->set_suitability(suit);
+    }
+    if (h->base.autotune == MD_TUNE_RF) {
+        // Sec. 5.3: the forest reads all the live statistics of the current
+        // positions and names the one configuration to run
+        double st[8];
+        if ((rc0 = live_stats(h, c.pos, st, c.s, true))) return rc0;
+        int pick = rf_predict(st, t->n());
+        std::vector<double> suit(t->n(), 0.0);
+        if (pick >= 0) suit[pick] = 1.0;
         t->set_suitability(suit);
     }
     std::vector<int> trial;

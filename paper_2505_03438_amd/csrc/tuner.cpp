@@ -15,11 +15,16 @@
 // suitability; the configurations within kExpertMargin of the most suitable
 // are trialled and the fastest of them is kept (no blacklist).
 //
+// Random Forest (Sec. 5.3): a forest fitted offline maps the live
+// statistics to one configuration, the only one the phase trials.
+//
 // Readings where the paper gives no number or is silent: a single point
 // predicts its own score; a falling line is clamped from below at half the
 // last score; "within" is inclusive; the retrial gap is ceil(total/4) phases;
 // ties go to the lower index.
 #include "tuner.h"
+
+#include "rf_model.h"
 
 #include <math.h>
 #include <string.h>
@@ -60,7 +65,7 @@ int Tuner::begin_phase(std::vector<int> &trial)
     trial.assign(n_, 0);
     std::fill(in_trial_.begin(), in_trial_.end(), 0);
     std::fill(scored_.begin(), scored_.end(), 0);
-    if (strategy_ == MD_TUNE_EXPERT) {
+    if (strategy_ == MD_TUNE_EXPERT || strategy_ == MD_TUNE_RF) {
         double top = 0.0;
         for (int c = 0; c < n_ && c < (int)suit_.size(); c++) top = std::max(top, suit_[c]);
         int cnt = 0;
@@ -267,6 +272,33 @@ const std::vector<md_fuzzy_rule> &builtin_rules()
     return rules;
 }
 
+// ------------------------------------------------------------------ random forest (Sec. 5.3)
+
+int rf_predict(const double *stats, int n_configs)
+{
+    double acc[rf::kClasses] = {};
+    for (int t = 0; t < rf::kTrees; t++) {
+        int k = rf::kRoot[t];
+        while (rf::kNodes[k].feature >= 0) {
+            const rf::Node &nd = rf::kNodes[k];
+            // the trees were fitted on single-precision features
+            double x = (double)(float)stats[nd.feature];
+            k = x <= nd.threshold ? nd.left : nd.right;
+        }
+        const double *p = rf::kProba + rf::kNodes[k].proba;
+        for (int c = 0; c < rf::kClasses; c++) acc[c] += p[c];
+    }
+    // mean class fraction over the trees; the first largest among the
+    // classes this space holds
+    int best = -1;
+    for (int c = 0; c < rf::kClasses; c++) {
+        acc[c] /= (double)rf::kTrees;
+        if (rf::kConfig[c] >= n_configs) continue;
+        if (best < 0 || acc[c] > acc[best]) best = c;
+    }
+    return best < 0 ? -1 : rf::kConfig[best];
+}
+
 void tuning_space(const md_config &base, std::vector<md_config> &space)
 {
     space.clear();
@@ -320,8 +352,9 @@ extern "C" int md_tuner_create(int32_t strategy, int32_t n_configs, int32_t tota
 {
     if (!out) return mdlj::fail(MD_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (strategy != MD_TUNE_FULL && strategy != MD_TUNE_PREDICTIVE && strategy != MD_TUNE_EXPERT)
-        return mdlj::fail(MD_ERR_INVALID_ARG, "strategy must be MD_TUNE_FULL, MD_TUNE_PREDICTIVE or MD_TUNE_EXPERT");
+    if (strategy != MD_TUNE_FULL && strategy != MD_TUNE_PREDICTIVE && strategy != MD_TUNE_EXPERT &&
+        strategy != MD_TUNE_RF)
+        return mdlj::fail(MD_ERR_INVALID_ARG, "strategy must be one of MD_TUNE_FULL .. MD_TUNE_RF");
     if (n_configs < 1 || total_phases < 1) return mdlj::fail(MD_ERR_INVALID_ARG, "n_configs, total_phases >= 1");
     if (!(rel_threshold >= 1.0) || !(blacklist_factor >= 1.0))
         return mdlj::fail(MD_ERR_INVALID_ARG, "thresholds must be >= 1");
@@ -350,6 +383,16 @@ extern "C" int md_tuner_set_suitability(md_tuner *t, const double *suitability)
         if (!(v >= 0.0 && v <= 1.0)) return mdlj::fail(MD_ERR_INVALID_ARG, "suitability must lie in [0, 1]");
     t->t.set_suitability(s);
     return MD_OK;
+}
+
+extern "C" int md_rf_predict(const double *stats, int32_t n_configs)
+{
+    if (!stats || n_configs < 1) return mdlj::fail(MD_ERR_INVALID_ARG, "bad arguments");
+    for (int k = 0; k < 8; k++)
+        if (!(stats[k] == stats[k])) return mdlj::fail(MD_ERR_INVALID_ARG, "statistics must not be NaN");
+    int c = mdlj::rf_predict(stats, n_configs);
+    if (c < 0) return mdlj::fail(MD_ERR_INVALID_ARG, "the model predicts no configuration of this space");
+    return c;
 }
 
 extern "C" int md_expert_suitability(const md_fuzzy_rule *rules, int32_t n_rules, int32_t n_configs,

@@ -1,5 +1,6 @@
 // Configuration-selection strategies (host only): Full Search (Sec. 2.2.5),
-// the Predictive strategy (Sec. 5.1) and the Expert strategy (Sec. 5.2).
+// the Predictive strategy (Sec. 5.1), the Expert strategy (Sec. 5.2) and the
+// Random Forest strategy (Sec. 5.3).
 #pragma once
 
 #include <math.h>
@@ -17,8 +18,8 @@ public:
 
     // Start a phase; fills trial[c] = 1 for configurations to trial.
     int begin_phase(std::vector<int> &trial);
-    // Expert strategy: the suitability of each configuration for the next
-    // phase (all 0: trial everything).
+    // Expert and Random Forest strategies: the suitability of each
+    // configuration for the next phase (all 0: trial everything).
     void set_suitability(const std::vector<double> &s) { suit_ = s; }
     // Score of a trialled configuration (lower is better).
     bool report(int config, double score);
@@ -58,6 +59,9 @@ std::string check_rules(const md_fuzzy_rule *rules, int n_rules, int n_configs);
 // fuzzy logic of Sec. 2.3) for the live statistics stats[8].
 void expert_suitability(const md_fuzzy_rule *rules, int n_rules, int n_configs, const double *stats,
                         std::vector<double> &suit);
+// Random Forest: the configuration (index below n_configs) the forest of
+// rf_model.h predicts for the live statistics stats[8], or -1.
+int rf_predict(const double *stats, int n_configs);
 // The built-in rules (written from Full Search scores on MI355X).
 const std::vector<md_fuzzy_rule> &builtin_rules();
 // Whether a rule set reads statistics that need the bin histogram (relative

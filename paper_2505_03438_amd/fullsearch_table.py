@@ -8,7 +8,7 @@ positions (Sec. 4, md_live_stats order) and every configuration's score from
 the second of two Full Search phases (ms per step, build time spread over the
 rebuild interval; the first phase is a warm-up).
 
-    python -m paper_2505_03438_amd.fullsearch_table [--quick]
+    python -m paper_2505_03438_amd.fullsearch_table [--quick] [--set selection]
 """
 from __future__ import annotations
 
@@ -49,6 +49,7 @@ def full_search(d, trial_steps: int = 10, dt: float = 0.005):
     for k in range(3):
         c.box[k] = float(box[k])
     c.precision = M.MD_FP32
+    c.skin = float(d.get("skin", 0.3))
     c.autotune = M.MD_TUNE_FULL
     c.tune_trial_steps = trial_steps
     h = M.md_create(c)
@@ -78,22 +79,26 @@ def full_search(d, trial_steps: int = 10, dt: float = 0.005):
     names = ["%s-csf%g-%s%s" % (CONTAINER[int(k.container)], float(k.csf), "n3l" if k.newton3 else "gather",
                                 "" if k.skin == cfgs[0].skin else "-skin%.3g" % k.skin)
              for k in cfgs]
-    return stats, dict(zip(names, scores)), names[chosen]
+    return stats, dict(zip(names, scores)), names[chosen], chosen
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--quick", action="store_true", help="two densities at 131,072 particles only")
+    ap.add_argument("--quick", action="store_true", help="two densities at 32,000 particles only")
+    ap.add_argument("--set", default="expert", choices=["expert", "selection"],
+                    help="expert: fluids, droplet and slab (the Expert rules' data); selection: the generative "
+                         "scenarios the Random Forest is trained on")
     args = ap.parse_args()
     M.lib()
     if not torch.cuda.is_available():
         sys.exit("no GPU")
-    for name, d in scenarios(args.quick):
-        stats, scores, chosen = full_search(d)
+    gen = W.selection_scenarios() if args.set == "selection" else scenarios(args.quick)
+    for name, d in gen:
+        stats, scores, chosen, index = full_search(d)
         print(json.dumps({"scenario": name, "n": int(d["pos"].shape[1]),
                           "stats": dict(zip(("mean", "rel_std", "median", "max", "n_bins", "n_empty", "cus",
                                              "skin"), stats)),
-                          "scores_ms": scores, "chosen": chosen}), flush=True)
+                          "features": stats, "scores_ms": scores, "chosen": chosen, "label": index}), flush=True)
 
 
 if __name__ == "__main__":

@@ -31,6 +31,7 @@ MD_TUNE_OFF = 0
 MD_TUNE_FULL = 1
 MD_TUNE_PREDICTIVE = 2
 MD_TUNE_EXPERT = 3
+MD_TUNE_RF = 4
 MD_SUIT_BAD = 0
 MD_SUIT_OKAY = 1
 MD_SUIT_GOOD = 2
@@ -111,6 +112,7 @@ _SIGS = {
     "md_get_trial_scores": (_i32, [_vp, _vp, _vp, _i32]),
     "md_set_expert_rules": (_i32, [_vp, _vp, _i32]),
     "md_expert_suitability": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+    "md_rf_predict": (_i32, [_vp, _i32]),
     "md_last_error": (ctypes.c_char_p, []),
     "md_batch_create": (_i32, [ctypes.POINTER(md_config), _i32, _vp, _vp, ctypes.POINTER(_vp)]),
     "md_batch_destroy": (None, [_vp]),
@@ -326,6 +328,12 @@ def md_expert_suitability(stats, n_configs: int = 7, rules=None):
     _check(lib().md_expert_suitability(arr, len(rules) if rules is not None else 0, n_configs, st, out),
            "md_expert_suitability")
     return list(out)
+
+
+def md_rf_predict(stats, n_configs: int = 7) -> int:
+    """Configuration the built-in Random Forest predicts (host only)."""
+    st = (ctypes.c_double * 8)(*[float(v) for v in stats])
+    return _check(lib().md_rf_predict(st, n_configs), "md_rf_predict")
 
 
 def md_timing(h: Handle, enable: bool, want: bool = True):

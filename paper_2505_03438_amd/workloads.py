@@ -252,3 +252,76 @@ def random_gas(n: int, L: float, rng: np.random.Generator):
     """n uniformly random positions in a cubic box (small tests only)."""
     pos = rng.uniform(0.0, L, size=(3, n))
     return np.ascontiguousarray(_wrap(pos, L)), np.array([L, L, L])
+
+
+def thinned_fcc(ncell: int, rho_max: float, field, rng: np.random.Generator, jitter: float = 0.06):
+    """Particles following a density field rho(x) <= rho_max without
+    overlaps: an FCC lattice at rho_max fills the cubic box (ncell unit cells
+    per side), each site is kept with probability rho(site) / rho_max, then
+    displaced within +-jitter lattice constants per axis; random order.
+    field(sites [3, m], L) -> densities [m]."""
+    a = (4.0 / rho_max) ** (1.0 / 3.0)
+    L = ncell * a
+    sites = fcc_sites(ncell, ncell, ncell, a)
+    keep = rng.random(sites.shape[1]) < np.clip(field(sites, L) / rho_max, 0.0, 1.0)
+    pos = sites[:, keep]
+    pos = pos + rng.uniform(-jitter * a, jitter * a, size=pos.shape)
+    pos = pos[:, rng.permutation(pos.shape[1])]
+    box = np.array([L, L, L])
+    return np.ascontiguousarray(_wrap(pos, L)), box
+
+
+def _periodic_d2(sites, c, L):
+    d = sites - np.asarray(c, dtype=np.float64)[:, None]
+    d -= L * np.rint(d / L)
+    return (d * d).sum(axis=0)
+
+
+def selection_scenarios(seed: int | None = None):
+    """Generative scenarios for training a configuration-selection model,
+    after the families of the paper's Random Forest dataset (uniform
+    distributions over a range of particle counts, clusters of Gaussian
+    blobs, a dense cuboid in a dilute gas, a sphere in an empty box), made
+    overlap-free by thinning a lattice, in boxes large enough to load the
+    GPU.  Yields (name, dict(pos, vel, box, skin))."""
+    rng = np.random.default_rng(seed_for(5) if seed is None else seed)
+    rho_max = 1.0
+
+    def emit(name, pos, box, skin=0.3):
+        vel = maxwell_boltzmann(pos.shape[1], 1.0, rng)
+        return name, dict(pos=pos, vel=vel, box=box, skin=skin)
+
+    # uniform: densities 0.02 .. 1.0 at three box sizes (and three skins at the middle size)
+    for ncell in (16, 32, 56):
+        for rho in (0.02, 0.05, 0.1, 0.2, 0.4, 0.6, 0.8, 1.0):
+            skins = (0.2, 0.3, 0.4) if ncell == 32 else (0.3,)
+            for skin in skins:
+                pos, box = thinned_fcc(ncell, rho_max, lambda s, L, r=rho: np.full(s.shape[1], r), rng)
+                yield emit("uniform-n%d-rho%.2f-skin%.1f" % (pos.shape[1], rho, skin), pos, box, skin)
+    # Gaussian blobs: k blobs of standard deviation L/12 at random centres
+    for ncell in (32, 56):
+        for k in (10, 40, 160):
+            def blobs(s, L, k=k):
+                cs = rng.uniform(0.0, L, size=(k, 3))
+                w = 2.0 * (L / 12.0) ** 2
+                acc = np.zeros(s.shape[1])
+                for c in cs:
+                    acc += np.exp(-_periodic_d2(s, c, L) / w)
+                return np.minimum(rho_max, 0.9 * acc)
+            pos, box = thinned_fcc(ncell, rho_max, blobs, rng)
+            yield emit("blobs-%d-n%d" % (k, pos.shape[1]), pos, box)
+    # dense cuboid (density 0.9) of thickness f L across the box, in a gas at 0.02
+    for ncell in (32, 56):
+        for f in (0.125, 0.25, 0.5):
+            def cuboid(s, L, f=f):
+                inside = np.abs(s[0] - 0.5 * L) < 0.5 * f * L
+                return np.where(inside, 0.9, 0.02)
+            pos, box = thinned_fcc(ncell, rho_max, cuboid, rng)
+            yield emit("cuboid-%.3f-n%d" % (f, pos.shape[1]), pos, box)
+    # sphere (density 0.85) of radius f L in an empty box
+    for ncell in (32, 56):
+        for f in (0.15, 0.25, 0.35):
+            def sphere(s, L, f=f):
+                return np.where(_periodic_d2(s, (0.5 * L,) * 3, L) < (f * L) ** 2, 0.85, 0.0)
+            pos, box = thinned_fcc(ncell, rho_max, sphere, rng)
+            yield emit("sphere-%.2f-n%d" % (f, pos.shape[1]), pos, box)

@@ -213,6 +213,42 @@ def test_expert_tuner_matches_oracle(M):
         M.Tuner(EXPERT, 2, 2).set_suitability([0.5, 1.5])
 
 
+def test_random_forest_matches_scikit_learn(M):
+    """The library's tree evaluator against scikit-learn's predict for the
+    same forest (refitted from the committed data with the same seed), on
+    the training scenarios and on perturbed and random statistics; and the
+    committed model header is the one that fit writes."""
+    import tempfile
+
+    import numpy as np
+    from paper_2505_03438_amd import rf_train as R
+    X, y = R.load()
+    model = R.fit(X, y)
+    rng = np.random.default_rng(5)
+    rows = [X] + [X * np.exp(rng.normal(0.0, 0.6, size=X.shape)) for _ in range(10)]
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    rows.append(lo + (hi - lo) * rng.random((500, X.shape[1])))
+    XX = np.vstack(rows)
+    want = model.predict(XX)
+    got = np.array([M.md_rf_predict(x) for x in XX])
+    assert np.array_equal(got, want)
+    assert set(want) == {4, 6}  # both classes occur, so the test sees both paths
+    with tempfile.TemporaryDirectory() as d:
+        out = os.path.join(d, "rf_model.h")
+        R.write_header(model, out)
+        assert open(out).read() == open(R.OUT).read()
+
+
+def test_random_forest_rejects(M):
+    with pytest.raises(RuntimeError, match="NaN"):
+        M.md_rf_predict([1.0, float("nan"), 1, 1, 1, 0, 256, 0.3])
+    with pytest.raises(RuntimeError, match="no configuration"):
+        M.md_rf_predict([32, 0, 32, 32, 27, 0, 256, 0.3], 4)  # classes are 4 and 6
+    # with the cluster lists outside the space (FP64) the forest falls back to the other class
+    assert M.md_rf_predict([2.32, 0.66, 2, 9, 729, 66, 256, 0.3], 7) == 6
+    assert M.md_rf_predict([2.32, 0.66, 2, 9, 729, 66, 256, 0.3], 6) == 4
+
+
 def test_tuner_rejects_bad_use(M):
     tu = M.Tuner(PREDICTIVE, 3, 4)
     tr = tu.begin_phase()

@@ -665,6 +665,71 @@ def test_skin_tuning_fp64_trajectory(orc):
     s.h.close()
 
 
+def test_random_forest_strategy_fp64_trajectory(orc):
+    """Random Forest strategy: each phase reads the live statistics, the
+    forest names one configuration, and that one alone is trialled and kept;
+    the trajectory equals the oracle's."""
+    import torch
+    d = W.plain_fcc_864()
+    nsteps = 120
+    p1, v1, _, log0 = orc.velocity_verlet(d["pos"], d["vel"], d["box"], orc.single(), 0.005, nsteps)
+    cfg = make_config(864, d["box"], container=0, precision=1, R=10)
+    cfg.autotune = M.MD_TUNE_RF
+    cfg.tune_interval = 40
+    cfg.tune_trial_steps = 3
+    cfg.total_steps_hint = nsteps
+    s = DeviceSystem(cfg, d["pos"], d["vel"])
+    st = M.md_live_stats(s.h, s.pos)
+    want = M.md_rf_predict(st, 6)
+    s.build()
+    s.forces(energy=False)
+    log = torch.zeros((nsteps, 4), dtype=torch.float64, device="cuda")
+    M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, nsteps, 1, log)
+    torch.cuda.synchronize()
+    log = log.cpu().numpy()
+    cnt = M.md_get_counters(s.h)
+    assert cnt["tuning_phases"] == 3 and cnt["trials"] == 3
+    assert cnt["config_index"] == want
+    assert np.array_equal(log[:, 3], log0[:, 3])
+    for k in (0, 1, 2):
+        assert np.abs(log[:, k] - log0[:, k]).max() <= 1e-10 * np.abs(log0[:, k]).max()
+    dx = s.by_id(s.pos) - p1
+    dx -= d["box"][:, None] * np.rint(dx / d["box"][:, None])
+    assert np.abs(dx).max() < 1e-9
+    s.h.close()
+
+
+def test_random_forest_picks_cluster_lists_for_small_sparse_gas(orc):
+    """A small dilute system (the family where cluster lists won the
+    training trials): the forest picks cluster lists, which then run with
+    the energy conserved."""
+    import torch
+    rng = np.random.default_rng(31)
+    pos, box = W.thinned_fcc(16, 1.0, lambda sites, L: np.full(sites.shape[1], 0.1), rng)
+    n = pos.shape[1]
+    vel = W.maxwell_boltzmann(n, 1.0, rng)
+    cfg = make_config(n, box, container=0, precision=0, R=10)
+    cfg.autotune = M.MD_TUNE_RF
+    cfg.tune_interval = 500  # one phase, at the start
+    cfg.tune_trial_steps = 5
+    cfg.total_steps_hint = 200
+    s = DeviceSystem(cfg, pos, vel)
+    st = M.md_live_stats(s.h, s.pos)
+    assert M.md_rf_predict(st, 7) == 6
+    s.build()
+    s.forces(energy=False)
+    log = torch.zeros((200, 4), dtype=torch.float64, device="cuda")
+    M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, 200, 1, log)
+    torch.cuda.synchronize()
+    log = log.cpu().numpy()
+    cnt = M.md_get_counters(s.h)
+    assert cnt["config_index"] == 6 and cnt["trials"] == 1 and cnt["force_family"] == 2
+    u_rc = orc.lj(6.25)[1]
+    E = (log[:, 0] - log[:, 3] * u_rc + log[:, 1]) / n
+    assert np.abs(E - E[0]).max() < 5e-3
+    s.h.close()
+
+
 def test_expert_rules_rejected_for_untuned_handle(orc):
     d = W.plain_fcc_864()
     s = DeviceSystem(make_config(864, d["box"], container=0, precision=1), d["pos"])
