@@ -47,6 +47,9 @@ VL_COUNTERS = {"kernel": "k_vlw_f32", "sha": "1e6ff319434eaf59",
                "plain": {"fetch_kib": 116584.2, "write_kib": 12377.9, "valu_flops_fp32_wave": 28004872.5}}
 
 
+STRATEGY_NAMES = {"forest": "random-forest", "expert": "expert", "auto": "predictive"}
+
+
 def force_sources_sha():
     import hashlib
     h = hashlib.sha256()
@@ -291,8 +294,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-expert", action="store_true",
-                    help="skip the runs under the Expert and Random Forest strategies")
+    ap.add_argument("--strategy", default="forest", choices=["forest", "expert", "auto"],
+                    help="selection strategy of the headline autotuned run: forest (Random Forest, Sec. 5.3), "
+                         "expert (fuzzy rules, Sec. 5.2) or auto (Predictive, Sec. 5.1)")
+    ap.add_argument("--no-other-strategies", action="store_true",
+                    help="skip the runs under the two other selection strategies")
     ap.add_argument("--extra", default="", help="comma-separated extra configs to time, e.g. "
                     "fixed:vl:1:0:5 (container:csf:n3l:R[:skin]) or auto+skin (Predictive with the skin tuned)")
     ap.add_argument("--ncell", type=int, default=64, help="FCC cells per side (64 -> 1,048,576 particles)")
@@ -341,19 +347,20 @@ def main():
                                                                "%.3f" % r["build_ms"] if r["build_ms"] else "-"))
         print(json.dumps({"probe": args.probe, "workload": wname, "result": r}), flush=True)
         return
-    auto = run(M, d, "auto", args.steps, args.warmup)
-    log("autotuned: %.3f ms/step, %.3e pairs/s, config %s" % (auto["ms_per_step"], auto["pairs_per_s"],
-                                                             auto["final_config"]))
-    expert = None
-    if not args.no_expert:
-        expert = run(M, d, "expert", args.steps, args.warmup)
-        log("expert rules: %.3f ms/step, %.3e pairs/s, config %s, %d trials" % (
-            expert["ms_per_step"], expert["pairs_per_s"], expert["final_config"], expert["counters"]["trials"]))
-    forest = None
-    if not args.no_expert:
-        forest = run(M, d, "forest", args.steps, args.warmup)
-        log("random forest: %.3f ms/step, %.3e pairs/s, config %s, %d trials" % (
-            forest["ms_per_step"], forest["pairs_per_s"], forest["final_config"], forest["counters"]["trials"]))
+    # the headline autotuner is the Random Forest strategy (Sec. 5.3, the paper's most successful
+    # one): a forest fitted to Full Search trials on generative scenarios, not on this workload
+    auto = run(M, d, args.strategy, args.steps, args.warmup)
+    log("autotuned (%s): %.3f ms/step, %.3e pairs/s, config %s, %d trials" % (
+        args.strategy, auto["ms_per_step"], auto["pairs_per_s"], auto["final_config"], auto["counters"]["trials"]))
+    others = {}
+    if not args.no_other_strategies:
+        for kind in ("forest", "expert", "auto"):
+            if kind == args.strategy:
+                continue
+            others[kind] = run(M, d, kind, args.steps, args.warmup)
+            log("%s: %.3f ms/step, %.3e pairs/s, config %s, %d trials" % (
+                STRATEGY_NAMES[kind], others[kind]["ms_per_step"], others[kind]["pairs_per_s"],
+                others[kind]["final_config"], others[kind]["counters"]["trials"]))
     plain = None
     if not args.no_plain:
         plain = run(M, d, "plain", args.steps, args.warmup)
@@ -407,10 +414,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "n": n, "density": 0.8 if args.workload != "slab" else 0.75,
                    "T": float(d.get("T", 1.0)), "rc": 2.5, "skin": 0.3, "dt": 0.005, "positions": "f64",
-                   "pair_arithmetic": "f32", "strategy": "predictive", "parallelism": "single-gpu"},
+                   "pair_arithmetic": "f32", "strategy": STRATEGY_NAMES[args.strategy],
+                   "parallelism": "single-gpu"},
         "autotuned": auto,
-        "expert_strategy": expert,
-        "random_forest_strategy": forest,
+        "other_strategies": {STRATEGY_NAMES[k]: v for k, v in others.items()} or None,
         "plain": plain,
         "fixed_configs": extra or None,
         "speedup_vs_plain": (auto["pairs_per_s"] / plain["pairs_per_s"]) if plain else None,
