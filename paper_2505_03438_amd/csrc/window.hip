@@ -280,6 +280,69 @@ __device__ __forceinline__ void load_window(const Window &w, const int4 *__restr
     }
 }
 
+// Single-precision build windows.  A window particle's coordinates relative
+// to its block's centre, in x units (u = L_x / 2^32; y and z scaled by
+// L_y / L_x and L_z / L_x), so that a candidate distance costs three float
+// subtractions instead of three integer subtractions and conversions.  The
+// offset to the centre is the true one when no window spans a whole periodic
+// dimension (build_float_ok); its rounding (at most 2^-24 of a window
+// extent) is far inside the build's guard band kBuildBand.
+struct FEntry {
+    float x, y, z;
+};
+
+constexpr float kBuildBand = 1.0f / 32768.0f;
+
+// Block centre in fixed point (cell units times 2^32 / nc).
+__device__ __forceinline__ void block_centre(const Geom &g, const Rect &rc, uint32_t &ox, uint32_t &oy, uint32_t &oz)
+{
+    ox = (uint32_t)((((uint64_t)(rc.xa + rc.xb + 1)) << 31) / (uint64_t)g.nc[0]);
+    oy = (uint32_t)((((uint64_t)(rc.y0 + rc.y1 + 1)) << 31) / (uint64_t)g.nc[1]);
+    oz = (uint32_t)((((uint64_t)(2 * rc.z + 1)) << 31) / (uint64_t)g.nc[2]);
+}
+
+__device__ __forceinline__ FEntry to_rel(const int4 &a, uint32_t ox, uint32_t oy, uint32_t oz, float ry, float rz)
+{
+    FEntry e;
+    e.x = (float)(int)((uint32_t)a.x - ox);
+    e.y = (float)(int)((uint32_t)a.y - oy) * ry;
+    e.z = (float)(int)((uint32_t)a.z - oz) * rz;
+    return e;
+}
+
+// Stage the window as FEntry (as load_window, four loads in flight).
+__device__ __forceinline__ void load_window_rel(const Geom &g, const Window &w, const int4 *__restrict__ st,
+                                                FEntry *lds)
+{
+    uint32_t ox, oy, oz;
+    block_centre(g, w.rc, ox, oy, oz);
+    float ry = g.ry, rz = g.rz;
+    int W = w.W;
+    int k = 0;
+    for (int p0 = threadIdx.x; p0 < W; p0 += 1024) {
+        int p1 = p0 + 256, p2 = p0 + 512, p3 = p0 + 768;
+        int4 a0, a1 = a0, a2 = a0, a3 = a0;
+        k = piece_from(w, k, p0);
+        a0 = st[w.pc_start[k] + (p0 - w.pc_win[k])];
+        if (p1 < W) {
+            k = piece_from(w, k, p1);
+            a1 = st[w.pc_start[k] + (p1 - w.pc_win[k])];
+        }
+        if (p2 < W) {
+            k = piece_from(w, k, p2);
+            a2 = st[w.pc_start[k] + (p2 - w.pc_win[k])];
+        }
+        if (p3 < W) {
+            k = piece_from(w, k, p3);
+            a3 = st[w.pc_start[k] + (p3 - w.pc_win[k])];
+        }
+        lds[p0] = to_rel(a0, ox, oy, oz, ry, rz);
+        if (p1 < W) lds[p1] = to_rel(a1, ox, oy, oz, ry, rz);
+        if (p2 < W) lds[p2] = to_rel(a2, ox, oy, oz, ry, rz);
+        if (p3 < W) lds[p3] = to_rel(a3, ox, oy, oz, ry, rz);
+    }
+}
+
 // XCD-aware block order: workgroup w runs on XCD w % 8; each XCD takes a
 // contiguous chunk of blocks.
 struct BlockIter {
@@ -530,6 +593,23 @@ __device__ __forceinline__ bool setup_block(const Geom &g, const int32_t *__rest
     }
     load_window(w, st, win);
     if (FAR && threadIdx.x == 0) win[kWinMax].set(far_entry(g, blk));
+    __syncthreads();
+    return true;
+}
+
+// setup_block for the single-precision build windows.
+template <bool HALF>
+__device__ __forceinline__ bool setup_block_rel(const Geom &g, const int32_t *__restrict__ cs,
+                                                const int4 *__restrict__ st, int4 blk, Window &w, FEntry *win,
+                                                int32_t *flags)
+{
+    __syncthreads();
+    make_window<HALF>(g, cs, blk, w);
+    if (w.W > (HALF ? kWinMaxHalf : kWinMax) || w.npart > 256) {  // never made by the packer
+        if (threadIdx.x == 0) atomicOr(&flags[3], 2);
+        return false;
+    }
+    load_window_rel(g, w, st, win);
     __syncthreads();
     return true;
 }
@@ -785,6 +865,30 @@ __device__ __forceinline__ uint32_t build_batch(const int4 &pi, const WinEntry<1
     return mask >> (nb - m);
 }
 
+// build_batch on single-precision relative coordinates (FEntry windows):
+// mask of the candidates with r2 < hi; amb if one lies within hw of mid.
+__device__ __forceinline__ uint32_t build_batch_rel(const FEntry &pi, const FEntry *__restrict__ q, int m, float hi,
+                                                    float mid, float hw, bool &amb)
+{
+    uint32_t mask = 0;
+    float near = 3.0e38f;
+    int nb = 0;
+    auto test = [&](const FEntry &e) {
+        float dx = e.x - pi.x, dy = e.y - pi.y, dz = e.z - pi.z;
+        float r2 = dx * dx + dy * dy + dz * dz;
+        mask = mask + mask + (r2 < hi ? 1u : 0u);
+        near = fminf(near, fabsf(r2 - mid));
+    };
+    for (; nb < m; nb += 4) {
+        test(q[nb]);
+        test(q[nb + 1]);
+        test(q[nb + 2]);
+        test(q[nb + 3]);
+    }
+    amb = near <= hw;
+    return mask >> (nb - m);
+}
+
 // Verlet lists (full windows: every pair within r_c + skin from both sides;
 // half windows: each pair once, in the forward half of the stencil).  Each
 // range of candidates is tested 32 positions at a time into a bit mask, then
@@ -792,7 +896,7 @@ __device__ __forceinline__ uint32_t build_batch(const int4 &pi, const WinEntry<1
 // offsets (window position times esz, the size of the force kernel's window
 // entry) and pad their last chunk with the offset of the far entry; half
 // lists hold window positions (esz 1) padded with 0.
-template <bool ISO, bool HALF>
+template <bool ISO, bool HALF, bool REL>
 __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                    const int32_t *__restrict__ cell_sorted,
                                                    const double *__restrict__ pos, Geom g, int n,
@@ -801,17 +905,28 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
                                                    uint16_t *__restrict__ nbr, int32_t *__restrict__ cnt, int maxn,
                                                    int esz, int32_t *__restrict__ flags)
 {
+    // REL: single-precision windows relative to the block centre (FEntry,
+    // the same 12 bytes as WinEntry<1>), with the wider band kBuildBand
     __shared__ WinEntry<1> win[(HALF ? kWinMaxHalf : kWinMax) + 4];  // + the reads past a batch
     __shared__ Window w;
+    FEntry *winf = (FEntry *)win;
     size_t N = (size_t)n;
     int cmax = 0;
+    const float rl2u = (float)(g.rl2 * g.S[0] * g.S[0]);
+    const float rel_hi = rl2u * (1.0f + kBuildBand), rel_lo = rl2u * (1.0f - kBuildBand);
+    const float rel_hw = rl2u * kBuildBand;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
-        if (!setup_block<1, HALF>(g, cs, st, blocks[blk], w, win, flags)) continue;
+        if (REL) {
+            if (!setup_block_rel<HALF>(g, cs, st, blocks[blk], w, winf, flags)) continue;
+        } else {
+            if (!setup_block<1, HALF>(g, cs, st, blocks[blk], w, win, flags)) continue;
+        }
         int i, k, x;
         if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
         int self = self_position<HALF>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
-        int4 pi = win[self].get();
+        int4 pi = REL ? make_int4(0, 0, 0, 0) : win[self].get();
+        FEntry pf = REL ? winf[self] : FEntry{0.f, 0.f, 0.f};
         uint4 *row = (uint4 *)nbr + i;
         int c = 0;
         Chunk ck;
@@ -820,7 +935,8 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
             for (int base = b; base < en; base += 32) {
                 int m = min(32, en - base);
                 bool amb;
-                uint32_t mask = build_batch<ISO>(pi, win + base, m, g, band, amb);
+                uint32_t mask = REL ? build_batch_rel(pf, winf + base, m, rel_hi, rl2u, rel_hw, amb)
+                                    : build_batch<ISO>(pi, win + base, m, g, band, amb);
                 unsigned us = (unsigned)(self - base);
                 if (us < (unsigned)m) mask &= ~(1u << (m - 1 - us));
                 if (amb) {
@@ -829,11 +945,18 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
                         int h = 31 - __builtin_clz(t);
                         t ^= 1u << h;
                         int p = base + m - 1 - h;
-                        float dx, dy, dz;
-                        staged_delta<ISO>(pi, win[p].get(), g, dx, dy, dz);
-                        float r2 = dx * dx + dy * dy + dz * dz;
-                        if (r2 >= g.rl2_lo &&
-                            !(exact_r2(pos, n, i, window_global(w, p), g.L[0], g.L[1], g.L[2]) < g.rl2))
+                        float r2, lo;
+                        if (REL) {
+                            float dx = winf[p].x - pf.x, dy = winf[p].y - pf.y, dz = winf[p].z - pf.z;
+                            r2 = dx * dx + dy * dy + dz * dz;
+                            lo = rel_lo;
+                        } else {
+                            float dx, dy, dz;
+                            staged_delta<ISO>(pi, win[p].get(), g, dx, dy, dz);
+                            r2 = dx * dx + dy * dy + dz * dz;
+                            lo = g.rl2_lo;
+                        }
+                        if (r2 >= lo && !(exact_r2(pos, n, i, window_global(w, p), g.L[0], g.L[1], g.L[2]) < g.rl2))
                             mask ^= 1u << h;
                     }
                 }
@@ -1370,6 +1493,15 @@ void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *b
     k_blk_write<<<nb, 64, lds, s>>>(g, cs, colsum, band_base, blocks, cap, flags, wmax);
 }
 
+// The single-precision build windows need every window to span less than
+// the box in each dimension: at most kBlkCells columns plus the reach on
+// both sides in x, the band's rows plus the reach in y, 2 r + 1 layers in z.
+bool build_float_ok(const Geom &g)
+{
+    int r = g.reach[0];
+    return g.nc[0] > kBlkCells + 2 * r && g.nc[1] > g.wband + 2 * r && g.nc[2] > 2 * r + 1;
+}
+
 // Size of the force kernels' LDS window entry (positions, plus the type when
 // there are several).
 static int window_entry_size(const Geom &g) { return g.nt == 1 ? (int)sizeof(WinEntry<1>) : (int)sizeof(WinEntry<2>); }
@@ -1383,20 +1515,29 @@ void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sor
     int cap = (int)window_block_cap(n, g);
     maxn = (maxn + 7) & ~7;
     int esz = half ? 1 : window_entry_size(g);
-    if (half) {
-        if (g.iso)
-            k_vlw_build<true, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                              nbr, cnt, maxn, esz, flags);
+    if (build_float_ok(g)) {
+        // relative single-precision windows (the scale of y and z is applied
+        // when staging, so one variant serves every box shape)
+        if (half)
+            k_vlw_build<true, true, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap,
+                                                                    blocks, nbr, cnt, maxn, esz, flags);
         else
-            k_vlw_build<false, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                               nbr, cnt, maxn, esz, flags);
+            k_vlw_build<true, false, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap,
+                                                                     blocks, nbr, cnt, maxn, esz, flags);
+    } else if (half) {
+        if (g.iso)
+            k_vlw_build<true, true, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap,
+                                                                     blocks, nbr, cnt, maxn, esz, flags);
+        else
+            k_vlw_build<false, true, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap,
+                                                                      blocks, nbr, cnt, maxn, esz, flags);
     } else {
         if (g.iso)
-            k_vlw_build<true, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                               nbr, cnt, maxn, esz, flags);
+            k_vlw_build<true, false, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap,
+                                                                      blocks, nbr, cnt, maxn, esz, flags);
         else
-            k_vlw_build<false, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap, blocks,
-                                                                nbr, cnt, maxn, esz, flags);
+            k_vlw_build<false, false, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, pos, g, n, nblk_p, cap,
+                                                                       blocks, nbr, cnt, maxn, esz, flags);
     }
 }
 

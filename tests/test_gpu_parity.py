@@ -259,6 +259,55 @@ def test_verlet_sets_bit_exact(orc, half, prec, csf):
     assert set(seen) == want
 
 
+@pytest.mark.parametrize("csf", [1.0, 0.5])
+@pytest.mark.parametrize("half", [0, 1])
+def test_verlet_sets_long_box(orc, half, csf):
+    """A box long enough in x (39 CSF-1 cells, more than a block and its
+    reach) for the single-precision build windows, and anisotropic (1:1/8:1/8,
+    so y and z are rescaled when staged): the sets still equal the oracle's."""
+    pos, box = _jittered(None, 8, jitter=0.1, shape=(64, 8, 8))
+    n = pos.shape[1]
+    cfg = make_config(n, box, container=1, newton3=half, precision=0, csf=csf)
+    s = DeviceSystem(cfg, pos)
+    s.build()
+    counts, rows = M.md_get_neighbors(s.h, 256)
+    counts = counts.cpu().numpy()
+    rows = rows.cpu().numpy()
+    ids = s.ids_np()
+    ref = orc.neighbor_rows(pos, box, (2.5 + 0.3) ** 2, np.arange(n))
+    if not half:
+        for k in range(n):
+            assert np.array_equal(np.sort(ids[rows[k, :counts[k]]]), ref[ids[k]]), k
+        return
+    seen = set()
+    for k in range(n):
+        for j in ids[rows[k, :counts[k]]]:
+            key = (min(ids[k], j), max(ids[k], j))
+            assert key not in seen, key
+            seen.add(key)
+    assert seen == {(i, j) for i in range(n) for j in ref[i] if i < j}
+
+
+def test_verlet_sets_large_cubic_box(orc):
+    """A cubic box of 36 CSF-1 cells per side (dilute, 108,000 particles):
+    rows of 3000 sampled particles equal the oracle's."""
+    rng = np.random.default_rng(12)
+    pos, box = W.jittered_fcc(30, 0.1, 0.1, rng)
+    n = pos.shape[1]
+    cfg = make_config(n, box, container=1, precision=0, max_neighbors=64)
+    s = DeviceSystem(cfg, pos)
+    s.build()
+    counts, rows = M.md_get_neighbors(s.h, 64)
+    counts = counts.cpu().numpy()
+    rows = rows.cpu().numpy()
+    ids = s.ids_np()
+    pick = rng.choice(n, 3000, replace=False)
+    ref = orc.neighbor_rows(pos, box, (2.5 + 0.3) ** 2, ids[pick])
+    assert counts.max() <= 64
+    for t, k in enumerate(pick):
+        assert np.array_equal(np.sort(ids[rows[k, :counts[k]]]), ref[t]), k
+
+
 # ---------------------------------------------------------------- integration
 
 def _run_nve(orc, prec, cont, nsteps=100, R=10, dt=0.005, energy_every=1, d=None):
