@@ -160,7 +160,7 @@ static void free_buffers(md_handle *h)
                     b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
                     b.cl_nbr_count, b.snap_pos, b.snap_vel,
                     b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart, b.pos_alt, b.stage_alt,
-                    b.w_blk, b.w_rown, b.w_rowb, b.w_nbr};
+                    b.w_blk, b.w_staged, b.w_rown, b.w_rowb, b.w_nbr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (b.host_flags) (void)hipHostFree(b.host_flags);
@@ -502,6 +502,14 @@ static int ensure_window(md_handle *h, int64_t maxn)
         if ((rc = dalloc(&b.w_blk, cap))) return rc;
         b.w_cap = cap;
     }
+    int64_t staged = window_staged_blocks(h->g);
+    if (staged > b.w_staged_cap) {
+        if (b.w_staged) (void)hipFree(b.w_staged);
+        b.w_staged = nullptr;
+        b.w_staged_cap = 0;
+        if ((rc = dalloc(&b.w_staged, staged))) return rc;
+        b.w_staged_cap = staged;
+    }
     int64_t rows = (int64_t)h->g.nc[1] * h->g.nc[2] + 1;
     if (rows > b.w_rows_cap) {
         for (int32_t **p : {&b.w_rown, &b.w_rowb}) {
@@ -529,9 +537,7 @@ static int build_blocks(md_handle *h, hipStream_t s)
     Buffers &b = h->b;
     int rc = ensure_window(h, h->cfg.max_neighbors);
     if (rc) return rc;
-    // the per-cell counts are no longer needed once the cells are built: the
-    // same buffer holds the window column sums of the packer
-    launch_blocks(h->g, b.cell_start, b.cell_count, b.w_rown, b.w_rowb, b.scan_blocks, b.w_blk, (int)b.w_cap,
+    launch_blocks(h->g, b.cell_start, b.w_staged, b.w_rown, b.w_rowb, b.scan_blocks, b.w_blk, (int)b.w_cap,
                   b.flags, h->cfg.newton3 == MD_N3L_ON, s);
     return MD_OK;
 }

@@ -94,6 +94,8 @@ struct Buffers {
     int4 *snap_stage = nullptr;
     // Verlet lists over LDS windows (FP32 gather-only)
     int4 *w_blk = nullptr;  // per block: first cell, last cell, particle range (or -1, -1)
+    int4 *w_staged = nullptr;  // the packer's per-band staging of blocks
+    int64_t w_staged_cap = 0;
     int32_t *w_rown = nullptr, *w_rowb = nullptr;
     uint16_t *w_nbr = nullptr;
     int64_t w_cap = 0, w_rows_cap = 0, w_nbr_cap = 0;
@@ -201,8 +203,10 @@ void launch_force(const ForceArgs &a, const Geom &g, hipStream_t s);
 int64_t window_block_cap(int64_t n, const Geom &g);
 int window_nbands(const Geom &g);
 int window_force_blocks();
-void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *band_n, int32_t *band_base,
+void launch_blocks(const Geom &g, const int32_t *cs, int4 *staged, int32_t *band_n, int32_t *band_base,
                    int32_t *scan_scratch, int4 *blocks, int cap, int32_t *flags, bool half, hipStream_t s);
+// Staging slots the packer needs (int4 each).
+int64_t window_staged_blocks(const Geom &g);
 void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
                       const Geom &g, int n, const int32_t *nblk_p, const int4 *blocks, uint16_t *nbr, int32_t *cnt,
                       int maxn, int32_t *flags, bool half, hipStream_t s);

@@ -431,19 +431,15 @@ __device__ __forceinline__ ColRanges column_ranges(const Geom &g, const Window &
 
 // ------------------------------------------------------------------ block partition
 
-// Particles of the window rows of a block band at column x: the window of a
-// block spanning columns xa..xb of band (z, y0 .. y1) is the sum over its
-// window columns.  Band bi of layer z covers y-rows bi * band .. ; colsum is
-// [layer][band][x].
+// Particles of the window rows of band e (layer z, y-rows bi * band ..) in
+// column x: the window of a block spanning columns xa..xb of the band is the
+// sum over its window columns.
 template <bool HALF>
-__global__ void k_colsum(Geom g, const int32_t *__restrict__ cs, int32_t *__restrict__ colsum)
+__device__ __forceinline__ int band_column_sum(const Geom &g, const int32_t *__restrict__ cs, int e, int x)
 {
     int nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
     int band = g.wband, nby = (ny + band - 1) / band;
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nz * nby * nx) return;
-    int x = e % nx, t = e / nx;
-    int bi = t % nby, z = t / nby;
+    int bi = e % nby, z = e / nby;
     int r = g.reach[0];
     int y0 = bi * band, nyb = min(band, ny - y0);
     int nrow = window_nrow(r, nyb, HALF);
@@ -454,7 +450,7 @@ __global__ void k_colsum(Geom g, const int32_t *__restrict__ cs, int32_t *__rest
         int cell = (wrap_dim(z + dz, nz) * ny + wrap_dim(y0 + dy, ny)) * nx + x;
         s += cs[cell + 1] - cs[cell];
     }
-    colsum[e] = s;
+    return s;
 }
 
 // Greedy packing of one band, by one wavefront: the band's column data is
@@ -463,13 +459,13 @@ __global__ void k_colsum(Geom g, const int32_t *__restrict__ cs, int32_t *__rest
 // fits the LDS tile (wmax positions).  Bands of one row are cut at particle
 // granularity (a block may start and end inside a cell, so that most blocks
 // hold exactly 256 particles and fill four wavefronts); bands of several rows
-// are cut at whole columns.  emit == false only counts.  A single column
-// whose window cannot be held reports flags[3].
+// are cut at whole columns.  Blocks nb with base + nb < cap are written (if
+// emit).  A single column whose window cannot be held reports flags[3].
 constexpr int kPackMaxX = 4096;
 
-__device__ int pack_band(int e, const Geom &g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
-                         int base, int4 *blocks, bool emit, int cap, int32_t *flags, int wmax, int *scol, int *snum,
-                         int *sst)
+template <bool HALF>
+__device__ int pack_band(int e, const Geom &g, const int32_t *__restrict__ cs, int base, int4 *blocks, bool emit,
+                         int cap, int32_t *flags, int wmax, int *scol, int *snum, int *sst)
 {
     int nx = g.nc[0], ny = g.nc[1];
     int band = g.wband, nby = (ny + band - 1) / band;
@@ -478,7 +474,7 @@ __device__ int pack_band(int e, const Geom &g, const int32_t *__restrict__ cs, c
     int r = g.reach[0];
     bool one_row = y0 == y1;
     for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-        scol[x] = colsum[(size_t)e * nx + x];
+        scol[x] = band_column_sum<HALF>(g, cs, e, x);
         int m = 0;
         for (int y = y0; y <= y1; y++) {
             int c = (z * ny + y) * nx + x;
@@ -549,21 +545,38 @@ __device__ int pack_band(int e, const Geom &g, const int32_t *__restrict__ cs, c
 }
 
 // The three per-column LDS arrays of the packer are sized at launch: 3 nx ints.
-__global__ void k_blk_count(const Geom g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
-                            int32_t *__restrict__ band_n, int wmax)
+// The counting pass also writes the first kBandCap blocks of its band to
+// staging (slots e * kBandCap ..); the writing pass copies them to their
+// final places, and packs again only a band with more blocks.
+constexpr int kBandCap = 16;
+
+template <bool HALF>
+__global__ void k_blk_count(const Geom g, const int32_t *__restrict__ cs, int32_t *__restrict__ band_n,
+                            int4 *__restrict__ staged, int32_t *flags, int wmax)
 {
     extern __shared__ int pack_lds[];
     int *scol = pack_lds, *snum = pack_lds + g.nc[0], *sst = pack_lds + 2 * g.nc[0];
-    int nb = pack_band(blockIdx.x, g, cs, colsum, 0, nullptr, false, 0, nullptr, wmax, scol, snum, sst);
-    if (threadIdx.x == 0) band_n[blockIdx.x] = nb;
+    int e = blockIdx.x;
+    int nb = pack_band<HALF>(e, g, cs, e * kBandCap, staged, true, (e + 1) * kBandCap, flags, wmax, scol, snum,
+                             sst);
+    if (threadIdx.x == 0) band_n[e] = nb;
 }
 
-__global__ void k_blk_write(const Geom g, const int32_t *__restrict__ cs, const int32_t *__restrict__ colsum,
-                            const int32_t *__restrict__ band_base, int4 *blocks, int cap, int32_t *flags, int wmax)
+template <bool HALF>
+__global__ void k_blk_write(const Geom g, const int32_t *__restrict__ cs, const int32_t *__restrict__ band_n,
+                            const int32_t *__restrict__ band_base, const int4 *__restrict__ staged, int4 *blocks,
+                            int cap, int32_t *flags, int wmax)
 {
     extern __shared__ int pack_lds[];
     int *scol = pack_lds, *snum = pack_lds + g.nc[0], *sst = pack_lds + 2 * g.nc[0];
-    pack_band(blockIdx.x, g, cs, colsum, band_base[blockIdx.x], blocks, true, cap, flags, wmax, scol, snum, sst);
+    int e = blockIdx.x;
+    int nb = band_n[e], base = band_base[e];
+    if (nb <= kBandCap) {
+        for (int j = threadIdx.x; j < nb; j += blockDim.x)
+            if (base + j < cap) blocks[base + j] = staged[e * kBandCap + j];
+    } else {
+        pack_band<HALF>(e, g, cs, base, blocks, true, cap, flags, wmax, scol, snum, sst);
+    }
 }
 
 // A staged position at least r_c + skin from every particle of the block
@@ -1474,24 +1487,28 @@ bool window_geometry_ok(const Geom &g, bool half)
     return g.wband >= 1 && g.wband <= kWinBlkRows && g.nc[1] >= g.wband + 2 * r && g.nc[0] <= kPackMaxX;
 }
 
-// Blocks of the windowed kernels: column sums, per-band block counts, their
-// scan, then the descriptors.  (Ordering each XCD's blocks by size, largest
-// first, was measured to gain nothing and cost a launch per build.)
-void launch_blocks(const Geom &g, const int32_t *cs, int32_t *colsum, int32_t *band_n, int32_t *band_base,
+// Blocks of the windowed kernels: per-band block counts (with the band's
+// first blocks staged), their scan, then the descriptors.  (Ordering each
+// XCD's blocks by size, largest first, was measured to gain nothing and cost
+// a launch per build.)
+void launch_blocks(const Geom &g, const int32_t *cs, int4 *staged, int32_t *band_n, int32_t *band_base,
                    int32_t *scan_scratch, int4 *blocks, int cap, int32_t *flags, bool half, hipStream_t s)
 {
     int nb = window_nbands(g);
     int wmax = half ? kWinMaxHalf : kWinMax;
-    int ncol = nb * g.nc[0];
-    if (half)
-        k_colsum<true><<<(ncol + 255) / 256, 256, 0, s>>>(g, cs, colsum);
-    else
-        k_colsum<false><<<(ncol + 255) / 256, 256, 0, s>>>(g, cs, colsum);
     size_t lds = 3 * (size_t)g.nc[0] * sizeof(int);  // <= 48 KB (nc[0] <= kPackMaxX)
-    k_blk_count<<<nb, 64, lds, s>>>(g, cs, colsum, band_n, wmax);
+    if (half)
+        k_blk_count<true><<<nb, 64, lds, s>>>(g, cs, band_n, staged, flags, wmax);
+    else
+        k_blk_count<false><<<nb, 64, lds, s>>>(g, cs, band_n, staged, flags, wmax);
     launch_scan(band_n, band_base, nb, scan_scratch, s);
-    k_blk_write<<<nb, 64, lds, s>>>(g, cs, colsum, band_base, blocks, cap, flags, wmax);
+    if (half)
+        k_blk_write<true><<<nb, 64, lds, s>>>(g, cs, band_n, band_base, staged, blocks, cap, flags, wmax);
+    else
+        k_blk_write<false><<<nb, 64, lds, s>>>(g, cs, band_n, band_base, staged, blocks, cap, flags, wmax);
 }
+
+int64_t window_staged_blocks(const Geom &g) { return (int64_t)window_nbands(g) * kBandCap; }
 
 // The single-precision build windows need every window to span less than
 // the box in each dimension: at most kBlkCells columns plus the reach on
