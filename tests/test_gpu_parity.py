@@ -308,6 +308,36 @@ def test_verlet_sets_large_cubic_box(orc):
         assert np.array_equal(np.sort(ids[rows[k, :counts[k]]]), ref[t]), k
 
 
+@pytest.mark.parametrize("cont", [(1, 0, 1.0), (1, 1, 1.0), (0, 0, 1.0), (0, 1, 1.0)],
+                         ids=["vl", "vl-n3l", "lc", "lc-n3l"])
+def test_long_cell_rows(orc, cont):
+    """Rows of 244 cells (about 4300 particles, 17 blocks of 256): more blocks
+    per band than the packer's counting pass stages, so the writing pass
+    packs those bands again.  Forces and pair counts against the oracle;
+    for Verlet lists also 1500 sampled rows."""
+    pos, box = _jittered(None, 8, jitter=0.1, shape=(400, 8, 8))
+    n = pos.shape[1]
+    F0, U0, W0, P0 = orc.forces(pos, box, orc.single(), cells=True)
+    cfg = make_config(n, box, container=cont[0], newton3=cont[1], csf=cont[2], precision=0)
+    s = DeviceSystem(cfg, pos)
+    s.build()
+    out = s.forces().cpu().numpy()
+    assert M.md_get_counters(s.h)["force_family"] == 1  # the windowed kernels ran
+    assert int(out[2]) == P0
+    assert rel_l2(s.by_id(s.force), F0) <= 1e-5
+    assert abs(out[0] - U0) <= 1e-6 * abs(U0)
+    if cont[0] == 1 and not cont[1]:
+        counts, rows = M.md_get_neighbors(s.h, 128)
+        counts = counts.cpu().numpy()
+        rows = rows.cpu().numpy()
+        ids = s.ids_np()
+        pick = np.random.default_rng(3).choice(n, 1500, replace=False)
+        ref = orc.neighbor_rows(pos, box, (2.5 + 0.3) ** 2, ids[pick])
+        for t, k in enumerate(pick):
+            assert np.array_equal(np.sort(ids[rows[k, :counts[k]]]), ref[t]), k
+    s.h.close()
+
+
 # ---------------------------------------------------------------- integration
 
 def _run_nve(orc, prec, cont, nsteps=100, R=10, dt=0.005, energy_every=1, d=None):
