@@ -286,11 +286,155 @@ def cpu_baseline(d, target_s=10.0, brute_s=2.0):
             "brute_force_sample": "%d FP64 brute-force rows (each scans all %d particles), %.1f s" % (m2, n, tb)}
 
 
+def bench_batched(M, W, steps, warmup, sample=64):
+    """The 4096 uneven systems advanced together (persistent launches, one
+    rebuild interval captured in a HIP graph), against the same systems each
+    run through its own handle (one launch sequence per system, timed on a
+    seeded sample and scaled to all 4096)."""
+    import numpy as np
+    import torch
+    syss = W.batched_systems()
+    nsys = len(syss)
+    offs = np.zeros(nsys + 1, np.int64)
+    offs[1:] = np.cumsum([sy["pos"].shape[1] for sy in syss])
+    boxes = np.stack([sy["box"] for sy in syss])
+    n = int(offs[-1])
+    dev = "cuda"
+
+    def cfg_for(nn, box):
+        c = M.config_default(nn, float(box[0]))
+        c.precision = M.MD_FP32
+        c.container = M.MD_CONTAINER_LC
+        c.rebuild_interval = 5
+        return c
+
+    pos = torch.tensor(np.concatenate([sy["pos"] for sy in syss], axis=1), dtype=torch.float64, device=dev)
+    vel = torch.tensor(np.concatenate([sy["vel"] for sy in syss], axis=1), dtype=torch.float32, device=dev)
+    force = torch.zeros((3, n), dtype=torch.float32, device=dev)
+    typ = torch.zeros(n, dtype=torch.int32, device=dev)
+    ids = torch.arange(n, dtype=torch.int32, device=dev)
+    lj = torch.tensor([1.0, 1.0], dtype=torch.float64, device=dev)
+    im = torch.ones(1, dtype=torch.float64, device=dev)
+    b = M.md_batch_create(cfg_for(n, boxes[0]), offs, boxes)
+    M.md_batch_build_cells(b, pos, vel, force, typ, ids)
+    out = torch.zeros(4 * nsys, dtype=torch.float64, device=dev)
+    M.md_batch_compute_forces(b, pos, typ, lj, force, out)
+    torch.cuda.synchronize()
+    pairs = float(out.view(nsys, 4)[:, 2].sum().item())
+    res = {}
+    for graph in (True, False):
+        M.md_batch_step(b, pos, vel, force, typ, ids, im, lj, 0.005, warmup, use_graph=graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M.md_batch_step(b, pos, vel, force, typ, ids, im, lj, 0.005, steps, use_graph=graph)
+        torch.cuda.synchronize()
+        res[graph] = (time.perf_counter() - t0) / steps
+    b.close()
+    # one handle per system, on a seeded sample
+    pick = np.random.default_rng(11).choice(nsys, sample, replace=False)
+    t_sum, n_sum = 0.0, 0
+    for sidx in pick:
+        sy = syss[sidx]
+        nn = sy["pos"].shape[1]
+        h = M.md_create(cfg_for(nn, sy["box"]))
+        p = torch.tensor(sy["pos"], dtype=torch.float64, device=dev)
+        v = torch.tensor(sy["vel"], dtype=torch.float32, device=dev)
+        f = torch.zeros((3, nn), dtype=torch.float32, device=dev)
+        t = torch.zeros(nn, dtype=torch.int32, device=dev)
+        i = torch.arange(nn, dtype=torch.int32, device=dev)
+        M.md_build_cells(h, p, v, f, t, i)
+        M.md_compute_forces(h, p, t, lj, f)
+        M.md_step(h, p, v, f, t, i, im, lj, 0.005, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M.md_step(h, p, v, f, t, i, im, lj, 0.005, steps)
+        torch.cuda.synchronize()
+        t_sum += (time.perf_counter() - t0) / steps
+        n_sum += nn
+        h.close()
+    per_system = t_sum * nsys / sample
+    return {"metric": "LJ pair-interactions/sec, 4096 batched systems (256-8192 particles each), "
+                      "persistent launches in a HIP graph",
+            "value": pairs / res[True], "unit": "pair-interactions/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": 1e3 * res[True], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "lj-batched-4096", "systems": nsys, "n": n, "pairs_per_step": pairs,
+                       "container": "linked cells CSF 1, gather-only", "rebuild_interval": 5, "dt": 0.005},
+            "direct_launches_ms_per_step": 1e3 * res[False],
+            "one_handle_per_system_ms_per_step": 1e3 * per_system,
+            "one_handle_per_system_how": "md_step per system on %d seeded systems (%d particles), scaled by "
+                                         "4096/%d" % (sample, n_sum, sample),
+            "speedup_vs_one_handle_per_system": per_system / res[True]}
+
+
+def bench_adjoint(M, W, reps):
+    """Forward forces and the adjoint (md_forces_backward) on the 131,072-
+    particle binary mixture, timed with HIP events on torch's stream."""
+    import numpy as np
+    import torch
+    d = W.binary_mixture()
+    pos0, box, types = d["pos"], d["box"], d["types"]
+    n = pos0.shape[1]
+    theta = W.perturb_params(np.array(d["eps"] + d["sig"]))
+    sig0 = d["sig"]
+    res = {}
+    for cont in ("lc", "vl"):
+        c = M.config_default(n, float(box[0]))
+        c.precision = M.MD_FP32
+        c.n_types = 2
+        c.container = M.MD_CONTAINER_LC if cont == "lc" else M.MD_CONTAINER_VL
+        for a in range(2):
+            for bb in range(2):
+                c.rc2[a * 2 + bb] = (2.5 * 0.5 * (sig0[a] + sig0[bb])) ** 2  # cutoffs fixed at theta_0
+        c.max_neighbors = 160
+        h = M.md_create(c)
+        dev = "cuda"
+        p = torch.tensor(pos0, dtype=torch.float64, device=dev)
+        v = torch.zeros((3, n), dtype=torch.float32, device=dev)
+        f = torch.zeros((3, n), dtype=torch.float32, device=dev)
+        t = torch.tensor(types, dtype=torch.int32, device=dev)
+        i = torch.arange(n, dtype=torch.int32, device=dev)
+        lj = torch.tensor(theta, dtype=torch.float64, device=dev)
+        out = torch.zeros(4, dtype=torch.float64, device=dev)
+        M.md_build_cells(h, p, v, f, t, i)
+        M.md_build_neighbors(h, p, t)
+        M.md_compute_forces(h, p, t, lj, f, out)
+        g = (f * 1e-3).contiguous()
+        gp = torch.zeros((3, n), dtype=torch.float64, device=dev)
+        gl = torch.zeros(4, dtype=torch.float64, device=dev)
+        M.md_forces_backward(h, p, t, lj, g, gp, gl)
+        torch.cuda.synchronize()
+        pairs = float(out[2].item())
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        for _ in range(reps):
+            M.md_compute_forces(h, p, t, lj, f)
+        e[1].record()
+        for _ in range(reps):
+            M.md_forces_backward(h, p, t, lj, g, gp, gl)
+        e[2].record()
+        torch.cuda.synchronize()
+        fwd = e[0].elapsed_time(e[1]) / reps
+        bwd = e[1].elapsed_time(e[2]) / reps
+        res[cont] = {"forward_ms": fwd, "backward_ms": bwd, "pairs": pairs,
+                     "backward_pairs_per_s": pairs / (bwd * 1e-3)}
+        h.close()
+    best = min(res, key=lambda k: res[k]["backward_ms"])
+    return {"metric": "adjoint (md_forces_backward) pair-interactions/sec, 131,072-particle binary LJ mixture",
+            "value": res[best]["backward_pairs_per_s"], "unit": "pair-interactions/s", "n_gpus": 1,
+            "steps": reps, "warmup": 1, "ms_per_step": res[best]["backward_ms"] + res[best]["forward_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "lj-mixture-131072", "n": n, "density": 1.2, "types": "80/20 A/B",
+                       "container": best, "reduction": "f64"},
+            "by_container": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 1000 for the fluid, "
-                    "2000 for the droplet and the slab)")
+                    "2000 for the droplet and the slab, 100 for the batched systems, 20 adjoint calls)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -302,16 +446,17 @@ def main():
     ap.add_argument("--extra", default="", help="comma-separated extra configs to time, e.g. "
                     "fixed:vl:1:0:5 (container:csf:n3l:R[:skin]) or auto+skin (Predictive with the skin tuned)")
     ap.add_argument("--ncell", type=int, default=64, help="FCC cells per side (64 -> 1,048,576 particles)")
-    ap.add_argument("--workload", default="fluid", choices=["fluid", "droplet", "slab"],
+    ap.add_argument("--workload", default="fluid", choices=["fluid", "droplet", "slab", "batched", "adjoint"],
                     help="fluid: the 1M homogeneous fluid (the benchmark line); droplet / slab: the 2M "
-                         "inhomogeneous systems (autotuner re-selection, measured for reference)")
+                         "inhomogeneous systems (autotuner re-selection); batched: 4096 small systems in one "
+                         "graph; adjoint: the force-matching gradient on the 131k mixture")
     ap.add_argument("--probe", default="", help="time only this configuration (e.g. fixed:vl:1:0:5) and print "
                     "its result; for profiler runs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="run a plain device-to-device copy of MIB MiB ten times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = 1000 if args.workload == "fluid" else 2000
+        args.steps = {"fluid": 1000, "batched": 100, "adjoint": 20}.get(args.workload, 2000)
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
               file=sys.stderr)
@@ -329,6 +474,12 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_mib": args.copy_probe, "launches": 10}), flush=True)
+        return
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(M, W, args.steps, min(args.warmup, 10))), flush=True)
+        return
+    if args.workload == "adjoint":
+        print(json.dumps(bench_adjoint(M, W, args.steps)), flush=True)
         return
     if args.workload == "fluid":
         d = W.homogeneous_fluid(ncell=args.ncell)
