@@ -1169,6 +1169,14 @@ extern "C" int md_forces_backward(md_handle *h, const double *pos, const int32_t
     a.grad_pos = grad_pos;
     a.gpart = h->b.gpart;
     a.flags = h->b.flags;
+    if (use_window(h->cfg, h->g) && h->cfg.newton3 == MD_N3L_OFF) {
+        // the blocks of the current cell build were packed for full windows
+        launch_adjoint_window(h->b.stage, h->b.cell_start, h->b.cell_sorted, h->g, (int)h->n,
+                              h->b.w_rowb + window_nbands(h->g), h->b.w_blk, h->b.tab, pos,
+                              (const float *)grad_force, grad_pos, h->b.gpart, h->b.flags, s);
+        launch_adjoint_finish(h->b.gpart, h->n > 0 ? window_force_blocks() : 0, lj, h->cfg.n_types, grad_lj, s);
+        return MD_OK;
+    }
     launch_adjoint(a, h->g, s);
     launch_adjoint_finish(h->b.gpart, h->n > 0 ? adjoint_blocks((int)h->n) : 0, lj, h->cfg.n_types, grad_lj, s);
     return MD_OK;

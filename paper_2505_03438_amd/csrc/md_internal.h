@@ -249,6 +249,11 @@ struct AdjointArgs {
 };
 int adjoint_blocks(int n);
 void launch_adjoint(const AdjointArgs &a, const Geom &g, hipStream_t s);
+// The adjoint over the gather windows (FP32; blocks packed for full windows);
+// per-workgroup partials in gpart[window_force_blocks()][8].
+void launch_adjoint_window(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, int n,
+                           const int32_t *nblk_p, const int4 *blocks, const PairTab *tab, const double *pos,
+                           const float *G, double *grad_pos, double *gpart, int32_t *flags, hipStream_t s);
 void launch_adjoint_finish(const double *gpart, int nblocks, const double *lj, int nt,
                            double *grad_lj, hipStream_t s);
 

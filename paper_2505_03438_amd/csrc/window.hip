@@ -360,9 +360,8 @@ struct BlockIter {
 // The particle of this thread in the block: its index i, block row k and
 // cell column x; false if the thread has none.
 __device__ __forceinline__ bool my_particle(const Geom &g, const Window &w, const int32_t *__restrict__ cell_sorted,
-                                            int &i, int &k, int &x)
+                                            int &i, int &k, int &x, int t = threadIdx.x)
 {
-    int t = threadIdx.x;
     if (t >= w.npart) return false;
     k = 0;
     while (k + 1 < w.nyb && w.bpref[k + 1] <= t) k++;
@@ -788,6 +787,165 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
         block_sum4(v, sh);
         if (threadIdx.x == 0)
             for (int k = 0; k < 4; k++) partials[blockIdx.x * 4 + k] = v[k];
+    }
+}
+
+// ------------------------------------------------------------------ adjoint
+
+// Adjoint of the forces (the differentiable extension) over the gather
+// windows, FP32 pairs: each thread gathers its particle's row
+//   dL/dx_i = sum_j J_ij (g_i - g_j),  J = phi I + 2 (dphi/dr2) d d^T,
+// from its stencil ranges (the cutoff prefilter, then the pair terms for the
+// survivors only, guard-band pairs decided from the FP64 positions; g_j read
+// from global memory).  The pair parameters are picked per pair by the
+// partner's type alone (this particle's type fixes the rest).  The parameter
+// terms
+//   (phi/eps_ab) d.(g_i - g_j),  144 eps q (4q - 1)/(sig r^2) d.(g_i - g_j)
+// are seen from both sides of each pair and halved when the per-workgroup
+// partials are summed.  FP64 accumulation of the gradient and the parameter
+// terms; 1/r^2 by the hardware reciprocal.  (Four or two threads per
+// particle, to occupy the GPU better on small systems, measured slower.)
+template <int NT, bool ISO>
+__global__ __launch_bounds__(256) void k_adjw_f32(
+    const int4 *__restrict__ st, const int32_t *__restrict__ cs, const int32_t *__restrict__ cell_sorted, Geom g,
+    int n, const int32_t *__restrict__ nblk_p, int cap, const int4 *__restrict__ blocks,
+    const PairTab *__restrict__ tabp, const double *__restrict__ pos, const float *__restrict__ G,
+    double *__restrict__ grad_pos, double *__restrict__ gpart, int32_t *__restrict__ flags)
+{
+    __shared__ WinEntry<NT> win[kWinMax + 4];  // + the reads past a batch
+    __shared__ Window w;
+    __shared__ double sh[8][256 / 64];
+    float hmax = 0.f;
+    for (int k = 0; k < NT * NT; k++) hmax = fmaxf(hmax, tabp->rc2_hi[k]);
+    const float uf = (float)(g.L[0] / 4294967296.0);
+    double gp[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // eps_ab[4], sig_ab[4]
+    size_t N = (size_t)n;
+    for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
+        int blk = it.blk;
+        if (!setup_block<NT>(g, cs, st, blocks[blk], w, win, flags)) continue;
+        int i, k, x;
+        if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        {
+            int self = self_position<false>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
+            int4 pi = win[self].get();
+            float gix = G[i], giy = G[N + i], giz = G[2 * N + i];
+            // the pair parameters for this particle's type against each
+            // partner type (picked per pair by the partner's type alone)
+            const int ti = NT == 1 ? 0 : pi.w;
+            float lo_[2], hi_[2], eps_[2], ieps_[2], sig2_[2], c144_[2];
+            double rc2_[2];
+            for (int tj = 0; tj < NT; tj++) {
+                int ab = ti * NT + tj;
+                lo_[tj] = tabp->rc2_lo[ab];
+                hi_[tj] = tabp->rc2_hi[ab];
+                rc2_[tj] = tabp->rc2[ab];
+                float e = (float)tabp->eps[ab], sg = (float)tabp->sig[ab];
+                eps_[tj] = e;
+                ieps_[tj] = 1.0f / e;
+                sig2_[tj] = sg * sg;
+                c144_[tj] = 144.0f * e / sg;
+            }
+            // parameter terms per partner type (FP64)
+            double ge0 = 0.0, ge1 = 0.0, gs0 = 0.0, gs1 = 0.0;
+            stencil_ranges<false>(g, w, k, x, self, [&](int b, int en) {
+                // global index of window position p: the range lies in one
+                // row, so in its first piece or the one after it
+                int k0 = piece_from(w, 0, b);
+                int split = k0 + 1 < 2 * w.nrow ? w.pc_win[k0 + 1] : INT_MAX;
+                int off0 = w.pc_start[k0] - w.pc_win[k0];
+                int off1 = k0 + 1 < 2 * w.nrow ? w.pc_start[k0 + 1] - w.pc_win[k0 + 1] : 0;
+                for (int base = b; base < en; base += 32) {
+                    int m = min(32, en - base);
+                    uint32_t mask = cut_batch<NT, ISO>(pi, win + base, m, g, hmax);
+                    unsigned us = (unsigned)(self - base);
+                    if (us < (unsigned)m) mask &= ~(1u << (m - 1 - us));
+                    while (mask) {
+                        int h = 31 - __builtin_clz(mask);
+                        mask ^= 1u << h;
+                        int p = base + m - 1 - h;
+                        int j = p + (p < split ? off0 : off1);
+                        float gjx = G[j], gjy = G[N + j], gjz = G[2 * N + j];
+                        int4 pj = win[p].get();
+                        bool t1 = NT > 1 && pj.w != 0;
+                        float dx, dy, dz;
+                        staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+                        float r2u = dx * dx + dy * dy + dz * dz;
+                        if (!within(r2u, t1 ? lo_[1] : lo_[0], t1 ? hi_[1] : hi_[0], t1 ? rc2_[1] : rc2_[0], pos, n,
+                                    i, j, g))
+                            continue;
+                        float dgx = gix - gjx, dgy = giy - gjy, dgz = giz - gjz;
+                        dx *= uf;
+                        dy *= uf;
+                        dz *= uf;
+                        float r2 = dx * dx + dy * dy + dz * dz;
+                        float eps = t1 ? eps_[1] : eps_[0];
+                        float ir2 = __builtin_amdgcn_rcpf(r2);
+                        float s2 = (t1 ? sig2_[1] : sig2_[0]) * ir2;
+                        float q = s2 * s2 * s2;
+                        float phi = 24.0f * eps * ir2 * q * (2.0f * q - 1.0f);
+                        float dphi = -48.0f * eps * ir2 * ir2 * q * (7.0f * q - 2.0f);
+                        float ddg = dx * dgx + dy * dgy + dz * dgz;
+                        float k2 = 2.0f * dphi * ddg;
+                        ax += (double)(phi * dgx + k2 * dx);
+                        ay += (double)(phi * dgy + k2 * dy);
+                        az += (double)(phi * dgz + k2 * dz);
+                        double de = (double)(phi * (t1 ? ieps_[1] : ieps_[0]) * ddg);
+                        double ds = (double)((t1 ? c144_[1] : c144_[0]) * ir2 * q * (4.0f * q - 1.0f) * ddg);
+                        ge0 += t1 ? 0.0 : de;
+                        ge1 += t1 ? de : 0.0;
+                        gs0 += t1 ? 0.0 : ds;
+                        gs1 += t1 ? ds : 0.0;
+                    }
+                }
+            });
+            gp[ti * NT] += ge0;
+            gp[4 + ti * NT] += gs0;
+            if (NT > 1) {
+                gp[ti * NT + 1] += ge1;
+                gp[4 + ti * NT + 1] += gs1;
+            }
+        }
+        grad_pos[i] = ax;
+        grad_pos[N + i] = ay;
+        grad_pos[2 * N + i] = az;
+    }
+    // the workgroup's parameter sums, fixed order
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+        for (int off = 32; off > 0; off >>= 1) gp[q] += __shfl_down(gp[q], off, 64);
+    __syncthreads();
+    int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 8; q++) sh[q][wv] = gp[q];
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double t = 0.0;
+        for (int v = 0; v < 256 / 64; v++) t += sh[threadIdx.x][v];
+        gpart[blockIdx.x * 8 + threadIdx.x] = t;
+    }
+}
+
+void launch_adjoint_window(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, int n,
+                           const int32_t *nblk_p, const int4 *blocks, const PairTab *tab, const double *pos,
+                           const float *G, double *grad_pos, double *gpart, int32_t *flags, hipStream_t s)
+{
+    if (n <= 0) return;
+    int cap = (int)window_block_cap(n, g);
+    if (g.nt == 1) {
+        if (g.iso)
+            k_adjw_f32<1, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, tab, pos,
+                                                          G, grad_pos, gpart, flags);
+        else
+            k_adjw_f32<1, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, tab, pos,
+                                                           G, grad_pos, gpart, flags);
+    } else {
+        if (g.iso)
+            k_adjw_f32<2, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, tab, pos,
+                                                          G, grad_pos, gpart, flags);
+        else
+            k_adjw_f32<2, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, tab, pos,
+                                                           G, grad_pos, gpart, flags);
     }
 }
 
