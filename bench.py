@@ -41,10 +41,10 @@ PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no 
 # per dispatch and per variant: "fused" also integrates each particle for the
 # next step (every step of a rebuild interval but its last), "plain" does not.
 # Valid while the force sources hash to "sha".
-VL_COUNTERS = {"kernel": "k_vlw_f32", "sha": "6bfa7e12171f1321",
+VL_COUNTERS = {"kernel": "k_vlw_f32", "sha": "85658f11d2ce11d1",
                "fetch_factor": 2.0, "write_factor": 1.0,
-               "fused": {"fetch_kib": 144728.4, "write_kib": 66142.8, "valu_flops_fp32_wave": 28150547.1},
-               "plain": {"fetch_kib": 116590.7, "write_kib": 12378.8, "valu_flops_fp32_wave": 28004872.5}}
+               "fused": {"fetch_kib": 144717.0, "write_kib": 66137.7, "valu_flops_fp32_wave": 28150547.1},
+               "plain": {"fetch_kib": 116566.7, "write_kib": 12376.0, "valu_flops_fp32_wave": 28004872.5}}
 
 
 STRATEGY_NAMES = {"forest": "random-forest", "expert": "expert", "auto": "predictive"}

@@ -515,8 +515,12 @@ def test_live_stats(orc):
 
 # ---------------------------------------------------------------- adjoint
 
-@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
-def test_adjoint_matches_oracle(orc, prec):
+@pytest.mark.parametrize("prec,cont", [(1, (0, 0)), (0, (0, 0)), (0, (1, 0)), (0, (0, 1)), (0, (2, 0))],
+                         ids=["fp64", "fp32-lc", "fp32-vl", "fp32-lc-n3l", "fp32-cl"])
+def test_adjoint_matches_oracle(orc, prec, cont):
+    """dL/dx and dL/d(eps, sigma) of the force-matching loss against the
+    oracle: FP32 gather structures run the windowed adjoint, the others (and
+    FP64) the per-particle kernel."""
     import torch
     d = W.binary_mixture(ncell=6, seed=11)
     pos, box, types = d["pos"], d["box"], d["types"]
@@ -527,7 +531,7 @@ def test_adjoint_matches_oracle(orc, prec):
     _, target, _, _ = orc.force_matching(pos, box, types, theta0, rc2, np.zeros((3, n)))
     theta = W.perturb_params(theta0, seed=2)
     L, F, gx, gt = orc.force_matching(pos, box, types, theta, rc2, target)
-    cfg = make_config(n, box, container=0, precision=prec, n_types=2, rc2=rc2)
+    cfg = make_config(n, box, container=cont[0], newton3=cont[1], precision=prec, n_types=2, rc2=rc2)
     s = DeviceSystem(cfg, pos, types=types, eps=list(theta[:2]), sig=list(theta[2:]))
     s.build()
     s.forces(energy=False)
