@@ -253,6 +253,176 @@ __global__ __launch_bounds__(256) void k_bforce(int n, const int4 *__restrict__ 
     }
 }
 
+// FP32 forces over work items of z-slabs: an item is a system and a range of
+// z cell layers [z0, z0 + t), the largest items first.  The workgroup stages
+// the layers the slab's stencils reach (the slab and h halo layers on either
+// side, or the whole system) into LDS: their cell starts, as LDS indices, and
+// their fixed-point positions.  Each thread then takes the slab's particles in
+// turn and tests its stencil candidates 32 at a time (distance test into a bit
+// mask), evaluating the pair force only for those within the cutoff band
+// (guard-band pairs decided from the FP64 positions).  When the staged layers
+// hold more particles than the LDS tile (the slabs are sized from the mean
+// density), the item reads its candidates from global memory instead.
+#ifndef MDLJ_BATCH_LDS_KB
+#define MDLJ_BATCH_LDS_KB 40
+#endif
+constexpr int kBSysLdsBytes = MDLJ_BATCH_LDS_KB * 1024;  // LDS tile per workgroup, at most
+
+// LDS words of an item's tables: layer bases (K + 1), layer offsets (K), cell
+// starts (K nc^2 + 1) and 16 words of positions read past the last batch.
+__host__ __device__ static inline int64_t bslab_table_words(int64_t K, int64_t nc2)
+{
+    return 2 * K + 2 + K * nc2 + 12;
+}
+
+__global__ __launch_bounds__(256) void k_bforce_slab(const int4 *__restrict__ items, const int64_t *__restrict__ offs,
+                                                     const int4 *__restrict__ st, const double *__restrict__ pos,
+                                                     int n, const BSys *__restrict__ sys, const int32_t *__restrict__ cs,
+                                                     const int32_t *__restrict__ cell_sorted, float *__restrict__ F,
+                                                     double *__restrict__ pe, int lds_bytes)
+{
+    extern __shared__ int sm[];
+    const int4 it = items[blockIdx.x];
+    const BSys &b = sys[it.x];
+    const int z0 = it.y, t = it.z, h = it.w;
+    const int p0 = (int)offs[it.x];
+    const int nc = b.nc, nofs = b.nofs, nc2 = nc * nc, cbase = b.cell_base;
+    const float lo = b.lo, hi = b.hi, sig2 = b.sig2, eps24 = b.eps24, eps4 = b.eps4, eps24w = b.eps24w;
+    const double rc2 = b.rc2, L = b.L;
+    const bool whole = t + 2 * h >= nc;
+    const int K = whole ? nc : t + 2 * h;          // staged layers
+    const int zlo = whole ? 0 : (z0 - h + nc) % nc;  // the first of them
+    int *lb = sm, *gofs = sm + K + 1, *scs = sm + 2 * K + 1;
+    int *pp = scs + K * nc2 + 1;
+    bool tile = 4 * bslab_table_words(K, nc2) <= lds_bytes;
+    if (tile) {
+        for (int k = threadIdx.x; k < K; k += blockDim.x) {
+            int zz = (zlo + k) % nc;
+            lb[k + 1] = cs[cbase + (zz + 1) * nc2] - cs[cbase + zz * nc2];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            lb[0] = 0;
+            for (int k = 0; k < K; k++) lb[k + 1] += lb[k];
+        }
+        __syncthreads();
+        tile = 4 * (bslab_table_words(K, nc2) + 3 * (int64_t)lb[K]) <= lds_bytes;
+    }
+    if (tile) {
+        for (int k = threadIdx.x; k < K; k += blockDim.x) {
+            int zz = (zlo + k) % nc;
+            gofs[k] = cs[cbase + zz * nc2] - p0 - lb[k];
+        }
+        __syncthreads();
+        for (int k = 0; k < K; k++) {
+            const int m = lb[k + 1] - lb[k], g = p0 + lb[k] + gofs[k];
+            int *dst = pp + 3 * lb[k];
+            for (int u = threadIdx.x; u < m; u += blockDim.x) {
+                int4 q = st[g + u];
+                dst[3 * u] = q.x;
+                dst[3 * u + 1] = q.y;
+                dst[3 * u + 2] = q.z;
+            }
+        }
+        for (int e = threadIdx.x; e < K * nc2; e += blockDim.x) {
+            int k = e / nc2, zz = (zlo + k) % nc;
+            scs[e] = cs[cbase + zz * nc2 + (e - k * nc2)] - p0 - gofs[k];
+        }
+        if (threadIdx.x == 0) scs[K * nc2] = lb[K];
+        __syncthreads();
+    }
+    const int i0 = cs[cbase + z0 * nc2] - p0, i1 = cs[cbase + (z0 + t) * nc2] - p0;
+    size_t N = (size_t)n;
+    for (int il = i0 + (int)threadIdx.x; il < i1; il += blockDim.x) {
+        const int i = p0 + il;
+        const int local = cell_sorted[i] - cbase;
+        const int cx = local % nc, cy = (local / nc) % nc, cz = local / nc2;
+        const int4 pi = st[i];
+        float fx = 0.f, fy = 0.f, fz = 0.f, eus = 0.f, ews = 0.f;
+        int np = 0;
+        auto pair = [&](int jg, int qx, int qy, int qz) {
+            float dx = (float)(int)((uint32_t)pi.x - (uint32_t)qx);
+            float dy = (float)(int)((uint32_t)pi.y - (uint32_t)qy);
+            float dz = (float)(int)((uint32_t)pi.z - (uint32_t)qz);
+            float r2 = dx * dx + dy * dy + dz * dz;
+            bool in = r2 < lo;
+            if (r2 >= lo && r2 < hi) in = exact_r2(pos, n, i, jg, L, L, L) < rc2;
+            float ir2 = __builtin_amdgcn_rcpf(r2);
+            float s2 = sig2 * ir2;
+            float q = s2 * s2 * s2;
+            float aa = q * (2.0f * q - 1.0f);
+            float phi = in ? eps24 * ir2 * aa : 0.0f;
+            fx += phi * dx;
+            fy += phi * dy;
+            fz += phi * dz;
+            if (pe) {
+                eus += in ? eps4 * q * (q - 1.0f) : 0.0f;
+                ews += in ? eps24w * aa : 0.0f;
+                np += in ? 1 : 0;
+            }
+        };
+        const int self = tile ? il - gofs[(cz - zlo + nc) % nc] : 0;  // the particle's LDS index
+        for (int a = 0; a < nofs; a++) {
+            int zz = cz + b.ofs[a];
+            zz = zz >= nc ? zz - nc : zz;
+            const int k = (zz - zlo + nc) % nc;  // < K: the slab's stencils stay in the staged layers
+            const int gz = tile ? gofs[k] + p0 : 0;
+            for (int bb = 0; bb < nofs; bb++) {
+                int yy = cy + b.ofs[bb];
+                yy = yy >= nc ? yy - nc : yy;
+                for (int e = 0; e < nofs; e++) {
+                    int xx = cx + b.ofs[e];
+                    xx = xx >= nc ? xx - nc : xx;
+                    if (tile) {
+                        const int c = (k * nc + yy) * nc + xx;
+                        const int jb = scs[c], je = scs[c + 1];
+                        for (int base = jb; base < je; base += 32) {
+                            const int m = min(32, je - base);
+                            uint32_t mask = 0;
+                            int nb = 0;
+                            for (; nb < m; nb += 4)
+                                for (int u = 0; u < 4; u++) {
+                                    const int *q = pp + 3 * (base + nb + u);
+                                    float dx = (float)(int)((uint32_t)pi.x - (uint32_t)q[0]);
+                                    float dy = (float)(int)((uint32_t)pi.y - (uint32_t)q[1]);
+                                    float dz = (float)(int)((uint32_t)pi.z - (uint32_t)q[2]);
+                                    float r2 = dx * dx + dy * dy + dz * dz;
+                                    mask = mask + mask + (r2 < hi ? 1u : 0u);
+                                }
+                            mask >>= nb - m;  // the reads past the batch
+                            unsigned us = (unsigned)(self - base);
+                            if (us < (unsigned)m) mask &= ~(1u << (m - 1 - us));
+                            while (mask) {
+                                int hb = 31 - __builtin_clz(mask);
+                                mask ^= 1u << hb;
+                                int jl = base + m - 1 - hb;
+                                const int *q = pp + 3 * jl;
+                                pair(jl + gz, q[0], q[1], q[2]);
+                            }
+                        }
+                    } else {
+                        const int c = cbase + (zz * nc + yy) * nc + xx;
+                        const int jb = cs[c], je = cs[c + 1];
+                        for (int j = jb; j < je; j++)
+                            if (j != i) {
+                                int4 q = st[j];
+                                pair(j, q.x, q.y, q.z);
+                            }
+                    }
+                }
+            }
+        }
+        F[i] = fx;
+        F[N + i] = fy;
+        F[2 * N + i] = fz;
+        if (pe) {
+            pe[i] = eus;
+            pe[N + i] = ews;
+            pe[2 * N + i] = (double)np;
+        }
+    }
+}
+
 // Velocity Verlet pass (as the single-system integrator) with per-system box.
 template <typename real>
 __global__ __launch_bounds__(256) void k_bintegrate(int n, double *__restrict__ pos, real *__restrict__ v,
@@ -345,6 +515,9 @@ struct md_batch {
     std::vector<BSys> hsys;
     BSys *sys = nullptr;
     int64_t *d_offs = nullptr;
+    int4 *items = nullptr;  // the FP32 force kernel's work items (system, z0, t, halo), largest first
+    int n_items = 0;
+    int sys_lds = 0;        // that kernel's LDS tile (bytes)
     int32_t *sys_of = nullptr;
     int64_t ncell = 0;
     int32_t *cell_id = nullptr, *slot = nullptr, *perm = nullptr, *perm2 = nullptr, *count = nullptr,
@@ -372,7 +545,7 @@ static size_t bsize(const md_config &c) { return c.precision == MD_FP64 ? 8 : 4;
 
 static void batch_free(md_batch *b)
 {
-    void *p[] = {b->sys,   b->d_offs, b->sys_of, b->cell_id,  b->slot,      b->perm,       b->perm2,
+    void *p[] = {b->sys,   b->d_offs, b->items, b->sys_of, b->cell_id,  b->slot,      b->perm,       b->perm2,
                  b->count, b->cell_start, b->cell_sorted, b->scan, b->tpos,  b->tvel,       b->tforce,
                  b->ttype, b->tids,   b->stage,  b->stage_ref, b->pe,       b->snap_pos,   b->snap_vel, b->flags};
     for (void *q : p)
@@ -381,6 +554,56 @@ static void batch_free(md_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+}
+
+// Work items of the FP32 force kernel.  A system whose layers all fit the LDS
+// tile is one item; a larger one is cut into z-slabs of t layers, t the
+// largest for which the slab and its halo layers fit with 20 % headroom over
+// the mean density.  Items run largest first.
+static bool upload_items(md_batch *b)
+{
+    std::vector<int4> items;
+    std::vector<int64_t> est;
+    int64_t lds = 0;
+    bool slabs = false;
+    for (int s = 0; s < b->n_sys; s++) {
+        const BSys &y = b->hsys[s];
+        const int nc = y.nc;
+        const int64_t nc2 = (int64_t)nc * nc, ns = b->offsets[s + 1] - b->offsets[s];
+        int h = 0;
+        for (int a = 0; a < y.nofs; a++) h = std::max(h, std::min(y.ofs[a], nc - y.ofs[a]));
+        const int64_t whole = 4 * (bslab_table_words(nc, nc2) + 3 * ns);
+        int t = nc;
+        if (whole > kBSysLdsBytes) {
+            slabs = true;
+            t = 1;
+            for (int tt = nc - 1; tt >= 1; tt--) {
+                const int K = tt + 2 * h;
+                if (K >= nc) continue;
+                const double need = 4.0 * ((double)bslab_table_words(K, nc2) + 3.0 * 1.2 * ns * K / nc);
+                if (need <= kBSysLdsBytes) {
+                    t = tt;
+                    break;
+                }
+            }
+        } else {
+            lds = std::max(lds, whole);
+        }
+        for (int z0 = 0; z0 < nc; z0 += t) {
+            const int tt = std::min(t, nc - z0);
+            items.push_back(make_int4(s, z0, tt, h));
+            est.push_back(ns * tt / nc);
+        }
+    }
+    std::vector<int> idx(items.size());
+    for (size_t k = 0; k < idx.size(); k++) idx[k] = (int)k;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return est[a] > est[c]; });
+    std::vector<int4> sorted(items.size());
+    for (size_t k = 0; k < idx.size(); k++) sorted[k] = items[idx[k]];
+    b->n_items = (int)sorted.size();
+    b->sys_lds = slabs ? kBSysLdsBytes : (int)lds;
+    if (hipMalloc((void **)&b->items, sizeof(int4) * sorted.size()) != hipSuccess) return false;
+    return hipMemcpy(b->items, sorted.data(), sizeof(int4) * sorted.size(), hipMemcpyHostToDevice) == hipSuccess;
 }
 
 extern "C" int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_t *offsets, const double *boxes,
@@ -450,6 +673,7 @@ extern "C" int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_
     };
     A((void **)&b->sys, sizeof(BSys) * n_sys);
     A((void **)&b->d_offs, sizeof(int64_t) * (n_sys + 1));
+
     A((void **)&b->sys_of, 4 * n);
     A((void **)&b->cell_id, 4 * n);
     A((void **)&b->slot, 4 * n);
@@ -474,6 +698,7 @@ extern "C" int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_
     if (ok) ok = hipMemcpy(b->sys, b->hsys.data(), sizeof(BSys) * n_sys, hipMemcpyHostToDevice) == hipSuccess;
     if (ok) ok = hipMemcpy(b->d_offs, offsets, sizeof(int64_t) * (n_sys + 1), hipMemcpyHostToDevice) == hipSuccess;
     if (ok) ok = hipMemcpy(b->sys_of, sys_of.data(), 4 * n, hipMemcpyHostToDevice) == hipSuccess;
+    if (ok) ok = upload_items(b);
     int32_t init[4] = {0, INT32_MAX, 0, 0};
     if (ok) ok = hipMemcpy(b->flags, init, sizeof(init), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
@@ -535,8 +760,9 @@ static void batch_forces(md_batch *b, const double *pos, void *force, bool energ
         k_bforce<double><<<bblocks(n), 256, 0, s>>>(n, b->stage, pos, b->sys_of, b->sys, b->cell_start,
                                                     b->cell_sorted, (double *)force, energy ? b->pe : nullptr);
     else
-        k_bforce<float><<<bblocks(n), 256, 0, s>>>(n, b->stage, pos, b->sys_of, b->sys, b->cell_start,
-                                                   b->cell_sorted, (float *)force, energy ? b->pe : nullptr);
+        k_bforce_slab<<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, pos, n, b->sys,
+                                                         b->cell_start, b->cell_sorted, (float *)force,
+                                                         energy ? b->pe : nullptr, b->sys_lds);
 }
 
 static void batch_integrate(md_batch *b, double *pos, void *vel, const void *force, const int32_t *type,

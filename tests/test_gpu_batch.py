@@ -86,6 +86,34 @@ def test_batched_forces_match_oracle(orc, M, prec):
         assert abs(out[s, 1] - W0) <= tolE * abs(W0), s
 
 
+def test_batched_fp32_slab_items(orc, M):
+    """FP32 forces of systems the force kernel splits differently: a system
+    staged whole in LDS (300 particles), systems cut into z-slabs (4,000 and
+    14,000), and a system packed into one corner of its box (6,000 particles in
+    an eighth of the volume), whose slabs are sized from the mean density so
+    that the dense ones overflow the LDS tile and read global memory."""
+    import torch
+    corner = W.batched_systems(n_sys=1, n_min=6000, n_max=6000, seed=44)[0]
+    corner = dict(corner, box=2.0 * corner["box"])
+    syss = (W.batched_systems(n_sys=2, n_min=300, n_max=300, seed=41)
+            + W.batched_systems(n_sys=2, n_min=4000, n_max=4000, seed=42)
+            + W.batched_systems(n_sys=1, n_min=14000, n_max=14000, seed=43) + [corner])
+    d = Dev(M, syss, 0)
+    M.md_batch_build_cells(d.b, d.pos, d.vel, d.force, d.type, d.ids)
+    out = torch.zeros(4 * len(syss), dtype=torch.float64, device="cuda")
+    M.md_batch_compute_forces(d.b, d.pos, d.type, d.lj, d.force, out)
+    torch.cuda.synchronize()
+    F = d.by_id(d.force)
+    out = out.cpu().numpy().reshape(-1, 4)
+    for s, sy in enumerate(syss):
+        F0, U0, W0, P0 = orc.forces(sy["pos"], sy["box"], orc.single())
+        r = slice(d.offs[s], d.offs[s + 1])
+        assert int(out[s, 2]) == P0, s
+        assert rel_l2(F[:, r], F0) <= 1e-5, s
+        assert abs(out[s, 0] - U0) <= 1e-6 * abs(U0), s
+        assert abs(out[s, 1] - W0) <= 1e-6 * abs(W0), s
+
+
 def test_batched_step_matches_oracle(orc, M):
     import torch
     syss = _systems(n_sys=6, n_max=700, seed=5)
