@@ -36,11 +36,11 @@ def _concat(syss):
 
 
 class Dev:
-    def __init__(self, M, syss, prec, R=5):
+    def __init__(self, M, syss, prec, R=5, csf=1.0):
         import torch
         self.offs, pos, vel, boxes = _concat(syss)
         n = pos.shape[1]
-        cfg = make_config(n, boxes[0], container=0, precision=prec, R=R)
+        cfg = make_config(n, boxes[0], container=0, precision=prec, R=R, csf=csf)
         self.b = M.md_batch_create(cfg, self.offs, boxes)
         real = self.b.real
         self.pos = torch.tensor(pos, dtype=torch.float64, device="cuda")
@@ -86,19 +86,22 @@ def test_batched_forces_match_oracle(orc, M, prec):
         assert abs(out[s, 1] - W0) <= tolE * abs(W0), s
 
 
-def test_batched_fp32_slab_items(orc, M):
+@pytest.mark.parametrize("csf", [1.0, 0.5], ids=["csf1", "csf05"])
+def test_batched_fp32_slab_items(orc, M, csf):
     """FP32 forces of systems the force kernel splits differently: a system
     staged whole in LDS (300 particles), systems cut into z-slabs (4,000 and
     14,000), and a system packed into one corner of its box (6,000 particles in
     an eighth of the volume), whose slabs are sized from the mean density so
-    that the dense ones overflow the LDS tile and read global memory."""
+    that the dense ones overflow the LDS tile and read global memory.  At
+    CSF 1/2 the stencil reaches two cells each way (rows of five cells, halos
+    of two layers)."""
     import torch
     corner = W.batched_systems(n_sys=1, n_min=6000, n_max=6000, seed=44)[0]
     corner = dict(corner, box=2.0 * corner["box"])
     syss = (W.batched_systems(n_sys=2, n_min=300, n_max=300, seed=41)
             + W.batched_systems(n_sys=2, n_min=4000, n_max=4000, seed=42)
             + W.batched_systems(n_sys=1, n_min=14000, n_max=14000, seed=43) + [corner])
-    d = Dev(M, syss, 0)
+    d = Dev(M, syss, 0, csf=csf)
     M.md_batch_build_cells(d.b, d.pos, d.vel, d.force, d.type, d.ids)
     out = torch.zeros(4 * len(syss), dtype=torch.float64, device="cuda")
     M.md_batch_compute_forces(d.b, d.pos, d.type, d.lj, d.force, out)
