@@ -256,13 +256,22 @@ int md_batch_compute_forces(md_batch *b, const double *pos, const int32_t *type,
                             const double *lj, void *force, double *out,
                             void *stream);
 
-/* nsteps of velocity Verlet for every system (rebuilding every R steps).
+/* nsteps of velocity Verlet for every system.  The cells are rebuilt every R
+ * steps, R at most cfg->rebuild_interval: a step at which a particle of any
+ * system has moved more than half the skin since the last rebuild is redone
+ * after a rebuild, and R is then shortened to the steps that passed; after a
+ * run of blocks without such a step (32, doubling after each failed try) a
+ * block one step longer is tried.  The trajectory does not depend on R.
  * use_graph != 0 captures one rebuild interval into a HIP graph and replays
  * it; 0 launches every kernel directly. */
 int md_batch_step(md_batch *b, double *pos, void *vel, void *force,
                   int32_t *type, int32_t *ids, const double *inv_mass,
                   const double *lj, double dt, int32_t nsteps,
                   int32_t use_graph, void *stream);
+
+/* The rebuild interval md_batch_step uses next (MD_ERR_INVALID_ARG if b is
+ * NULL). */
+int md_batch_rebuild_interval(const md_batch *b);
 
 /* ---------------------------------------------------------------------- */
 /* Scores of the autotuner's trials: scores (HOST double[n]) gets, per

@@ -518,6 +518,10 @@ struct md_batch {
     int4 *items = nullptr;  // the FP32 force kernel's work items (system, z0, t, halo), largest first
     int n_items = 0;
     int sys_lds = 0;        // that kernel's LDS tile (bytes)
+    // Rebuild interval in use (at most cfg.rebuild_interval): shortened to the
+    // block step of a skin violation, lengthened by one after `backoff` blocks
+    // in a row without one (the backoff doubling after each failed try).
+    int r_eff = 1, calm = 0, backoff = 32;
     int32_t *sys_of = nullptr;
     int64_t ncell = 0;
     int32_t *cell_id = nullptr, *slot = nullptr, *perm = nullptr, *perm2 = nullptr, *count = nullptr,
@@ -625,6 +629,7 @@ extern "C" int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MD_ERR_NO_DEVICE, "no HIP device");
     md_batch *b = new md_batch();
     b->cfg = *cfg;
+    b->r_eff = std::max(1, cfg->rebuild_interval);
     b->n_sys = n_sys;
     b->n = offsets[n_sys];
     b->offsets.assign(offsets, offsets + n_sys + 1);
@@ -709,6 +714,8 @@ extern "C" int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_
     *out = b;
     return MD_OK;
 }
+
+extern "C" int md_batch_rebuild_interval(const md_batch *b) { return b ? b->r_eff : MD_ERR_INVALID_ARG; }
 
 extern "C" void md_batch_destroy(md_batch *b)
 {
@@ -865,14 +872,18 @@ extern "C" int md_batch_step(md_batch *b, double *pos, void *vel, void *force, i
     hipStream_t s = (hipStream_t)stream;
     k_bprep<<<(b->n_sys + 255) / 256, 256, 0, s>>>(b->sys, b->n_sys, lj, b->cfg.rc2[0]);
     BatchCtx c{pos, vel, force, type, ids, inv_mass, dt, s};
-    int R = b->cfg.rebuild_interval;
     size_t rs = bsize(b->cfg);
     size_t n = (size_t)b->n;
     const void *key[8] = {pos, vel, force, type, ids, inv_mass, lj, stream};
     int st = 0;
     while (st < nsteps) {
+        // a block one step longer than the interval in use, after enough calm
+        // blocks, tries whether the motion now allows it (launched directly:
+        // the graph holds the interval in use)
+        const bool probe = b->r_eff < b->cfg.rebuild_interval && b->calm >= b->backoff;
+        const int R = probe ? b->r_eff + 1 : b->r_eff;
         int len = std::min(R, nsteps - st);
-        bool graphable = use_graph && st > 0 && len == R;
+        bool graphable = use_graph && st > 0 && len == R && !probe;
         int rc;
         if (graphable) {
             bool same = b->exec && b->graph_R == R && b->graph_dt == dt && memcmp(key, b->graph_key, sizeof(key)) == 0;
@@ -922,8 +933,19 @@ extern "C" int md_batch_step(md_batch *b, double *pos, void *vel, void *force, i
                 batch_forces(b, pos, force, false, s);
             }
             st += v;
+            // a block of v steps would have passed
+            if (probe) b->backoff = std::min(2 * b->backoff, 1 << 12);
+            b->r_eff = std::max(1, std::min(b->r_eff, v));
+            b->calm = 0;
         } else {
             st += len;
+            if (probe && len == R) {
+                b->r_eff = R;
+                b->backoff = 32;
+                b->calm = 0;
+            } else {
+                b->calm++;
+            }
         }
     }
     // final half kick

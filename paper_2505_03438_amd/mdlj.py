@@ -119,6 +119,7 @@ _SIGS = {
     "md_batch_build_cells": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "md_batch_compute_forces": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "md_batch_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i32, _i32, _vp]),
+    "md_batch_rebuild_interval": (_i32, [_vp]),
     "md_tuner_create": (_i32, [_i32, _i32, _i32, _d, _d, ctypes.POINTER(_vp)]),
     "md_tuner_destroy": (None, [_vp]),
     "md_tuner_begin_phase": (_i32, [_vp, _vp]),
@@ -402,6 +403,10 @@ def md_batch_step(b: Batch, pos, vel, force, type, ids, inv_mass, lj, dt, nsteps
                                _ptr(lj, torch.float64, 2 * b.n_types, "lj"), float(dt), int(nsteps),
                                1 if use_graph else 0, _stream(stream)),
            "md_batch_step")
+
+
+def md_batch_rebuild_interval(b: Batch) -> int:
+    return int(lib().md_batch_rebuild_interval(b.ptr))
 
 
 # ---------------------------------------------------------------- tuner engine (host only)

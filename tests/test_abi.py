@@ -75,6 +75,10 @@ def test_create_rejects_bad_configs(M):
     assert "symmetric" in M.md_last_error()
 
 
+def test_batch_rebuild_interval_null(M):
+    assert M.lib().md_batch_rebuild_interval(None) == M.MD_ERR_INVALID_ARG
+
+
 @pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
                     reason="a device may be present")
 def test_create_without_device_fails_cleanly(M):

@@ -36,11 +36,11 @@ def _concat(syss):
 
 
 class Dev:
-    def __init__(self, M, syss, prec, R=5, csf=1.0):
+    def __init__(self, M, syss, prec, R=5, csf=1.0, skin=0.3):
         import torch
         self.offs, pos, vel, boxes = _concat(syss)
         n = pos.shape[1]
-        cfg = make_config(n, boxes[0], container=0, precision=prec, R=R, csf=csf)
+        cfg = make_config(n, boxes[0], container=0, precision=prec, R=R, csf=csf, skin=skin)
         self.b = M.md_batch_create(cfg, self.offs, boxes)
         real = self.b.real
         self.pos = torch.tensor(pos, dtype=torch.float64, device="cuda")
@@ -134,6 +134,31 @@ def test_batched_step_matches_oracle(orc, M):
         dx -= sy["box"][0] * np.rint(dx / sy["box"][0])
         assert np.abs(dx).max() < 1e-9, s
         assert np.abs(V[:, r] - v1).max() < 1e-8, s
+
+
+def test_batched_interval_adapts(orc, M):
+    """A thin skin (0.1) with a long maximum interval (10): skin violations
+    shorten the rebuild interval the batch uses, and the trajectory still
+    follows the oracle's."""
+    import torch
+    syss = _systems(n_sys=4, n_max=700, seed=23)
+    d = Dev(M, syss, 1, R=10, skin=0.1)
+    assert M.md_batch_rebuild_interval(d.b) == 10
+    M.md_batch_build_cells(d.b, d.pos, d.vel, d.force, d.type, d.ids)
+    M.md_batch_compute_forces(d.b, d.pos, d.type, d.lj, d.force)
+    M.md_batch_step(d.b, d.pos, d.vel, d.force, d.type, d.ids, d.im, d.lj, 0.005, 60, use_graph=True)
+    torch.cuda.synchronize()
+    r = M.md_batch_rebuild_interval(d.b)
+    assert 1 <= r < 10
+    X = d.by_id(d.pos)
+    V = d.by_id(d.vel)
+    for s, sy in enumerate(syss):
+        p1, v1, _, _ = orc.velocity_verlet(sy["pos"], sy["vel"], sy["box"], orc.single(), 0.005, 60)
+        rs = slice(d.offs[s], d.offs[s + 1])
+        dx = X[:, rs] - p1
+        dx -= sy["box"][0] * np.rint(dx / sy["box"][0])
+        assert np.abs(dx).max() < 1e-9, s
+        assert np.abs(V[:, rs] - v1).max() < 1e-8, s
 
 
 def test_graph_replays_equal_eager(M):
