@@ -329,7 +329,7 @@ def bench_batched(M, W, steps, warmup, sample=64):
         M.md_batch_step(b, pos, vel, force, typ, ids, im, lj, 0.005, steps, use_graph=graph)
         torch.cuda.synchronize()
         res[graph] = (time.perf_counter() - t0) / steps
-    r_used = M.md_batch_rebuild_interval(b)
+    bc = M.md_batch_get_counters(b)
     b.close()
     # one handle per system, on a seeded sample
     pick = np.random.default_rng(11).choice(nsys, sample, replace=False)
@@ -361,7 +361,8 @@ def bench_batched(M, W, steps, warmup, sample=64):
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "lj-batched-4096", "systems": nsys, "n": n, "pairs_per_step": pairs,
                        "container": "linked cells CSF 1, gather-only", "rebuild_interval_max": 5,
-                       "rebuild_interval_at_end": r_used, "dt": 0.005},
+                       "rebuild_interval_at_end": bc["rebuild_interval"], "dt": 0.005},
+            "batch_counters": bc,
             "direct_launches_ms_per_step": 1e3 * res[False],
             "one_handle_per_system_ms_per_step": 1e3 * per_system,
             "one_handle_per_system_how": "md_step per system on %d seeded systems (%d particles), scaled by "

@@ -269,9 +269,11 @@ int md_batch_step(md_batch *b, double *pos, void *vel, void *force,
                   const double *lj, double dt, int32_t nsteps,
                   int32_t use_graph, void *stream);
 
-/* The rebuild interval md_batch_step uses next (MD_ERR_INVALID_ARG if b is
- * NULL). */
-int md_batch_rebuild_interval(const md_batch *b);
+/* Counters of md_batch_step since md_batch_create: out (HOST int64[4]) =
+ * { rebuilds (one per block of steps), forced_rebuilds (blocks cut short by
+ * a particle that moved more than half the skin), steps, the rebuild
+ * interval the next block uses }.  MD_ERR_INVALID_ARG if b or out is NULL. */
+int md_batch_get_counters(const md_batch *b, int64_t *out);
 
 /* ---------------------------------------------------------------------- */
 /* Scores of the autotuner's trials: scores (HOST double[n]) gets, per

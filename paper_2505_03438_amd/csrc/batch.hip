@@ -522,6 +522,7 @@ struct md_batch {
     // block step of a skin violation, lengthened by one after `backoff` blocks
     // in a row without one (the backoff doubling after each failed try).
     int r_eff = 1, calm = 0, backoff = 32;
+    int64_t n_rebuilds = 0, n_forced = 0, n_steps = 0;  // since md_batch_create
     int32_t *sys_of = nullptr;
     int64_t ncell = 0;
     int32_t *cell_id = nullptr, *slot = nullptr, *perm = nullptr, *perm2 = nullptr, *count = nullptr,
@@ -715,7 +716,15 @@ extern "C" int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_
     return MD_OK;
 }
 
-extern "C" int md_batch_rebuild_interval(const md_batch *b) { return b ? b->r_eff : MD_ERR_INVALID_ARG; }
+extern "C" int md_batch_get_counters(const md_batch *b, int64_t *out)
+{
+    if (!b || !out) return fail(MD_ERR_INVALID_ARG, "NULL argument");
+    out[0] = b->n_rebuilds;
+    out[1] = b->n_forced;
+    out[2] = b->n_steps;
+    out[3] = b->r_eff;
+    return MD_OK;
+}
 
 extern "C" void md_batch_destroy(md_batch *b)
 {
@@ -916,6 +925,7 @@ extern "C" int md_batch_step(md_batch *b, double *pos, void *vel, void *force, i
         int32_t f[2];
         if ((rc = batch_read_flags(b, s, f))) return rc;
         int v = f[1];
+        b->n_rebuilds++;
         if (v >= 1 && v < len) {
             // a particle outgrew the skin at block step v: redo steps 1 .. v-1
             // from the snapshot taken after the block's rebuild; the next
@@ -933,12 +943,15 @@ extern "C" int md_batch_step(md_batch *b, double *pos, void *vel, void *force, i
                 batch_forces(b, pos, force, false, s);
             }
             st += v;
+            b->n_steps += v;
+            b->n_forced++;
             // a block of v steps would have passed
             if (probe) b->backoff = std::min(2 * b->backoff, 1 << 12);
             b->r_eff = std::max(1, std::min(b->r_eff, v));
             b->calm = 0;
         } else {
             st += len;
+            b->n_steps += len;
             if (probe && len == R) {
                 b->r_eff = R;
                 b->backoff = 32;

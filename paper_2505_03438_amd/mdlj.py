@@ -119,7 +119,7 @@ _SIGS = {
     "md_batch_build_cells": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "md_batch_compute_forces": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "md_batch_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i32, _i32, _vp]),
-    "md_batch_rebuild_interval": (_i32, [_vp]),
+    "md_batch_get_counters": (_i32, [_vp, _vp]),
     "md_tuner_create": (_i32, [_i32, _i32, _i32, _d, _d, ctypes.POINTER(_vp)]),
     "md_tuner_destroy": (None, [_vp]),
     "md_tuner_begin_phase": (_i32, [_vp, _vp]),
@@ -405,8 +405,10 @@ def md_batch_step(b: Batch, pos, vel, force, type, ids, inv_mass, lj, dt, nsteps
            "md_batch_step")
 
 
-def md_batch_rebuild_interval(b: Batch) -> int:
-    return int(lib().md_batch_rebuild_interval(b.ptr))
+def md_batch_get_counters(b: Batch) -> dict:
+    out = (ctypes.c_int64 * 4)()
+    _check(lib().md_batch_get_counters(b.ptr, out), "md_batch_get_counters")
+    return dict(zip(("rebuilds", "forced_rebuilds", "steps", "rebuild_interval"), (int(x) for x in out)))
 
 
 # ---------------------------------------------------------------- tuner engine (host only)

@@ -75,8 +75,8 @@ def test_create_rejects_bad_configs(M):
     assert "symmetric" in M.md_last_error()
 
 
-def test_batch_rebuild_interval_null(M):
-    assert M.lib().md_batch_rebuild_interval(None) == M.MD_ERR_INVALID_ARG
+def test_batch_counters_null(M):
+    assert M.lib().md_batch_get_counters(None, None) == M.MD_ERR_INVALID_ARG
 
 
 @pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),

@@ -143,13 +143,16 @@ def test_batched_interval_adapts(orc, M):
     import torch
     syss = _systems(n_sys=4, n_max=700, seed=23)
     d = Dev(M, syss, 1, R=10, skin=0.1)
-    assert M.md_batch_rebuild_interval(d.b) == 10
+    assert M.md_batch_get_counters(d.b) == dict(rebuilds=0, forced_rebuilds=0, steps=0, rebuild_interval=10)
     M.md_batch_build_cells(d.b, d.pos, d.vel, d.force, d.type, d.ids)
     M.md_batch_compute_forces(d.b, d.pos, d.type, d.lj, d.force)
     M.md_batch_step(d.b, d.pos, d.vel, d.force, d.type, d.ids, d.im, d.lj, 0.005, 60, use_graph=True)
     torch.cuda.synchronize()
-    r = M.md_batch_rebuild_interval(d.b)
-    assert 1 <= r < 10
+    cnt = M.md_batch_get_counters(d.b)
+    assert 1 <= cnt["rebuild_interval"] < 10
+    assert cnt["steps"] == 60 and cnt["forced_rebuilds"] >= 1
+    # blocks of at most 10 steps, and the last block of a call is never cut short
+    assert cnt["rebuilds"] >= max(6, cnt["forced_rebuilds"] + 1)
     X = d.by_id(d.pos)
     V = d.by_id(d.vel)
     for s, sy in enumerate(syss):
