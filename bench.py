@@ -113,11 +113,12 @@ def make_cfg(M, n, box, kind, steps):
     c.precision = M.MD_FP32
     c.skin = 0.3
     c.max_neighbors = 128
-    if kind == "plain":
+    if kind.startswith("plain"):
+        # plain[:<R>]: linked cells, CSF 1, gather-only, rebuilt every R steps (10 by default)
         c.container = M.MD_CONTAINER_LC
         c.csf = 1.0
         c.newton3 = M.MD_N3L_OFF
-        c.rebuild_interval = 10
+        c.rebuild_interval = int(kind.split(":")[1]) if ":" in kind else 10
     elif kind.startswith("fixed:"):
         # fixed:<container>:<csf>:<n3l>:<R>[:<skin>], e.g. fixed:vl:1:0:5
         parts = kind.split(":")
@@ -517,8 +518,12 @@ def main():
                 others[kind]["final_config"], others[kind]["counters"]["trials"]))
     plain = None
     if not args.no_plain:
-        plain = run(M, d, "plain", args.steps, args.warmup)
-        log("plain LC: %.3f ms/step, %.3e pairs/s" % (plain["ms_per_step"], plain["pairs_per_s"]))
+        # at the autotuned run's rebuild interval: the same skin and interval, so that neither
+        # run redoes more blocks of steps than the other
+        plain = run(M, d, "plain:%d" % auto["final_config"]["rebuild_interval"], args.steps, args.warmup)
+        log("plain LC (R %d): %.3f ms/step, %.3e pairs/s, %d forced rebuilds" % (
+            auto["final_config"]["rebuild_interval"], plain["ms_per_step"], plain["pairs_per_s"],
+            plain["counters"]["forced_rebuilds"]))
     extra = {}
     for kind in [k for k in args.extra.split(",") if k]:
         extra[kind] = run(M, d, kind, args.steps, args.warmup)
