@@ -302,11 +302,11 @@ def bench_batched(M, W, steps, warmup, sample=64):
     n = int(offs[-1])
     dev = "cuda"
 
-    def cfg_for(nn, box):
+    def cfg_for(nn, box, R=5):
         c = M.config_default(nn, float(box[0]))
         c.precision = M.MD_FP32
         c.container = M.MD_CONTAINER_LC
-        c.rebuild_interval = 5
+        c.rebuild_interval = R
         return c
 
     pos = torch.tensor(np.concatenate([sy["pos"] for sy in syss], axis=1), dtype=torch.float64, device=dev)
@@ -338,7 +338,8 @@ def bench_batched(M, W, steps, warmup, sample=64):
     for sidx in pick:
         sy = syss[sidx]
         nn = sy["pos"].shape[1]
-        h = M.md_create(cfg_for(nn, sy["box"]))
+        # at the interval the batch ended with, so that the two are compared at equal rebuild work
+        h = M.md_create(cfg_for(nn, sy["box"], bc["rebuild_interval"]))
         p = torch.tensor(sy["pos"], dtype=torch.float64, device=dev)
         v = torch.tensor(sy["vel"], dtype=torch.float32, device=dev)
         f = torch.zeros((3, nn), dtype=torch.float32, device=dev)
@@ -366,8 +367,9 @@ def bench_batched(M, W, steps, warmup, sample=64):
             "batch_counters": bc,
             "direct_launches_ms_per_step": 1e3 * res[False],
             "one_handle_per_system_ms_per_step": 1e3 * per_system,
-            "one_handle_per_system_how": "md_step per system on %d seeded systems (%d particles), scaled by "
-                                         "4096/%d" % (sample, n_sum, sample),
+            "one_handle_per_system_how": "md_step per system on %d seeded systems (%d particles), rebuilt "
+                                         "every %d steps, scaled by 4096/%d" % (sample, n_sum,
+                                                                                bc["rebuild_interval"], sample),
             "speedup_vs_one_handle_per_system": per_system / res[True]}
 
 
