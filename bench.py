@@ -47,7 +47,7 @@ VL_COUNTERS = {"kernel": "k_vlw_f32", "sha": "85658f11d2ce11d1",
                "plain": {"fetch_kib": 116566.7, "write_kib": 12376.0, "valu_flops_fp32_wave": 28004872.5}}
 
 
-STRATEGY_NAMES = {"forest": "random-forest", "expert": "expert", "auto": "predictive"}
+STRATEGY_NAMES = {"forest": "random-forest", "expert": "expert", "auto": "predictive", "full": "full-search"}
 
 
 def force_sources_sha():
@@ -106,7 +106,16 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def make_cfg(M, n, box, kind, steps):
+def space_size(kind):
+    """Configurations a tuning phase of this strategy may trial: every
+    structure of the space for Full Search and Predictive (its first phases),
+    one for the Random Forest, an upper bound for the Expert rules."""
+    if kind.startswith("forest"):
+        return 1
+    return 10 if kind.endswith("+skin") else 7
+
+
+def make_cfg(M, n, box, kind, steps, warmup=0):
     c = M.config_default(n, float(box[0]))
     for d in range(3):
         c.box[d] = float(box[d])
@@ -129,30 +138,41 @@ def make_cfg(M, n, box, kind, steps):
         c.csf = float(csf)
         c.newton3 = int(n3)
         c.rebuild_interval = int(R)
-    else:  # autotuned: Predictive ("auto"), Expert rules ("expert"), Random Forest ("forest"); "+skin": skin tuned
+    else:
+        # autotuned: Predictive ("auto"), Full Search ("full"), Expert rules ("expert"),
+        # Random Forest ("forest"); "+skin": the skin tuned too
         c.container = M.MD_CONTAINER_LC
         c.rebuild_interval = 10
         c.autotune = (M.MD_TUNE_EXPERT if kind.startswith("expert") else
-                      M.MD_TUNE_RF if kind.startswith("forest") else M.MD_TUNE_PREDICTIVE)
+                      M.MD_TUNE_RF if kind.startswith("forest") else
+                      M.MD_TUNE_FULL if kind.startswith("full") else M.MD_TUNE_PREDICTIVE)
         c.tune_skin = 1 if kind.endswith("+skin") else 0
-        # two tuning phases (at steps 0 and steps/2): a phase trials every
-        # configuration for tune_trial_steps steps, so shorter intervals would
-        # spend most of a 1000-step run in trials (with four phases the
-        # retrial gap of a quarter of the run is one phase, and every phase
-        # trials the whole space)
+        # two tuning phases, at the first timed step and half-way (the
+        # warm-up steps come before the first); each trial runs
+        # tune_trial_steps steps, sized so that a first phase trialling the
+        # whole space fits into half the run (2 to 10 steps per trial)
+        c.tune_first = max(0, warmup)
         c.tune_interval = max(1, steps // 2)
-        c.tune_trial_steps = 10
+        c.tune_trial_steps = max(2, min(10, steps // (2 * space_size(kind))))
         c.total_steps_hint = steps
     return c
 
 
-def run(M, d, kind, steps, warmup, probe_steps=50):
+def melt(M, d, hot_steps=400, cool_steps=300, T_hot=2.5, chunk=25):
+    """Untimed preparation of the fluid: the jittered lattice is heated at
+    T_hot (velocities rescaled every chunk steps) until it has melted, then
+    brought back to the workload's temperature the same way; finally the
+    velocities are rescaled to that temperature exactly, with zero net
+    momentum.  Runs through the library (fixed Verlet lists).  Returns a copy
+    of d holding the melted state (particle order by id) and what the melt
+    did."""
     import numpy as np
     import torch
     n = d["pos"].shape[1]
+    T = float(d.get("T", 1.0))
+    c = make_cfg(M, n, d["box"], "fixed:vl:1:0:5", 1)
+    h = M.md_create(c)
     dev = "cuda"
-    cfg = make_cfg(M, n, d["box"], kind, steps)
-    h = M.md_create(cfg)
     pos = torch.tensor(d["pos"], dtype=torch.float64, device=dev)
     vel = torch.tensor(d["vel"], dtype=torch.float32, device=dev)
     force = torch.zeros((3, n), dtype=torch.float32, device=dev)
@@ -163,39 +183,180 @@ def run(M, d, kind, steps, warmup, probe_steps=50):
     M.md_build_cells(h, pos, vel, force, typ, ids)
     M.md_build_neighbors(h, pos, typ)
     M.md_compute_forces(h, pos, typ, lj, force)
-    if warmup > 0:
-        M.md_step(h, pos, vel, force, typ, ids, im, lj, 0.005, warmup)
+
+    def rescale(T_to):
+        v = vel.double()
+        v -= v.mean(dim=1, keepdim=True)
+        K = 0.5 * float((v * v).sum().item())
+        vel.copy_((v * (T_to / (2.0 * K / (3 * n - 3))) ** 0.5).float())
+
+    for k in range(0, hot_steps, chunk):
+        M.md_step(h, pos, vel, force, typ, ids, im, lj, 0.005, chunk)
+        rescale(T_hot)
+    for k in range(0, cool_steps, chunk):
+        M.md_step(h, pos, vel, force, typ, ids, im, lj, 0.005, chunk)
+        rescale(T)
     torch.cuda.synchronize()
+    idn = ids.cpu().numpy()
+    P = np.empty((3, n))
+    V = np.empty((3, n))
+    P[:, idn] = pos.cpu().numpy()
+    V[:, idn] = vel.double().cpu().numpy()
+    h.close()
+    box = np.asarray(d["box"], dtype=np.float64)[:, None]
+    dx = P - d["pos"]
+    dx -= box * np.round(dx / box)
+    out = dict(d)
+    out["pos"] = P
+    out["vel"] = V.astype(np.float32)
+    info = {"melt_steps": hot_steps + cool_steps, "T_hot": T_hot, "hot_steps": hot_steps,
+            "cool_steps": cool_steps, "rescale_every": chunk,
+            "msd_from_lattice": float((dx * dx).sum(axis=0).mean())}
+    return out, info
+
+
+def _median(xs):
+    xs = sorted(xs)
+    m = len(xs)
+    return xs[m // 2] if m % 2 else 0.5 * (xs[m // 2 - 1] + xs[m // 2])
+
+
+def run(M, d, kind, steps, warmup, repeats=1, probe_steps=50, keep_state=False):
+    """Time kind on the state d: per repeat, a fresh handle from the same
+    state, warmup untimed steps, then steps timed steps (host clock around
+    one md_step call, bracketed by device synchronisations).  Reports the
+    median and range over the repeats; the counters, configuration and
+    kernel times come from the last repeat."""
+    import numpy as np
+    import torch
+    n = d["pos"].shape[1]
+    dev = "cuda"
+    pos0 = torch.tensor(d["pos"], dtype=torch.float64, device=dev)
+    vel0 = torch.tensor(d["vel"], dtype=torch.float32, device=dev)
+    lj = torch.tensor([1.0, 1.0], dtype=torch.float64, device=dev)
+    im = torch.ones(1, dtype=torch.float64, device=dev)
     every = 10
-    logt = torch.zeros((steps // every, 4), dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    M.md_step(h, pos, vel, force, typ, ids, im, lj, 0.005, steps, every, logt)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    lg = logt.cpu().numpy()
-    pairs_mean = float(lg[:, 3].mean()) if len(lg) else float("nan")
+    walls, pairs_all, energies = [], [], None
+    for rep in range(repeats):
+        cfg = make_cfg(M, n, d["box"], kind, steps, warmup)
+        h = M.md_create(cfg)
+        pos = pos0.clone()
+        vel = vel0.clone()
+        force = torch.zeros((3, n), dtype=torch.float32, device=dev)
+        typ = torch.zeros(n, dtype=torch.int32, device=dev)
+        ids = torch.arange(n, dtype=torch.int32, device=dev)
+        M.md_build_cells(h, pos, vel, force, typ, ids)
+        M.md_build_neighbors(h, pos, typ)
+        M.md_compute_forces(h, pos, typ, lj, force)
+        if warmup > 0:
+            M.md_step(h, pos, vel, force, typ, ids, im, lj, 0.005, warmup)
+        logt = torch.zeros((max(steps // every, 1), 4), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M.md_step(h, pos, vel, force, typ, ids, im, lj, 0.005, steps, every, logt)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        lg = logt.cpu().numpy()[: steps // every]
+        pairs_all.append(float(lg[:, 3].mean()) if len(lg) else float("nan"))
+        energies = lg
+        if rep + 1 < repeats:
+            h.close()
     cnt = M.md_get_counters(h)
     cfg_now = M.md_get_config(h)
-    # force-kernel time of the configuration in use, HIP events on the same stream
-    M.md_timing(h, True)
-    M.md_step(h, pos, vel, force, typ, ids, im, lj, 0.005, probe_steps)
+    trial = None
+    if cfg.autotune:
+        sc, cf = M.md_get_trial_scores(h)
+        trial = [{"container": int(k.container), "newton3": int(k.newton3), "csf": float(k.csf),
+                  "skin": float(k.skin), "score_ms": (None if v != v else float(v))} for v, k in zip(sc, cf)]
+    final = None
+    if keep_state:
+        torch.cuda.synchronize()
+        final = {"pos": pos.clone(), "ids": ids.clone(), "force": force.clone(), "typ": typ}
+    # force-kernel time of the configuration in use (for a tuned run: the chosen one, on a
+    # fixed handle from the state the run ended in, so that no tuning phase falls inside),
+    # HIP events on the launch stream
+    hp = h
+    if cfg.autotune:
+        fc = dict(container=int(cfg_now.container), newton3=int(cfg_now.newton3), csf=float(cfg_now.csf),
+                  skin=float(cfg_now.skin))
+        hp = M.md_create(make_cfg(M, n, d["box"], fixed_kind(fc, int(cfg_now.rebuild_interval)), probe_steps))
+        pos, vel, force = pos.clone(), vel.clone(), force.clone()
+        typ, ids = typ.clone(), ids.clone()
+        M.md_build_cells(hp, pos, vel, force, typ, ids)
+        M.md_build_neighbors(hp, pos, typ)
+        M.md_compute_forces(hp, pos, typ, lj, force)
+    M.md_timing(hp, True)
+    M.md_step(hp, pos, vel, force, typ, ids, im, lj, 0.005, probe_steps)
     torch.cuda.synchronize()
-    tm = M.md_timing(h, False)
+    tm = M.md_timing(hp, False)
+    if hp is not h:
+        hp.close()
     force_ms = tm["force_ms"] / max(tm["force_passes"], 1)
     build_ms = tm["build_ms"] / max(tm["builds"], 1) if tm["builds"] else None
+    lg = energies
     E = lg[:, 0] - lg[:, 3] * (-0.016316891136) + lg[:, 1]
-    res = dict(kind=kind, steps=steps, wall_s=wall, ms_per_step=1e3 * wall / steps,
+    wall = _median(walls)
+    pairs_mean = _median(pairs_all)
+    rates = [p * steps / w for p, w in zip(pairs_all, walls)]
+    res = dict(kind=kind, steps=steps, repeats=repeats, wall_s=wall, ms_per_step=1e3 * wall / steps,
+               ms_per_step_range=[1e3 * min(walls) / steps, 1e3 * max(walls) / steps],
                steps_per_s=steps / wall, pairs_per_step=pairs_mean,
-               pairs_per_s=pairs_mean * steps / wall,
+               pairs_per_s=_median(rates), pairs_per_s_range=[min(rates), max(rates)],
                force_kernel_ms=force_ms, build_ms=build_ms, counters=cnt,
+               tune={"tune_first": int(cfg.tune_first), "tune_interval": int(cfg.tune_interval),
+                     "tune_trial_steps": int(cfg.tune_trial_steps), "trial_scores": trial} if cfg.autotune else None,
                final_config=dict(container=int(cfg_now.container), newton3=int(cfg_now.newton3),
                                  csf=float(cfg_now.csf), rebuild_interval=int(cfg_now.rebuild_interval),
                                  skin=float(cfg_now.skin)),
                energy_per_particle_first_last=[float(E[0] / n), float(E[-1] / n)] if len(E) else None)
-    h.close()
+    if final is not None:
+        res["_final"] = final
+        res["_handle"] = h
+    else:
+        h.close()
     return res
+
+
+def fixed_kind(c, R):
+    """fixed:... kind of a tuning-space configuration at rebuild interval R."""
+    cont = {0: "lc", 1: "vl", 2: "cl"}[int(c["container"])]
+    return "fixed:%s:%g:%d:%d:%g" % (cont, c["csf"], int(c["newton3"]), int(R), c["skin"])
+
+
+def oracle_error(M, d, r):
+    """FP64-oracle error of the forces, energy and pair count of the state
+    the run ended in (the library's forces there, from its last step and
+    from a fresh md_compute_forces call on the same handle)."""
+    import numpy as np
+    import torch
+    from oracle import oracle as orc
+    st, h = r["_final"], r["_handle"]
+    n = d["pos"].shape[1]
+    idn = st["ids"].cpu().numpy()
+    P = np.empty((3, n))
+    P[:, idn] = st["pos"].cpu().numpy()
+    F_step = np.empty((3, n))
+    F_step[:, idn] = st["force"].double().cpu().numpy()
+    lj = torch.tensor([1.0, 1.0], dtype=torch.float64, device="cuda")
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    f = torch.zeros_like(st["force"])
+    M.md_build_cells(h, st["pos"], None, f, st["typ"], st["ids"])
+    M.md_build_neighbors(h, st["pos"], st["typ"])
+    M.md_compute_forces(h, st["pos"], st["typ"], lj, f, out)
+    torch.cuda.synchronize()
+    idn = st["ids"].cpu().numpy()
+    F = np.empty((3, n))
+    F[:, idn] = f.double().cpu().numpy()
+    o = out.cpu().numpy()
+    Fr, U, W, npairs = orc.forces(P, d["box"], orc.single(), cells=True)
+    frms = np.sqrt((Fr * Fr).sum() / n)
+    h.close()
+    return {"force_rel_l2": float(np.linalg.norm(F - Fr) / np.linalg.norm(Fr)),
+            "force_max_abs_over_frms": float(np.sqrt(((F - Fr) ** 2).sum(axis=0)).max() / frms),
+            "last_step_force_rel_l2": float(np.linalg.norm(F_step - Fr) / np.linalg.norm(Fr)),
+            "U_rel": float(abs(o[0] - U) / abs(U)), "W_rel": float(abs(o[1] - W) / abs(W)),
+            "n_pairs": int(o[2]), "n_pairs_oracle": int(npairs), "n_pairs_equal": int(o[2]) == int(npairs),
+            "how": "final state of the headline run's last repeat, FP64 cell-list oracle on the host"}
 
 
 def measured_peaks():
@@ -444,7 +605,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--strategy", default="forest", choices=["forest", "expert", "auto"],
+    ap.add_argument("--no-fixed", action="store_true", help="skip the fixed runs of every configuration of the space")
+    ap.add_argument("--repeats", type=int, default=5, help="timed repeats per run (median and range reported)")
+    ap.add_argument("--melt-steps", type=int, default=700,
+                    help="untimed steps that melt the fluid's starting lattice (heated, then cooled back)")
+    ap.add_argument("--strategy", default="forest", choices=["forest", "expert", "auto", "full"],
                     help="selection strategy of the headline autotuned run: forest (Random Forest, Sec. 5.3), "
                          "expert (fuzzy rules, Sec. 5.2) or auto (Predictive, Sec. 5.1)")
     ap.add_argument("--no-other-strategies", action="store_true",
@@ -487,6 +652,7 @@ def main():
     if args.workload == "adjoint":
         print(json.dumps(bench_adjoint(M, W, args.steps)), flush=True)
         return
+    melt_info = None
     if args.workload == "fluid":
         d = W.homogeneous_fluid(ncell=args.ncell)
         wname = "lj-fluid-%d" % d["pos"].shape[1]
@@ -498,50 +664,69 @@ def main():
         wname = "lj-slab-%d" % d["pos"].shape[1]
     n = d["pos"].shape[1]
     log("workload: %s, box %s" % (wname, d["box"]))
+    if args.workload == "fluid" and args.melt_steps > 0:
+        t0 = time.perf_counter()
+        d, melt_info = melt(M, d, hot_steps=args.melt_steps * 4 // 7, cool_steps=args.melt_steps * 3 // 7)
+        log("melted: %d untimed steps in %.1f s, mean squared displacement from the lattice %.2f" % (
+            melt_info["melt_steps"], time.perf_counter() - t0, melt_info["msd_from_lattice"]))
     if args.probe:
-        r = run(M, d, args.probe, args.steps, args.warmup)
+        r = run(M, d, args.probe, args.steps, args.warmup, repeats=args.repeats)
         log("%s: %.3f ms/step, force %.3f ms, build %s ms" % (args.probe, r["ms_per_step"], r["force_kernel_ms"],
                                                                "%.3f" % r["build_ms"] if r["build_ms"] else "-"))
-        print(json.dumps({"probe": args.probe, "workload": wname, "result": r}), flush=True)
+        print(json.dumps({"probe": args.probe, "workload": wname, "melt": melt_info, "result": r}), flush=True)
         return
+    reps = args.repeats
+
+    def show(name, r):
+        log("%s: %.3f ms/step (%.3f-%.3f), %.3e pairs/s, force %.3f ms, config %s, %d phases, %d trials" % (
+            name, r["ms_per_step"], r["ms_per_step_range"][0], r["ms_per_step_range"][1], r["pairs_per_s"],
+            r["force_kernel_ms"], r["final_config"], r["counters"]["tuning_phases"], r["counters"]["trials"]))
+
     # the headline autotuner is the Random Forest strategy (Sec. 5.3, the paper's most successful
     # one): a forest fitted to Full Search trials on generative scenarios, not on this workload
-    auto = run(M, d, args.strategy, args.steps, args.warmup)
-    log("autotuned (%s): %.3f ms/step, %.3e pairs/s, config %s, %d trials" % (
-        args.strategy, auto["ms_per_step"], auto["pairs_per_s"], auto["final_config"], auto["counters"]["trials"]))
+    auto = run(M, d, args.strategy, args.steps, args.warmup, repeats=reps, keep_state=True)
+    show("autotuned (%s)" % STRATEGY_NAMES[args.strategy], auto)
+    if auto["counters"]["trials"] < 1:
+        log("error: the autotuned run trialled no configuration")
+        sys.exit(3)
     others = {}
     if not args.no_other_strategies:
-        for kind in ("forest", "expert", "auto"):
+        for kind in ("forest", "expert", "auto", "full"):
             if kind == args.strategy:
                 continue
-            others[kind] = run(M, d, kind, args.steps, args.warmup)
-            log("%s: %.3f ms/step, %.3e pairs/s, config %s, %d trials" % (
-                STRATEGY_NAMES[kind], others[kind]["ms_per_step"], others[kind]["pairs_per_s"],
-                others[kind]["final_config"], others[kind]["counters"]["trials"]))
+            others[kind] = run(M, d, kind, args.steps, args.warmup, repeats=reps)
+            show(STRATEGY_NAMES[kind], others[kind])
+    R_final = auto["final_config"]["rebuild_interval"]
     plain = None
     if not args.no_plain:
         # at the autotuned run's rebuild interval: the same skin and interval, so that neither
         # run redoes more blocks of steps than the other
-        plain = run(M, d, "plain:%d" % auto["final_config"]["rebuild_interval"], args.steps, args.warmup)
-        log("plain LC (R %d): %.3f ms/step, %.3e pairs/s, %d forced rebuilds" % (
-            auto["final_config"]["rebuild_interval"], plain["ms_per_step"], plain["pairs_per_s"],
-            plain["counters"]["forced_rebuilds"]))
-    extra = {}
+        plain = run(M, d, "plain:%d" % R_final, args.steps, args.warmup, repeats=reps)
+        show("plain LC (R %d)" % R_final, plain)
+    fixed = {}
+    if not args.no_fixed:
+        # every configuration of the tuning space, fixed, at the autotuned run's interval: the
+        # best of them is the paper's "best single configuration" (Sec. 7)
+        for c in auto["tune"]["trial_scores"] or []:
+            kind = fixed_kind(c, R_final)
+            fixed[kind] = run(M, d, kind, args.steps, args.warmup, repeats=reps)
+            show(kind, fixed[kind])
     for kind in [k for k in args.extra.split(",") if k]:
-        extra[kind] = run(M, d, kind, args.steps, args.warmup)
-        log("%s: %.3f ms/step, %.3e pairs/s, force %.3f ms" % (kind, extra[kind]["ms_per_step"],
-                                                             extra[kind]["pairs_per_s"],
-                                                             extra[kind]["force_kernel_ms"]))
+        fixed[kind] = run(M, d, kind, args.steps, args.warmup, repeats=reps)
+        show(kind, fixed[kind])
+    best_fixed = min(fixed, key=lambda k: fixed[k]["ms_per_step"]) if fixed else None
     achieved = FLOPS_PER_PAIR * auto["pairs_per_step"] / (auto["force_kernel_ms"] * 1e-3)
     kname = force_kernel_name(auto["final_config"], auto["counters"]["force_family"])
-    R_final = auto["final_config"]["rebuild_interval"]
     traffic = measured_traffic(kname, R_final)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32, "traffic": traffic, "kernel": kname,
-            "traffic_unit": "bytes per launch (HBM, counters; variants weighted as a rebuild interval of "
-                            "R = %d steps runs them: fused (R - 1)/R, plain 1/R)" % R_final,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, calibrated against a "
+                            "device copy; fused and plain variants weighted as a rebuild interval of R = %d "
+                            "steps runs them)" % R_final,
             "hbm_GBps_at_kernel_time": (traffic / (auto["force_kernel_ms"] * 1e-3) / 1e9) if traffic else None,
             "kernel_ms": auto["force_kernel_ms"],
+            "kernel_ms_how": "mean force-pass time over %d further steps of the headline run's handle, HIP "
+                             "events on the launch stream" % 50,
             "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED}
     issued = measured_flops(kname, R_final)
     roof["valu_fp32_issued"] = ({"flops_per_launch": issued,
@@ -553,6 +738,12 @@ def main():
         roof["measured_peaks"] = measured_peaks()
     except (OSError, RuntimeError) as e:
         roof["measured_peaks"] = {"error": str(e)}
+    err = oracle_error(M, d, auto)
+    log("oracle error of the final state: force rel L2 %.2e, max |dF|/F_rms %.2e, pairs equal %s" % (
+        err["force_rel_l2"], err["force_max_abs_over_frms"], err["n_pairs_equal"]))
+    for r in [auto] + list(others.values()):
+        r.pop("_final", None)
+        r.pop("_handle", None)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(d)
@@ -576,12 +767,19 @@ def main():
         "config": {"workload": wname, "n": n, "density": 0.8 if args.workload != "slab" else 0.75,
                    "T": float(d.get("T", 1.0)), "rc": 2.5, "skin": 0.3, "dt": 0.005, "positions": "f64",
                    "pair_arithmetic": "f32", "strategy": STRATEGY_NAMES[args.strategy],
-                   "parallelism": "single-gpu"},
+                   "tune_first": auto["tune"]["tune_first"], "tune_interval": auto["tune"]["tune_interval"],
+                   "tune_trial_steps": auto["tune"]["tune_trial_steps"], "repeats": reps,
+                   "value_is": "median over the repeats; each repeat a fresh handle from the same state",
+                   "start_state": melt_info or "as generated", "parallelism": "single-gpu"},
         "autotuned": auto,
         "other_strategies": {STRATEGY_NAMES[k]: v for k, v in others.items()} or None,
         "plain": plain,
-        "fixed_configs": extra or None,
+        "fixed_configs": fixed or None,
+        "best_fixed": best_fixed,
         "speedup_vs_plain": (auto["pairs_per_s"] / plain["pairs_per_s"]) if plain else None,
+        "speedup_vs_best_fixed": (fixed[best_fixed]["ms_per_step"] / auto["ms_per_step"]) if best_fixed else None,
+        "speedup_vs_full_search": (others["full"]["ms_per_step"] / auto["ms_per_step"]) if "full" in others else None,
+        "oracle_error": err,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

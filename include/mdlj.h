@@ -81,6 +81,10 @@ extern "C" {
 #define MD_FLAG_LIST_OVERFLOW 1u  /* a neighbour row exceeded max_neighbors   */
 #define MD_FLAG_SKIN_EXCEEDED 2u  /* a particle moved >= skin/2 since a build */
 #define MD_FLAG_NONFINITE 4u      /* a non-finite force or position appeared  */
+#define MD_FLAG_WINDOW_FALLBACK 8u /* a cell neighbourhood held more particles
+                                      than an LDS window tile: the handle
+                                      switched to the global (non-windowed)
+                                      kernels, with the same results        */
 
 typedef struct md_handle md_handle;
 
@@ -111,6 +115,10 @@ typedef struct md_config {
                               skin, each with its rebuild interval derived
                               from the motion (a joint skin / R search); 0
                               (default): the skin stays fixed               */
+    int32_t tune_first;    /* steps (counted over the handle's md_step calls)
+                              before the first tuning phase, >= 0; 0: the
+                              first step.  Later phases follow every
+                              tune_interval steps                           */
 } md_config;
 
 /* Fill *cfg with defaults for n particles in a cubic box of side L:
@@ -137,7 +145,12 @@ void md_destroy(md_handle *h);
  * the pair kernels and records them as the reference for the skin check.
  * Positions belong in [0, box[d]); one more than a cell outside the box, or
  * a non-finite one, is binned into an edge cell and sets MD_FLAG_NONFINITE
- * (this call does not wait to see it; md_step does). */
+ * (this call does not wait to see it; md_step does).  Where the FP32
+ * configuration runs over LDS cell windows, this call synchronises the stream
+ * once to read the window packer's verdict: if some cell neighbourhood holds
+ * more particles than a window tile (densities far above a liquid's), the
+ * handle switches to the global kernels for good and md_status reports
+ * MD_FLAG_WINDOW_FALLBACK; results are unchanged. */
 int md_build_cells(md_handle *h, double *pos, void *vel, void *force,
                    int32_t *type, int32_t *ids, void *stream);
 
@@ -171,8 +184,9 @@ int md_compute_forces(md_handle *h, const double *pos, const int32_t *type,
  * receives { U, K = 1/2 sum m v^2, W, n_pairs }.  Synchronises the stream
  * once per rebuild interval (to read the skin check).  MD_ERR_NONFINITE when
  * MD_FLAG_NONFINITE is set (by this call or an earlier one, until md_status
- * clears it); MD_ERR_INVALID_ARG when a cell neighbourhood outgrows the LDS
- * tile of the windowed kernels. */
+ * clears it).  A rebuild whose cell neighbourhoods outgrow the LDS tile of
+ * the windowed kernels switches the handle to the global kernels and redoes
+ * the affected steps (MD_FLAG_WINDOW_FALLBACK). */
 int md_step(md_handle *h, double *pos, void *vel, void *force, int32_t *type,
             int32_t *ids, const double *inv_mass, const double *lj, double dt,
             int32_t nsteps, int32_t energy_every, double *log, void *stream);

@@ -128,6 +128,7 @@ struct md_handle {
     int64_t steps_done = 0;       // md_step steps since creation
     uint32_t sticky = 0;          // flag bits already read back from the device
     bool truncated = false;       // the current lists overflowed max_neighbors
+    bool no_window = false;       // a cell neighbourhood overflowed the LDS windows: global kernels only
     bool energy_gather = true;    // the last energy partials saw each pair twice
     bool replay_no_log = false;   // the next block replays: its first step's log entry is done
     int64_t next_phase = 0;       // step index of the next tuning phase
@@ -250,6 +251,7 @@ static int validate_config(const md_config *c)
     if (c->autotune != MD_TUNE_OFF && (c->tune_interval < 1 || c->tune_trial_steps < 2))
         return fail(MD_ERR_INVALID_ARG, "tune_interval >= 1 and tune_trial_steps >= 2 required");
     if (c->tune_skin != 0 && c->tune_skin != 1) return fail(MD_ERR_INVALID_ARG, "tune_skin must be 0 or 1");
+    if (c->tune_first < 0) return fail(MD_ERR_INVALID_ARG, "tune_first must be >= 0");
     return MD_OK;
 }
 
@@ -348,6 +350,7 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
         h->space.swap(fit);
         int total_phases = std::max(1, (int)((cfg->total_steps_hint + cfg->tune_interval - 1) / cfg->tune_interval));
         h->tuner = new Tuner(cfg->autotune, (int)h->space.size(), total_phases, 2.0, 10.0);
+        h->next_phase = cfg->tune_first;
         set_builtin_rules(h);
     }
     if (hipDeviceSynchronize() != hipSuccess) {
@@ -384,6 +387,7 @@ static int check_handle(md_handle *h)
 
 // Counting sort into cells + gather into cell order + copy back in place.
 static bool use_window(const md_config &c, const Geom &g);
+static bool use_window(const md_handle *h) { return !h->no_window && use_window(h->cfg, h->g); }
 static int build_blocks(md_handle *h, hipStream_t s);
 
 // Where the particle arrays of a time-stepping call currently live.  Inside
@@ -396,8 +400,15 @@ struct CurArrays {
     int32_t **type, **ids;
 };
 
+// check_window: when the configuration runs over LDS windows, wait for the
+// block packer and read whether some cell neighbourhood exceeds the window
+// tile; if so the handle switches to the global kernels (and md_status
+// reports MD_FLAG_WINDOW_FALLBACK).  Without it (the rebuilds inside md_step's
+// blocks) the flag is read at the block's end and the block is redone.
+static int window_overflow_fallback(md_handle *h, hipStream_t s);
+
 static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, int32_t *type, int32_t *ids,
-                            hipStream_t s, const CurArrays *cur = nullptr)
+                            hipStream_t s, const CurArrays *cur = nullptr, bool check_window = true)
 {
     const Geom &g = h->g;
     Buffers &b = h->b;
@@ -442,7 +453,24 @@ static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, i
     h->age = 0;
     h->built = true;
     h->lists = false;
-    if (use_window(h->cfg, h->g)) return build_blocks(h, s);
+    if (!use_window(h)) return MD_OK;
+    if ((rc = build_blocks(h, s))) return rc;
+    if (!check_window) return MD_OK;
+    MD_HIP(hipMemcpyAsync(h->b.host_flags + 3, h->b.flags + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MD_HIP(hipStreamSynchronize(s));
+    if (h->b.host_flags[3] & 1u) return window_overflow_fallback(h, s);
+    return MD_OK;
+}
+
+// The packer met a cell column whose window exceeds the LDS tile: the
+// windowed kernels would skip its blocks, so the handle uses the global
+// kernels from now on (the cells are valid for them as they are).
+static int window_overflow_fallback(md_handle *h, hipStream_t s)
+{
+    h->no_window = true;
+    h->sticky |= MD_FLAG_WINDOW_FALLBACK;
+    h->lists = false;
+    launch_fill_i32(h->b.flags + 3, 0, 1, s);
     return MD_OK;
 }
 
@@ -546,7 +574,7 @@ static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
 {
     Buffers &b = h->b;
     int n = (int)h->n;
-    if (use_window(h->cfg, h->g) && h->cfg.container == MD_CONTAINER_VL) {
+    if (use_window(h) && h->cfg.container == MD_CONTAINER_VL) {
         int rc = ensure_window(h, h->cfg.max_neighbors);
         if (rc) return rc;
         const Geom &g = h->g;
@@ -629,7 +657,7 @@ static ForceArgs force_args(md_handle *h, const double *pos, const int32_t *type
     a.force = force;
     a.partials = h->b.partials;
     a.flags = h->b.flags;
-    a.window = use_window(h->cfg, h->g);
+    a.window = use_window(h);
     if (a.window) {
         a.w_nblk = h->b.w_rowb + window_nbands(h->g);
         a.w_blk = h->b.w_blk;
@@ -745,10 +773,11 @@ static void timing_collect(md_handle *h)
 // Cells and lists for the current positions.  with_force = false inside a
 // step, after the drift: the forces of the previous step have been used by
 // both kicks and are about to be recomputed, so they are not reordered.
-static int rebuild(md_handle *h, const StepCtx &c, bool with_force = true)
+static int rebuild(md_handle *h, const StepCtx &c, bool with_force = true, bool check_window = true)
 {
     CurArrays cur{&c.pos, &c.vel, &c.force, &c.type, &c.ids};
-    int rc = build_cells_impl(h, c.pos, c.vel, with_force ? c.force : nullptr, c.type, c.ids, c.s, &cur);
+    int rc = build_cells_impl(h, c.pos, c.vel, with_force ? c.force : nullptr, c.type, c.ids, c.s, &cur,
+                              check_window);
     if (rc) return rc;
     return build_lists_impl(h, c.pos, c.s);
 }
@@ -781,7 +810,9 @@ static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, b
     if (force_rebuild || h->age >= h->cfg.rebuild_interval) {
         hipEvent_t e0 = timing_event(h), e1 = nullptr;
         if (e0) MD_HIP(hipEventRecord(e0, c.s));
-        int rc = rebuild(h, c, false);
+        // a block's scheduled rebuild leaves the window check to the block's
+        // end (read_flags); a forced one checks at once
+        int rc = rebuild(h, c, false, force_rebuild);
         if (rc) return rc;
         if (e0 && (e1 = timing_event(h))) {
             MD_HIP(hipEventRecord(e1, c.s));
@@ -801,7 +832,7 @@ static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, b
 // displacement partials of that integration (the autotuner's motion).
 static bool fusable(const md_handle *h)
 {
-    return use_window(h->cfg, h->g) && h->cfg.container == MD_CONTAINER_VL && h->cfg.newton3 == MD_N3L_OFF &&
+    return use_window(h) && h->cfg.container == MD_CONTAINER_VL && h->cfg.newton3 == MD_N3L_OFF &&
            h->lists;
 }
 
@@ -876,6 +907,10 @@ static int snapshot(md_handle *h, const StepCtx &c, bool restore, bool with_forc
     return MD_OK;
 }
 
+// Bit of read_flags' out[0] (above the device flag bits): the block's cell
+// build overflowed the LDS windows and its forces must be redone.
+constexpr int32_t kWindowRedo = 1 << 16;
+
 // Read the device flags (synchronises the stream).
 static int read_flags(md_handle *h, hipStream_t s, int32_t out[4])
 {
@@ -894,16 +929,17 @@ static int read_flags(md_handle *h, hipStream_t s, int32_t out[4])
                     "a position outside the box (beyond one cell) or a non-finite position or force appeared; "
                     "md_status clears the flag");
     }
-    if (h->b.host_flags[3]) {
-        // 1: the packer met a single cell column whose window exceeds the
-        // tile; 2: a kernel met a block whose window does (never made by the
-        // packer)
-        char msg[200];
-        snprintf(msg, sizeof(msg),
-                 "a cell neighbourhood exceeds the windowed traversal's LDS tile (code %u; density far above "
-                 "liquid); use MD_N3L_ON or csf 0.5",
-                 (unsigned)h->b.host_flags[3]);
-        return fail(MD_ERR_INVALID_ARG, msg);
+    if (h->b.host_flags[3] & 1u) {
+        // the packer of this block's cell build met a cell column whose
+        // window exceeds the tile (the kernels skipped its blocks): switch to
+        // the global kernels; the caller redoes the block's forces
+        int rc = window_overflow_fallback(h, s);
+        if (rc) return rc;
+        out[0] |= kWindowRedo;
+    } else if (h->b.host_flags[3]) {
+        // a kernel met a block whose window does not fit, which the packer
+        // never makes
+        return fail(MD_ERR_HIP, "internal error: a windowed kernel met an unpacked block");
     }
     return MD_OK;
 }
@@ -969,6 +1005,31 @@ static int run_block(md_handle *h, const StepCtx &c, int s0, int s_end, int *nex
     int v = f[1];
     int first_used = rebuild_first ? s0 + 1 : s0;  // first step whose forces used the checked structure
     bool overflow = (f[0] & MD_FLAG_LIST_OVERFLOW) != 0;
+    if (f[0] & kWindowRedo) {
+        // the cell build of step s0 overflowed the LDS windows (only a
+        // block's own rebuild is checked here; every other build is checked
+        // when it is made): rebuild the lists for the global kernels from the
+        // snapshot and redo step s0's forces; the rest of the block is run
+        // again
+        if (!rebuild_first) return fail(MD_ERR_HIP, "internal error: window overflow outside a block's rebuild");
+        launch_fill_i32(h->b.flags, 0, 1, c.s);
+        if ((rc = snapshot(h, c, true, false))) return rc;
+        for (;;) {
+            if (has_lists(h->cfg) && (rc = build_lists_impl(h, c.pos, c.s))) return rc;
+            if ((rc = step_forces(h, c, s0))) return rc;
+            if (!has_lists(h->cfg)) break;
+            // the global lists must not be truncated either
+            if ((rc = read_flags(h, c.s, f))) return rc;
+            if (!(f[0] & MD_FLAG_LIST_OVERFLOW)) break;
+            if (h->cfg.max_neighbors >= 4096)
+                return fail(MD_ERR_LIST_OVERFLOW, "neighbour rows exceed the largest max_neighbors (4096)");
+            h->cfg.max_neighbors = std::min(4096, std::max(h->cfg.max_neighbors * 3 / 2, f[2] + 16));
+            launch_fill_i32(h->b.flags, 0, 1, c.s);
+        }
+        h->age = 0;
+        *next = s0 + 1;
+        return MD_OK;
+    }
     if (overflow && rebuild_first && has_lists(h->cfg) && h->cfg.max_neighbors < 4096) {
         // the lists built at step s0 were truncated: grow them, rebuild the
         // lists from the snapshot (the cells are still valid for it) and redo
@@ -1100,6 +1161,7 @@ extern "C" int md_step(md_handle *h, double *pos, void *vel, void *force, int32_
     // grow them, rebuild and recompute the entry forces
     int32_t f0[4];
     if ((rc = read_flags(h, c.s, f0))) return rc;
+    if (f0[0] & kWindowRedo) h->built = false;  // structures for the global kernels
     if (f0[0] & MD_FLAG_LIST_OVERFLOW) {
         h->sticky |= (uint32_t)f0[0];
         h->truncated = true;
@@ -1169,7 +1231,7 @@ extern "C" int md_forces_backward(md_handle *h, const double *pos, const int32_t
     a.grad_pos = grad_pos;
     a.gpart = h->b.gpart;
     a.flags = h->b.flags;
-    if (use_window(h->cfg, h->g) && h->cfg.newton3 == MD_N3L_OFF) {
+    if (use_window(h) && h->cfg.newton3 == MD_N3L_OFF) {
         // the blocks of the current cell build were packed for full windows
         launch_adjoint_window(h->b.stage, h->b.cell_start, h->b.cell_sorted, h->g, (int)h->n,
                               h->b.w_rowb + window_nbands(h->g), h->b.w_blk, h->b.tab, pos,
@@ -1279,7 +1341,7 @@ extern "C" int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows, in
         const Buffers &b = h->b;
         launch_cl_rows(n, b.cell_sorted, b.cell_start, b.cl_base, b.cl_start, b.cl_count, b.cl_nbr, b.cl_nbr_count,
                        b.cl_cap, max_per_row, counts, rows, (hipStream_t)stream);
-    } else if (use_window(h->cfg, h->g)) {
+    } else if (use_window(h)) {
         const Geom &g = h->g;
         launch_vlw_decode(h->b.cell_start, h->b.cell_sorted, g, n, h->b.w_rowb + window_nbands(g), h->b.w_blk,
                           h->b.w_nbr, h->b.nbr_count, max_per_row, counts, rows, h->cfg.newton3 == MD_N3L_ON,
@@ -1351,7 +1413,7 @@ extern "C" int md_get_counters(md_handle *h, int64_t *out)
     out[3] = h->trials;
     out[4] = h->config_index;
     out[5] = h->list_entries;
-    out[6] = h->cfg.container == MD_CONTAINER_CL ? 2 : use_window(h->cfg, h->g) ? 1 : 0;
+    out[6] = h->cfg.container == MD_CONTAINER_CL ? 2 : use_window(h) ? 1 : 0;
     return MD_OK;
 }
 
@@ -1404,16 +1466,16 @@ int apply_config(md_handle *h, const md_config &nc)
 // for, each for tune_trial_steps steps starting with a rebuild, score each by
 // its per-step time plus its build time spread over its rebuild interval
 // (the weighted average of build and force time), keep the best.  The trial
-// steps advance the simulation.  A phase that does not fit into the rest of
-// this md_step call is postponed to the next call.
+// steps advance the simulation.  A phase whose trials (as many as the
+// strategy asks for this phase) do not fit into the rest of this md_step call
+// is postponed to the next call.
 int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
 {
     Tuner *t = h->tuner;
     int T = h->base.tune_trial_steps;
-    int rc0, live = 0;
-    for (int k = 0; k < t->n(); k++) live += t->blacklisted(k) ? 0 : 1;
+    int rc0;
     *next = s0;
-    if ((int64_t)live * T > (int64_t)(c.nsteps - s0)) {
+    if ((int64_t)T > (int64_t)(c.nsteps - s0)) {  // not even one trial fits
         h->next_phase = h->steps_done + c.nsteps;
         return MD_OK;
     }
@@ -1436,6 +1498,17 @@ int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
         std::vector<double> suit(t->n(), 0.0);
         if (pick >= 0) suit[pick] = 1.0;
         t->set_suitability(suit);
+    }
+    {
+        std::vector<int> plan;
+        int count = t->plan_phase(plan);
+        if ((int64_t)count * T > (int64_t)(c.nsteps - s0)) {
+            h->next_phase = h->steps_done + c.nsteps;
+            // the statistics' histogram took the cell arrays: rebuild at the
+            // next step
+            if (!h->built) h->age = INT32_MAX / 2;
+            return MD_OK;
+        }
     }
     std::vector<int> trial;
     t->begin_phase(trial);

@@ -48,56 +48,57 @@ Tuner::Tuner(int strategy, int n_configs, int total_phases, double rel_threshold
     score_.assign(n_, 0.0);
 }
 
-double Tuner::predict(int c) const
+double Tuner::predict(int c, int phase) const
 {
     const std::vector<Point> &h = hist_[c];
     const Point &b = h.back();
     if (h.size() == 1) return b.score;
     const Point &a = h[h.size() - 2];
     double slope = (b.score - a.score) / (double)(b.phase - a.phase);
-    double p = b.score + slope * (double)(phase_ - b.phase);
+    double p = b.score + slope * (double)(phase - b.phase);
     return std::max(p, 0.5 * b.score);
 }
 
-int Tuner::begin_phase(std::vector<int> &trial)
+int Tuner::plan_phase(std::vector<int> &trial) const
 {
-    phase_++;
+    int phase = phase_ + 1;
     trial.assign(n_, 0);
-    std::fill(in_trial_.begin(), in_trial_.end(), 0);
-    std::fill(scored_.begin(), scored_.end(), 0);
+    int cnt = 0;
     if (strategy_ == MD_TUNE_EXPERT || strategy_ == MD_TUNE_RF) {
         double top = 0.0;
         for (int c = 0; c < n_ && c < (int)suit_.size(); c++) top = std::max(top, suit_[c]);
-        int cnt = 0;
         for (int c = 0; c < n_; c++) {
             double sc = c < (int)suit_.size() ? suit_[c] : 0.0;
-            bool t = top <= 0.0 || (sc > 0.0 && sc >= top - kExpertMargin);
-            trial[c] = t ? 1 : 0;
-            in_trial_[c] = trial[c];
+            trial[c] = top <= 0.0 || (sc > 0.0 && sc >= top - kExpertMargin) ? 1 : 0;
             cnt += trial[c];
         }
         return cnt;
     }
-    bool all = strategy_ == MD_TUNE_FULL || phase_ < 2;
+    bool all = strategy_ == MD_TUNE_FULL || phase < 2;
     double best = INFINITY;
     if (!all)
         for (int c = 0; c < n_; c++)
-            if (!black_[c] && !hist_[c].empty()) best = std::min(best, predict(c));
-    int cnt = 0;
+            if (!black_[c] && !hist_[c].empty()) best = std::min(best, predict(c, phase));
     for (int c = 0; c < n_; c++) {
         if (black_[c]) continue;
         bool t = all || hist_[c].empty();
         if (!t) {
-            bool near = predict(c) <= rel_ * best;
-            bool stale = phase_ - hist_[c].back().phase >= retrial_;
+            bool near = predict(c, phase) <= rel_ * best;
+            bool stale = phase - hist_[c].back().phase >= retrial_;
             t = near || stale;
         }
-        if (t) {
-            trial[c] = 1;
-            in_trial_[c] = 1;
-            cnt++;
-        }
+        trial[c] = t ? 1 : 0;
+        cnt += trial[c];
     }
+    return cnt;
+}
+
+int Tuner::begin_phase(std::vector<int> &trial)
+{
+    int cnt = plan_phase(trial);
+    phase_++;
+    std::fill(scored_.begin(), scored_.end(), 0);
+    for (int c = 0; c < n_; c++) in_trial_[c] = (char)trial[c];
     return cnt;
 }
 

@@ -16,6 +16,9 @@ class Tuner {
 public:
     Tuner(int strategy, int n_configs, int total_phases, double rel_threshold, double blacklist_factor);
 
+    // The trial set the next phase would have (trial[c] = 1 for
+    // configurations to trial) and its size; changes nothing.
+    int plan_phase(std::vector<int> &trial) const;
     // Start a phase; fills trial[c] = 1 for configurations to trial.
     int begin_phase(std::vector<int> &trial);
     // Expert and Random Forest strategies: the suitability of each
@@ -38,7 +41,7 @@ private:
         int phase;
         double score;
     };
-    double predict(int c) const;
+    double predict(int c, int phase) const;
 
     int strategy_, n_, retrial_;
     double rel_, black_factor_;

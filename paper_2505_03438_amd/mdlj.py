@@ -38,6 +38,7 @@ MD_SUIT_GOOD = 2
 MD_FLAG_LIST_OVERFLOW = 1
 MD_FLAG_SKIN_EXCEEDED = 2
 MD_FLAG_NONFINITE = 4
+MD_FLAG_WINDOW_FALLBACK = 8
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmdlj.so")
 
@@ -60,6 +61,7 @@ class md_config(ctypes.Structure):
         ("tune_trial_steps", ctypes.c_int32),
         ("total_steps_hint", ctypes.c_int32),
         ("tune_skin", ctypes.c_int32),
+        ("tune_first", ctypes.c_int32),
     ]
 
 

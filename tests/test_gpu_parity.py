@@ -651,6 +651,53 @@ def test_autotuned_fp64_trajectory(orc, strategy):
     assert np.abs(dx).max() < 1e-9
 
 
+@pytest.mark.parametrize("strategy", [4, 2, 1, 3], ids=["forest", "predictive", "full", "expert"])
+def test_short_run_tunes(orc, strategy):
+    """A short run (5 warm-up steps, then 20 steps, as the benchmark line is
+    run) still holds a tuning phase: the first phase is put at the first step
+    after the warm-up (tune_first), and a phase is postponed only when the
+    trials the strategy asks for (one for the forest, every structure for
+    Full Search and the first Predictive phases) do not fit into the call.
+    The trial steps advance the simulation: the FP64 trajectory equals the
+    oracle's."""
+    import torch
+    d = W.plain_fcc_864()
+    warm, nsteps = 5, 20
+    p1, v1, _, log0 = orc.velocity_verlet(d["pos"], d["vel"], d["box"], orc.single(), 0.005, warm + nsteps)
+    n = 864
+    cfg = make_config(n, d["box"], container=0, precision=1, R=10)
+    cfg.autotune = strategy
+    space = 1 if strategy == M.MD_TUNE_RF else 6
+    cfg.tune_first = warm
+    cfg.tune_interval = nsteps // 2
+    cfg.tune_trial_steps = max(2, min(10, nsteps // (2 * space)))
+    cfg.total_steps_hint = nsteps
+    s = DeviceSystem(cfg, d["pos"], d["vel"])
+    s.build()
+    s.forces(energy=False)
+    log_w = torch.zeros((warm, 4), dtype=torch.float64, device="cuda")
+    M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, warm, 1, log_w)
+    torch.cuda.synchronize()
+    assert M.md_get_counters(s.h)["tuning_phases"] == 0  # none during the warm-up
+    log = torch.zeros((nsteps, 4), dtype=torch.float64, device="cuda")
+    M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, nsteps, 1, log)
+    torch.cuda.synchronize()
+    log = np.concatenate([log_w.cpu().numpy(), log.cpu().numpy()])
+    cnt = M.md_get_counters(s.h)
+    assert cnt["tuning_phases"] >= 1 and cnt["trials"] >= 1, cnt
+    if strategy == M.MD_TUNE_RF:
+        assert cnt["tuning_phases"] == 2 and cnt["trials"] == 2, cnt
+    if strategy == M.MD_TUNE_FULL:
+        assert cnt["trials"] == 6, cnt  # one phase of every structure; the second does not fit
+    assert cnt["config_index"] >= 0
+    assert np.array_equal(log[:, 3], log0[:, 3])
+    for k in (0, 1, 2):
+        assert np.abs(log[:, k] - log0[:, k]).max() <= 1e-10 * np.abs(log0[:, k]).max()
+    dx = s.by_id(s.pos) - p1
+    dx -= d["box"][:, None] * np.rint(dx / d["box"][:, None])
+    assert np.abs(dx).max() < 1e-9
+
+
 INF = float("inf")
 
 
