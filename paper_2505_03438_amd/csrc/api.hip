@@ -160,7 +160,7 @@ static void free_buffers(md_handle *h)
                     b.nbr, b.nbr_count, b.partials, b.kpart, b.dpart, b.flags, b.tab, b.cl_start,
                     b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
                     b.cl_nbr_count, b.snap_pos, b.snap_vel,
-                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart, b.pos_alt, b.stage_alt,
+                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart, b.stat, b.stat_count, b.pos_alt, b.stage_alt,
                     b.w_blk, b.w_staged, b.w_rown, b.w_rowb, b.w_nbr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1263,35 +1263,58 @@ static int live_stats(md_handle *h, const double *pos, double *out, hipStream_t 
     out[6] = (double)cus;
     out[7] = h->cfg.skin;
     if (!hist) return MD_OK;
-    if ((rc = ensure_cells(h, g))) return rc;
-    launch_fill_i32(h->b.cell_count, 0, g.ncell, s);
-    launch_bin_counts((int)h->n, pos, g, h->b.cell_count, s);
-    std::vector<int32_t> cnt(g.ncell);
-    MD_HIP(hipMemcpyAsync(cnt.data(), h->b.cell_count, g.ncell * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    MD_HIP(hipStreamSynchronize(s));
-    // the histogram cells now hold counts, not a valid structure
-    h->built = false;
-    double sum = 0.0;
-    int64_t mx = 0, empty = 0;
-    for (int32_t v : cnt) {
-        sum += v;
-        mx = std::max<int64_t>(mx, v);
-        empty += v == 0;
+    Buffers &b = h->b;
+    if (!b.stat && (rc = dalloc(&b.stat, (size_t)(8 + kStatBins)))) return rc;
+    if ((int64_t)g.ncell > b.stat_count_cap) {
+        if (b.stat_count) (void)hipFree(b.stat_count);
+        b.stat_count = nullptr;
+        b.stat_count_cap = 0;
+        if ((rc = dalloc(&b.stat_count, (size_t)g.ncell))) return rc;
+        b.stat_count_cap = g.ncell;
     }
-    double mean = sum / (double)nb;
-    double var = 0.0;
-    for (int32_t v : cnt) var += ((double)v - mean) * ((double)v - mean);
-    var /= (double)nb;
-    // median: the middle order statistic(s), found by selection
-    std::nth_element(cnt.begin(), cnt.begin() + nb / 2, cnt.end());
-    double hi = (double)cnt[nb / 2];
-    double med = hi;
-    if (nb % 2 == 0) med = 0.5 * ((double)*std::max_element(cnt.begin(), cnt.begin() + nb / 2) + hi);
+    launch_fill_i32(b.stat_count, 0, g.ncell, s);
+    launch_bin_counts((int)h->n, pos, g, b.stat_count, s);
+    launch_bin_summary(g.ncell, b.stat_count, b.stat, s);
+    std::vector<int32_t> sm(8 + kStatBins);
+    MD_HIP(hipMemcpyAsync(sm.data(), b.stat, sm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MD_HIP(hipStreamSynchronize(s));
+    int64_t sum, sumsq;
+    memcpy(&sum, &sm[0], 8);
+    memcpy(&sumsq, &sm[2], 8);
+    double mean = (double)sum / (double)nb;
+    // population variance from the integer sums (exact up to the final
+    // divisions)
+    double var = ((double)sumsq - (double)sum * (double)sum / (double)nb) / (double)nb;
+    var = std::max(var, 0.0);
+    // median: the middle order statistic(s), from the histogram of counts
+    auto order_stat = [&](int64_t k, double &v) {  // k-th smallest (0-based); false past the histogram
+        int64_t c = 0;
+        for (int b = 0; b < kStatBins - 1; b++) {
+            c += sm[8 + b];
+            if (c > k) {
+                v = (double)b;
+                return true;
+            }
+        }
+        return false;
+    };
+    double hi = 0.0, lo = 0.0;
+    bool ok = order_stat(nb / 2, hi) && (nb % 2 == 1 || order_stat(nb / 2 - 1, lo));
+    if (!ok) {
+        // a middle bin holds kStatBins - 1 or more particles: select on the
+        // host from the counts themselves
+        std::vector<int32_t> cnt(g.ncell);
+        MD_HIP(hipMemcpy(cnt.data(), b.stat_count, g.ncell * sizeof(int32_t), hipMemcpyDeviceToHost));
+        std::nth_element(cnt.begin(), cnt.begin() + nb / 2, cnt.end());
+        hi = (double)cnt[nb / 2];
+        if (nb % 2 == 0) lo = (double)*std::max_element(cnt.begin(), cnt.begin() + nb / 2);
+    }
+    double med = nb % 2 ? hi : 0.5 * (lo + hi);
     out[0] = mean;
     out[1] = mean > 0.0 ? sqrt(var) / mean : 0.0;
     out[2] = med;
-    out[3] = (double)mx;
-    out[5] = (double)empty;
+    out[3] = (double)sm[4];
+    out[5] = (double)sm[5];
     return MD_OK;
 }
 
@@ -1447,6 +1470,12 @@ extern "C" const char *md_last_error(void) { return g_err.c_str(); }
 
 // ------------------------------------------------------------------ tuning
 
+// Whether two configurations of the tuning space build the same structure.
+static bool same_structure(const md_config &a, const md_config &b)
+{
+    return a.container == b.container && a.newton3 == b.newton3 && a.csf == b.csf && a.skin == b.skin;
+}
+
 // Switch the handle to configuration nc (same particles, box, cutoffs,
 // precision); the structures are rebuilt at the next step.
 int apply_config(md_handle *h, const md_config &nc)
@@ -1481,8 +1510,7 @@ int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
     }
     if (h->base.autotune == MD_TUNE_EXPERT) {
         // Sec. 5.2: the rules read the live statistics of the current
-        // positions (the histogram only if a rule needs more than counts;
-        // every trial starts with a rebuild, so the cell arrays are free)
+        // positions (the histogram only if a rule needs more than counts)
         double st[8];
         if ((rc0 = live_stats(h, c.pos, st, c.s, rules_need_histogram(h->rules)))) return rc0;
         std::vector<double> suit;
@@ -1504,20 +1532,21 @@ int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
         int count = t->plan_phase(plan);
         if ((int64_t)count * T > (int64_t)(c.nsteps - s0)) {
             h->next_phase = h->steps_done + c.nsteps;
-            // the statistics' histogram took the cell arrays: rebuild at the
-            // next step
-            if (!h->built) h->age = INT32_MAX / 2;
             return MD_OK;
         }
     }
     std::vector<int> trial;
-    t->begin_phase(trial);
+    int ntrial = t->begin_phase(trial);
     h->phases++;
     int s = s0, last_k = -1, rc;
     for (int k = 0; k < (int)trial.size(); k++) {
         if (!trial[k]) continue;
         md_config kc = h->space[k];
-        if ((rc = apply_config(h, kc))) return rc;
+        // a phase whose one trial is the configuration in use runs it on,
+        // without the rebuild a switch needs
+        bool keep = ntrial == 1 && same_structure(kc, h->cfg) && h->built &&
+                    (h->lists || !has_lists(h->cfg));
+        if (!keep && (rc = apply_config(h, kc))) return rc;
         // the interval follows from the motion and this configuration's skin
         kc.rebuild_interval = h->cfg.rebuild_interval = derived_interval(h);
         MD_HIP(hipEventRecord(h->ev0, c.s));

@@ -116,6 +116,55 @@ void launch_bin_counts(int n, const double *pos, const Geom &g, int32_t *count, 
     k_bin_counts<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(n, pos, g, count);
 }
 
+// Summary of the bin counts for the live statistics: out[0..1] int64 sum
+// and sum of squares, out as int32 from word 4: [4] max, [5] empty bins,
+// [8 + v] number of bins holding v particles (v < kStatBins - 1; the last
+// bin counts every larger value).  out must be zeroed first.
+__global__ void k_bin_summary(int nb, const int32_t *__restrict__ count, int32_t *out)
+{
+    __shared__ int32_t hist[kStatBins];
+    __shared__ unsigned long long s1, s2;
+    __shared__ int32_t smax, sempty;
+    for (int k = threadIdx.x; k < kStatBins; k += blockDim.x) hist[k] = 0;
+    if (threadIdx.x == 0) {
+        s1 = s2 = 0ull;
+        smax = sempty = 0;
+    }
+    __syncthreads();
+    unsigned long long a = 0, b = 0;
+    int mx = 0, em = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
+        int v = count[i];
+        a += (unsigned long long)v;
+        b += (unsigned long long)v * (unsigned long long)v;
+        mx = max(mx, v);
+        em += v == 0;
+        atomicAdd(&hist[min(v, kStatBins - 1)], 1);
+    }
+    atomicAdd(&s1, a);
+    atomicAdd(&s2, b);
+    atomicMax(&smax, mx);
+    atomicAdd(&sempty, em);
+    __syncthreads();
+    unsigned long long *o64 = (unsigned long long *)out;
+    for (int k = threadIdx.x; k < kStatBins; k += blockDim.x)
+        if (hist[k]) atomicAdd(&out[8 + k], hist[k]);
+    if (threadIdx.x == 0) {
+        atomicAdd(&o64[0], s1);
+        atomicAdd(&o64[1], s2);
+        atomicMax(&out[4], smax);
+        atomicAdd(&out[5], sempty);
+    }
+}
+
+void launch_bin_summary(int nb, const int32_t *count, int32_t *out, hipStream_t s)
+{
+    launch_fill_i32(out, 0, 8 + kStatBins, s);
+    if (nb <= 0) return;
+    int blocks = std::min(256, (nb + kBlock - 1) / kBlock);
+    k_bin_summary<<<blocks, kBlock, 0, s>>>(nb, count, out);
+}
+
 // ------------------------------------------------------------------ K2: exclusive scan
 // Three passes: per-block totals, a scan of the totals in one block, and the
 // per-block scan plus offset.  out has n + 1 entries (out[n] = total).

@@ -58,6 +58,9 @@ struct Geom {
 };
 
 // Device buffers and state of one handle.
+// Bins of the count histogram in the live-statistics summary.
+constexpr int kStatBins = 1024;
+
 struct Buffers {
     int32_t *cell_id = nullptr, *slot = nullptr, *perm = nullptr, *perm2 = nullptr;
     int32_t *cell_count = nullptr, *cell_start = nullptr, *cell_sorted = nullptr;
@@ -101,6 +104,9 @@ struct Buffers {
     int64_t w_cap = 0, w_rows_cap = 0, w_nbr_cap = 0;
     // adjoint
     double *gpart = nullptr;     // per-block parameter-gradient partials [blocks][8]
+    int32_t *stat = nullptr;     // live-statistics summary of the bin counts [8 + kStatBins]
+    int32_t *stat_count = nullptr;  // live-statistics bin counts (their own array: the
+    int64_t stat_count_cap = 0;     // structure's cells stay valid)
     uint32_t *host_flags = nullptr;  // pinned
 };
 
@@ -141,6 +147,7 @@ void launch_stage(int n, const double *pos, const int32_t *type, const Geom &g, 
 void launch_prepare_tab(const double *lj, const double *rc2_host, const Geom &g, PairTab *tab,
                         hipStream_t s);
 void launch_bin_counts(int n, const double *pos, const Geom &g, int32_t *count, hipStream_t s);
+void launch_bin_summary(int nb, const int32_t *count, int32_t *out, hipStream_t s);
 
 // force.hip
 struct IntegrateArgs {

@@ -79,3 +79,32 @@ def rel_l2(a, b):
     b = np.asarray(b, dtype=np.float64)
     nb = math.sqrt(float((b * b).sum()))
     return math.sqrt(float(((a - b) ** 2).sum())) / (nb if nb > 0 else 1.0)
+
+
+# Per-particle force bound, relative to the RMS force of the reference: the
+# FP32 pair arithmetic carries a relative error of a few 1e-7 per pair force
+# (fixed-point displacement 2^-24, r^2 within 7e-7, rcp and the products), so
+# a particle's error is at most about 1e-6 of the sum of its pair-force
+# magnitudes, which stays below 50 F_rms in the workloads (close contacts of
+# a hot liquid); FP64 carries 1e-15 per pair.  Bounds: 1e-4 F_rms (FP32),
+# 1e-10 F_rms (FP64), beside the relative L2 bars 1e-5 / 1e-12.
+FP32_FMAX, FP64_FMAX = 1e-4, 1e-10
+
+
+def assert_forces(F, F0, fp64, rel=None, fmax=None, what=""):
+    """Relative L2 error over all 3n components and the largest per-particle
+    error |F_i - F0_i| / F_rms(F0), both within their bars."""
+    F = np.asarray(F, dtype=np.float64)
+    F0 = np.asarray(F0, dtype=np.float64)
+    rel = (1e-12 if fp64 else 1e-5) if rel is None else rel
+    fmax = (FP64_FMAX if fp64 else FP32_FMAX) if fmax is None else fmax
+    e = rel_l2(F, F0)
+    assert e <= rel, ("rel L2", e, what)
+    n = F0.shape[-1]
+    if n == 0:
+        return
+    frms = math.sqrt(float((F0 * F0).sum()) / n)
+    if frms == 0.0:
+        return
+    worst = float(np.sqrt(((F - F0) ** 2).sum(axis=0)).max()) / frms
+    assert worst <= fmax, ("max |dF_i|/F_rms", worst, what)
