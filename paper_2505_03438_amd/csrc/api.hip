@@ -130,6 +130,7 @@ struct md_handle {
     bool truncated = false;       // the current lists overflowed max_neighbors
     bool no_window = false;       // a cell neighbourhood overflowed the LDS windows: global kernels only
     bool energy_gather = true;    // the last energy partials saw each pair twice
+    int epart_blocks = 0;         // partial slots the last energy force pass wrote
     bool replay_no_log = false;   // the next block replays: its first step's log entry is done
     int64_t next_phase = 0;       // step index of the next tuning phase
     double rate[4] = {0, 0, 0, 0};  // recent largest displacements per step (fixed-point units)
@@ -673,7 +674,10 @@ static int forces_impl(md_handle *h, const double *pos, const int32_t *type, voi
     if (force_blocks(a) > kMaxPartials) return fail(MD_ERR_INVALID_ARG, "too many particles for the reduction");
     if (h->cfg.newton3 == MD_N3L_ON) launch_zero(force, 3 * h->n * (int64_t)real_size(h->cfg), s);
     launch_force(a, h->g, s);
-    if (energy) h->energy_gather = h->cfg.newton3 == MD_N3L_OFF;
+    if (energy) {
+        h->energy_gather = h->cfg.newton3 == MD_N3L_OFF;
+        h->epart_blocks = force_blocks(a);
+    }
     return MD_OK;
 }
 
@@ -802,8 +806,9 @@ static int one_step(md_handle *h, const StepCtx &c, int s, bool force_rebuild, b
         if (track) h->dpart_blocks = integrate_blocks((int)h->n);
     }
     if (log_prev) {
-        ForceArgs fa = force_args(h, c.pos, c.type, c.force, true);
-        launch_log_entry(h->b.partials, force_blocks(fa), h->energy_gather, h->b.kpart, h->kpart_blocks,
+        // the slots the energy pass wrote: a tuning trial may have switched the
+        // configuration (and the kernel's partial count) since
+        launch_log_entry(h->b.partials, h->epart_blocks, h->energy_gather, h->b.kpart, h->kpart_blocks,
                          c.log + 4 * (s / c.energy_every - 1), c.s);
     }
     h->age++;
@@ -856,7 +861,10 @@ static int step_forces(md_handle *h, const StepCtx &c, int s, bool fuse, bool tr
         a.pos_out = b.pos_alt;
         a.stage_out = b.stage_alt;
         launch_force(a, h->g, c.s);
-        if (energy) h->energy_gather = true;
+        if (energy) {
+            h->energy_gather = true;
+            h->epart_blocks = force_blocks(a);
+        }
         std::swap(c.pos, b.pos_alt);
         std::swap(b.stage, b.stage_alt);
         h->started = s + 1;
@@ -1082,8 +1090,7 @@ static int finish_steps(md_handle *h, const StepCtx &c)
     bool log_last = logs_step(c, c.nsteps - 1);
     launch_integrate(integ_args(h, c, 1, 0, log_last, c.nsteps), h->g, c.s);
     if (log_last) {
-        ForceArgs fa = force_args(h, c.pos, c.type, c.force, true);
-        launch_log_entry(h->b.partials, force_blocks(fa), h->energy_gather, h->b.kpart,
+        launch_log_entry(h->b.partials, h->epart_blocks, h->energy_gather, h->b.kpart,
                          integrate_blocks((int)h->n), c.log + 4 * (c.nsteps / c.energy_every - 1), c.s);
     }
     return MD_OK;
