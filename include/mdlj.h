@@ -347,6 +347,32 @@ int md_expert_suitability(const md_fuzzy_rule *rules, int32_t n_rules,
  * MD_ERR_INVALID_ARG for a NaN statistic or if no class fits n_configs. */
 int md_rf_predict(const double *stats, int32_t n_configs);
 
+/* Allocation-free forces, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Needs no handle: computes what md_compute_forces computes
+ * with linked cells, gather-only (cfg->container and cfg->newton3 are not
+ * read), in cfg->precision, for the cfg->n particles of pos (DEVICE
+ * double[3][n]) and type (DEVICE int32[n]) in the caller's order, which is
+ * left unchanged; force (DEVICE real[3][n]) is written in the same order,
+ * out (DEVICE double[4] or NULL) gets { U, W, n_pairs, 0 }.  Every
+ * intermediate array (cells, the cell-order copy, staging, partial sums)
+ * lives in a fixed device scratch of MD_NOALLOC_SCRATCH_MIB MiB that each
+ * GPU holds from this call's first use on it until the process ends; the
+ * call allocates nothing.  Limits: n <= MD_NOALLOC_MAX_N, and cells plus
+ * particles must fit the scratch (MD_ERR_INVALID_ARG otherwise, before any
+ * work is enqueued).  Calls on one GPU share its scratch: calls that overlap
+ * in time on one GPU (other streams, other host threads) race and give
+ * undefined results; calls ordered on one stream are safe.  Positions must
+ * lie in the box (a non-finite one gives undefined forces; nothing faults).
+ * Enqueues on stream and returns. */
+#define MD_NOALLOC_MAX_N 131072
+#define MD_NOALLOC_SCRATCH_MIB 16
+int md_compute_forces_noalloc(const md_config *cfg, const double *pos,
+                              const int32_t *type, const double *lj,
+                              void *force, double *out, void *stream);
+/* MD_NOALLOC_MAX_N, as the library was built. */
+int64_t md_noalloc_max_particles(void);
+
 /* Configuration-selection engine, usable on its own with externally measured
  * scores (host only; needs no GPU).  Sec. 2.2.5 Full Search and Sec. 5.1
  * Predictive: trial all in the first two phases; predict each configuration

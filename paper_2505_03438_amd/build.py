@@ -16,7 +16,7 @@ PROBE_LIB = os.path.join(HERE, "libmdprobe.so")  # measurement probe, not the MD
 INCLUDE = os.path.join(ROOT, "include")
 
 SOURCES = ["cells.hip", "force.hip", "window.hip", "integrate.hip", "adjoint.hip", "clusters.hip", "batch.hip",
-           "api.hip", "tuner.cpp"]
+           "api.hip", "noalloc.hip", "tuner.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

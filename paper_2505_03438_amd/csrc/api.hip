@@ -256,6 +256,10 @@ static int validate_config(const md_config *c)
     return MD_OK;
 }
 
+namespace mdlj {
+int validate_md_config(const md_config *c) { return validate_config(c); }
+}  // namespace mdlj
+
 extern "C" int md_config_default(md_config *cfg, int64_t n, double L)
 {
     if (!cfg) return fail(MD_ERR_INVALID_ARG, "cfg is NULL");

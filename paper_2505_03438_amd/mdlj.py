@@ -116,6 +116,8 @@ _SIGS = {
     "md_expert_suitability": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "md_rf_predict": (_i32, [_vp, _i32]),
     "md_last_error": (ctypes.c_char_p, []),
+    "md_compute_forces_noalloc": (_i32, [ctypes.POINTER(md_config), _vp, _vp, _vp, _vp, _vp, _vp]),
+    "md_noalloc_max_particles": (_i64, []),
     "md_batch_create": (_i32, [ctypes.POINTER(md_config), _i32, _vp, _vp, ctypes.POINTER(_vp)]),
     "md_batch_destroy": (None, [_vp]),
     "md_batch_build_cells": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -246,6 +248,23 @@ def md_compute_forces(h: Handle, pos, type, lj, force, out=None, stream=None):
     _check(lib().md_compute_forces(h.ptr, p, t, _ptr(lj, torch.float64, 2 * h.n_types, "lj"), f,
                                    _ptr(out, torch.float64, 4, "out"), _stream(stream)),
            "md_compute_forces")
+
+
+def md_compute_forces_noalloc(cfg: md_config, pos, type, lj, force, out=None, stream=None):
+    """Allocation-free forces without a handle (linked cells, gather-only),
+    arrays in the caller's order."""
+    n = int(cfg.n)
+    real = torch.float64 if cfg.precision == MD_FP64 else torch.float32
+    _check(lib().md_compute_forces_noalloc(ctypes.byref(cfg), _ptr(pos, torch.float64, 3 * n, "pos"),
+                                           _ptr(type, torch.int32, n, "type"),
+                                           _ptr(lj, torch.float64, 2 * int(cfg.n_types), "lj"),
+                                           _ptr(force, real, 3 * n, "force"), _ptr(out, torch.float64, 4, "out"),
+                                           _stream(stream)),
+           "md_compute_forces_noalloc")
+
+
+def md_noalloc_max_particles() -> int:
+    return int(lib().md_noalloc_max_particles())
 
 
 def md_step(h: Handle, pos, vel, force, type, ids, inv_mass, lj, dt, nsteps, energy_every=0,
