@@ -27,34 +27,38 @@ FLOPS_PER_PAIR = 26  # FP32 flops per interacting unordered pair (d 3, r2 5, 1/r
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (published)
 PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
 
-# Counters of the Verlet-list force kernel (k_vlw_f32, 1M fluid, CSF 1,
-# gather-only), from rocprofv3 --pmc runs, averaged over the run's dispatches:
-# HBM traffic from FETCH_SIZE and WRITE_SIZE (KiB per dispatch; separate
-# runs), each scaled by what the counter reads for a plain 512 MiB device
-# copy (FETCH_SIZE reads half the bytes the copy moves: factor 2.0;
-# WRITE_SIZE reads them exactly: 1.0); FP32 work from SQ_INSTS_VALU_FLOPS_FP32
-# (per dispatch, in wavefront instructions weighted by flops per lane, so 64
-# lanes' flops each).  Valid only for the kernel sources they were taken on
-# (sha256 prefix of window.hip, pair.h, md_internal.h, verlet.h); otherwise reported as
-# null.
-# Counter runs of the Verlet-list gather force kernel (fluid, CSF 1, R 7),
-# per dispatch and per variant: "fused" also integrates each particle for the
-# next step (every step of a rebuild interval but its last), "plain" does not.
-# Valid while the force sources hash to "sha".
-VL_COUNTERS = {"kernel": "k_vlw_f32", "sha": "85658f11d2ce11d1",
-               "fetch_factor": 2.0, "write_factor": 1.0,
-               "fused": {"fetch_kib": 144717.0, "write_kib": 66137.7, "valu_flops_fp32_wave": 28150547.1},
-               "plain": {"fetch_kib": 116566.7, "write_kib": 12376.0, "valu_flops_fp32_wave": 28004872.5}}
+# Counters of the FP32 force kernels on the 1M fluid (CSF 1, gather-only,
+# rebuild interval 5), from rocprofv3 --pmc runs of bench.py --probe,
+# averaged over each kernel's dispatches: HBM traffic from FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch; separate runs), each scaled by what the
+# counter reads for a plain 512 MiB device copy (FETCH_SIZE reads half the
+# bytes the copy moves: factor 2.0; WRITE_SIZE reads them exactly: 1.0); FP32
+# work from SQ_INSTS_VALU_FLOPS_FP32 (per dispatch, in wavefront instructions
+# weighted by flops per lane, so 64 lanes' flops each).  The Verlet-list
+# kernel runs in two variants: "fused" also integrates each particle for the
+# next step (every step of a rebuild interval but its last), "plain" does
+# not.  An entry is valid only while the sources it was taken on hash to its
+# "sha" (sha256 prefix of the files listed); otherwise the line reports null.
+COUNTERS = {
+    "k_vlw_f32": {"files": ("window.hip", "pair.h", "verlet.h"), "sha": "3c9748c96580ed40",
+                  "fused": {"fetch_kib": 144214.7, "write_kib": 65973.6, "valu_flops_fp32_wave": 27915643.4},
+                  "plain": {"fetch_kib": 116187.6, "write_kib": 12353.3, "valu_flops_fp32_wave": 27789802.0}},
+    "k_lcw_f32": {"files": ("window.hip", "pair.h"), "sha": "821d95465d945c1f",
+                  "plain": {"fetch_kib": 14199.9, "write_kib": 12297.1, "valu_flops_fp32_wave": 108230629.7}},
+    "k_cl_f32": {"files": ("clusters.hip", "pair.h"), "sha": "73358d53d6bfb4ee",
+                 "plain": {"fetch_kib": 568813.1, "write_kib": 25605.1, "valu_flops_fp32_wave": 191531839.3}},
+}
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
 STRATEGY_NAMES = {"forest": "random-forest", "expert": "expert", "auto": "predictive", "full": "full-search"}
 
 
-def force_sources_sha():
+def sources_sha(files):
     import hashlib
     h = hashlib.sha256()
     base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2505_03438_amd", "csrc")
-    for f in ("window.hip", "pair.h", "md_internal.h", "verlet.h"):
+    for f in files:
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -67,28 +71,38 @@ def _variant_mix(R):
     return (R - 1) / R
 
 
+def _counter_entry(kname):
+    t = COUNTERS.get(kname)
+    if not t or sources_sha(t["files"]) != t["sha"]:
+        return None
+    return t
+
+
+def _weighted(t, R, per):
+    if "fused" not in t:
+        return per(t["plain"])
+    w = _variant_mix(R)
+    return w * per(t["fused"]) + (1.0 - w) * per(t["plain"])
+
+
 def measured_traffic(kname, R):
     """HBM bytes per launch of the force kernel from the counter runs (the
-    variants weighted as a rebuild interval of R steps runs them), or None if
-    they do not cover this kernel as it is now."""
-    t = VL_COUNTERS
-    if kname != t["kernel"] or force_sources_sha() != t["sha"]:
+    Verlet-list variants weighted as a rebuild interval of R steps runs them),
+    or None if they do not cover this kernel as it is now."""
+    t = _counter_entry(kname)
+    if t is None:
         return None
-    w = _variant_mix(R)
-    by = {k: 1024.0 * (t[k]["fetch_kib"] * t["fetch_factor"] + t[k]["write_kib"] * t["write_factor"])
-          for k in ("fused", "plain")}
-    return w * by["fused"] + (1.0 - w) * by["plain"]
+    return _weighted(t, R, lambda v: 1024.0 * (v["fetch_kib"] * FETCH_FACTOR + v["write_kib"] * WRITE_FACTOR))
 
 
 def measured_flops(kname, R):
     """FP32 flops issued per launch of the force kernel (every lane of every
     VALU instruction, idle lanes of divergent loops included; variants
     weighted as in measured_traffic), or None."""
-    t = VL_COUNTERS
-    if kname != t["kernel"] or force_sources_sha() != t["sha"]:
+    t = _counter_entry(kname)
+    if t is None:
         return None
-    w = _variant_mix(R)
-    return 64.0 * (w * t["fused"]["valu_flops_fp32_wave"] + (1.0 - w) * t["plain"]["valu_flops_fp32_wave"])
+    return 64.0 * _weighted(t, R, lambda v: v["valu_flops_fp32_wave"])
 
 
 def log(*a):

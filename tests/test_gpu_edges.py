@@ -169,7 +169,7 @@ def test_edge_pairs(orc, lib, system, cont, prec):
     else:
         # isolated pairs: each particle feels one pair force (or none, then
         # exactly zero): relative error per particle
-        tol = 1e-12 if prec == 1 else 1e-5
+        tol = 1e-12 if prec == 1 else 2e-6  # per pair: rcp, products, fixed-point sums
         mag0 = np.sqrt((F0 * F0).sum(axis=0))
         err = np.sqrt(((F - F0) ** 2).sum(axis=0))
         assert (err <= tol * mag0).all(), np.flatnonzero(err > tol * mag0)
