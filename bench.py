@@ -126,7 +126,7 @@ def space_size(kind):
     one for the Random Forest, an upper bound for the Expert rules."""
     if kind.startswith("forest"):
         return 1
-    return 10 if kind.endswith("+skin") else 7
+    return 11 if kind.endswith("+skin") else 8
 
 
 def make_cfg(M, n, box, kind, steps, warmup=0):
@@ -148,7 +148,8 @@ def make_cfg(M, n, box, kind, steps, warmup=0):
         _, cont, csf, n3, R = parts[:5]
         if len(parts) > 5:
             c.skin = float(parts[5])
-        c.container = {"lc": M.MD_CONTAINER_LC, "vl": M.MD_CONTAINER_VL, "cl": M.MD_CONTAINER_CL}[cont]
+        c.container = {"lc": M.MD_CONTAINER_LC, "vl": M.MD_CONTAINER_VL, "cl": M.MD_CONTAINER_CL,
+                       "pvl": M.MD_CONTAINER_PVL}[cont]
         c.csf = float(csf)
         c.newton3 = int(n3)
         c.rebuild_interval = int(R)
@@ -333,7 +334,7 @@ def run(M, d, kind, steps, warmup, repeats=1, probe_steps=50, keep_state=False):
 
 def fixed_kind(c, R):
     """fixed:... kind of a tuning-space configuration at rebuild interval R."""
-    cont = {0: "lc", 1: "vl", 2: "cl"}[int(c["container"])]
+    cont = {0: "lc", 1: "vl", 2: "cl", 3: "pvl"}[int(c["container"])]
     return "fixed:%s:%g:%d:%d:%g" % (cont, c["csf"], int(c["newton3"]), int(R), c["skin"])
 
 
@@ -421,6 +422,8 @@ def force_kernel_name(c, family):
     cluster pairs)."""
     if family == 2:
         return "k_cl_f32"
+    if c["container"] == 3:
+        return "k_pvl_f32"
     if c["container"] == 1:
         return ("k_vlwh_f32" if c["newton3"] else "k_vlw_f32") if family == 1 else "k_vl_f32"
     return ("k_lcwh_f32" if c["newton3"] else "k_lcw_f32") if family == 1 else "k_lc_f32"

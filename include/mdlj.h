@@ -59,6 +59,10 @@ extern "C" {
 #define MD_CONTAINER_VL 1 /* Verlet lists with skin, rebuilt every R steps  */
 #define MD_CONTAINER_CL 2 /* cluster-pair lists (8-particle clusters; FP32,
                              gather-only)                                   */
+#define MD_CONTAINER_PVL 3 /* pairwise Verlet lists (sorted cell pairs: per
+                              neighbour cell a prefix of its order along the
+                              pair's direction; FP32, gather-only, CSF 1,
+                              at least three cells per dimension)          */
 
 /* traversal (Sec. 2.2.2, Table 1: N3L column) */
 #define MD_N3L_OFF 0 /* each pair evaluated from both sides, gather only  */
@@ -213,7 +217,11 @@ int md_live_stats(md_handle *h, const double *pos, double *out, void *stream);
  * int32[n][max_per_row], row-major) its entries, both in the cell order the
  * arrays are in.  For cluster lists a particle's entries are all particles of
  * the j-clusters listed for its cluster, itself excluded: a superset of its
- * partners within r_c + skin.  Rows longer than max_per_row are truncated
+ * partners within r_c + skin.  For pairwise Verlet lists a particle's entries
+ * are its candidates: the other particles of its cell and, per neighbour
+ * cell, the stored prefix of that cell's order along the pair's direction
+ * (also a superset of its partners within r_c + skin).  Rows longer than
+ * max_per_row are truncated
  * (counts still give the full length).  MD_ERR_INVALID_ARG for linked cells.
  * For inspection and tests. */
 int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows,

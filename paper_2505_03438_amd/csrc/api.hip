@@ -161,7 +161,7 @@ static void free_buffers(md_handle *h)
                     b.nbr, b.nbr_count, b.partials, b.kpart, b.dpart, b.flags, b.tab, b.cl_start,
                     b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
                     b.cl_nbr_count, b.snap_pos, b.snap_vel,
-                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart, b.stat, b.stat_count, b.pos_alt, b.stage_alt,
+                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart, b.stat, b.stat_count, b.pvl_perm, b.pvl_cnt, b.pvl_s, b.pvl_entries, b.pos_alt, b.stage_alt,
                     b.w_blk, b.w_staged, b.w_rown, b.w_rowb, b.w_nbr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -237,8 +237,12 @@ static int validate_config(const md_config *c)
         }
     if (!(c->skin >= 0.0) || !isfinite(c->skin)) return fail(MD_ERR_INVALID_ARG, "skin must be >= 0");
     if (!(c->csf >= 0.5 && c->csf <= 1.0)) return fail(MD_ERR_INVALID_ARG, "csf must lie in [0.5, 1]");
-    if (c->container != MD_CONTAINER_LC && c->container != MD_CONTAINER_VL && c->container != MD_CONTAINER_CL)
+    if (c->container != MD_CONTAINER_LC && c->container != MD_CONTAINER_VL && c->container != MD_CONTAINER_CL &&
+        c->container != MD_CONTAINER_PVL)
         return fail(MD_ERR_INVALID_ARG, "bad container");
+    if (c->container == MD_CONTAINER_PVL &&
+        (c->newton3 != MD_N3L_OFF || c->precision != MD_FP32 || c->csf != 1.0))
+        return fail(MD_ERR_INVALID_ARG, "pairwise Verlet lists are FP32, gather-only, on CSF-1 cells");
     if (c->newton3 != MD_N3L_OFF && c->newton3 != MD_N3L_ON) return fail(MD_ERR_INVALID_ARG, "bad newton3");
     if (c->container == MD_CONTAINER_CL && c->newton3 != MD_N3L_OFF)
         return fail(MD_ERR_INVALID_ARG, "cluster lists are gather-only (newton3 = MD_N3L_OFF)");
@@ -291,6 +295,8 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
     if (rc) return rc;
     Geom g;
     if ((rc = make_geom(*cfg, cfg->csf, g))) return rc;
+    if (cfg->container == MD_CONTAINER_PVL && !pvl_geometry_ok(g))
+        return fail(MD_ERR_INVALID_ARG, "pairwise Verlet lists need at least three cells of side r_c + skin per dimension");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MD_ERR_NO_DEVICE, "no HIP device");
     md_handle *h = new md_handle();
@@ -349,7 +355,8 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
         for (const md_config &k : h->space) {
             Geom gk;
             std::string keep_err = g_err;
-            if (make_geom(k, k.csf, gk) == MD_OK) fit.push_back(k);
+            if (make_geom(k, k.csf, gk) == MD_OK && (k.container != MD_CONTAINER_PVL || pvl_geometry_ok(gk)))
+                fit.push_back(k);
             g_err = keep_err;
         }
         h->space.swap(fit);
@@ -575,6 +582,28 @@ static int build_blocks(md_handle *h, hipStream_t s)
     return MD_OK;
 }
 
+// Pairwise Verlet lists: 13 sorted orders and projections and 26 prefix
+// lengths per particle.
+static int ensure_pvl(md_handle *h)
+{
+    Buffers &b = h->b;
+    int64_t n = std::max<int64_t>(h->n, 1);
+    if (n > b.pvl_cap) {
+        void *ptrs[] = {b.pvl_perm, b.pvl_cnt, b.pvl_s};
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+        b.pvl_perm = b.pvl_cnt = nullptr;
+        b.pvl_s = nullptr;
+        b.pvl_cap = 0;
+        int rc;
+        if ((rc = dalloc(&b.pvl_perm, (size_t)13 * n)) || (rc = dalloc(&b.pvl_cnt, (size_t)26 * n)) ||
+            (rc = dalloc(&b.pvl_s, (size_t)13 * n)))
+            return rc;
+        b.pvl_cap = n;
+    }
+    return MD_OK;
+}
+
 static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
 {
     Buffers &b = h->b;
@@ -592,6 +621,10 @@ static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
         launch_fill_i32(b.flags + 2, 0, 1, s);
         launch_vl_build(n, b.stage, b.cell_start, b.cell_sorted, pos, h->g, h->cfg.newton3, b.nbr, b.nbr_count,
                         n, h->cfg.max_neighbors, b.flags, s);
+    } else if (h->cfg.container == MD_CONTAINER_PVL) {
+        int rc = ensure_pvl(h);
+        if (rc) return rc;
+        launch_pvl_build(n, b.stage, b.cell_start, b.cell_sorted, h->g, b.pvl_s, b.pvl_perm, b.pvl_cnt, s);
     } else if (h->cfg.container == MD_CONTAINER_CL) {
         int rc = ensure_clusters(h);
         if (rc) return rc;
@@ -658,6 +691,8 @@ static ForceArgs force_args(md_handle *h, const double *pos, const int32_t *type
     a.cl_ld = h->b.cl_cap;
     a.n_clusters = (int)h->b.cl_cap;
     a.cl_ncl = h->b.cl_base ? h->b.cl_base + h->g.ncell : nullptr;
+    a.pvl_perm = h->b.pvl_perm;
+    a.pvl_cnt = h->b.pvl_cnt;
     a.tab = h->b.tab;
     a.force = force;
     a.partials = h->b.partials;
@@ -1371,7 +1406,11 @@ extern "C" int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows, in
     if (!h->built || !h->lists) return fail(MD_ERR_NOT_BUILT, "lists not built");
     if (max_per_row < 1 || (h->n > 0 && (!counts || !rows))) return fail(MD_ERR_INVALID_ARG, "bad arguments");
     int n = (int)h->n;
-    if (h->cfg.container == MD_CONTAINER_CL) {
+    if (h->cfg.container == MD_CONTAINER_PVL) {
+        const Buffers &b = h->b;
+        launch_pvl_rows(n, b.cell_start, b.cell_sorted, h->g, b.pvl_perm, b.pvl_cnt, max_per_row, counts, rows,
+                        (hipStream_t)stream);
+    } else if (h->cfg.container == MD_CONTAINER_CL) {
         const Buffers &b = h->b;
         launch_cl_rows(n, b.cell_sorted, b.cell_start, b.cl_base, b.cl_start, b.cl_count, b.cl_nbr, b.cl_nbr_count,
                        b.cl_cap, max_per_row, counts, rows, (hipStream_t)stream);
@@ -1420,6 +1459,20 @@ static int list_entries(md_handle *h, int64_t *entries)
     if (!h->built || !h->lists || !has_lists(h->cfg)) return MD_OK;
     int32_t m = (int32_t)h->n;
     const int32_t *cnt = b.nbr_count;
+    if (h->cfg.container == MD_CONTAINER_PVL) {
+        // candidates: own cells and stored prefixes
+        if (!h->b.pvl_entries) {
+            int rc = dalloc(&h->b.pvl_entries, 1);
+            if (rc) return rc;
+        }
+        unsigned long long e = 0;
+        MD_HIP(hipDeviceSynchronize());
+        MD_HIP(hipMemcpy(h->b.pvl_entries, &e, sizeof(e), hipMemcpyHostToDevice));
+        launch_pvl_entries(m, b.cell_start, b.cell_sorted, b.pvl_cnt, h->b.pvl_entries, nullptr);
+        MD_HIP(hipMemcpy(&e, h->b.pvl_entries, sizeof(e), hipMemcpyDeviceToHost));
+        *entries = (int64_t)e;
+        return MD_OK;
+    }
     if (h->cfg.container == MD_CONTAINER_CL) {
         if (!b.cl_base || !b.cl_nbr_count) return MD_OK;
         MD_HIP(hipDeviceSynchronize());

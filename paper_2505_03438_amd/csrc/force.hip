@@ -399,6 +399,10 @@ void launch_force(const ForceArgs &a, const Geom &g, hipStream_t s)
         launch_cluster_force(a, g, s);
         return;
     }
+    if (a.container == MD_CONTAINER_PVL) {
+        launch_pvl_force(a, g, s);
+        return;
+    }
     if (a.window) {
         launch_window_force(a, g, s);
         return;

@@ -104,6 +104,12 @@ struct Buffers {
     int64_t w_cap = 0, w_rows_cap = 0, w_nbr_cap = 0;
     // adjoint
     double *gpart = nullptr;     // per-block parameter-gradient partials [blocks][8]
+    // pairwise Verlet lists: per direction (13) the sorted in-cell order and
+    // projections, per neighbour slot (26) each particle's prefix length
+    uint16_t *pvl_perm = nullptr, *pvl_cnt = nullptr;
+    float *pvl_s = nullptr;
+    int64_t pvl_cap = 0;
+    unsigned long long *pvl_entries = nullptr;
     int32_t *stat = nullptr;     // live-statistics summary of the bin counts [8 + kStatBins]
     int32_t *stat_count = nullptr;  // live-statistics bin counts (their own array: the
     int64_t stat_count_cap = 0;     // structure's cells stay valid)
@@ -186,6 +192,7 @@ struct ForceArgs {
     int64_t cl_ld;
     int n_clusters;
     const int32_t *cl_ncl;  // device: number of clusters
+    const uint16_t *pvl_perm, *pvl_cnt;  // pairwise Verlet lists: sorted orders, prefix lengths
     const PairTab *tab;
     void *force;
     double *partials;  // per-block {U, W, n_pairs, 0}
@@ -263,6 +270,18 @@ void launch_adjoint_window(const int4 *st, const int32_t *cs, const int32_t *cel
                            const float *G, double *grad_pos, double *gpart, int32_t *flags, hipStream_t s);
 void launch_adjoint_finish(const double *gpart, int nblocks, const double *lj, int nt,
                            double *grad_lj, hipStream_t s);
+
+// pairwise.hip
+// Pairwise Verlet lists need cells of side >= r_c + skin (reach 1) and at
+// least three cells per dimension.
+bool pvl_geometry_ok(const Geom &g);
+void launch_pvl_build(int n, const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, float *sv,
+                      uint16_t *perm, uint16_t *cnt, hipStream_t s);
+void launch_pvl_force(const ForceArgs &a, const Geom &g, hipStream_t s);
+void launch_pvl_rows(int n, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, const uint16_t *perm,
+                     const uint16_t *cnt, int maxr, int32_t *counts, int32_t *rows, hipStream_t s);
+void launch_pvl_entries(int n, const int32_t *cs, const int32_t *cell_sorted, const uint16_t *cnt,
+                        unsigned long long *out, hipStream_t s);
 
 // clusters.hip
 int cluster_force_blocks();

@@ -327,6 +327,14 @@ void tuning_space(const md_config &base, std::vector<md_config> &space)
         c.newton3 = MD_N3L_OFF;
         space.push_back(c);
     }
+    // pairwise Verlet lists (FP32, gather-only, CSF-1 cells; left out by the
+    // caller where the box holds fewer than three such cells per dimension)
+    if (base.precision == MD_FP32) {
+        c.container = MD_CONTAINER_PVL;
+        c.csf = 1.0;
+        c.newton3 = MD_N3L_OFF;
+        space.push_back(c);
+    }
     // joint skin / rebuild-interval search: Verlet lists at other skins (a
     // larger skin buys a longer interval with longer lists)
     if (base.tune_skin && base.skin > 0.0)

@@ -73,7 +73,8 @@ bool rules_need_histogram(const std::vector<md_fuzzy_rule> &rules);
 
 // The GPU configuration space the autotuner explores for a base config:
 // linked cells (CSF 1 and 0.5) and Verlet lists, gather-only or with
-// Newton's third law, cluster lists (gather-only, FP32), and with tune_skin
+// Newton's third law, cluster lists and pairwise Verlet lists (gather-only,
+// FP32), and with tune_skin
 // Verlet lists at 2/3, 4/3 and 5/3 of the skin.  The rebuild interval is not
 // a trial dimension: it is derived from the measured particle motion (the
 // most steps that keep displacements within the configuration's skin).

@@ -25,6 +25,7 @@ MD_FP64 = 1
 MD_CONTAINER_LC = 0
 MD_CONTAINER_VL = 1
 MD_CONTAINER_CL = 2
+MD_CONTAINER_PVL = 3
 MD_N3L_OFF = 0
 MD_N3L_ON = 1
 MD_TUNE_OFF = 0

@@ -30,14 +30,25 @@ FP32_F, FP64_F = 1e-5, 1e-12
 FP32_E, FP64_E = 1e-6, 1e-12
 
 CONTAINERS = [(0, 0, 1.0), (0, 1, 1.0), (0, 0, 0.5), (0, 1, 0.5), (1, 0, 1.0), (1, 1, 1.0), (1, 0, 0.5),
-              (1, 1, 0.5), (2, 0, 1.0), (2, 0, 0.5)]
-CNAMES = ["lc", "lc-n3l", "lc-csf.5", "lc-n3l-csf.5", "vl", "vl-n3l", "vl-csf.5", "vl-n3l-csf.5", "cl", "cl-csf.5"]
+              (1, 1, 0.5), (2, 0, 1.0), (2, 0, 0.5), (3, 0, 1.0)]
+CNAMES = ["lc", "lc-n3l", "lc-csf.5", "lc-n3l-csf.5", "vl", "vl-n3l", "vl-csf.5", "vl-n3l-csf.5", "cl", "cl-csf.5",
+          "pvl"]
 
 
-def _fp32_only(cont, prec):
-    """Cluster-pair lists run in FP32 only."""
-    if cont[0] == 2 and prec == 1:
-        pytest.skip("cluster lists are FP32-only")
+def _fp32_only(cont, prec, box=None):
+    """Cluster-pair and pairwise Verlet lists run in FP32 only; pairwise
+    lists need three cells of side r_c + skin per dimension."""
+    if cont[0] in (2, 3) and prec == 1:
+        pytest.skip("cluster and pairwise lists are FP32-only")
+    if box is not None and not fits(cont, box):
+        pytest.skip("pairwise lists need three cells per dimension")
+
+
+def fits(cont, box, prec=0):
+    """Whether container cont runs on this machine and precision."""
+    if cont[0] in (2, 3) and prec == 1:
+        return False
+    return cont[0] != 3 or all(int(b // 2.8) >= 3 for b in box)
 
 
 def _jittered(ncell, seed, density=0.8, jitter=0.08, shape=None):
@@ -97,6 +108,7 @@ def test_forces_match_oracle(orc, prec, cont, size):
     ncell, seed = size
     pos, box = _jittered(ncell, seed)
     assert min(box) >= 5.6  # 2 (r_c + skin)
+    _fp32_only(cont, prec, box)
     n = pos.shape[1]
     F0, U0, W0, P0 = orc.forces(pos, box, orc.single())
     cfg = make_config(n, box, container=cont[0], newton3=cont[1], csf=cont[2], precision=prec)
@@ -124,7 +136,7 @@ def test_anisotropic_box_and_two_types(orc, prec):
     p = orc.Params(e, sg, rc2)
     F0, U0, W0, P0 = orc.forces(pos, box, p, types)
     for cont in CONTAINERS:
-        if cont[0] == 2 and prec == 1:
+        if not fits(cont, box, prec):
             continue
         cfg = make_config(n, box, container=cont[0], newton3=cont[1], csf=cont[2], precision=prec,
                           n_types=2, rc2=rc2)
@@ -151,6 +163,8 @@ def test_small_box_wrapping_stencil(orc):
         pos = np.ascontiguousarray(pos[:, keep])
         F0, U0, W0, P0 = orc.forces(pos, box, orc.single())
         for cont in CONTAINERS:
+            if not fits(cont, box):
+                continue
             cfg = make_config(pos.shape[1], box, container=cont[0], newton3=cont[1], csf=cont[2])
             s = DeviceSystem(cfg, pos)
             s.build()
@@ -166,7 +180,9 @@ def test_tiny_and_empty_systems(orc):
     box = np.array([8.0, 8.0, 8.0])
     F0, U0, _, P0 = orc.forces(pos, box, orc.single())
     for cont in CONTAINERS:
-        prec = 0 if cont[0] == 2 else 1
+        if not fits(cont, box):
+            continue
+        prec = 0 if cont[0] in (2, 3) else 1
         cfg = make_config(2, box, container=cont[0], newton3=cont[1], csf=cont[2], precision=prec)
         s = DeviceSystem(cfg, pos)
         s.build()
@@ -187,7 +203,7 @@ def test_forces_need_lists_after_cell_build(orc):
     forces until the lists are built again (no stale or unbuilt lists)."""
     pos, box = _jittered(6, 8, jitter=0.1)
     n = pos.shape[1]
-    for cont in (1, 2):
+    for cont in (1, 2, 3):
         cfg = make_config(n, box, container=cont, precision=0)
         s = DeviceSystem(cfg, pos)
         M.md_build_cells(s.h, s.pos, s.vel, s.force, s.type, s.ids)
@@ -370,7 +386,8 @@ def test_nve_fp64_trajectory(orc, cont):
     assert np.abs(s.by_id(s.vel) - v1).max() < 1e-9
 
 
-@pytest.mark.parametrize("cont", [(1, 0, 1.0), (2, 0, 1.0), (0, 0, 0.5)], ids=["vl", "cl", "lc-csf.5"])
+@pytest.mark.parametrize("cont", [(1, 0, 1.0), (2, 0, 1.0), (0, 0, 0.5), (3, 0, 1.0)],
+                         ids=["vl", "cl", "lc-csf.5", "pvl"])
 def test_nve_fp32_energy_conservation(orc, cont):
     s, log = _run_nve(orc, 0, cont, nsteps=400, R=10)
     u_rc = orc.lj(6.25)[1]
@@ -435,6 +452,57 @@ def test_cluster_lists_cover_verlet_pairs(orc, csf):
         for j in ids[rows[k, :counts[k]]]:
             pairs.add((ids[k], j))
     assert all((j, i) in pairs for (i, j) in pairs)
+
+
+@pytest.mark.parametrize("shape", [(6, 7, 8), (12, 12, 12), (5, 6, 14)], ids=["box678", "box12", "aniso"])
+def test_pairwise_lists_cover_verlet_pairs(orc, shape):
+    """Pairwise Verlet lists: every pair within r_c + skin at the build lies
+    in a particle's candidates (its own cell and, per neighbour cell, the
+    stored prefix of that cell's order along the pair's direction), every
+    candidate is a neighbour-cell particle, and the prefixes prune: fewer
+    candidates than the 27-cell stencil.  Forces and pair count exact."""
+    pos, box = _jittered(None, 23, jitter=0.1, shape=shape)
+    n = pos.shape[1]
+    assert fits((3, 0, 1.0), box)
+    cfg = make_config(n, box, container=3)
+    s = DeviceSystem(cfg, pos)
+    s.build()
+    counts, rows = M.md_get_neighbors(s.h, 512)
+    counts, rows = counts.cpu().numpy(), rows.cpu().numpy()
+    assert counts.max() <= 512
+    cnt = M.md_get_counters(s.h)
+    assert cnt["list_entries"] == int(counts.sum())
+    ids = s.ids_np()
+    ref = orc.neighbor_rows(pos, box, (2.5 + 0.3) ** 2, np.arange(n))
+    nc = np.floor(box / 2.8).astype(int)
+    cell_of, order, start = orc.cells(pos, box, nc)
+    stencil = 0
+    for k in range(n):
+        got = ids[rows[k, :counts[k]]]
+        assert len(set(got.tolist())) == len(got)  # no candidate twice
+        assert ids[k] not in set(got.tolist())
+        assert set(ref[ids[k]].tolist()) <= set(got.tolist()), k
+        ci = np.array(np.unravel_index(cell_of[ids[k]], nc[::-1])[::-1])
+        for j in got:
+            cj = np.array(np.unravel_index(cell_of[j], nc[::-1])[::-1])
+            dc = (cj - ci + 1) % nc
+            assert (dc <= 2).all(), (k, j)
+        stencil += sum(start[c + 1] - start[c] for c in _stencil_cells(ci, nc)) - 1
+    assert counts.sum() < 0.5 * stencil
+    F0, U0, W0, P0 = orc.forces(pos, box, orc.single())
+    out = s.forces().cpu().numpy()
+    assert int(out[2]) == P0
+    assert_forces(s.by_id(s.force), F0, False)
+
+
+def _stencil_cells(ci, nc):
+    out = []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                c = (ci + np.array([dx, dy, dz])) % nc
+                out.append(int((c[2] * nc[1] + c[1]) * nc[0] + c[0]))
+    return out
 
 
 def test_skin_violation_forces_rebuild(orc):
@@ -870,9 +938,9 @@ def test_expert_rules_rejected_for_untuned_handle(orc):
 
 
 def test_autotuned_fp32_energy_conservation(orc):
-    """FP32 autotuned run over all seven configurations (cluster lists
-    included): the total energy stays conserved across configuration
-    switches."""
+    """FP32 autotuned run over all eight configurations (cluster and
+    pairwise lists included): the total energy stays conserved across
+    configuration switches."""
     import torch
     d = W.plain_fcc_864()
     nsteps = 400
@@ -888,7 +956,7 @@ def test_autotuned_fp32_energy_conservation(orc):
     M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, nsteps, 1, log)
     torch.cuda.synchronize()
     log = log.cpu().numpy()
-    assert M.md_get_counters(s.h)["trials"] >= 14
+    assert M.md_get_counters(s.h)["trials"] >= 16
     u_rc = orc.lj(6.25)[1]
     E = (log[:, 0] - log[:, 3] * u_rc + log[:, 1]) / 864
     assert np.abs(E - E[0]).max() < 5e-3

@@ -112,7 +112,7 @@ def test_dense_step_redoes_block(orc):
     st = M.md_status(s.h)
     assert st & M.MD_FLAG_WINDOW_FALLBACK, st
     cnt = M.md_get_counters(s.h)
-    assert cnt["tuning_phases"] == 1 and cnt["trials"] == 7, cnt
+    assert cnt["tuning_phases"] == 1 and cnt["trials"] == 8, cnt
     log = log.cpu().numpy()
     assert np.array_equal(log[:, 3], log0[:, 3])
     assert np.abs(log[:, 0] - log0[:, 0]).max() <= 1e-6 * np.abs(log0[:, 0]).max()
