@@ -126,7 +126,7 @@ def space_size(kind):
     one for the Random Forest, an upper bound for the Expert rules."""
     if kind.startswith("forest"):
         return 1
-    return 11 if kind.endswith("+skin") else 8
+    return 12 if kind.endswith("+skin") else 9
 
 
 def make_cfg(M, n, box, kind, steps, warmup=0):
@@ -149,7 +149,7 @@ def make_cfg(M, n, box, kind, steps, warmup=0):
         if len(parts) > 5:
             c.skin = float(parts[5])
         c.container = {"lc": M.MD_CONTAINER_LC, "vl": M.MD_CONTAINER_VL, "cl": M.MD_CONTAINER_CL,
-                       "pvl": M.MD_CONTAINER_PVL}[cont]
+                       "pvl": M.MD_CONTAINER_PVL, "vlc": M.MD_CONTAINER_VLC}[cont]
         c.csf = float(csf)
         c.newton3 = int(n3)
         c.rebuild_interval = int(R)
@@ -334,7 +334,7 @@ def run(M, d, kind, steps, warmup, repeats=1, probe_steps=50, keep_state=False):
 
 def fixed_kind(c, R):
     """fixed:... kind of a tuning-space configuration at rebuild interval R."""
-    cont = {0: "lc", 1: "vl", 2: "cl", 3: "pvl"}[int(c["container"])]
+    cont = {0: "lc", 1: "vl", 2: "cl", 3: "pvl", 4: "vlc"}[int(c["container"])]
     return "fixed:%s:%g:%d:%d:%g" % (cont, c["csf"], int(c["newton3"]), int(R), c["skin"])
 
 
@@ -424,6 +424,8 @@ def force_kernel_name(c, family):
         return "k_cl_f32"
     if c["container"] == 3:
         return "k_pvl_f32"
+    if c["container"] == 4:
+        return "k_vlc_f32"
     if c["container"] == 1:
         return ("k_vlwh_f32" if c["newton3"] else "k_vlw_f32") if family == 1 else "k_vl_f32"
     return ("k_lcwh_f32" if c["newton3"] else "k_lcw_f32") if family == 1 else "k_lc_f32"

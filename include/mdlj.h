@@ -63,6 +63,11 @@ extern "C" {
                               neighbour cell a prefix of its order along the
                               pair's direction; FP32, gather-only, CSF 1,
                               at least three cells per dimension)          */
+#define MD_CONTAINER_VLC 4 /* Verlet list cells: each pair once, in a list
+                              owned by a cell, traversed with the C08 cell
+                              colouring (Newton's third law without
+                              atomics; FP32, newton3 = MD_N3L_ON, CSF 1, at
+                              least three cells per dimension)             */
 
 /* traversal (Sec. 2.2.2, Table 1: N3L column) */
 #define MD_N3L_OFF 0 /* each pair evaluated from both sides, gather only  */

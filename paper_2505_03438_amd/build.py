@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libmdlj.so")
 PROBE_LIB = os.path.join(HERE, "libmdprobe.so")  # measurement probe, not the MD path
 INCLUDE = os.path.join(ROOT, "include")
 
-SOURCES = ["cells.hip", "force.hip", "window.hip", "integrate.hip", "adjoint.hip", "clusters.hip", "pairwise.hip", "batch.hip",
+SOURCES = ["cells.hip", "force.hip", "window.hip", "integrate.hip", "adjoint.hip", "clusters.hip", "pairwise.hip", "vlcells.hip", "batch.hip",
            "api.hip", "noalloc.hip", "tuner.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -161,7 +161,7 @@ static void free_buffers(md_handle *h)
                     b.nbr, b.nbr_count, b.partials, b.kpart, b.dpart, b.flags, b.tab, b.cl_start,
                     b.cl_count, b.cl_cell, b.cl_centre, b.cl_half, b.cl_base, b.cl_key, b.cl_nbr,
                     b.cl_nbr_count, b.snap_pos, b.snap_vel,
-                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart, b.stat, b.stat_count, b.pvl_perm, b.pvl_cnt, b.pvl_s, b.pvl_entries, b.pos_alt, b.stage_alt,
+                    b.snap_force, b.snap_type, b.snap_ids, b.snap_stage, b.gpart, b.stat, b.stat_count, b.pvl_perm, b.pvl_cnt, b.pvl_s, b.pvl_entries, b.vlc_nbr, b.vlc_seg, b.vlc_part, b.pos_alt, b.stage_alt,
                     b.w_blk, b.w_staged, b.w_rown, b.w_rowb, b.w_nbr};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -238,8 +238,11 @@ static int validate_config(const md_config *c)
     if (!(c->skin >= 0.0) || !isfinite(c->skin)) return fail(MD_ERR_INVALID_ARG, "skin must be >= 0");
     if (!(c->csf >= 0.5 && c->csf <= 1.0)) return fail(MD_ERR_INVALID_ARG, "csf must lie in [0.5, 1]");
     if (c->container != MD_CONTAINER_LC && c->container != MD_CONTAINER_VL && c->container != MD_CONTAINER_CL &&
-        c->container != MD_CONTAINER_PVL)
+        c->container != MD_CONTAINER_PVL && c->container != MD_CONTAINER_VLC)
         return fail(MD_ERR_INVALID_ARG, "bad container");
+    if (c->container == MD_CONTAINER_VLC &&
+        (c->newton3 != MD_N3L_ON || c->precision != MD_FP32 || c->csf != 1.0))
+        return fail(MD_ERR_INVALID_ARG, "Verlet list cells are FP32, with Newton's third law, on CSF-1 cells");
     if (c->container == MD_CONTAINER_PVL &&
         (c->newton3 != MD_N3L_OFF || c->precision != MD_FP32 || c->csf != 1.0))
         return fail(MD_ERR_INVALID_ARG, "pairwise Verlet lists are FP32, gather-only, on CSF-1 cells");
@@ -295,8 +298,9 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
     if (rc) return rc;
     Geom g;
     if ((rc = make_geom(*cfg, cfg->csf, g))) return rc;
-    if (cfg->container == MD_CONTAINER_PVL && !pvl_geometry_ok(g))
-        return fail(MD_ERR_INVALID_ARG, "pairwise Verlet lists need at least three cells of side r_c + skin per dimension");
+    if ((cfg->container == MD_CONTAINER_PVL || cfg->container == MD_CONTAINER_VLC) && !pvl_geometry_ok(g))
+        return fail(MD_ERR_INVALID_ARG,
+                    "pairwise lists and Verlet list cells need at least three cells of side r_c + skin per dimension");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MD_ERR_NO_DEVICE, "no HIP device");
     md_handle *h = new md_handle();
@@ -355,7 +359,8 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
         for (const md_config &k : h->space) {
             Geom gk;
             std::string keep_err = g_err;
-            if (make_geom(k, k.csf, gk) == MD_OK && (k.container != MD_CONTAINER_PVL || pvl_geometry_ok(gk)))
+            if (make_geom(k, k.csf, gk) == MD_OK &&
+                ((k.container != MD_CONTAINER_PVL && k.container != MD_CONTAINER_VLC) || pvl_geometry_ok(gk)))
                 fit.push_back(k);
             g_err = keep_err;
         }
@@ -604,6 +609,33 @@ static int ensure_pvl(md_handle *h)
     return MD_OK;
 }
 
+// Verlet list cells: entries [maxn][n], segment ends [4][n], per-cube
+// energy partials [ncell][4].
+static int ensure_vlc(md_handle *h, int32_t maxn)
+{
+    Buffers &b = h->b;
+    int64_t n = std::max<int64_t>(h->n, 1);
+    int rc;
+    if (n > b.vlc_cap || maxn > b.vlc_maxn) {
+        if (b.vlc_nbr) (void)hipFree(b.vlc_nbr);
+        if (b.vlc_seg) (void)hipFree(b.vlc_seg);
+        b.vlc_nbr = b.vlc_seg = nullptr;
+        b.vlc_cap = 0;
+        b.vlc_maxn = 0;
+        if ((rc = dalloc(&b.vlc_nbr, (size_t)maxn * n)) || (rc = dalloc(&b.vlc_seg, (size_t)4 * n))) return rc;
+        b.vlc_cap = n;
+        b.vlc_maxn = maxn;
+    }
+    if ((int64_t)h->g.ncell > b.vlc_part_cap) {
+        if (b.vlc_part) (void)hipFree(b.vlc_part);
+        b.vlc_part = nullptr;
+        b.vlc_part_cap = 0;
+        if ((rc = dalloc(&b.vlc_part, (size_t)4 * h->g.ncell))) return rc;
+        b.vlc_part_cap = h->g.ncell;
+    }
+    return MD_OK;
+}
+
 static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
 {
     Buffers &b = h->b;
@@ -621,6 +653,12 @@ static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
         launch_fill_i32(b.flags + 2, 0, 1, s);
         launch_vl_build(n, b.stage, b.cell_start, b.cell_sorted, pos, h->g, h->cfg.newton3, b.nbr, b.nbr_count,
                         n, h->cfg.max_neighbors, b.flags, s);
+    } else if (h->cfg.container == MD_CONTAINER_VLC) {
+        int rc = ensure_vlc(h, h->cfg.max_neighbors);
+        if (rc) return rc;
+        launch_fill_i32(b.flags + 2, 0, 1, s);
+        launch_vlc_build(n, b.stage, b.cell_start, b.cell_sorted, pos, h->g, b.vlc_nbr, b.vlc_seg, b.nbr_count,
+                         h->cfg.max_neighbors, b.flags, s);
     } else if (h->cfg.container == MD_CONTAINER_PVL) {
         int rc = ensure_pvl(h);
         if (rc) return rc;
@@ -693,6 +731,10 @@ static ForceArgs force_args(md_handle *h, const double *pos, const int32_t *type
     a.cl_ncl = h->b.cl_base ? h->b.cl_base + h->g.ncell : nullptr;
     a.pvl_perm = h->b.pvl_perm;
     a.pvl_cnt = h->b.pvl_cnt;
+    a.vlc_nbr = h->b.vlc_nbr;
+    a.vlc_seg = h->b.vlc_seg;
+    a.vlc_part = h->b.vlc_part;
+    a.vlc_blocks = vlc_force_blocks(h->g);
     a.tab = h->b.tab;
     a.force = force;
     a.partials = h->b.partials;
@@ -1406,7 +1448,11 @@ extern "C" int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows, in
     if (!h->built || !h->lists) return fail(MD_ERR_NOT_BUILT, "lists not built");
     if (max_per_row < 1 || (h->n > 0 && (!counts || !rows))) return fail(MD_ERR_INVALID_ARG, "bad arguments");
     int n = (int)h->n;
-    if (h->cfg.container == MD_CONTAINER_PVL) {
+    if (h->cfg.container == MD_CONTAINER_VLC) {
+        const Buffers &b = h->b;
+        launch_vlc_rows(n, b.cell_start, b.cell_sorted, h->g, b.vlc_nbr, b.vlc_seg, max_per_row, counts, rows,
+                        (hipStream_t)stream);
+    } else if (h->cfg.container == MD_CONTAINER_PVL) {
         const Buffers &b = h->b;
         launch_pvl_rows(n, b.cell_start, b.cell_sorted, h->g, b.pvl_perm, b.pvl_cnt, max_per_row, counts, rows,
                         (hipStream_t)stream);

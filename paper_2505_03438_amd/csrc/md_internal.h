@@ -110,6 +110,11 @@ struct Buffers {
     float *pvl_s = nullptr;
     int64_t pvl_cap = 0;
     unsigned long long *pvl_entries = nullptr;
+    // Verlet list cells: entries [max][n], segment ends [4][n], per-cube partials
+    uint16_t *vlc_nbr = nullptr, *vlc_seg = nullptr;
+    double *vlc_part = nullptr;
+    int64_t vlc_cap = 0, vlc_part_cap = 0;
+    int32_t vlc_maxn = 0;
     int32_t *stat = nullptr;     // live-statistics summary of the bin counts [8 + kStatBins]
     int32_t *stat_count = nullptr;  // live-statistics bin counts (their own array: the
     int64_t stat_count_cap = 0;     // structure's cells stay valid)
@@ -193,6 +198,9 @@ struct ForceArgs {
     int n_clusters;
     const int32_t *cl_ncl;  // device: number of clusters
     const uint16_t *pvl_perm, *pvl_cnt;  // pairwise Verlet lists: sorted orders, prefix lengths
+    const uint16_t *vlc_nbr, *vlc_seg;   // Verlet list cells: entries, segment ends per role
+    double *vlc_part;                    // Verlet list cells: per-cube energy partials
+    int vlc_blocks;                      // Verlet list cells: partial slots written with energies
     const PairTab *tab;
     void *force;
     double *partials;  // per-block {U, W, n_pairs, 0}
@@ -282,6 +290,16 @@ void launch_pvl_rows(int n, const int32_t *cs, const int32_t *cell_sorted, const
                      const uint16_t *cnt, int maxr, int32_t *counts, int32_t *rows, hipStream_t s);
 void launch_pvl_entries(int n, const int32_t *cs, const int32_t *cell_sorted, const uint16_t *cnt,
                         unsigned long long *out, hipStream_t s);
+
+// vlcells.hip (Verlet list cells traversed with the C08 colouring; the same
+// geometry needs as pairwise lists)
+void launch_vlc_build(int n, const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
+                      const Geom &g, uint16_t *nbr, uint16_t *seg, int32_t *cnt, int maxn, int32_t *flags,
+                      hipStream_t s);
+void launch_vlc_force(const ForceArgs &a, const Geom &g, hipStream_t s);
+int vlc_force_blocks(const Geom &g);
+void launch_vlc_rows(int n, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, const uint16_t *nbr,
+                     const uint16_t *seg, int maxr, int32_t *counts, int32_t *rows, hipStream_t s);
 
 // clusters.hip
 int cluster_force_blocks();

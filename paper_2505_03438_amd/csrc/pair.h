@@ -155,6 +155,48 @@ __device__ __forceinline__ double min_image(double d, double L)
     return d;
 }
 
+// Deterministic block sum of up to 4 doubles over a block of NTH threads
+// (wave shuffles then LDS), the result valid in thread 0.
+template <int NTH>
+__device__ __forceinline__ void block_sum4_n(double v[4], double *sh /* [4 * NTH/64] */)
+{
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < 4; k++) sh[wave * 4 + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 4; k++) {
+            double s = 0.0;
+            for (int w = 0; w < NTH / 64; w++) s += sh[w * 4 + k];
+            v[k] = s;
+        }
+    }
+}
+
+// Fixed point of the LDS force accumulators: force value c is held as c * K
+// rounded toward zero to an even number of units, K = 2^62 / 1e10, in two's
+// complement.  The resolution (4e-9 force units) is far below FP32 rounding
+// of the forces, for small forces too (the integer and fraction parts are
+// split toward zero, so a negative value keeps its full relative precision);
+// a sum is exact up to |c| ~ 4.6e8 (a pair closer than ~0.2 sigma), beyond
+// which the conversion saturates.
+constexpr float kFixHi = 0.10737418f;           // K / 2^32 = 2^30 / 1e10
+constexpr double kFixInv = 2.168404344971009e-9;  // 1e10 / 2^62
+
+__device__ __forceinline__ unsigned long long to_fix(float c)
+{
+    float t = c * kFixHi;                     // in units of 2^32
+    float h = truncf(t);                      // integer part, exact
+    int hi = (int)h;                          // saturating conversion
+    int lo = (int)((t - h) * 2147483648.0f);  // the fraction (exact) in units of 2, |lo| < 2^31
+    return (unsigned long long)((long long)hi * 4294967296LL + (long long)lo * 2LL);
+}
+
+__device__ __forceinline__ float from_fix(unsigned long long v) { return (float)((double)(long long)v * kFixInv); }
+
 // Deterministic block sum of up to 4 doubles (wave shuffles then LDS), the
 // result valid in thread 0.
 __device__ __forceinline__ void block_sum4(double v[4], double *sh /* [4 * kBlock/64] */)

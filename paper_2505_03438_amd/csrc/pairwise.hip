@@ -205,8 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_pvl_f32(int n, const int4 *__restric
     size_t N = (size_t)n;
     if (i < n) {
         int4 pi = st[i];
-        auto pair = [&](int j) {
-            int4 pj = st[j];
+        auto pair_at = [&](int j, const int4 &pj) {
             float dx, dy, dz;
             staged_delta<ISO>(pi, pj, g, dx, dy, dz);
             float r2 = dx * dx + dy * dy + dz * dz;
@@ -221,6 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_pvl_f32(int n, const int4 *__restric
         int cx, cy, cz;
         pvl_cell_xyz(c, g, cx, cy, cz);
         int s0 = cs[c], e0 = cs[c + 1];
+        auto pair = [&](int j) { pair_at(j, st[j]); };
         for (int j = s0; j < e0; j++)
             if (j != i) pair(j);
         for (int q = 0; q < 2 * kPvlDirs; q++) {
@@ -231,15 +231,18 @@ __global__ __launch_bounds__(kBlock) void k_pvl_f32(int n, const int4 *__restric
             int m = cnt[(size_t)q * N + i];
             // the walked part of B's order: [first, first + m) ascending
             const uint16_t *pp = perm + (size_t)d * N + s0B + (fwd ? 0 : mB - m);
-            int k = 0;
-            for (; k + 4 <= m; k += 4) {  // four independent index loads in flight
-                int j0 = pp[k], j1 = pp[k + 1], j2 = pp[k + 2], j3 = pp[k + 3];
-                pair(s0B + j0);
-                pair(s0B + j1);
-                pair(s0B + j2);
-                pair(s0B + j3);
+            for (int k0 = 0; k0 < m; k0 += 4) {
+                // four indices, then four positions, loaded before any is used
+                int jj[4];
+                int4 pj[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) jj[u] = s0B + (k0 + u < m ? (int)pp[k0 + u] : (int)pp[0]);
+#pragma unroll
+                for (int u = 0; u < 4; u++) pj[u] = st[jj[u]];
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+                    if (k0 + u < m) pair_at(jj[u], pj[u]);
             }
-            for (; k < m; k++) pair(s0B + (int)pp[k]);
         }
         F[i] = fx;
         F[N + i] = fy;

@@ -1370,26 +1370,7 @@ struct HalfAcc {
     unsigned long long x[kWinMaxHalf], y[kWinMaxHalf], z[kWinMaxHalf];
 };
 
-// Fixed point of the accumulators: force value c is held as c * K rounded
-// toward zero to an even number of units, K = 2^62 / 1e10, in two's
-// complement.  The resolution (4e-9 force units) is far below FP32 rounding
-// of the forces, for small forces too (the integer and fraction parts are
-// split toward zero, so a negative value keeps its full relative precision);
-// a window position's sum is exact up to |c| ~ 4.6e8 (a pair closer than
-// ~0.2 sigma), beyond which the conversion saturates.
-constexpr float kFixHi = 0.10737418f;           // K / 2^32 = 2^30 / 1e10
-constexpr double kFixInv = 2.168404344971009e-9;  // 1e10 / 2^62
-
-__device__ __forceinline__ unsigned long long to_fix(float c)
-{
-    float t = c * kFixHi;                     // in units of 2^32
-    float h = truncf(t);                      // integer part, exact
-    int hi = (int)h;                          // saturating conversion
-    int lo = (int)((t - h) * 2147483648.0f);  // the fraction (exact) in units of 2, |lo| < 2^31
-    return (unsigned long long)((long long)hi * 4294967296LL + (long long)lo * 2LL);
-}
-
-__device__ __forceinline__ float from_fix(unsigned long long v) { return (float)((double)(long long)v * kFixInv); }
+// (The fixed-point accumulators, to_fix and from_fix, are in pair.h.)
 
 // Head of the half-window force kernels: window laid out and staged,
 // accumulators cleared; false (uniformly) if the window does not fit.

@@ -26,6 +26,7 @@ MD_CONTAINER_LC = 0
 MD_CONTAINER_VL = 1
 MD_CONTAINER_CL = 2
 MD_CONTAINER_PVL = 3
+MD_CONTAINER_VLC = 4
 MD_N3L_OFF = 0
 MD_N3L_ON = 1
 MD_TUNE_OFF = 0

@@ -30,25 +30,26 @@ FP32_F, FP64_F = 1e-5, 1e-12
 FP32_E, FP64_E = 1e-6, 1e-12
 
 CONTAINERS = [(0, 0, 1.0), (0, 1, 1.0), (0, 0, 0.5), (0, 1, 0.5), (1, 0, 1.0), (1, 1, 1.0), (1, 0, 0.5),
-              (1, 1, 0.5), (2, 0, 1.0), (2, 0, 0.5), (3, 0, 1.0)]
+              (1, 1, 0.5), (2, 0, 1.0), (2, 0, 0.5), (3, 0, 1.0), (4, 1, 1.0)]
 CNAMES = ["lc", "lc-n3l", "lc-csf.5", "lc-n3l-csf.5", "vl", "vl-n3l", "vl-csf.5", "vl-n3l-csf.5", "cl", "cl-csf.5",
-          "pvl"]
+          "pvl", "vlc"]
 
 
 def _fp32_only(cont, prec, box=None):
-    """Cluster-pair and pairwise Verlet lists run in FP32 only; pairwise
-    lists need three cells of side r_c + skin per dimension."""
-    if cont[0] in (2, 3) and prec == 1:
-        pytest.skip("cluster and pairwise lists are FP32-only")
+    """Cluster-pair lists, pairwise Verlet lists and Verlet list cells run in
+    FP32 only; the last two need three cells of side r_c + skin per
+    dimension."""
+    if cont[0] in (2, 3, 4) and prec == 1:
+        pytest.skip("cluster lists, pairwise lists and list cells are FP32-only")
     if box is not None and not fits(cont, box):
-        pytest.skip("pairwise lists need three cells per dimension")
+        pytest.skip("pairwise lists and list cells need three cells per dimension")
 
 
 def fits(cont, box, prec=0):
     """Whether container cont runs on this machine and precision."""
-    if cont[0] in (2, 3) and prec == 1:
+    if cont[0] in (2, 3, 4) and prec == 1:
         return False
-    return cont[0] != 3 or all(int(b // 2.8) >= 3 for b in box)
+    return cont[0] not in (3, 4) or all(int(b // 2.8) >= 3 for b in box)
 
 
 def _jittered(ncell, seed, density=0.8, jitter=0.08, shape=None):
@@ -182,7 +183,7 @@ def test_tiny_and_empty_systems(orc):
     for cont in CONTAINERS:
         if not fits(cont, box):
             continue
-        prec = 0 if cont[0] in (2, 3) else 1
+        prec = 0 if cont[0] in (2, 3, 4) else 1
         cfg = make_config(2, box, container=cont[0], newton3=cont[1], csf=cont[2], precision=prec)
         s = DeviceSystem(cfg, pos)
         s.build()
@@ -203,8 +204,8 @@ def test_forces_need_lists_after_cell_build(orc):
     forces until the lists are built again (no stale or unbuilt lists)."""
     pos, box = _jittered(6, 8, jitter=0.1)
     n = pos.shape[1]
-    for cont in (1, 2, 3):
-        cfg = make_config(n, box, container=cont, precision=0)
+    for cont in (1, 2, 3, 4):
+        cfg = make_config(n, box, container=cont, newton3=1 if cont == 4 else 0, precision=0)
         s = DeviceSystem(cfg, pos)
         M.md_build_cells(s.h, s.pos, s.vel, s.force, s.type, s.ids)
         with pytest.raises(RuntimeError, match="md_build_neighbors"):
@@ -386,8 +387,8 @@ def test_nve_fp64_trajectory(orc, cont):
     assert np.abs(s.by_id(s.vel) - v1).max() < 1e-9
 
 
-@pytest.mark.parametrize("cont", [(1, 0, 1.0), (2, 0, 1.0), (0, 0, 0.5), (3, 0, 1.0)],
-                         ids=["vl", "cl", "lc-csf.5", "pvl"])
+@pytest.mark.parametrize("cont", [(1, 0, 1.0), (2, 0, 1.0), (0, 0, 0.5), (3, 0, 1.0), (4, 1, 1.0)],
+                         ids=["vl", "cl", "lc-csf.5", "pvl", "vlc"])
 def test_nve_fp32_energy_conservation(orc, cont):
     s, log = _run_nve(orc, 0, cont, nsteps=400, R=10)
     u_rc = orc.lj(6.25)[1]
@@ -493,6 +494,39 @@ def test_pairwise_lists_cover_verlet_pairs(orc, shape):
     out = s.forces().cpu().numpy()
     assert int(out[2]) == P0
     assert_forces(s.by_id(s.force), F0, False)
+
+
+@pytest.mark.parametrize("shape", [(6, 7, 8), (8, 8, 8), (5, 6, 14)], ids=["box678", "box8", "aniso"])
+def test_list_cells_hold_each_pair_once(orc, shape):
+    """Verlet list cells: every pair within r_c + skin at the build exactly
+    once over all lists (each in the row of the particle whose cell comes
+    first in the C08 base step that owns the cell pair), and the C08 colour
+    passes give the oracle's forces and pair count.  Box 678 has an odd cell
+    count in x (three colours there)."""
+    pos, box = _jittered(None, 29, jitter=0.1, shape=shape)
+    n = pos.shape[1]
+    assert fits((4, 1, 1.0), box)
+    cfg = make_config(n, box, container=4, newton3=1)
+    s = DeviceSystem(cfg, pos)
+    s.build()
+    counts, rows = M.md_get_neighbors(s.h, 256)
+    counts, rows = counts.cpu().numpy(), rows.cpu().numpy()
+    assert counts.max() <= 256
+    ids = s.ids_np()
+    ref = orc.neighbor_rows(pos, box, (2.5 + 0.3) ** 2, np.arange(n))
+    seen = set()
+    for k in range(n):
+        for j in ids[rows[k, :counts[k]]]:
+            key = (min(ids[k], j), max(ids[k], j))
+            assert key not in seen, key
+            seen.add(key)
+    assert seen == {(i, j) for i in range(n) for j in ref[i] if i < j}
+    assert M.md_get_counters(s.h)["list_entries"] == len(seen)
+    F0, U0, W0, P0 = orc.forces(pos, box, orc.single())
+    out = s.forces().cpu().numpy()
+    assert int(out[2]) == P0
+    assert_forces(s.by_id(s.force), F0, False)
+    assert abs(out[0] - U0) <= FP32_E * abs(U0)
 
 
 def _stencil_cells(ci, nc):
@@ -938,9 +972,9 @@ def test_expert_rules_rejected_for_untuned_handle(orc):
 
 
 def test_autotuned_fp32_energy_conservation(orc):
-    """FP32 autotuned run over all eight configurations (cluster and
-    pairwise lists included): the total energy stays conserved across
-    configuration switches."""
+    """FP32 autotuned run over all nine configurations (cluster lists,
+    pairwise lists and list cells included): the total energy stays
+    conserved across configuration switches."""
     import torch
     d = W.plain_fcc_864()
     nsteps = 400
@@ -956,7 +990,7 @@ def test_autotuned_fp32_energy_conservation(orc):
     M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, nsteps, 1, log)
     torch.cuda.synchronize()
     log = log.cpu().numpy()
-    assert M.md_get_counters(s.h)["trials"] >= 16
+    assert M.md_get_counters(s.h)["trials"] >= 18
     u_rc = orc.lj(6.25)[1]
     E = (log[:, 0] - log[:, 3] * u_rc + log[:, 1]) / 864
     assert np.abs(E - E[0]).max() < 5e-3
