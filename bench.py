@@ -278,11 +278,16 @@ def run(M, d, kind, steps, warmup, repeats=1, probe_steps=50, keep_state=False):
             h.close()
     cnt = M.md_get_counters(h)
     cfg_now = M.md_get_config(h)
+    names = {0: "lc", 1: "vl", 2: "cl", 3: "pvl", 4: "vlc"}
+    choices = None
     trial = None
     if cfg.autotune:
         sc, cf = M.md_get_trial_scores(h)
         trial = [{"container": int(k.container), "newton3": int(k.newton3), "csf": float(k.csf),
                   "skin": float(k.skin), "score_ms": (None if v != v else float(v))} for v, k in zip(sc, cf)]
+        choices = ["%s%s csf %g skin %g" % (names[int(cf[c].container)], " n3l" if int(cf[c].newton3) else "",
+                                            float(cf[c].csf), float(cf[c].skin))
+                   for c in M.md_get_phase_choices(h)]
     final = None
     if keep_state:
         torch.cuda.synchronize()
@@ -319,7 +324,8 @@ def run(M, d, kind, steps, warmup, repeats=1, probe_steps=50, keep_state=False):
                pairs_per_s=_median(rates), pairs_per_s_range=[min(rates), max(rates)],
                force_kernel_ms=force_ms, build_ms=build_ms, counters=cnt,
                tune={"tune_first": int(cfg.tune_first), "tune_interval": int(cfg.tune_interval),
-                     "tune_trial_steps": int(cfg.tune_trial_steps), "trial_scores": trial} if cfg.autotune else None,
+                     "tune_trial_steps": int(cfg.tune_trial_steps), "phase_choices": choices,
+                     "trial_scores": trial} if cfg.autotune else None,
                final_config=dict(container=int(cfg_now.container), newton3=int(cfg_now.newton3),
                                  csf=float(cfg_now.csf), rebuild_interval=int(cfg_now.rebuild_interval),
                                  skin=float(cfg_now.skin)),
@@ -636,9 +642,11 @@ def main():
     ap.add_argument("--extra", default="", help="comma-separated extra configs to time, e.g. "
                     "fixed:vl:1:0:5 (container:csf:n3l:R[:skin]) or auto+skin (Predictive with the skin tuned)")
     ap.add_argument("--ncell", type=int, default=64, help="FCC cells per side (64 -> 1,048,576 particles)")
-    ap.add_argument("--workload", default="fluid", choices=["fluid", "droplet", "slab", "batched", "adjoint"],
+    ap.add_argument("--workload", default="fluid",
+                    choices=["fluid", "droplet", "slab", "explode", "batched", "adjoint"],
                     help="fluid: the 1M homogeneous fluid (the benchmark line); droplet / slab: the 2M "
-                         "inhomogeneous systems (autotuner re-selection); batched: 4096 small systems in one "
+                         "inhomogeneous systems (autotuner re-selection); explode: a hot 1M-particle liquid sphere "
+                         "expanding into a box of 27 times its volume; batched: 4096 small systems in one "
                          "graph; adjoint: the force-matching gradient on the 131k mixture")
     ap.add_argument("--probe", default="", help="time only this configuration (e.g. fixed:vl:1:0:5) and print "
                     "its result; for profiler runs")
@@ -678,6 +686,9 @@ def main():
     elif args.workload == "droplet":
         d = W.droplet()
         wname = "lj-droplet-%d" % d["pos"].shape[1]
+    elif args.workload == "explode":
+        d = W.exploding_liquid()
+        wname = "lj-exploding-liquid-%d" % d["pos"].shape[1]
     else:
         d = W.slab()
         wname = "lj-slab-%d" % d["pos"].shape[1]
@@ -697,9 +708,10 @@ def main():
     reps = args.repeats
 
     def show(name, r):
-        log("%s: %.3f ms/step (%.3f-%.3f), %.3e pairs/s, force %.3f ms, config %s, %d phases, %d trials" % (
+        log("%s: %.3f ms/step (%.3f-%.3f), %.3e pairs/s, force %.3f ms, config %s, %d phases, %d trials%s" % (
             name, r["ms_per_step"], r["ms_per_step_range"][0], r["ms_per_step_range"][1], r["pairs_per_s"],
-            r["force_kernel_ms"], r["final_config"], r["counters"]["tuning_phases"], r["counters"]["trials"]))
+            r["force_kernel_ms"], r["final_config"], r["counters"]["tuning_phases"], r["counters"]["trials"],
+            (", phases chose %s" % r["tune"]["phase_choices"]) if r.get("tune") else ""))
 
     # the headline autotuner is the Random Forest strategy (Sec. 5.3, the paper's most successful
     # one): a forest fitted to Full Search trials on generative scenarios, not on this workload
@@ -770,7 +782,7 @@ def main():
     res = {
         "metric": "LJ pair-interactions/sec and MD steps/sec, 1M-particle fluid, autotuned vs plain"
                   if args.workload == "fluid" else
-                  "LJ pair-interactions/sec and MD steps/sec, 2M-particle %s, autotuned vs plain" % args.workload,
+                  "LJ pair-interactions/sec and MD steps/sec, %s, autotuned vs plain" % wname,
         "value": auto["pairs_per_s"],
         "unit": "pair-interactions/s",
         "n_gpus": 1,

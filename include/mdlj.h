@@ -236,6 +236,12 @@ int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows,
  * last call, then cleared.  Synchronises the handle's work. */
 int md_status(md_handle *h, uint32_t *flags);
 
+/* The tuning-space index each tuning phase chose, in phase order (Sec.
+ * 2.2.5: the selection of every phase): writes the first min(n, phases)
+ * into configs (HOST int32[n]; NULL with n = 0 to ask for the count) and
+ * returns the number of phases so far, or an error. */
+int md_get_phase_choices(md_handle *h, int32_t *configs, int32_t n);
+
 /* Configuration the handle currently uses (after tuning decisions). */
 int md_get_config(md_handle *h, md_config *cfg);
 

@@ -125,6 +125,7 @@ struct md_handle {
     mdlj::Tuner *tuner = nullptr;
     std::vector<md_config> space;
     std::vector<md_fuzzy_rule> rules;  // Expert strategy
+    std::vector<int32_t> phase_choices;  // configuration chosen by each tuning phase
     int64_t steps_done = 0;       // md_step steps since creation
     uint32_t sticky = 0;          // flag bits already read back from the device
     bool truncated = false;       // the current lists overflowed max_neighbors
@@ -1563,6 +1564,15 @@ extern "C" int md_get_trial_scores(md_handle *h, double *scores, md_config *conf
     return m;
 }
 
+extern "C" int md_get_phase_choices(md_handle *h, int32_t *configs, int32_t n)
+{
+    if (!h) return fail(MD_ERR_INVALID_ARG, "NULL handle");
+    if (n < 0 || (n > 0 && !configs)) return fail(MD_ERR_INVALID_ARG, "configs needs room for n entries");
+    int m = (int)h->phase_choices.size();
+    for (int k = 0; k < m && k < n; k++) configs[k] = h->phase_choices[k];
+    return m;
+}
+
 extern "C" int md_timing(md_handle *h, int32_t enable, double *out)
 {
     int rc = check_handle(h);
@@ -1692,6 +1702,7 @@ int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
     if (chosen < 0) return fail(MD_ERR_INVALID_ARG, "tuning phase without scores");
     if (chosen != last_k && (rc = apply_config(h, h->space[chosen]))) return rc;
     h->config_index = chosen;
+    h->phase_choices.push_back(chosen);
     h->next_phase = h->steps_done + s0 + h->base.tune_interval;
     *next = s;
     return MD_OK;

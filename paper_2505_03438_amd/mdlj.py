@@ -113,6 +113,7 @@ _SIGS = {
     "md_get_config": (_i32, [_vp, ctypes.POINTER(md_config)]),
     "md_get_counters": (_i32, [_vp, _vp]),
     "md_timing": (_i32, [_vp, _i32, _vp]),
+    "md_get_phase_choices": (_i32, [_vp, _vp, _i32]),
     "md_get_trial_scores": (_i32, [_vp, _vp, _vp, _i32]),
     "md_set_expert_rules": (_i32, [_vp, _vp, _i32]),
     "md_expert_suitability": (_i32, [_vp, _i32, _i32, _vp, _vp]),
@@ -322,6 +323,15 @@ def md_get_counters(h: Handle):
     keys = ("rebuilds", "forced_rebuilds", "tuning_phases", "trials", "config_index", "list_entries",
             "force_family")
     return dict(zip(keys, list(out)))
+
+
+def md_get_phase_choices(h: Handle):
+    """Tuning-space index chosen by every tuning phase so far."""
+    m = lib().md_get_phase_choices(h.ptr, None, 0)
+    _check(m if m < 0 else 0, "md_get_phase_choices")
+    out = (ctypes.c_int32 * max(m, 1))()
+    lib().md_get_phase_choices(h.ptr, out, m)
+    return list(out[:m])
 
 
 def md_get_trial_scores(h: Handle, n_max: int = 64):

@@ -136,6 +136,16 @@ def droplet(n: int = 2_000_000, density: float = 0.8, T: float = 0.7, fill: floa
                 eps=[1.0], sig=[1.0], rc=2.5, skin=0.3, dt=0.005, T=T)
 
 
+def exploding_liquid(n: int = 1_048_576, density: float = 0.8, T: float = 2.0, fill: float = 1.0 / 27.0,
+                     seed: int | None = None):
+    """A hot liquid sphere (T well above the critical temperature) in a box
+    of 27 times its volume: it expands into the vacuum, so the spread of the
+    particles over the cells falls as the run goes (the exploding liquid of
+    Sec. 6.2, at GPU size)."""
+    d = droplet(n=n, density=density, T=T, fill=fill, seed=seed_for(2) + 1 if seed is None else seed)
+    return d
+
+
 def slab(n: int = 2_000_000, rho_l: float = 0.75, rho_v: float = 0.02, T: float = 0.7,
          seed: int | None = None, jitter: float = 0.06):
     """Two-phase slab: liquid (rho_l) of thickness Lz/3 centred along z in a

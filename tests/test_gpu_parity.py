@@ -856,6 +856,57 @@ def test_expert_strategy_fp64_trajectory(orc, rules):
     s.h.close()
 
 
+def test_reselection_as_liquid_explodes(orc):
+    """Re-selection as the load imbalance changes (the exploding liquid of
+    Sec. 6.2): a hot liquid cube (864 particles, T = 4) expands into a box
+    27 times its volume.  Expert rules over the relative spread of the bin
+    counts (a Sec. 4 statistic) call linked cells at CSF 1/2 suitable while
+    the particles are clumped (spread >= 3) and Verlet lists once they have
+    spread out; a phase every 60 steps.  The phases choose the first, then
+    the second, as the spread falls from 4.0 to 2.1 (the oracle's spread
+    crosses 3 between steps 180 and 240), and every step of the FP64
+    trajectory equals the oracle's."""
+    import torch
+    rng = np.random.default_rng(7)
+    pos, cube = W.jittered_fcc(6, 0.8, 0.05, rng)
+    Lb = 30.0
+    pos = pos + (Lb - cube[0]) / 2
+    box = np.array([Lb] * 3)
+    vel = W.maxwell_boltzmann(pos.shape[1], 4.0, rng)
+    n = pos.shape[1]
+    nsteps = 600
+    p1, v1, _, log0 = orc.velocity_verlet(pos, vel, box, orc.single(), 0.005, nsteps)
+    cfg = make_config(n, box, container=0, precision=1, R=10)
+    cfg.autotune = M.MD_TUNE_EXPERT
+    cfg.tune_interval = 60
+    cfg.tune_trial_steps = 3
+    cfg.total_steps_hint = nsteps
+    s = DeviceSystem(cfg, pos, vel)
+    clumped, spread = (1, (3.0, 3.0, INF, INF)), (1, (-INF, -INF, 3.0, 3.0))
+    M.md_set_expert_rules(s.h, [{"if": [clumped], "config": 2, "then": M.MD_SUIT_GOOD},
+                                {"if": [spread], "config": 2, "then": M.MD_SUIT_BAD},
+                                {"if": [spread], "config": 4, "then": M.MD_SUIT_GOOD},
+                                {"if": [clumped], "config": 4, "then": M.MD_SUIT_BAD}])
+    s.build()
+    s.forces(energy=False)
+    log = torch.zeros((nsteps, 4), dtype=torch.float64, device="cuda")
+    M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, nsteps, 1, log)
+    torch.cuda.synchronize()
+    choices = M.md_get_phase_choices(s.h)
+    assert choices == [2, 2, 2, 2, 4, 4, 4, 4, 4, 4], choices
+    _, cfgs = M.md_get_trial_scores(s.h)
+    assert (int(cfgs[2].container), float(cfgs[2].csf)) == (M.MD_CONTAINER_LC, 0.5)
+    assert int(cfgs[4].container) == M.MD_CONTAINER_VL
+    log = log.cpu().numpy()
+    assert np.array_equal(log[:, 3], log0[:, 3])
+    for k in (0, 1, 2):
+        assert np.abs(log[:, k] - log0[:, k]).max() <= 1e-10 * np.abs(log0[:, k]).max()
+    dx = s.by_id(s.pos) - p1
+    dx -= box[:, None] * np.rint(dx / box[:, None])
+    assert np.abs(dx).max() < 1e-9
+    s.h.close()
+
+
 def test_skin_tuning_fp64_trajectory(orc):
     """Joint skin / rebuild-interval search: the tuning space gains Verlet
     lists at 2/3, 4/3 and 5/3 of the skin; Full Search trials them all, and
