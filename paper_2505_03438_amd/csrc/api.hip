@@ -51,6 +51,10 @@ int make_geom(const md_config &c, double csf, Geom &g)
         double ndd = floor(c.box[d] / side_min);
         if (ndd > 4096.0) ndd = 4096.0;
         int nd = ndd < 1.0 ? 1 : (int)ndd;
+        // Verlet list cells: an even count where there are more than three
+        // (slightly larger cells), so that the C08 colouring needs two
+        // colours per dimension, not three
+        if (c.container == MD_CONTAINER_VLC && nd > 3 && nd % 2) nd--;
         g.nc[d] = nd;
         g.L[d] = c.box[d];
         g.inv_w[d] = (double)nd / c.box[d];

@@ -24,7 +24,7 @@
 
 namespace mdlj {
 
-constexpr int kVlcMax = 512;   // particles of a cube staged in LDS
+constexpr int kVlcMax = 256;   // particles of a cube staged in LDS (a liquid cube holds ~140)
 constexpr int kVlcThreads = 128;
 
 __device__ __forceinline__ int vlc_wrap(int v, int nc) { return v < 0 ? v + nc : (v >= nc ? v - nc : v); }
