@@ -450,8 +450,14 @@ static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, i
         }
         launch_cl_sort(n, b.cell_start, pos, ids, b.cell_id, b.perm, g, b.cl_key, b.cell_sorted, b.perm2, s);
     } else {
-        // the keys go to the gather's id buffer, written again by the gather
-        launch_scatter_sort(n, b.cell_id, b.slot, b.cell_start, ids, b.perm, b.tmp_ids, b.cell_sorted, b.perm2, s);
+        // every cell ordered by x, then id (the Verlet-list build bisects its
+        // stencil rows by x)
+        if (!b.cl_key) {
+            int rc2 = dalloc(&b.cl_key, (size_t)std::max<int64_t>(h->n, 1));
+            if (rc2) return rc2;
+        }
+        launch_scatter_sort_x(n, b.cell_id, b.slot, b.cell_start, ids, pos, g, b.perm, b.cl_key, b.cell_sorted,
+                              b.perm2, s);
     }
     launch_gather(n, h->cfg.precision, b.perm2, pos, vel, force, type, ids, b.tmp_pos, b.tmp_vel, b.tmp_force,
                   b.tmp_type, b.tmp_ids, b.cell_id, b.cell_sorted, g, b.stage, b.stage_ref, s);

@@ -367,6 +367,48 @@ void launch_scatter_sort(int n, const int32_t *cell_id, const int32_t *slot, con
     k_cell_rank<<<nb, kBlock, 0, s>>>(n, start, key, cell_of_slot, perm, perm_out);
 }
 
+// The same with every cell ordered by its staged x coordinate, then id.
+// Cells are numbered x-fastest, so any run of consecutive cells along x (a
+// row of a pair stencil) is then ordered by x as well, and a traversal can
+// bound a row's candidates to an interval of x by bisection.
+__global__ void k_scatter_xkeys(int n, const int32_t *__restrict__ cell_id, const int32_t *__restrict__ slot,
+                                const int32_t *__restrict__ start, const int32_t *__restrict__ ids,
+                                const double *__restrict__ pos, double S0, int32_t *__restrict__ perm,
+                                uint64_t *__restrict__ key, int32_t *__restrict__ cell_of_slot)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = cell_id[i];
+    int p = start[c] + slot[i];
+    perm[p] = i;
+    key[p] = ((uint64_t)quantise(pos[i], S0) << 32) | (uint32_t)ids[i];
+    cell_of_slot[p] = c;
+}
+
+__global__ void k_cell_rank64(int n, const int32_t *__restrict__ start, const uint64_t *__restrict__ key,
+                              const int32_t *__restrict__ cell_of_slot, const int32_t *__restrict__ perm,
+                              int32_t *__restrict__ perm_out)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int c = cell_of_slot[k];
+    int b = start[c], e = start[c + 1];
+    uint64_t kk = key[k];
+    int r = 0;
+    for (int m = b; m < e; m++) r += key[m] < kk ? 1 : 0;
+    perm_out[b + r] = perm[k];
+}
+
+void launch_scatter_sort_x(int n, const int32_t *cell_id, const int32_t *slot, const int32_t *start,
+                           const int32_t *ids, const double *pos, const Geom &g, int32_t *perm, uint64_t *key,
+                           int32_t *cell_of_slot, int32_t *perm_out, hipStream_t s)
+{
+    if (n <= 0) return;
+    int nb = (n + kBlock - 1) / kBlock;
+    k_scatter_xkeys<<<nb, kBlock, 0, s>>>(n, cell_id, slot, start, ids, pos, g.S[0], perm, key, cell_of_slot);
+    k_cell_rank64<<<nb, kBlock, 0, s>>>(n, start, key, cell_of_slot, perm, perm_out);
+}
+
 void launch_cell_sort(int n, const int32_t *start, const int32_t *ids, const int32_t *cell_id, const int32_t *perm,
                       int32_t *key, int32_t *cell_of_slot, int32_t *perm_out, hipStream_t s)
 {

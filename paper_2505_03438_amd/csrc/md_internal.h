@@ -148,6 +148,9 @@ void launch_scatter_sort(int n, const int32_t *cell_id, const int32_t *slot, con
                          hipStream_t s);
 void launch_cell_sort(int n, const int32_t *start, const int32_t *ids, const int32_t *cell_id, const int32_t *perm,
                       int32_t *key, int32_t *cell_of_slot, int32_t *perm_out, hipStream_t s);
+void launch_scatter_sort_x(int n, const int32_t *cell_id, const int32_t *slot, const int32_t *start,
+                           const int32_t *ids, const double *pos, const Geom &g, int32_t *perm, uint64_t *key,
+                           int32_t *cell_of_slot, int32_t *perm_out, hipStream_t s);
 void launch_gather(int n, int precision, const int32_t *perm, const double *pos, const void *vel,
                    const void *force, const int32_t *type, const int32_t *ids, double *tpos,
                    void *tvel, void *tforce, int32_t *ttype, int32_t *tids, const int32_t *cell_id,

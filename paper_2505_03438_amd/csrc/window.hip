@@ -654,6 +654,182 @@ __device__ __forceinline__ void stencil_ranges(const Geom &g, const Window &w, i
     }
 }
 
+// First position p in [b, e) of an x-ordered run of a build window with
+// x >= t (e if none).
+__device__ __forceinline__ int first_at_least(const FEntry *__restrict__ win, int b, int e, float t)
+{
+    while (b < e) {
+        int m = (b + e) >> 1;
+        if (win[m].x < t)
+            b = m + 1;
+        else
+            e = m;
+    }
+    return b;
+}
+
+// First position p in [b, e) with x > t.
+__device__ __forceinline__ int first_above(const FEntry *__restrict__ win, int b, int e, float t)
+{
+    while (b < e) {
+        int m = (b + e) >> 1;
+        if (win[m].x <= t)
+            b = m + 1;
+        else
+            e = m;
+    }
+    return b;
+}
+
+// stencil_ranges for the single-precision build windows, each range cut to
+// the candidates that can lie within the list radius.  Every cell is ordered
+// by x (launch_scatter_sort_x) and a range is a run of consecutive cells
+// along x, so it is ordered by x.  A row of cells at layer offset dz and row
+// offset dy lies at least gy from the particle in y and gz in z (0 for its
+// own row and layer), so its candidates within the radius have
+// |dx| < sqrt(rl2 - gy^2 - gz^2); the range is cut to that interval by
+// bisection.  The gaps are shrunk and the interval widened by 2^-10 of the
+// cell size and the radius, far beyond the rounding of the relative
+// coordinates, so that no candidate whose FP32 distance passes the list test
+// (or falls in its guard band) is cut: the lists are the same as those of the
+// uncut ranges.  rl2: the radius squared in relative units (the upper edge of
+// the build's band); hy, hz: the cell height and depth in the same units.
+template <bool HALF, typename Fn>
+__device__ __forceinline__ void stencil_ranges_cut(const Geom &g, const Window &w, const FEntry *__restrict__ win,
+                                                   const FEntry &pf, int k, int x, int self, float rl2, float hy,
+                                                   float hz, Fn &&fn)
+{
+    constexpr float kMargin = 1.0f / 1024.0f;
+    int r = w.r, nyb = w.nyb;
+    // the particle's own cell in relative units: y in [ylo, ylo + hy) (block
+    // row k of nyb, the centre in the middle of the rows), z in [-hz/2, hz/2)
+    float ylo = ((float)k - 0.5f * (float)nyb) * hy, zlo = -0.5f * hz;
+    float py = pf.y - ylo, pz = pf.z - zlo;  // offsets inside the own cell
+    auto gap = [&](int d, float p, float h) {
+        float v = d < 0 ? p + (float)(-d - 1) * h : (d > 0 ? (float)d * h - p : 0.0f);
+        return fmaxf(v - kMargin * h, 0.0f);
+    };
+    const float rlm = rl2 * (1.0f + kMargin);
+    auto cut = [&](int b, int e, int dz, int dy) {
+        if (b >= e) return;
+        float gy = gap(dy, py, hy), gz = gap(dz, pz, hz);
+        float rx2 = rlm - gy * gy - gz * gz;
+        if (rx2 <= 0.0f) return;
+        float rx = sqrtf(rx2) * (1.0f + kMargin);
+        int lb = first_at_least(win, b, e, pf.x - rx);
+        int ub = first_above(win, lb, e, pf.x + rx);
+        if (lb < ub) fn(lb, ub);
+    };
+    // one contiguous range per row: these windows never span a whole row
+    int m = column_of(g, w, x);
+    auto row = [&](int dz, int dy) {
+        int rr = row_index(r, nyb, HALF, dz, k + dy);
+        cut((int)w.col[rr][m - r], (int)w.col[rr][m + r + 1], dz, dy);
+    };
+    if (!HALF) {
+        for (int dz = -r; dz <= r; dz++)
+            for (int dy = -r; dy <= r; dy++) row(dz, dy);
+    } else {
+        for (int dz = 1; dz <= r; dz++)
+            for (int dy = -r; dy <= r; dy++) row(dz, dy);
+        for (int dy = 1; dy <= r; dy++) row(0, dy);
+        int own = row_index(r, nyb, true, 0, k);
+        cut(self + 1, (int)w.col[own][m + 1], 0, 0);
+        cut((int)w.col[own][m + 1], (int)w.col[own][m + r + 1], 0, 0);
+    }
+}
+
+// First position p in [b, e) of a force window with x_p - xi >= t (staged
+// units, minimum image), and the first with x_p - xi > t.
+template <int NT>
+__device__ __forceinline__ int first_at_least_i(const WinEntry<NT> *__restrict__ win, int b, int e, uint32_t xi,
+                                                int t)
+{
+    while (b < e) {
+        int m = (b + e) >> 1;
+        if ((int)((uint32_t)win[m].x - xi) < t)
+            b = m + 1;
+        else
+            e = m;
+    }
+    return b;
+}
+
+template <int NT>
+__device__ __forceinline__ int first_above_i(const WinEntry<NT> *__restrict__ win, int b, int e, uint32_t xi, int t)
+{
+    while (b < e) {
+        int m = (b + e) >> 1;
+        if ((int)((uint32_t)win[m].x - xi) <= t)
+            b = m + 1;
+        else
+            e = m;
+    }
+    return b;
+}
+
+// Whether the force windows' stencil rows can be cut by x: at least 2r + 3
+// cells per dimension, so that a row's minimum-image x differences to the
+// particle are ordered along the row (they span less than half the box) and
+// a neighbour row's nearest image is the one beside the particle's cell.
+__device__ __forceinline__ bool can_cut(const Geom &g, int r)
+{
+    return g.nc[0] >= 2 * r + 3 && g.nc[1] >= 2 * r + 3 && g.nc[2] >= 2 * r + 3;
+}
+
+// stencil_ranges for the linked-cell force windows, each range cut to the
+// candidates that can lie within the cutoff.  The cells were ordered by x at
+// the last build (launch_scatter_sort_x) and every particle has since moved
+// by at most the skin check's bound d (half the skin: a step whose particles
+// moved further is redone after a rebuild), so along a stencil row the
+// current x coordinates are ordered up to 2d.  A bisection that stops at p
+// with x_{p-1} - xi < t has seen an entry below t, so every particle before p
+// lies below t + 2d (and symmetrically at the upper end): the cut interval is
+// widened by 2d on each side.  The y and z gaps to a neighbour row are taken
+// from the row's cells as built, less d for its particles' motion; 2^-10 of
+// a cell and of the radius are added to every margin, far beyond the
+// rounding, so that no pair within the upper edge of the cutoff's guard band
+// is cut.  rc2: that edge squared (x units); drift: d in x units.
+template <int NT, typename Fn>
+__device__ __forceinline__ void stencil_ranges_drift(const Geom &g, const Window &w,
+                                                     const WinEntry<NT> *__restrict__ win, const int4 &pi, int k,
+                                                     int x, float rc2, float drift, Fn &&fn)
+{
+    constexpr float kMargin = 1.0f / 1024.0f;
+    int r = w.r, nyb = w.nyb;
+    ColRanges cr = column_ranges(g, w, x, -r, r);
+    // the particle's offsets from the low corner of its cell as built, in x units
+    int cy = w.rc.y0 + k, cz = w.rc.z;
+    uint32_t y0 = (uint32_t)(((uint64_t)cy << 32) / (uint64_t)g.nc[1]);
+    uint32_t z0 = (uint32_t)(((uint64_t)cz << 32) / (uint64_t)g.nc[2]);
+    float py = (float)(int)((uint32_t)pi.y - y0) * g.ry, pz = (float)(int)((uint32_t)pi.z - z0) * g.rz;
+    float hy = 4294967296.0f / (float)g.nc[1] * g.ry, hz = 4294967296.0f / (float)g.nc[2] * g.rz;
+    auto gap = [&](int d, float p, float h) {
+        float v = d < 0 ? p + (float)(-d - 1) * h : (d > 0 ? (float)d * h - p : 0.0f);
+        return fmaxf(v - drift - kMargin * h, 0.0f);
+    };
+    const float rcm = rc2 * (1.0f + kMargin);
+    const float wide = 2.0f * drift * (1.0f + kMargin);
+    uint32_t xi = (uint32_t)pi.x;
+    auto cut = [&](int b, int e, int dz, int dy) {
+        if (b >= e) return;
+        float gy = gap(dy, py, hy), gz = gap(dz, pz, hz);
+        float rx2 = rcm - gy * gy - gz * gz;
+        if (rx2 <= 0.0f) return;
+        float rx = sqrtf(rx2) * (1.0f + kMargin) + wide;
+        int t = (int)ceilf(rx);
+        int lb = first_at_least_i(win, b, e, xi, -t);
+        int ub = first_above_i(win, lb, e, xi, t);
+        if (lb < ub) fn(lb, ub);
+    };
+    for (int dz = -r; dz <= r; dz++)
+        for (int dy = -r; dy <= r; dy++) {
+            int rr = row_index(r, nyb, false, dz, k + dy);
+            cut((int)w.col[rr][cr.a0], (int)w.col[rr][cr.b0 + 1], dz, dy);
+            if (cr.b1 >= cr.a1) cut((int)w.col[rr][cr.a1], (int)w.col[rr][cr.b1 + 1], dz, dy);
+        }
+}
+
 // One candidate pair (i, window position p) of the gather traversals, branch
 // free: the FP32 cutoff decision, the pair force added to f and the energy
 // terms.  Returns true if the pair lies inside the guard band of the cutoff;
@@ -731,10 +907,10 @@ __device__ __forceinline__ float max_hi(const TabF<NT> &t)
     return h;
 }
 
-// Each thread scans the window ranges of its stencil 32 candidates at a
-// time: a cheap distance test gives the mask of those that may interact,
-// and only they are evaluated (guard-band pairs decided from the FP64
-// positions).
+// Each thread scans the window ranges of its stencil (cut by x when the box
+// allows it, stencil_ranges_drift) 32 candidates at a time: a cheap distance
+// test gives the mask of those that may interact, and only they are
+// evaluated (guard-band pairs decided from the FP64 positions).
 template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                  const int32_t *__restrict__ cell_sorted, Geom g, int n,
@@ -750,6 +926,9 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
     TabF<NT> t;
     t.load(tabp);
     const float hi = max_hi(t);
+    // the motion allowed since the build (no bound without a skin)
+    const float drift = sqrtf(g.disp2);
+    const bool cut = can_cut(g, g.reach[0]) && drift < 1.0e30f;
     float eu = 0.f, ew = 0.f;
     int np = 0;
     size_t N = (size_t)n;
@@ -761,7 +940,7 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
         int self = self_position<false>(w, cs, i, k, column_of(g, w, x), cell_sorted[i]);
         int4 pi = win[self].get();
         float fx = 0.f, fy = 0.f, fz = 0.f;
-        stencil_ranges<false>(g, w, k, x, self, [&](int b, int en) {
+        auto batches = [&](int b, int en) {
             for (int base = b; base < en; base += 32) {
                 int m = min(32, en - base);
                 uint32_t mask = cut_batch<NT, ISO>(pi, win + base, m, g, hi);
@@ -777,7 +956,11 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
                                                     ew, np);
                 }
             }
-        });
+        };
+        if (cut)
+            stencil_ranges_drift<NT>(g, w, win, pi, k, x, hi, drift, batches);
+        else
+            stencil_ranges<false>(g, w, k, x, self, batches);
         F[i] = fx;
         F[N + i] = fy;
         F[2 * N + i] = fz;
@@ -1062,8 +1245,9 @@ __device__ __forceinline__ uint32_t build_batch_rel(const FEntry &pi, const FEnt
 
 // Verlet lists (full windows: every pair within r_c + skin from both sides;
 // half windows: each pair once, in the forward half of the stencil).  Each
-// range of candidates is tested 32 positions at a time into a bit mask, then
-// the set bits are appended in window order.  Full lists hold LDS byte
+// range of candidates (with the single-precision windows first cut to its x
+// interval, stencil_ranges_cut) is tested 32 positions at a time into a bit
+// mask, then the set bits are appended in window order.  Full lists hold LDS byte
 // offsets (window position times esz, the size of the force kernel's window
 // entry) and pad their last chunk with the offset of the far entry; half
 // lists hold window positions (esz 1) padded with 0.
@@ -1086,6 +1270,8 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
     const float rl2u = (float)(g.rl2 * g.S[0] * g.S[0]);
     const float rel_hi = rl2u * (1.0f + kBuildBand), rel_lo = rl2u * (1.0f - kBuildBand);
     const float rel_hw = rl2u * kBuildBand;
+    // cell height and depth in relative units (y and z scaled to x units)
+    const float hy = 4294967296.0f / (float)g.nc[1] * g.ry, hz = 4294967296.0f / (float)g.nc[2] * g.rz;
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
         if (REL) {
@@ -1102,7 +1288,7 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
         int c = 0;
         Chunk ck;
         const Band band(g);
-        stencil_ranges<HALF>(g, w, k, x, self, [&](int b, int en) {
+        auto batches = [&](int b, int en) {
             for (int base = b; base < en; base += 32) {
                 int m = min(32, en - base);
                 bool amb;
@@ -1138,7 +1324,11 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
                     list_append(__umul24((unsigned)(base + m - 1 - h), (unsigned)esz), c, ck, row, N, maxn);
                 }
             }
-        });
+        };
+        if (REL)
+            stencil_ranges_cut<HALF>(g, w, winf, pf, k, x, self, rel_hi, hy, hz, batches);
+        else
+            stencil_ranges<HALF>(g, w, k, x, self, batches);
         list_finish(c, ck, row, N, maxn, HALF ? 0u : (uint32_t)(kWinMax * esz));
         if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
         cmax = max(cmax, c);

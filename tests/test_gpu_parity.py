@@ -84,6 +84,11 @@ def test_fcc_lattice(orc, prec, cont):
 
 @pytest.mark.parametrize("csf", [1.0, 0.5])
 def test_cell_contents_bit_exact(orc, csf):
+    """Every cell holds exactly the oracle's particles (the counting sort),
+    and inside a cell they are ordered by their staged x coordinate
+    floor(x 2^32 / L_x), then by id: the order the Verlet-list build relies
+    on when it bisects a stencil row by x.  (The oracle orders a cell by id;
+    the paper leaves the order inside a cell open.)"""
     pos, box = _jittered((7, 6, 9), 3)
     n = pos.shape[1]
     cfg = make_config(n, box, container=0, csf=csf)
@@ -91,9 +96,14 @@ def test_cell_contents_bit_exact(orc, csf):
     s.build()
     nc = orc.cell_dims(box, csf * 2.8)
     cell_of, order, start = orc.cells(pos, box, nc)
-    assert np.array_equal(s.ids_np(), order)
+    ids = s.ids_np()
+    qx = np.floor(np.clip(pos[0] * (4294967296.0 / box[0]), 0.0, 4294967295.0))
+    for c in range(int(np.prod(nc))):
+        got = ids[start[c]:start[c + 1]]
+        assert np.array_equal(np.sort(got), np.sort(order[start[c]:start[c + 1]])), c
+        assert np.array_equal(np.lexsort((got, qx[got])), np.arange(len(got))), c
     # positions were permuted, not altered
-    assert np.array_equal(s.pos.cpu().numpy(), pos[:, order])
+    assert np.array_equal(s.pos.cpu().numpy(), pos[:, ids])
 
 
 # ---------------------------------------------------------------- forces
