@@ -122,8 +122,11 @@ typedef struct md_config {
     int32_t tune_skin;     /* 1: the tuning space also holds Verlet lists
                               (gather-only, CSF 1) at 2/3, 4/3 and 5/3 of the
                               skin, each with its rebuild interval derived
-                              from the motion (a joint skin / R search); 0
-                              (default): the skin stays fixed               */
+                              from the motion (a joint skin / R search);
+                              under MD_TUNE_EXPERT and MD_TUNE_RF a named
+                              structure is trialled at every skin the space
+                              holds for it; 0 (default): the skin stays
+                              fixed                                         */
     int32_t tune_first;    /* steps (counted over the handle's md_step calls)
                               before the first tuning phase, >= 0; 0: the
                               first step.  Later phases follow every

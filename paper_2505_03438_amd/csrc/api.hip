@@ -1606,6 +1606,12 @@ static bool same_structure(const md_config &a, const md_config &b)
     return a.container == b.container && a.newton3 == b.newton3 && a.csf == b.csf && a.skin == b.skin;
 }
 
+// Whether two configurations differ at most in the skin.
+static bool same_method(const md_config &a, const md_config &b)
+{
+    return a.container == b.container && a.newton3 == b.newton3 && a.csf == b.csf;
+}
+
 // Switch the handle to configuration nc (same particles, box, cutoffs,
 // precision); the structures are rebuilt at the next step.
 int apply_config(md_handle *h, const md_config &nc)
@@ -1652,10 +1658,34 @@ int run_tuning_phase(md_handle *h, const StepCtx &c, int s0, int *next)
         // positions and names the one configuration to run
         double st[8];
         if ((rc0 = live_stats(h, c.pos, st, c.s, true))) return rc0;
-        int pick = rf_predict(st, t->n());
+        // the forest's classes are configurations of the FP32 space without
+        // skin variants: map each by its structure (at the base skin)
+        md_config cb = h->base;
+        cb.precision = MD_FP32;
+        cb.tune_skin = 0;
+        std::vector<md_config> canon;
+        tuning_space(cb, canon);
+        int pick = rf_predict_mapped(st, [&](int k) {
+            if (k < 0 || k >= (int)canon.size()) return -1;
+            for (int j = 0; j < (int)h->space.size(); j++)
+                if (same_method(h->space[j], canon[k]) && h->space[j].skin == h->base.skin) return j;
+            return -1;
+        });
         std::vector<double> suit(t->n(), 0.0);
         if (pick >= 0) suit[pick] = 1.0;
         t->set_suitability(suit);
+    }
+    if ((h->base.autotune == MD_TUNE_EXPERT || h->base.autotune == MD_TUNE_RF) && h->base.tune_skin) {
+        // the rules and the forest name structures; with the skin tuned, a
+        // named structure's other skins are trialled beside it (the skin is a
+        // parameter measured per phase, like the rebuild interval)
+        std::vector<double> suit = t->suitability();
+        std::vector<double> wide = suit;
+        int m = (int)h->space.size();
+        for (int a = 0; a < m && a < (int)suit.size(); a++)
+            for (int b = 0; b < m && b < (int)suit.size(); b++)
+                if (a != b && same_method(h->space[a], h->space[b])) wide[b] = std::max(wide[b], suit[a]);
+        t->set_suitability(wide);
     }
     {
         std::vector<int> plan;

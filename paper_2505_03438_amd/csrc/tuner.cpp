@@ -277,6 +277,11 @@ const std::vector<md_fuzzy_rule> &builtin_rules()
 
 int rf_predict(const double *stats, int n_configs)
 {
+    return rf_predict_mapped(stats, [n_configs](int k) { return k < n_configs ? k : -1; });
+}
+
+int rf_predict_mapped(const double *stats, const std::function<int(int)> &map)
+{
     double acc[rf::kClasses] = {};
     for (int t = 0; t < rf::kTrees; t++) {
         int k = rf::kRoot[t];
@@ -294,10 +299,10 @@ int rf_predict(const double *stats, int n_configs)
     int best = -1;
     for (int c = 0; c < rf::kClasses; c++) {
         acc[c] /= (double)rf::kTrees;
-        if (rf::kConfig[c] >= n_configs) continue;
+        if (map(rf::kConfig[c]) < 0) continue;
         if (best < 0 || acc[c] > acc[best]) best = c;
     }
-    return best < 0 ? -1 : rf::kConfig[best];
+    return best < 0 ? -1 : map(rf::kConfig[best]);
 }
 
 void tuning_space(const md_config &base, std::vector<md_config> &space)

@@ -6,6 +6,7 @@
 #include <math.h>
 
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "mdlj.h"
@@ -24,6 +25,7 @@ public:
     // Expert and Random Forest strategies: the suitability of each
     // configuration for the next phase (all 0: trial everything).
     void set_suitability(const std::vector<double> &s) { suit_ = s; }
+    const std::vector<double> &suitability() const { return suit_; }
     // Score of a trialled configuration (lower is better).
     bool report(int config, double score);
     // Finish the phase; returns the chosen configuration or -1 if a trialled
@@ -65,6 +67,9 @@ void expert_suitability(const md_fuzzy_rule *rules, int n_rules, int n_configs, 
 // Random Forest: the configuration (index below n_configs) the forest of
 // rf_model.h predicts for the live statistics stats[8], or -1.
 int rf_predict(const double *stats, int n_configs);
+// The same with the forest's classes (indices of the FP32 tuning space
+// without skin variants) mapped to another space by map (-1: not in it).
+int rf_predict_mapped(const double *stats, const std::function<int(int)> &map);
 // The built-in rules (written from Full Search scores on MI355X).
 const std::vector<md_fuzzy_rule> &builtin_rules();
 // Whether a rule set reads statistics that need the bin histogram (relative

@@ -978,7 +978,8 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
 // Adjoint of the forces (the differentiable extension) over the gather
 // windows, FP32 pairs: each thread gathers its particle's row
 //   dL/dx_i = sum_j J_ij (g_i - g_j),  J = phi I + 2 (dphi/dr2) d d^T,
-// from its stencil ranges (the cutoff prefilter, then the pair terms for the
+// from its stencil ranges (cut by x where the box allows it, as in the
+// linked-cell force; the cutoff prefilter, then the pair terms for the
 // survivors only, guard-band pairs decided from the FP64 positions; g_j read
 // from global memory).  The pair parameters are picked per pair by the
 // partner's type alone (this particle's type fixes the rest).  The parameter
@@ -1000,6 +1001,9 @@ __global__ __launch_bounds__(256) void k_adjw_f32(
     __shared__ double sh[8][256 / 64];
     float hmax = 0.f;
     for (int k = 0; k < NT * NT; k++) hmax = fmaxf(hmax, tabp->rc2_hi[k]);
+    // stencil rows cut by x as in the linked-cell force (stencil_ranges_drift)
+    const float drift = sqrtf(g.disp2);
+    const bool cut = can_cut(g, g.reach[0]) && drift < 1.0e30f;
     const float uf = (float)(g.L[0] / 4294967296.0);
     double gp[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // eps_ab[4], sig_ab[4]
     size_t N = (size_t)n;
@@ -1031,7 +1035,7 @@ __global__ __launch_bounds__(256) void k_adjw_f32(
             }
             // parameter terms per partner type (FP64)
             double ge0 = 0.0, ge1 = 0.0, gs0 = 0.0, gs1 = 0.0;
-            stencil_ranges<false>(g, w, k, x, self, [&](int b, int en) {
+            auto batches = [&](int b, int en) {
                 // global index of window position p: the range lies in one
                 // row, so in its first piece or the one after it
                 int k0 = piece_from(w, 0, b);
@@ -1081,7 +1085,11 @@ __global__ __launch_bounds__(256) void k_adjw_f32(
                         gs1 += t1 ? ds : 0.0;
                     }
                 }
-            });
+            };
+            if (cut)
+                stencil_ranges_drift<NT>(g, w, win, pi, k, x, hmax, drift, batches);
+            else
+                stencil_ranges<false>(g, w, k, x, self, batches);
             gp[ti * NT] += ge0;
             gp[4 + ti * NT] += gs0;
             if (NT > 1) {

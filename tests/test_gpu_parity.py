@@ -957,6 +957,48 @@ def test_skin_tuning_fp64_trajectory(orc):
     s.h.close()
 
 
+@pytest.mark.parametrize("strategy", ["forest", "expert"])
+def test_named_structure_trials_its_skins(orc, strategy):
+    """With the skin tuned, the structure the forest (or the rules) names is
+    trialled at every skin of the space: Verlet lists at 0.3 and at 0.2, 0.4
+    and 0.5 in each phase, nothing else for the forest; the trajectory still
+    equals the oracle's."""
+    import torch
+    d = W.plain_fcc_864()
+    nsteps = 120
+    p1, v1, _, log0 = orc.velocity_verlet(d["pos"], d["vel"], d["box"], orc.single(), 0.005, nsteps)
+    cfg = make_config(864, d["box"], container=0, precision=1, R=10)
+    cfg.autotune = M.MD_TUNE_RF if strategy == "forest" else M.MD_TUNE_EXPERT
+    cfg.tune_skin = 1
+    cfg.tune_interval = 60
+    cfg.tune_trial_steps = 3
+    cfg.total_steps_hint = nsteps
+    s = DeviceSystem(cfg, d["pos"], d["vel"])
+    s.build()
+    s.forces(energy=False)
+    log = torch.zeros((nsteps, 4), dtype=torch.float64, device="cuda")
+    M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, nsteps, 1, log)
+    torch.cuda.synchronize()
+    log = log.cpu().numpy()
+    cnt = M.md_get_counters(s.h)
+    scores, cfgs = M.md_get_trial_scores(s.h)
+    vl = [k for k, c in enumerate(cfgs) if int(c.container) == M.MD_CONTAINER_VL and int(c.newton3) == 0]
+    assert len(vl) == 4
+    assert cnt["tuning_phases"] == 2
+    assert all(np.isfinite(scores[k]) for k in vl)
+    if strategy == "forest":
+        assert cnt["trials"] == 8
+        assert all(np.isnan(scores[k]) for k in range(len(cfgs)) if k not in vl)
+    assert cnt["config_index"] in vl
+    assert np.array_equal(log[:, 3], log0[:, 3])
+    for k in (0, 1, 2):
+        assert np.abs(log[:, k] - log0[:, k]).max() <= 1e-10 * np.abs(log0[:, k]).max()
+    dx = s.by_id(s.pos) - p1
+    dx -= d["box"][:, None] * np.rint(dx / d["box"][:, None])
+    assert np.abs(dx).max() < 1e-9
+    s.h.close()
+
+
 def test_random_forest_strategy_fp64_trajectory(orc):
     """Random Forest strategy: each phase reads the live statistics, the
     forest names one configuration, and that one alone is trialled and kept;
