@@ -365,7 +365,9 @@ int md_expert_suitability(const md_fuzzy_rule *rules, int32_t n_rules,
  * statistics stats (HOST double[8], md_live_stats order): the class with the
  * largest mean leaf fraction over the trees, features compared in single
  * precision, ties to the first class, among the classes below n_configs.
- * A tuning phase under MD_TUNE_RF trials that configuration alone.
+ * A tuning phase under MD_TUNE_RF trials that configuration alone (with
+ * tune_skin, at every skin the space holds for it); the handle maps the
+ * class to its own space by structure (container, CSF, N3L).
  * MD_ERR_INVALID_ARG for a NaN statistic or if no class fits n_configs. */
 int md_rf_predict(const double *stats, int32_t n_configs);
 
