@@ -660,6 +660,60 @@ def test_adjoint_matches_oracle(orc, prec, cont):
     assert rel_l2(glj.cpu().numpy(), gt) <= tol_t
 
 
+@pytest.mark.parametrize("cont", [(0, 0, 1.0), (1, 0, 1.0)], ids=["lc", "vl"])
+def test_forces_and_adjoint_between_builds(orc, cont):
+    """Between builds the particles move by up to half the skin, while the
+    stencil rows of the linked-cell force and of the adjoint (ordered by x
+    when the cells were built) are cut by x with that motion as margin.  A hot
+    binary mixture (T = 3, five cells per dimension, so the rows are cut) is
+    stepped one step per call: the FP32 forces after every step, and the
+    adjoint at the end (its structure built steps earlier), match the oracle
+    at the current positions."""
+    import torch
+    d = W.binary_mixture(ncell=10, seed=5, T=3.0)
+    pos, vel, box, types = d["pos"], d["vel"], d["box"], d["types"]
+    n = pos.shape[1]
+    theta0 = np.array(d["eps"] + d["sig"])
+    e0, s0 = orc.mix(d["eps"], d["sig"])
+    rc2 = (2.5 * s0) ** 2
+    assert int(box[0] // 2.8) >= 5
+    cfg = make_config(n, box, container=cont[0], newton3=cont[1], csf=cont[2], n_types=2, rc2=rc2, R=8)
+    s = DeviceSystem(cfg, pos, vel, types=types, eps=d["eps"], sig=d["sig"])
+    s.build()
+    s.forces(energy=False)
+    log = torch.zeros((1, 4), dtype=torch.float64, device="cuda")
+    moved = 0.0
+    for step in range(12):
+        M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, 1, 1, log)
+        torch.cuda.synchronize()
+        p = s.by_id(s.pos)
+        _, F0, _, _ = orc.force_matching(p, box, types, theta0, rc2, np.zeros((3, n)))
+        assert_forces(s.by_id(s.force), F0, False, what=step)
+        dp = p - pos
+        dp -= box[:, None] * np.rint(dp / box[:, None])
+        moved = max(moved, float(np.sqrt((dp ** 2).sum(axis=0)).max()))
+    cnt = M.md_get_counters(s.h)
+    assert cnt["rebuilds"] < 13  # the structure was reused between builds
+    assert moved > 0.15  # the run went past half the skin: the skin check rebuilt it
+    # the adjoint at the final positions, on the structure as it stands
+    p = s.by_id(s.pos)
+    _, target, _, _ = orc.force_matching(p, box, types, theta0, rc2, np.zeros((3, n)))
+    theta = W.perturb_params(theta0, seed=2)
+    _, F, gx, gt = orc.force_matching(p, box, types, theta, rc2, target)
+    s.lj.copy_(torch.tensor(theta, dtype=torch.float64))
+    s.forces(energy=False)
+    assert_forces(s.by_id(s.force), F, False, what="perturbed")
+    ids = s.ids_np()
+    g = ((2.0 / (3 * n)) * (s.force.to(torch.float64) - torch.tensor(target[:, ids], device="cuda")))
+    g = g.to(s.h.real).contiguous()
+    gpos = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+    glj = torch.zeros(4, dtype=torch.float64, device="cuda")
+    M.md_forces_backward(s.h, s.pos, s.type, s.lj, g, gpos, glj)
+    torch.cuda.synchronize()
+    assert rel_l2(s.by_id(gpos), gx) <= 1e-4
+    assert rel_l2(glj.cpu().numpy(), gt) <= 1e-5
+
+
 # ---------------------------------------------------------------- full-size fluid
 
 def test_fluid_1m_full_size(orc):
