@@ -130,7 +130,7 @@ def space_size(kind):
     at each skin), an upper bound for the Expert rules."""
     if kind.startswith("forest"):
         return 4 if kind.endswith("+skin") else 1
-    return 12 if kind.endswith("+skin") else 9
+    return 13 if kind.endswith("+skin") else 10
 
 
 def make_cfg(M, n, box, kind, steps, warmup=0):
@@ -147,7 +147,8 @@ def make_cfg(M, n, box, kind, steps, warmup=0):
         c.newton3 = M.MD_N3L_OFF
         c.rebuild_interval = int(kind.split(":")[1]) if ":" in kind else 10
     elif kind.startswith("fixed:"):
-        # fixed:<container>:<csf>:<n3l>:<R>[:<skin>], e.g. fixed:vl:1:0:5
+        # fixed:<container>:<csf>:<n3l>:<R>[:<skin>], e.g. fixed:vl:1:0:5 (n3l 2: the C08
+        # traversal of linked cells)
         parts = kind.split(":")
         _, cont, csf, n3, R = parts[:5]
         if len(parts) > 5:
@@ -289,7 +290,7 @@ def run(M, d, kind, steps, warmup, repeats=1, probe_steps=50, keep_state=False):
         sc, cf = M.md_get_trial_scores(h)
         trial = [{"container": int(k.container), "newton3": int(k.newton3), "csf": float(k.csf),
                   "skin": float(k.skin), "score_ms": (None if v != v else float(v))} for v, k in zip(sc, cf)]
-        choices = ["%s%s csf %g skin %g" % (names[int(cf[c].container)], " n3l" if int(cf[c].newton3) else "",
+        choices = ["%s%s csf %g skin %g" % (names[int(cf[c].container)], ("", " n3l", " c08")[int(cf[c].newton3)],
                                             float(cf[c].csf), float(cf[c].skin))
                    for c in M.md_get_phase_choices(h)]
     final = None

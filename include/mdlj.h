@@ -72,6 +72,11 @@ extern "C" {
 /* traversal (Sec. 2.2.2, Table 1: N3L column) */
 #define MD_N3L_OFF 0 /* each pair evaluated from both sides, gather only  */
 #define MD_N3L_ON 1  /* each pair once, j-side scattered with atomics     */
+#define MD_N3L_C08 2 /* each pair once through the C08 colouring of cubes
+                        of cells (Table 1's C08): linked cells only, FP32,
+                        CSF 1, at least three cells per dimension; both
+                        sides summed in the workgroup, no atomics on the
+                        forces                                             */
 
 /* autotuning strategy (Sec. 2.2.5 Full Search, Sec. 5.1 Predictive) */
 #define MD_TUNE_OFF 0
@@ -110,7 +115,7 @@ typedef struct md_config {
     double csf;            /* cell size factor in (0, 1]: cell side >=
                               csf (r_c,max + skin), stretched to fit the box  */
     int32_t container;     /* MD_CONTAINER_*                                   */
-    int32_t newton3;       /* MD_N3L_OFF / MD_N3L_ON                           */
+    int32_t newton3;       /* MD_N3L_OFF / MD_N3L_ON / MD_N3L_C08              */
     int32_t rebuild_interval; /* R >= 1: rebuild cells and lists every R steps */
     int32_t max_neighbors; /* list row capacity: particles per Verlet row, or
                               j-clusters per i-cluster for cluster lists;

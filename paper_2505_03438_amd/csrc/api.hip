@@ -51,10 +51,11 @@ int make_geom(const md_config &c, double csf, Geom &g)
         double ndd = floor(c.box[d] / side_min);
         if (ndd > 4096.0) ndd = 4096.0;
         int nd = ndd < 1.0 ? 1 : (int)ndd;
-        // Verlet list cells: an even count where there are more than three
-        // (slightly larger cells), so that the C08 colouring needs two
-        // colours per dimension, not three
-        if (c.container == MD_CONTAINER_VLC && nd > 3 && nd % 2) nd--;
+        // the C08 colouring (Verlet list cells, linked cells with
+        // MD_N3L_C08): an even count where there are more than three
+        // (slightly larger cells), so that it needs two colours per
+        // dimension, not three
+        if ((c.container == MD_CONTAINER_VLC || c.newton3 == MD_N3L_C08) && nd > 3 && nd % 2) nd--;
         g.nc[d] = nd;
         g.L[d] = c.box[d];
         g.inv_w[d] = (double)nd / c.box[d];
@@ -214,6 +215,13 @@ static int ensure_cells(md_handle *h, const Geom &g)
 // Containers that keep neighbour lists (Verlet lists, cluster-pair lists).
 static bool has_lists(const md_config &c) { return c.container != MD_CONTAINER_LC; }
 
+// Configurations that need at least three cells per dimension (their
+// traversals pair each cell with distinct neighbours).
+static bool needs_three_cells(const md_config &c)
+{
+    return c.container == MD_CONTAINER_PVL || c.container == MD_CONTAINER_VLC || c.newton3 == MD_N3L_C08;
+}
+
 static int ensure_list(md_handle *h, int64_t maxn)
 {
     if (maxn <= h->b.nbr_cap && h->b.nbr) return MD_OK;
@@ -251,7 +259,10 @@ static int validate_config(const md_config *c)
     if (c->container == MD_CONTAINER_PVL &&
         (c->newton3 != MD_N3L_OFF || c->precision != MD_FP32 || c->csf != 1.0))
         return fail(MD_ERR_INVALID_ARG, "pairwise Verlet lists are FP32, gather-only, on CSF-1 cells");
-    if (c->newton3 != MD_N3L_OFF && c->newton3 != MD_N3L_ON) return fail(MD_ERR_INVALID_ARG, "bad newton3");
+    if (c->newton3 != MD_N3L_OFF && c->newton3 != MD_N3L_ON && c->newton3 != MD_N3L_C08)
+        return fail(MD_ERR_INVALID_ARG, "bad newton3");
+    if (c->newton3 == MD_N3L_C08 && (c->container != MD_CONTAINER_LC || c->precision != MD_FP32 || c->csf != 1.0))
+        return fail(MD_ERR_INVALID_ARG, "the C08 traversal is for FP32 linked cells on CSF-1 cells");
     if (c->container == MD_CONTAINER_CL && c->newton3 != MD_N3L_OFF)
         return fail(MD_ERR_INVALID_ARG, "cluster lists are gather-only (newton3 = MD_N3L_OFF)");
     if (c->container == MD_CONTAINER_CL && c->precision != MD_FP32)
@@ -303,9 +314,9 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
     if (rc) return rc;
     Geom g;
     if ((rc = make_geom(*cfg, cfg->csf, g))) return rc;
-    if ((cfg->container == MD_CONTAINER_PVL || cfg->container == MD_CONTAINER_VLC) && !pvl_geometry_ok(g))
-        return fail(MD_ERR_INVALID_ARG,
-                    "pairwise lists and Verlet list cells need at least three cells of side r_c + skin per dimension");
+    if (needs_three_cells(*cfg) && !pvl_geometry_ok(g))
+        return fail(MD_ERR_INVALID_ARG, "pairwise lists, Verlet list cells and the C08 traversal need at least "
+                                        "three cells of side r_c + skin per dimension");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MD_ERR_NO_DEVICE, "no HIP device");
     md_handle *h = new md_handle();
@@ -364,8 +375,7 @@ extern "C" int md_create(const md_config *cfg, md_handle **out)
         for (const md_config &k : h->space) {
             Geom gk;
             std::string keep_err = g_err;
-            if (make_geom(k, k.csf, gk) == MD_OK &&
-                ((k.container != MD_CONTAINER_PVL && k.container != MD_CONTAINER_VLC) || pvl_geometry_ok(gk)))
+            if (make_geom(k, k.csf, gk) == MD_OK && (!needs_three_cells(k) || pvl_geometry_ok(gk)))
                 fit.push_back(k);
             g_err = keep_err;
         }
@@ -411,6 +421,7 @@ static int check_handle(md_handle *h)
 static bool use_window(const md_config &c, const Geom &g);
 static bool use_window(const md_handle *h) { return !h->no_window && use_window(h->cfg, h->g); }
 static int build_blocks(md_handle *h, hipStream_t s);
+static int ensure_cube_part(md_handle *h);
 
 // Where the particle arrays of a time-stepping call currently live.  Inside
 // md_step a cell build does not copy the reordered arrays back: the current
@@ -481,6 +492,7 @@ static int build_cells_impl(md_handle *h, double *pos, void *vel, void *force, i
     h->age = 0;
     h->built = true;
     h->lists = false;
+    if (h->cfg.newton3 == MD_N3L_C08 && (rc = ensure_cube_part(h))) return rc;
     if (!use_window(h)) return MD_OK;
     if ((rc = build_blocks(h, s))) return rc;
     if (!check_window) return MD_OK;
@@ -543,7 +555,7 @@ static int ensure_clusters(md_handle *h)
 static bool use_window(const md_config &c, const Geom &g)
 {
     return (c.container == MD_CONTAINER_VL || c.container == MD_CONTAINER_LC) && c.precision == MD_FP32 &&
-           window_geometry_ok(g, c.newton3 == MD_N3L_ON);
+           c.newton3 != MD_N3L_C08 && window_geometry_ok(g, c.newton3 == MD_N3L_ON);
 }
 
 static int ensure_window(md_handle *h, int64_t maxn)
@@ -620,6 +632,20 @@ static int ensure_pvl(md_handle *h)
     return MD_OK;
 }
 
+// Per-cube energy partials [ncell][4] of the C08 traversals.
+static int ensure_cube_part(md_handle *h)
+{
+    Buffers &b = h->b;
+    if ((int64_t)h->g.ncell <= b.vlc_part_cap) return MD_OK;
+    if (b.vlc_part) (void)hipFree(b.vlc_part);
+    b.vlc_part = nullptr;
+    b.vlc_part_cap = 0;
+    int rc = dalloc(&b.vlc_part, (size_t)4 * h->g.ncell);
+    if (rc) return rc;
+    b.vlc_part_cap = h->g.ncell;
+    return MD_OK;
+}
+
 // Verlet list cells: entries [maxn][n], segment ends [4][n], per-cube
 // energy partials [ncell][4].
 static int ensure_vlc(md_handle *h, int32_t maxn)
@@ -637,14 +663,7 @@ static int ensure_vlc(md_handle *h, int32_t maxn)
         b.vlc_cap = n;
         b.vlc_maxn = maxn;
     }
-    if ((int64_t)h->g.ncell > b.vlc_part_cap) {
-        if (b.vlc_part) (void)hipFree(b.vlc_part);
-        b.vlc_part = nullptr;
-        b.vlc_part_cap = 0;
-        if ((rc = dalloc(&b.vlc_part, (size_t)4 * h->g.ncell))) return rc;
-        b.vlc_part_cap = h->g.ncell;
-    }
-    return MD_OK;
+    return ensure_cube_part(h);
 }
 
 static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
@@ -764,7 +783,7 @@ static int forces_impl(md_handle *h, const double *pos, const int32_t *type, voi
 {
     ForceArgs a = force_args(h, pos, type, force, energy);
     if (force_blocks(a) > kMaxPartials) return fail(MD_ERR_INVALID_ARG, "too many particles for the reduction");
-    if (h->cfg.newton3 == MD_N3L_ON) launch_zero(force, 3 * h->n * (int64_t)real_size(h->cfg), s);
+    if (h->cfg.newton3 != MD_N3L_OFF) launch_zero(force, 3 * h->n * (int64_t)real_size(h->cfg), s);
     launch_force(a, h->g, s);
     if (energy) {
         h->energy_gather = h->cfg.newton3 == MD_N3L_OFF;

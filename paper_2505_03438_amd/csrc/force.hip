@@ -352,7 +352,7 @@ int force_blocks(const ForceArgs &a)
 {
     if (a.n <= 0) return 0;
     if (a.container == MD_CONTAINER_CL) return cluster_force_blocks();
-    if (a.container == MD_CONTAINER_VLC) return a.vlc_blocks;
+    if (a.container == MD_CONTAINER_VLC || a.newton3 == MD_N3L_C08) return a.vlc_blocks;
     if (a.window) return window_force_blocks();
     return (a.n + kBlock - 1) / kBlock;
 }
@@ -406,6 +406,10 @@ void launch_force(const ForceArgs &a, const Geom &g, hipStream_t s)
     }
     if (a.container == MD_CONTAINER_VLC) {
         launch_vlc_force(a, g, s);
+        return;
+    }
+    if (a.newton3 == MD_N3L_C08) {
+        launch_lc08_force(a, g, s);
         return;
     }
     if (a.window) {

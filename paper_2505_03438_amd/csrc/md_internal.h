@@ -300,6 +300,7 @@ void launch_vlc_build(int n, const int4 *st, const int32_t *cs, const int32_t *c
                       const Geom &g, uint16_t *nbr, uint16_t *seg, int32_t *cnt, int maxn, int32_t *flags,
                       hipStream_t s);
 void launch_vlc_force(const ForceArgs &a, const Geom &g, hipStream_t s);
+void launch_lc08_force(const ForceArgs &a, const Geom &g, hipStream_t s);
 int vlc_force_blocks(const Geom &g);
 void launch_vlc_rows(int n, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, const uint16_t *nbr,
                      const uint16_t *seg, int maxr, int32_t *counts, int32_t *rows, hipStream_t s);

@@ -348,6 +348,14 @@ void tuning_space(const md_config &base, std::vector<md_config> &space)
         c.newton3 = MD_N3L_ON;
         space.push_back(c);
     }
+    // linked cells with the C08 colouring (FP32, CSF-1 cells; left out like
+    // pairwise lists on small boxes)
+    if (base.precision == MD_FP32) {
+        c.container = MD_CONTAINER_LC;
+        c.csf = 1.0;
+        c.newton3 = MD_N3L_C08;
+        space.push_back(c);
+    }
     // joint skin / rebuild-interval search: Verlet lists at other skins (a
     // larger skin buys a longer interval with longer lists)
     if (base.tune_skin && base.skin > 0.0)

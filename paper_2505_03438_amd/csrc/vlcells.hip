@@ -264,6 +264,173 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
     }
 }
 
+// ------------------------------------------------------------------ linked cells, C08 traversal
+
+// Linked cells traversed with the C08 colouring (Table 1), no lists: the
+// base step of base cell b covers the fourteen cell pairs of the cube (see
+// the top of this file), so a colour's cubes run concurrently with both sides
+// of every pair summed in the workgroup's LDS.  The work of a cube is spread
+// over its threads as tasks (cell pair, particle of the pair's first cell):
+// a task tests the particles of the pair's second cell (those after it when
+// the base cell pairs with itself) 32 at a time against the largest upper
+// edge of the cutoffs' guard bands, then evaluates the pairs that pass
+// (guard-band pairs decided from the FP64 positions); the i side is summed
+// in registers and added once per task, the j side goes to the LDS
+// accumulators.  Cell pair p: first cube cell A, second B (the partners of
+// the four roles in order).
+constexpr int kC08Pairs = 14;
+
+__device__ __forceinline__ void c08_pair(int p, int &A, int &B)
+{
+    if (p < 8) {
+        A = 0;
+        B = vlc_partner(0, p);
+    } else if (p < 11) {
+        A = 1;
+        B = vlc_partner(1, p - 8);
+    } else if (p < 13) {
+        A = 2;
+        B = vlc_partner(2, p - 11);
+    } else {
+        A = 4;
+        B = vlc_partner(3, 0);
+    }
+}
+
+template <int NT, bool ISO, bool ENERGY>
+__global__ __launch_bounds__(kVlcThreads) void k_lc08_f32(VlcColour col, int n, const int4 *__restrict__ st,
+                                                          const int32_t *__restrict__ cs,
+                                                          const PairTab *__restrict__ tabp, Geom g,
+                                                          const double *__restrict__ pos, float *__restrict__ F,
+                                                          double *__restrict__ cube_part)
+{
+    __shared__ int4 wp[kVlcMax];
+    __shared__ unsigned long long ax[kVlcMax], ay[kVlcMax], az[kVlcMax];
+    __shared__ int cst[8], base[9], tpre[kC08Pairs + 1];
+    __shared__ double sh[4 * kVlcThreads / 64];
+    int b = blockIdx.x;
+    int ix = b % col.cnt[0], t = b / col.cnt[0];
+    int iy = t % col.cnt[1], iz = t / col.cnt[1];
+    int bx = vlc_colour_coord(col.k[0], ix, g.nc[0]), by = vlc_colour_coord(col.k[1], iy, g.nc[1]),
+        bz = vlc_colour_coord(col.k[2], iz, g.nc[2]);
+    if (threadIdx.x < 8) {
+        int ex, ey, ez;
+        vlc_e(threadIdx.x, ex, ey, ez);
+        int c = vlc_cell(g, bx + ex, by + ey, bz + ez);
+        cst[threadIdx.x] = cs[c];
+        base[threadIdx.x + 1] = cs[c + 1] - cs[c];  // counts for now
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        base[0] = 0;
+        for (int e = 0; e < 8; e++) base[e + 1] += base[e];
+        tpre[0] = 0;
+        for (int p = 0; p < kC08Pairs; p++) {
+            int A, B;
+            c08_pair(p, A, B);
+            tpre[p + 1] = tpre[p] + (base[A + 1] - base[A]);
+        }
+    }
+    __syncthreads();
+    const int M = base[8];
+    const bool lds = M <= kVlcMax;
+    TabF<NT> tb;
+    tb.load(tabp);
+    float hmax = tb.hi[0];
+    for (int k = 1; k < NT * NT; k++) hmax = fmaxf(hmax, tb.hi[k]);
+    size_t N = (size_t)n;
+    if (lds) {
+        int e = 0;
+        for (int p = threadIdx.x; p < M; p += kVlcThreads) {
+            while (base[e + 1] <= p) e++;
+            wp[p] = st[cst[e] + (p - base[e])];
+            ax[p] = ay[p] = az[p] = 0ull;
+        }
+    }
+    __syncthreads();
+    float eu = 0.f, ew = 0.f;
+    int np = 0;
+    const int T = tpre[kC08Pairs];
+    for (int task = threadIdx.x; task < T; task += kVlcThreads) {
+        int p = 0;
+        while (tpre[p + 1] <= task) p++;
+        int A, B;
+        c08_pair(p, A, B);
+        int a = task - tpre[p];
+        int li = base[A] + a, i = cst[A] + a;
+        int4 pi = lds ? wp[li] : st[i];
+        int jb = A == B ? li + 1 : base[B], je = base[B + 1];  // candidates, cube positions
+        int joff = cst[B] - base[B];                          // cube position -> particle index
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        for (int q0 = jb; q0 < je; q0 += 32) {
+            int m = min(32, je - q0);
+            uint32_t mask = 0;
+            for (int u = 0; u < m; u++) {
+                int4 pj = lds ? wp[q0 + u] : st[q0 + u + joff];
+                float dx, dy, dz;
+                staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+                float r2 = dx * dx + dy * dy + dz * dz;
+                mask |= (r2 < hmax ? 1u : 0u) << u;
+            }
+            while (mask) {
+                int u = __builtin_ctz(mask);
+                mask &= mask - 1;
+                int lj = q0 + u, j = lj + joff;
+                int4 pj = lds ? wp[lj] : st[j];
+                float dx, dy, dz;
+                staged_delta<ISO>(pi, pj, g, dx, dy, dz);
+                float r2 = dx * dx + dy * dy + dz * dz;
+                int ab = NT == 1 ? 0 : pi.w * NT + pj.w;
+                bool in = within(r2, tb.pick(tb.lo, ab), tb.pick(tb.hi, ab), tb.pickd(tb.rc2, ab), pos, n, i, j, g);
+                if (!in) continue;
+                float phi = lj_f32<NT, ENERGY>(r2, ab, true, tb, eu, ew, np);
+                float px = phi * dx, py = phi * dy, pz = phi * dz;
+                fx += px;
+                fy += py;
+                fz += pz;
+                if (lds) {
+                    atomicAdd(&ax[lj], to_fix(-px));
+                    atomicAdd(&ay[lj], to_fix(-py));
+                    atomicAdd(&az[lj], to_fix(-pz));
+                } else {
+                    atomicAdd(&F[j], -px);
+                    atomicAdd(&F[N + j], -py);
+                    atomicAdd(&F[2 * N + j], -pz);
+                }
+            }
+        }
+        if (lds) {
+            atomicAdd(&ax[li], to_fix(fx));
+            atomicAdd(&ay[li], to_fix(fy));
+            atomicAdd(&az[li], to_fix(fz));
+        } else {
+            atomicAdd(&F[i], fx);
+            atomicAdd(&F[N + i], fy);
+            atomicAdd(&F[2 * N + i], fz);
+        }
+    }
+    __syncthreads();
+    if (lds) {
+        // the cube is this colour's alone: plain read-modify-write
+        int e = 0;
+        for (int p = threadIdx.x; p < M; p += kVlcThreads) {
+            while (base[e + 1] <= p) e++;
+            int j = cst[e] + (p - base[e]);
+            if (ax[p]) F[j] += from_fix(ax[p]);
+            if (ay[p]) F[N + j] += from_fix(ay[p]);
+            if (az[p]) F[2 * N + j] += from_fix(az[p]);
+        }
+    }
+    if (ENERGY) {
+        double v[4] = {(double)eu, (double)ew, (double)np, 0.0};
+        block_sum4_n<kVlcThreads>(v, sh);
+        if (threadIdx.x == 0) {
+            int bc = (bz * g.nc[1] + by) * g.nc[0] + bx;
+            for (int k = 0; k < 4; k++) cube_part[(size_t)bc * 4 + k] = v[k];
+        }
+    }
+}
+
 // Fixed-order sum of the per-cube partials into nb slots of partials.
 __global__ void k_vlc_fold(const double *__restrict__ cube_part, int ncell, int nb, double *__restrict__ partials)
 {
@@ -368,6 +535,35 @@ void launch_vlc_force(const ForceArgs &a, const Geom &g, hipStream_t s)
     } else {
         if (g.iso) a.energy ? launch_vlc_t<2, true, true>(a, g, s) : launch_vlc_t<2, true, false>(a, g, s);
         else a.energy ? launch_vlc_t<2, false, true>(a, g, s) : launch_vlc_t<2, false, false>(a, g, s);
+    }
+}
+
+template <int NT, bool ISO, bool EN>
+static void launch_lc08_t(const ForceArgs &a, const Geom &g, hipStream_t s)
+{
+    VlcColour cols[27];
+    int m = vlc_colours(g, cols);
+    for (int k = 0; k < m; k++) {
+        int grid = cols[k].cnt[0] * cols[k].cnt[1] * cols[k].cnt[2];
+        if (grid <= 0) continue;
+        k_lc08_f32<NT, ISO, EN><<<grid, kVlcThreads, 0, s>>>(cols[k], a.n, a.stage, a.cell_start, a.tab, g, a.pos,
+                                                             (float *)a.force, a.vlc_part);
+    }
+    if (EN) {
+        int nb = vlc_force_blocks(g);
+        k_vlc_fold<<<(nb + kBlock - 1) / kBlock, kBlock, 0, s>>>(a.vlc_part, g.ncell, nb, a.partials);
+    }
+}
+
+void launch_lc08_force(const ForceArgs &a, const Geom &g, hipStream_t s)
+{
+    if (a.n <= 0) return;
+    if (g.nt == 1) {
+        if (g.iso) a.energy ? launch_lc08_t<1, true, true>(a, g, s) : launch_lc08_t<1, true, false>(a, g, s);
+        else a.energy ? launch_lc08_t<1, false, true>(a, g, s) : launch_lc08_t<1, false, false>(a, g, s);
+    } else {
+        if (g.iso) a.energy ? launch_lc08_t<2, true, true>(a, g, s) : launch_lc08_t<2, true, false>(a, g, s);
+        else a.energy ? launch_lc08_t<2, false, true>(a, g, s) : launch_lc08_t<2, false, false>(a, g, s);
     }
 }
 

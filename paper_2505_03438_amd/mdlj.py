@@ -29,6 +29,7 @@ MD_CONTAINER_PVL = 3
 MD_CONTAINER_VLC = 4
 MD_N3L_OFF = 0
 MD_N3L_ON = 1
+MD_N3L_C08 = 2
 MD_TUNE_OFF = 0
 MD_TUNE_FULL = 1
 MD_TUNE_PREDICTIVE = 2

@@ -29,27 +29,34 @@ def _lib():
 FP32_F, FP64_F = 1e-5, 1e-12
 FP32_E, FP64_E = 1e-6, 1e-12
 
+# (container, newton3, csf); newton3 2 is the C08 traversal of linked cells
 CONTAINERS = [(0, 0, 1.0), (0, 1, 1.0), (0, 0, 0.5), (0, 1, 0.5), (1, 0, 1.0), (1, 1, 1.0), (1, 0, 0.5),
-              (1, 1, 0.5), (2, 0, 1.0), (2, 0, 0.5), (3, 0, 1.0), (4, 1, 1.0)]
+              (1, 1, 0.5), (2, 0, 1.0), (2, 0, 0.5), (3, 0, 1.0), (4, 1, 1.0), (0, 2, 1.0)]
 CNAMES = ["lc", "lc-n3l", "lc-csf.5", "lc-n3l-csf.5", "vl", "vl-n3l", "vl-csf.5", "vl-n3l-csf.5", "cl", "cl-csf.5",
-          "pvl", "vlc"]
+          "pvl", "vlc", "lc-c08"]
+
+
+def fp32_only(cont):
+    """Cluster-pair lists, pairwise Verlet lists, Verlet list cells and the
+    C08 traversal run in FP32 only."""
+    return cont[0] in (2, 3, 4) or cont[1] == 2
 
 
 def _fp32_only(cont, prec, box=None):
-    """Cluster-pair lists, pairwise Verlet lists and Verlet list cells run in
-    FP32 only; the last two need three cells of side r_c + skin per
-    dimension."""
-    if cont[0] in (2, 3, 4) and prec == 1:
-        pytest.skip("cluster lists, pairwise lists and list cells are FP32-only")
+    """Skip the FP32-only structures in FP64, and those needing three cells of
+    side r_c + skin per dimension (pairwise lists, list cells, C08) on
+    smaller boxes."""
+    if fp32_only(cont) and prec == 1:
+        pytest.skip("cluster lists, pairwise lists, list cells and the C08 traversal are FP32-only")
     if box is not None and not fits(cont, box):
-        pytest.skip("pairwise lists and list cells need three cells per dimension")
+        pytest.skip("pairwise lists, list cells and the C08 traversal need three cells per dimension")
 
 
 def fits(cont, box, prec=0):
     """Whether container cont runs on this machine and precision."""
-    if cont[0] in (2, 3, 4) and prec == 1:
+    if fp32_only(cont) and prec == 1:
         return False
-    return cont[0] not in (3, 4) or all(int(b // 2.8) >= 3 for b in box)
+    return (cont[0] not in (3, 4) and cont[1] != 2) or all(int(b // 2.8) >= 3 for b in box)
 
 
 def _jittered(ncell, seed, density=0.8, jitter=0.08, shape=None):
@@ -193,7 +200,7 @@ def test_tiny_and_empty_systems(orc):
     for cont in CONTAINERS:
         if not fits(cont, box):
             continue
-        prec = 0 if cont[0] in (2, 3, 4) else 1
+        prec = 0 if fp32_only(cont) else 1
         cfg = make_config(2, box, container=cont[0], newton3=cont[1], csf=cont[2], precision=prec)
         s = DeviceSystem(cfg, pos)
         s.build()
@@ -397,8 +404,8 @@ def test_nve_fp64_trajectory(orc, cont):
     assert np.abs(s.by_id(s.vel) - v1).max() < 1e-9
 
 
-@pytest.mark.parametrize("cont", [(1, 0, 1.0), (2, 0, 1.0), (0, 0, 0.5), (3, 0, 1.0), (4, 1, 1.0)],
-                         ids=["vl", "cl", "lc-csf.5", "pvl", "vlc"])
+@pytest.mark.parametrize("cont", [(1, 0, 1.0), (2, 0, 1.0), (0, 0, 0.5), (3, 0, 1.0), (4, 1, 1.0), (0, 2, 1.0)],
+                         ids=["vl", "cl", "lc-csf.5", "pvl", "vlc", "lc-c08"])
 def test_nve_fp32_energy_conservation(orc, cont):
     s, log = _run_nve(orc, 0, cont, nsteps=400, R=10)
     u_rc = orc.lj(6.25)[1]
@@ -1129,9 +1136,9 @@ def test_expert_rules_rejected_for_untuned_handle(orc):
 
 
 def test_autotuned_fp32_energy_conservation(orc):
-    """FP32 autotuned run over all nine configurations (cluster lists,
-    pairwise lists and list cells included): the total energy stays
-    conserved across configuration switches."""
+    """FP32 autotuned run over all ten configurations (cluster lists,
+    pairwise lists, list cells and the C08 traversal included): the total
+    energy stays conserved across configuration switches."""
     import torch
     d = W.plain_fcc_864()
     nsteps = 400
@@ -1147,7 +1154,7 @@ def test_autotuned_fp32_energy_conservation(orc):
     M.md_step(s.h, s.pos, s.vel, s.force, s.type, s.ids, s.inv_mass, s.lj, 0.005, nsteps, 1, log)
     torch.cuda.synchronize()
     log = log.cpu().numpy()
-    assert M.md_get_counters(s.h)["trials"] >= 18
+    assert M.md_get_counters(s.h)["trials"] >= 20
     u_rc = orc.lj(6.25)[1]
     E = (log[:, 0] - log[:, 3] * u_rc + log[:, 1]) / 864
     assert np.abs(E - E[0]).max() < 5e-3
