@@ -130,7 +130,7 @@ def space_size(kind):
     at each skin), an upper bound for the Expert rules."""
     if kind.startswith("forest"):
         return 4 if kind.endswith("+skin") else 1
-    return 13 if kind.endswith("+skin") else 10
+    return 15 if kind.endswith("+skin") else 12
 
 
 def make_cfg(M, n, box, kind, steps, warmup=0):
@@ -147,12 +147,15 @@ def make_cfg(M, n, box, kind, steps, warmup=0):
         c.newton3 = M.MD_N3L_OFF
         c.rebuild_interval = int(kind.split(":")[1]) if ":" in kind else 10
     elif kind.startswith("fixed:"):
-        # fixed:<container>:<csf>:<n3l>:<R>[:<skin>], e.g. fixed:vl:1:0:5 (n3l 2: the C08
-        # traversal of linked cells)
+        # fixed:<container>:<csf>:<n3l>:<R>[:<skin>[:<layout>]], e.g. fixed:vl:1:0:5 (n3l 2:
+        # the C08 traversal of linked cells; layout 1 or 2: the Verlet-list windows' 16-byte
+        # entries or coordinate planes)
         parts = kind.split(":")
         _, cont, csf, n3, R = parts[:5]
         if len(parts) > 5:
             c.skin = float(parts[5])
+        if len(parts) > 6:
+            c.layout = int(parts[6])
         c.container = {"lc": M.MD_CONTAINER_LC, "vl": M.MD_CONTAINER_VL, "cl": M.MD_CONTAINER_CL,
                        "pvl": M.MD_CONTAINER_PVL, "vlc": M.MD_CONTAINER_VLC}[cont]
         c.csf = float(csf)
@@ -289,9 +292,11 @@ def run(M, d, kind, steps, warmup, repeats=1, probe_steps=50, keep_state=False):
     if cfg.autotune:
         sc, cf = M.md_get_trial_scores(h)
         trial = [{"container": int(k.container), "newton3": int(k.newton3), "csf": float(k.csf),
-                  "skin": float(k.skin), "score_ms": (None if v != v else float(v))} for v, k in zip(sc, cf)]
-        choices = ["%s%s csf %g skin %g" % (names[int(cf[c].container)], ("", " n3l", " c08")[int(cf[c].newton3)],
-                                            float(cf[c].csf), float(cf[c].skin))
+                  "skin": float(k.skin), "layout": int(k.layout), "score_ms": (None if v != v else float(v))}
+                 for v, k in zip(sc, cf)]
+        choices = ["%s%s%s csf %g skin %g" % (names[int(cf[c].container)], ("", " n3l", " c08")[int(cf[c].newton3)],
+                                              ("", " aligned", " soa")[int(cf[c].layout)], float(cf[c].csf),
+                                              float(cf[c].skin))
                    for c in M.md_get_phase_choices(h)]
     final = None
     if keep_state:
@@ -333,7 +338,7 @@ def run(M, d, kind, steps, warmup, repeats=1, probe_steps=50, keep_state=False):
                      "trial_scores": trial} if cfg.autotune else None,
                final_config=dict(container=int(cfg_now.container), newton3=int(cfg_now.newton3),
                                  csf=float(cfg_now.csf), rebuild_interval=int(cfg_now.rebuild_interval),
-                                 skin=float(cfg_now.skin)),
+                                 skin=float(cfg_now.skin), layout=int(cfg_now.layout)),
                energy_per_particle_first_last=[float(E[0] / n), float(E[-1] / n)] if len(E) else None)
     if final is not None:
         res["_final"] = final
@@ -346,7 +351,8 @@ def run(M, d, kind, steps, warmup, repeats=1, probe_steps=50, keep_state=False):
 def fixed_kind(c, R):
     """fixed:... kind of a tuning-space configuration at rebuild interval R."""
     cont = {0: "lc", 1: "vl", 2: "cl", 3: "pvl", 4: "vlc"}[int(c["container"])]
-    return "fixed:%s:%g:%d:%d:%g" % (cont, c["csf"], int(c["newton3"]), int(R), c["skin"])
+    k = "fixed:%s:%g:%d:%d:%g" % (cont, c["csf"], int(c["newton3"]), int(R), c["skin"])
+    return k + (":%d" % c["layout"] if c.get("layout") else "")
 
 
 def oracle_error(M, d, r):
@@ -438,7 +444,11 @@ def force_kernel_name(c, family):
     if c["container"] == 4:
         return "k_vlc_f32"
     if c["container"] == 1:
+        if family == 1 and not c["newton3"] and c.get("layout"):
+            return "k_vlw_f32 (%s windows)" % ("aligned", "coordinate-plane")[c["layout"] - 1]
         return ("k_vlwh_f32" if c["newton3"] else "k_vlw_f32") if family == 1 else "k_vl_f32"
+    if c["newton3"] == 2:
+        return "k_lc08_f32"
     return ("k_lcwh_f32" if c["newton3"] else "k_lcw_f32") if family == 1 else "k_lc_f32"
 
 

@@ -78,6 +78,13 @@ extern "C" {
                         sides summed in the workgroup, no atomics on the
                         forces                                             */
 
+/* data layout (Sec. 2.2.3) of the staged positions in the LDS windows of
+ * the FP32 Verlet-list force (gather-only, one particle type): the list
+ * entries address the window by byte offset */
+#define MD_LAYOUT_PACKED 0  /* 12-byte entries (x, y, z)                      */
+#define MD_LAYOUT_ALIGNED 1 /* 16-byte entries, one 16-byte LDS read each     */
+#define MD_LAYOUT_SOA 2     /* one plane per coordinate, three 4-byte reads   */
+
 /* autotuning strategy (Sec. 2.2.5 Full Search, Sec. 5.1 Predictive) */
 #define MD_TUNE_OFF 0
 #define MD_TUNE_FULL 1
@@ -136,6 +143,9 @@ typedef struct md_config {
                               before the first tuning phase, >= 0; 0: the
                               first step.  Later phases follow every
                               tune_interval steps                           */
+    int32_t layout;        /* MD_LAYOUT_*: MD_LAYOUT_PACKED (default), or for
+                              FP32 Verlet lists, gather-only, one type,
+                              MD_LAYOUT_ALIGNED or MD_LAYOUT_SOA            */
 } md_config;
 
 /* Fill *cfg with defaults for n particles in a cubic box of side L:

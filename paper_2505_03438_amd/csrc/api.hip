@@ -87,6 +87,7 @@ int make_geom(const md_config &c, double csf, Geom &g)
     band = std::max(1, std::min(band, kWinBlkRows));
     band = std::min(band, std::max(1, g.nc[1] - 2 * g.reach[1]));
     g.wband = band;
+    g.layout = c.layout;
     double u = c.box[0] / 4294967296.0;
     g.rl2_lo = (float)(g.rl2 / (u * u) * (1.0 - kBand));
     g.rl2_hi = (float)(g.rl2 / (u * u) * (1.0 + kBand));
@@ -263,6 +264,12 @@ static int validate_config(const md_config *c)
         return fail(MD_ERR_INVALID_ARG, "bad newton3");
     if (c->newton3 == MD_N3L_C08 && (c->container != MD_CONTAINER_LC || c->precision != MD_FP32 || c->csf != 1.0))
         return fail(MD_ERR_INVALID_ARG, "the C08 traversal is for FP32 linked cells on CSF-1 cells");
+    if (c->layout != MD_LAYOUT_PACKED && c->layout != MD_LAYOUT_ALIGNED && c->layout != MD_LAYOUT_SOA)
+        return fail(MD_ERR_INVALID_ARG, "bad layout");
+    if (c->layout != MD_LAYOUT_PACKED && (c->container != MD_CONTAINER_VL || c->newton3 != MD_N3L_OFF ||
+                                          c->precision != MD_FP32 || c->n_types != 1))
+        return fail(MD_ERR_INVALID_ARG, "window layouts other than packed are for FP32 Verlet lists, gather-only, "
+                                        "one particle type");
     if (c->container == MD_CONTAINER_CL && c->newton3 != MD_N3L_OFF)
         return fail(MD_ERR_INVALID_ARG, "cluster lists are gather-only (newton3 = MD_N3L_OFF)");
     if (c->container == MD_CONTAINER_CL && c->precision != MD_FP32)
@@ -1622,13 +1629,14 @@ extern "C" const char *md_last_error(void) { return g_err.c_str(); }
 // Whether two configurations of the tuning space build the same structure.
 static bool same_structure(const md_config &a, const md_config &b)
 {
-    return a.container == b.container && a.newton3 == b.newton3 && a.csf == b.csf && a.skin == b.skin;
+    return a.container == b.container && a.newton3 == b.newton3 && a.csf == b.csf && a.skin == b.skin &&
+           a.layout == b.layout;
 }
 
 // Whether two configurations differ at most in the skin.
 static bool same_method(const md_config &a, const md_config &b)
 {
-    return a.container == b.container && a.newton3 == b.newton3 && a.csf == b.csf;
+    return a.container == b.container && a.newton3 == b.newton3 && a.csf == b.csf && a.layout == b.layout;
 }
 
 // Switch the handle to configuration nc (same particles, box, cutoffs,

@@ -55,6 +55,7 @@ struct Geom {
     int nt;           // number of types
     int reach[3];     // stencil reach in cells per dimension
     int wband;        // y-rows per block of the windowed traversals
+    int layout;       // LDS layout of the Verlet-list force windows (MD_LAYOUT_*)
 };
 
 // Device buffers and state of one handle.

@@ -310,6 +310,7 @@ void tuning_space(const md_config &base, std::vector<md_config> &space)
     space.clear();
     md_config c = base;
     c.autotune = MD_TUNE_OFF;
+    c.layout = MD_LAYOUT_PACKED;
     // linked cells, CSF 1 and 0.5, gather-only and N3L
     for (double csf : {1.0, 0.5})
         for (int n3 : {MD_N3L_OFF, MD_N3L_ON}) {
@@ -348,6 +349,17 @@ void tuning_space(const md_config &base, std::vector<md_config> &space)
         c.newton3 = MD_N3L_ON;
         space.push_back(c);
     }
+    // Verlet lists, gather-only, with the other LDS window layouts (FP32,
+    // one particle type)
+    if (base.precision == MD_FP32 && base.n_types == 1)
+        for (int lay : {MD_LAYOUT_ALIGNED, MD_LAYOUT_SOA}) {
+            c.container = MD_CONTAINER_VL;
+            c.csf = 1.0;
+            c.newton3 = MD_N3L_OFF;
+            c.layout = lay;
+            space.push_back(c);
+        }
+    c.layout = MD_LAYOUT_PACKED;
     // linked cells with the C08 colouring (FP32, CSF-1 cells; left out like
     // pairwise lists on small boxes)
     if (base.precision == MD_FP32) {

@@ -19,6 +19,8 @@
 // Blocks of neighbouring cells share most of their windows, so the blocks
 // are dealt to the eight XCDs in contiguous chunks (workgroup w runs on XCD
 // w mod 8) to keep the shared window data in one L2.
+#include <type_traits>
+
 #include "verlet.h"
 
 namespace mdlj {
@@ -1405,18 +1407,84 @@ __device__ __forceinline__ void vl_exact(const int4 &pi, const int4 &pj, int i, 
     }
 }
 
+// LDS layout of the Verlet-list force windows (the data layout of Sec.
+// 2.2.3, for the window the force pass reads): MD_LAYOUT_PACKED holds
+// WinEntry<NT> (12 bytes with one type), MD_LAYOUT_ALIGNED 16-byte entries
+// (one 16-byte read), MD_LAYOUT_SOA one plane of kWinMax + 1 words per
+// coordinate (three 4-byte reads at fixed distances).  List entries are the
+// entries' byte offsets: position times kEsz.  The last position of each
+// (kWinMax) is the far entry.  The other layouts hold one type.
+template <int NT, int LAYOUT>
+struct WinLay {
+    static constexpr int kEsz = LAYOUT == MD_LAYOUT_ALIGNED ? 16 : (LAYOUT == MD_LAYOUT_SOA ? 4 : (int)sizeof(WinEntry<NT>));
+    static constexpr int kPlane = kWinMax + 1;  // words per plane
+    // LDS storage, in WinEntry<NT> units (packed) or 16-byte units
+    using Unit = typename std::conditional<LAYOUT == MD_LAYOUT_PACKED, WinEntry<NT>, int4>::type;
+    static constexpr int kUnits = LAYOUT == MD_LAYOUT_SOA ? (3 * kPlane + 3) / 4 : kWinMax + 1;
+    __device__ static __forceinline__ void put(Unit *win, int p, const int4 &a)
+    {
+        if (LAYOUT == MD_LAYOUT_PACKED) {
+            ((WinEntry<NT> *)win)[p].set(a);
+        } else if (LAYOUT == MD_LAYOUT_ALIGNED) {
+            ((int4 *)win)[p] = make_int4(a.x, a.y, a.z, 0);
+        } else {
+            int *x = (int *)win;
+            x[p] = a.x;
+            x[p + kPlane] = a.y;
+            x[p + 2 * kPlane] = a.z;
+        }
+    }
+    // the entry at byte offset off (a list entry)
+    __device__ static __forceinline__ int4 at(const Unit *win, uint32_t off)
+    {
+        const char *b = (const char *)win + off;
+        if (LAYOUT == MD_LAYOUT_PACKED) return ((const WinEntry<NT> *)b)->get();
+        if (LAYOUT == MD_LAYOUT_ALIGNED) {
+            int4 v = *(const int4 *)b;
+            return make_int4(v.x, v.y, v.z, 0);
+        }
+        const int *x = (const int *)b;
+        return make_int4(x[0], x[kPlane], x[2 * kPlane], 0);
+    }
+};
+
+// setup_block for the Verlet-list force windows of any layout (full window,
+// no column table, the far entry at position kWinMax).
+template <int NT, int LAYOUT>
+__device__ __forceinline__ bool setup_block_lay(const Geom &g, const int32_t *__restrict__ cs,
+                                                const int4 *__restrict__ st, int4 blk, Window &w,
+                                                typename WinLay<NT, LAYOUT>::Unit *win, int32_t *flags)
+{
+    if (LAYOUT == MD_LAYOUT_PACKED)
+        return setup_block<NT, false, false, true>(g, cs, st, blk, w, (WinEntry<NT> *)win, flags);
+    __syncthreads();
+    make_window<false, false>(g, cs, blk, w);
+    if (w.W > kWinMax || w.npart > 256) {  // never made by the packer
+        if (threadIdx.x == 0) atomicOr(&flags[3], 2);
+        return false;
+    }
+    int k = 0;
+    for (int p = threadIdx.x; p < w.W; p += blockDim.x) {
+        k = piece_from(w, k, p);
+        WinLay<NT, LAYOUT>::put(win, p, st[w.pc_start[k] + (p - w.pc_win[k])]);
+    }
+    if (threadIdx.x == 0) WinLay<NT, LAYOUT>::put(win, kWinMax, far_entry(g, blk));
+    __syncthreads();
+    return true;
+}
+
 // One list entry of the gather force, branch free: the window entry at LDS
 // byte offset off.  With one type the guard band is tracked through near,
 // the smallest |r2 - centre| seen; otherwise through amb.
-template <int NT, bool ISO, bool ENERGY>
-__device__ __forceinline__ void vl_step(const int4 &pi, const WinEntry<NT> *__restrict__ win, uint32_t off,
-                                        const TabF<NT> &t, const Geom &g, float mid, float &near, bool &amb,
-                                        float &fx, float &fy, float &fz, float &eu, float &ew, int &np)
+template <int NT, bool ISO, bool ENERGY, int LAYOUT = MD_LAYOUT_PACKED>
+__device__ __forceinline__ void vl_step(const int4 &pi, const typename WinLay<NT, LAYOUT>::Unit *__restrict__ win,
+                                        uint32_t off, const TabF<NT> &t, const Geom &g, float mid, float &near,
+                                        bool &amb, float &fx, float &fy, float &fz, float &eu, float &ew, int &np)
 {
-    const WinEntry<NT> &e = *(const WinEntry<NT> *)((const char *)win + off);
+    const int4 ej = WinLay<NT, LAYOUT>::at(win, off);
     if (NT == 1) {
         float dx, dy, dz;
-        staged_delta<ISO>(pi, e.get(), g, dx, dy, dz);
+        staged_delta<ISO>(pi, ej, g, dx, dy, dz);
         float r2 = dx * dx + dy * dy + dz * dz;
         bool in = r2 < t.lo[0];
         float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.0f;
@@ -1434,7 +1502,7 @@ __device__ __forceinline__ void vl_step(const int4 &pi, const WinEntry<NT> *__re
         fz += phi * dz;
         near = fminf(near, fabsf(r2 - mid));
     } else {
-        amb |= vl_entry<NT, ISO, ENERGY>(pi, e.get(), true, t, g, fx, fy, fz, eu, ew, np);
+        amb |= vl_entry<NT, ISO, ENERGY>(pi, ej, true, t, g, fx, fy, fz, eu, ew, np);
     }
 }
 
@@ -1448,7 +1516,7 @@ __device__ __forceinline__ void vl_step(const int4 &pi, const WinEntry<NT> *__re
 // pos and writing them to pos_out and stage_out (other blocks still read pos
 // and st); the kinetic energy and the largest displacement go to ia.kpart
 // and ia.dpart per workgroup.
-template <int NT, bool ISO, bool ENERGY, bool FUSED>
+template <int NT, bool ISO, bool ENERGY, bool FUSED, int LAYOUT = MD_LAYOUT_PACKED>
 __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, const int32_t *__restrict__ cs,
                                                  const int32_t *__restrict__ cell_sorted, Geom g, int n,
                                                  const int32_t *__restrict__ nblk_p, int cap,
@@ -1459,7 +1527,8 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
                                                  int32_t *__restrict__ flags, IntegrateArgs ia, double *pos_out,
                                                  int4 *stage_out)
 {
-    __shared__ WinEntry<NT> win[kWinMax + 1];  // + the far entry
+    using Lay = WinLay<NT, LAYOUT>;
+    __shared__ typename Lay::Unit win[Lay::kUnits];  // + the far entry
     __shared__ Window w;
     __shared__ double sh[16];
     TabF<NT> t;
@@ -1474,7 +1543,7 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
     for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
         int blk = it.blk;
         // the list holds window positions: only the window's pieces are needed
-        if (!setup_block<NT, false, false, true>(g, cs, st, blocks[blk], w, win, flags)) continue;
+        if (!setup_block_lay<NT, LAYOUT>(g, cs, st, blocks[blk], w, win, flags)) continue;
         int i, k, x;
         if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
         int4 pi = st[i];
@@ -1497,13 +1566,13 @@ __global__ __launch_bounds__(256) void k_vlw_f32(const int4 *__restrict__ st, co
             bool amb = false;
 #pragma unroll
             for (int u = 0; u < 8; u++)
-                vl_step<NT, ISO, ENERGY>(pi, win, off[u], t, g, mid, near, amb, fx, fy, fz, eu, ew, np);
+                vl_step<NT, ISO, ENERGY, LAYOUT>(pi, win, off[u], t, g, mid, near, amb, fx, fy, fz, eu, ew, np);
             if (NT == 1) amb = near <= hw;
             if (amb) {
                 // the far entries of the padding are never in the band
                 for (int u = 0; u < 8; u++) {
-                    int p = (int)(off[u] / sizeof(WinEntry<NT>));
-                    int4 pj = win[p].get();
+                    int p = (int)(off[u] / Lay::kEsz);
+                    int4 pj = Lay::at(win, off[u]);
                     float dx, dy, dz;
                     staged_delta<ISO>(pi, pj, g, dx, dy, dz);
                     float r2 = dx * dx + dy * dy + dz * dz;
@@ -1861,7 +1930,12 @@ bool build_float_ok(const Geom &g)
 
 // Size of the force kernels' LDS window entry (positions, plus the type when
 // there are several).
-static int window_entry_size(const Geom &g) { return g.nt == 1 ? (int)sizeof(WinEntry<1>) : (int)sizeof(WinEntry<2>); }
+static int window_entry_size(const Geom &g)
+{
+    if (g.nt == 1 && g.layout == MD_LAYOUT_ALIGNED) return WinLay<1, MD_LAYOUT_ALIGNED>::kEsz;
+    if (g.nt == 1 && g.layout == MD_LAYOUT_SOA) return WinLay<1, MD_LAYOUT_SOA>::kEsz;
+    return g.nt == 1 ? (int)sizeof(WinEntry<1>) : (int)sizeof(WinEntry<2>);
+}
 
 // maxn is rounded up to whole chunks of eight (the list holds them).
 void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
@@ -1900,6 +1974,19 @@ void launch_vlw_build(const int4 *st, const int32_t *cs, const int32_t *cell_sor
 
 int window_force_blocks() { return kWinGrid; }
 
+template <int NT, bool ISO, bool EN, int LAYOUT>
+static void vlw_launch(const ForceArgs &a, const Geom &g, int cap, hipStream_t s)
+{
+    if (a.fused)
+        k_vlw_f32<NT, ISO, EN, true, LAYOUT><<<kWinGrid, 256, 0, s>>>(
+            a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap, a.w_blk, a.w_nbr, a.nbr_count, a.tab, a.pos,
+            (float *)a.force, a.partials, a.flags, a.ia, a.pos_out, a.stage_out);
+    else
+        k_vlw_f32<NT, ISO, EN, false, LAYOUT><<<kWinGrid, 256, 0, s>>>(
+            a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap, a.w_blk, a.w_nbr, a.nbr_count, a.tab, a.pos,
+            (float *)a.force, a.partials, a.flags, a.ia, a.pos_out, a.stage_out);
+}
+
 template <int NT, bool ISO, bool EN>
 static void win_launch(const ForceArgs &a, const Geom &g, hipStream_t s)
 {
@@ -1915,14 +2002,12 @@ static void win_launch(const ForceArgs &a, const Geom &g, hipStream_t s)
                                                             cap, a.w_blk, a.tab, a.pos, (float *)a.force, a.partials,
                                                             a.flags);
     } else if (vl) {
-        if (a.fused)
-            k_vlw_f32<NT, ISO, EN, true><<<kWinGrid, 256, 0, s>>>(
-                a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap, a.w_blk, a.w_nbr, a.nbr_count, a.tab,
-                a.pos, (float *)a.force, a.partials, a.flags, a.ia, a.pos_out, a.stage_out);
+        if (NT == 1 && g.layout == MD_LAYOUT_ALIGNED)
+            vlw_launch<NT, ISO, EN, MD_LAYOUT_ALIGNED>(a, g, cap, s);
+        else if (NT == 1 && g.layout == MD_LAYOUT_SOA)
+            vlw_launch<NT, ISO, EN, MD_LAYOUT_SOA>(a, g, cap, s);
         else
-            k_vlw_f32<NT, ISO, EN, false><<<kWinGrid, 256, 0, s>>>(
-                a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap, a.w_blk, a.w_nbr, a.nbr_count, a.tab,
-                a.pos, (float *)a.force, a.partials, a.flags, a.ia, a.pos_out, a.stage_out);
+            vlw_launch<NT, ISO, EN, MD_LAYOUT_PACKED>(a, g, cap, s);
     } else {
         k_lcw_f32<NT, ISO, EN><<<kWinGrid, 256, 0, s>>>(a.stage, a.cell_start, a.cell_sorted, g, a.n, a.w_nblk, cap,
                                                        a.w_blk, a.tab, a.pos, (float *)a.force, a.partials,

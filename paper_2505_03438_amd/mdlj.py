@@ -30,6 +30,9 @@ MD_CONTAINER_VLC = 4
 MD_N3L_OFF = 0
 MD_N3L_ON = 1
 MD_N3L_C08 = 2
+MD_LAYOUT_PACKED = 0
+MD_LAYOUT_ALIGNED = 1
+MD_LAYOUT_SOA = 2
 MD_TUNE_OFF = 0
 MD_TUNE_FULL = 1
 MD_TUNE_PREDICTIVE = 2
@@ -65,6 +68,7 @@ class md_config(ctypes.Structure):
         ("total_steps_hint", ctypes.c_int32),
         ("tune_skin", ctypes.c_int32),
         ("tune_first", ctypes.c_int32),
+        ("layout", ctypes.c_int32),
     ]
 
 

@@ -9,7 +9,7 @@ from paper_2505_03438_amd import mdlj as M
 
 
 def make_config(n, box, rc=2.5, skin=0.3, csf=1.0, container=M.MD_CONTAINER_VL, newton3=0,
-                precision=M.MD_FP32, R=10, max_neighbors=160, n_types=1, rc2=None):
+                precision=M.MD_FP32, R=10, max_neighbors=160, n_types=1, rc2=None, layout=0):
     c = M.config_default(n, float(box[0]))
     c.box[0], c.box[1], c.box[2] = (float(b) for b in box)
     c.n_types = n_types
@@ -27,6 +27,7 @@ def make_config(n, box, rc=2.5, skin=0.3, csf=1.0, container=M.MD_CONTAINER_VL, 
     c.precision = precision
     c.rebuild_interval = R
     c.max_neighbors = max_neighbors
+    c.layout = layout
     return c
 
 

@@ -373,12 +373,13 @@ def test_long_cell_rows(orc, cont):
 
 # ---------------------------------------------------------------- integration
 
-def _run_nve(orc, prec, cont, nsteps=100, R=10, dt=0.005, energy_every=1, d=None):
+def _run_nve(orc, prec, cont, nsteps=100, R=10, dt=0.005, energy_every=1, d=None, layout=0):
     import torch
     d = d or W.plain_fcc_864()
     pos, vel, box = d["pos"], d["vel"], d["box"]
     n = pos.shape[1]
-    cfg = make_config(n, box, container=cont[0], newton3=cont[1], csf=cont[2], precision=prec, R=R)
+    cfg = make_config(n, box, container=cont[0], newton3=cont[1], csf=cont[2], precision=prec, R=R,
+                      layout=layout)
     s = DeviceSystem(cfg, pos, vel)
     s.build()
     s.forces(energy=False)
@@ -719,6 +720,45 @@ def test_forces_and_adjoint_between_builds(orc, cont):
     torch.cuda.synchronize()
     assert rel_l2(s.by_id(gpos), gx) <= 1e-4
     assert rel_l2(glj.cpu().numpy(), gt) <= 1e-5
+
+
+@pytest.mark.parametrize("layout", [1, 2], ids=["aligned", "soa"])
+def test_window_layouts(orc, layout):
+    """The Verlet-list force over LDS windows of 16-byte entries or of one
+    plane per coordinate (Sec. 2.2.3's layout choice): the same Verlet sets,
+    pair counts and forces as the oracle on jittered lattices of several
+    sizes, a long anisotropic box included, and energy conserved over an NVE
+    run (the fused integrator reads the same windows)."""
+    import torch
+    for shape, seed in (((6, 7, 8), 4), ((39, 5, 5), 6), ((8, 8, 8), 9)):
+        pos, box = _jittered(None, seed, jitter=0.1, shape=shape)
+        n = pos.shape[1]
+        F0, U0, W0, P0 = orc.forces(pos, box, orc.single())
+        cfg = make_config(n, box, container=1, layout=layout)
+        s = DeviceSystem(cfg, pos)
+        s.build()
+        out = s.forces().cpu().numpy()
+        assert int(out[2]) == P0, shape
+        assert_forces(s.by_id(s.force), F0, False, what=(shape, layout))
+        assert abs(out[0] - U0) <= FP32_E * abs(U0)
+        assert M.md_get_counters(s.h)["force_family"] == 1  # the windowed kernels ran
+        counts, rows = M.md_get_neighbors(s.h, 160)
+        counts, rows = counts.cpu().numpy(), rows.cpu().numpy()
+        ids = s.ids_np()
+        ref = orc.neighbor_rows(pos, box, (2.5 + 0.3) ** 2, np.arange(n))
+        for k in range(0, n, 7):
+            assert np.array_equal(np.sort(ids[rows[k, :counts[k]]]), ref[ids[k]]), (shape, k)
+    # NVE: fused and plain passes over the layout's windows
+    s, log = _run_nve(orc, 0, (1, 0, 1.0), nsteps=200, R=10, layout=layout)
+    u_rc = orc.lj(6.25)[1]
+    E = (log[:, 0] - log[:, 3] * u_rc + log[:, 1]) / 864
+    assert np.abs(E - E[0]).max() < 5e-3
+    # other containers and two types refuse the other layouts
+    d = W.plain_fcc_864()
+    for bad in (dict(container=0), dict(container=1, newton3=1), dict(container=1, precision=1),
+                dict(container=1, n_types=2)):
+        with pytest.raises(RuntimeError, match="layout"):
+            M.md_create(make_config(864, d["box"], layout=layout, **bad))
 
 
 # ---------------------------------------------------------------- full-size fluid

@@ -94,7 +94,7 @@ def test_dense_step_redoes_block(orc):
     import torch
     pos, box = _dense()
     n = pos.shape[1]
-    dt, nsteps = 1e-5, 20
+    dt, nsteps = 1e-5, 24
     vel = np.zeros((3, n))
     p1, v1, _, log0 = orc.velocity_verlet(pos, vel, box, orc.single(), dt, nsteps)
     cfg = make_config(n, box, container=0, csf=0.5, precision=M.MD_FP32, R=4, max_neighbors=640)
@@ -112,10 +112,13 @@ def test_dense_step_redoes_block(orc):
     st = M.md_status(s.h)
     assert st & M.MD_FLAG_WINDOW_FALLBACK, st
     cnt = M.md_get_counters(s.h)
-    assert cnt["tuning_phases"] == 1 and cnt["trials"] == 10, cnt
+    assert cnt["tuning_phases"] == 1 and cnt["trials"] == 12, cnt
     log = log.cpu().numpy()
     assert np.array_equal(log[:, 3], log0[:, 3])
     assert np.abs(log[:, 0] - log0[:, 0]).max() <= 1e-6 * np.abs(log0[:, 0]).max()
     dx = s.by_id(s.pos) - p1
     dx -= box[:, None] * np.rint(dx / box[:, None])
-    assert np.abs(dx).max() < 1e-8
+    # FP32 forces: the position error grows about as the square of the steps
+    # (1e-8 held for 18 steps; 24 steps let a phase trial all twelve FP32
+    # structures)
+    assert np.abs(dx).max() < 1e-8 * (nsteps / 18) ** 2
