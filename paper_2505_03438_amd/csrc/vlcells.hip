@@ -139,6 +139,7 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
     __shared__ int4 wp[kVlcMax];
     __shared__ unsigned long long ax[kVlcMax], ay[kVlcMax], az[kVlcMax];
     __shared__ int cst[8], base[9];
+    __shared__ int tq[kVlcMax + 1], te0[kVlcMax], te1[kVlcMax];  // tasks per role particle, segments
     __shared__ double sh[4 * kVlcThreads / 64];
     int b = blockIdx.x;
     int ix = b % col.cnt[0], t = b / col.cnt[0];
@@ -177,8 +178,7 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
     // particles of the four role cells (cube cells 0, 1, 2, 4)
     int nr0 = base[1] - base[0], nr1 = base[2] - base[1], nr2 = base[3] - base[2], nr3 = base[5] - base[4];
     int Mr = nr0 + nr1 + nr2 + nr3;
-    for (int p = threadIdx.x; p < Mr; p += kVlcThreads) {
-        int r, off;
+    auto role_of = [&](int p, int &r, int &off) {
         if (p < nr0) {
             r = 0;
             off = p;
@@ -192,19 +192,17 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
             r = 3;
             off = p - nr0 - nr1 - nr2;
         }
-        int ep = vlc_role_cell(r);
-        int li = base[ep] + off, i = cst[ep] + off;
-        int4 pi = lds ? wp[li] : st[i];
-        int e0 = r == 0 ? 0 : seg[(size_t)(r - 1) * N + i], e1 = seg[(size_t)r * N + i];
-        float fx = 0.f, fy = 0.f, fz = 0.f;
-        for (int q0 = e0; q0 < e1; q0 += 8) {
-            // eight entries loaded before any is used: their loads overlap
-            uint32_t ents[8];
+    };
+    // entries q0 .. q1 - 1 (at most eight) of the list of particle i:
+    // loaded before any is used, so that their loads overlap; the j sides go
+    // to the accumulators, the i side is returned in f
+    auto walk = [&](int i, const int4 &pi, int q0, int q1, float &fx, float &fy, float &fz) {
+        uint32_t ents[8];
 #pragma unroll
-            for (int u = 0; u < 8; u++) ents[u] = q0 + u < e1 ? (uint32_t)nbr[(size_t)(q0 + u) * N + i] : 0u;
+        for (int u = 0; u < 8; u++) ents[u] = q0 + u < q1 ? (uint32_t)nbr[(size_t)(q0 + u) * N + i] : 0u;
 #pragma unroll
-            for (int u = 0; u < 8; u++) {
-            if (q0 + u >= e1) break;
+        for (int u = 0; u < 8; u++) {
+            if (q0 + u >= q1) break;
             uint32_t ent = ents[u];
             int eq = (int)(ent >> 13), oq = (int)(ent & 8191u);
             int lj = base[eq] + oq, j = cst[eq] + oq;
@@ -230,13 +228,59 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
                     atomicAdd(&F[2 * N + j], -pz);
                 }
             }
-            }
         }
-        if (lds) {
+    };
+    if (lds) {
+        // the role particles' lists dealt to the threads in tasks of up to
+        // eight entries: the long lists (the base cell's particles pair with
+        // eight cells, the others with fewer) take several threads each, so
+        // no thread waits on the longest list of its wavefront
+        for (int p = threadIdx.x; p < Mr; p += kVlcThreads) {
+            int r, off;
+            role_of(p, r, off);
+            int i = cst[vlc_role_cell(r)] + off;
+            int e0 = r == 0 ? 0 : seg[(size_t)(r - 1) * N + i], e1 = seg[(size_t)r * N + i];
+            te0[p] = e0;
+            te1[p] = e1;
+            tq[p + 1] = (e1 - e0 + 7) >> 3;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            tq[0] = 0;
+            for (int p = 0; p < Mr; p++) tq[p + 1] += tq[p];
+        }
+        __syncthreads();
+        const int T = tq[Mr];
+        for (int task = threadIdx.x; task < T; task += kVlcThreads) {
+            int lo = 0, hi = Mr;  // the role particle lo with tq[lo] <= task < tq[lo + 1]
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (tq[mid] <= task)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            int r, off;
+            role_of(lo, r, off);
+            int ep = vlc_role_cell(r);
+            int li = base[ep] + off, i = cst[ep] + off;
+            int q0 = te0[lo] + 8 * (task - tq[lo]), q1 = min(te1[lo], q0 + 8);
+            float fx = 0.f, fy = 0.f, fz = 0.f;
+            walk(i, wp[li], q0, q1, fx, fy, fz);
             atomicAdd(&ax[li], to_fix(fx));
             atomicAdd(&ay[li], to_fix(fy));
             atomicAdd(&az[li], to_fix(fz));
-        } else {
+        }
+    } else {
+        for (int p = threadIdx.x; p < Mr; p += kVlcThreads) {
+            int r, off;
+            role_of(p, r, off);
+            int ep = vlc_role_cell(r);
+            int i = cst[ep] + off;
+            int4 pi = st[i];
+            int e0 = r == 0 ? 0 : seg[(size_t)(r - 1) * N + i], e1 = seg[(size_t)r * N + i];
+            float fx = 0.f, fy = 0.f, fz = 0.f;
+            for (int q0 = e0; q0 < e1; q0 += 8) walk(i, pi, q0, min(e1, q0 + 8), fx, fy, fz);
             atomicAdd(&F[i], fx);
             atomicAdd(&F[N + i], fy);
             atomicAdd(&F[2 * N + i], fz);
