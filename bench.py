@@ -490,9 +490,10 @@ def cpu_baseline(d, target_s=10.0, brute_s=2.0):
 
 def bench_batched(M, W, steps, warmup, sample=64):
     """The 4096 uneven systems advanced together (persistent launches, one
-    rebuild interval captured in a HIP graph), against the same systems each
-    run through its own handle (one launch sequence per system, timed on a
-    seeded sample and scaled to all 4096)."""
+    rebuild interval captured in a HIP graph) with Verlet lists, against the
+    same batch with linked cells and against the same systems each run
+    through its own handle (one launch sequence per system, timed on a seeded
+    sample and scaled to all 4096)."""
     import numpy as np
     import torch
     syss = W.batched_systems()
@@ -503,36 +504,42 @@ def bench_batched(M, W, steps, warmup, sample=64):
     n = int(offs[-1])
     dev = "cuda"
 
-    def cfg_for(nn, box, R=5):
+    def cfg_for(nn, box, R=5, container=M.MD_CONTAINER_VL):
         c = M.config_default(nn, float(box[0]))
         c.precision = M.MD_FP32
-        c.container = M.MD_CONTAINER_LC
+        c.container = container
         c.rebuild_interval = R
         return c
 
-    pos = torch.tensor(np.concatenate([sy["pos"] for sy in syss], axis=1), dtype=torch.float64, device=dev)
-    vel = torch.tensor(np.concatenate([sy["vel"] for sy in syss], axis=1), dtype=torch.float32, device=dev)
-    force = torch.zeros((3, n), dtype=torch.float32, device=dev)
-    typ = torch.zeros(n, dtype=torch.int32, device=dev)
-    ids = torch.arange(n, dtype=torch.int32, device=dev)
     lj = torch.tensor([1.0, 1.0], dtype=torch.float64, device=dev)
     im = torch.ones(1, dtype=torch.float64, device=dev)
-    b = M.md_batch_create(cfg_for(n, boxes[0]), offs, boxes)
-    M.md_batch_build_cells(b, pos, vel, force, typ, ids)
-    out = torch.zeros(4 * nsys, dtype=torch.float64, device=dev)
-    M.md_batch_compute_forces(b, pos, typ, lj, force, out)
-    torch.cuda.synchronize()
-    pairs = float(out.view(nsys, 4)[:, 2].sum().item())
-    res = {}
-    for graph in (True, False):
-        M.md_batch_step(b, pos, vel, force, typ, ids, im, lj, 0.005, warmup, use_graph=graph)
+
+    def run(container, graphs):
+        pos = torch.tensor(np.concatenate([sy["pos"] for sy in syss], axis=1), dtype=torch.float64, device=dev)
+        vel = torch.tensor(np.concatenate([sy["vel"] for sy in syss], axis=1), dtype=torch.float32, device=dev)
+        force = torch.zeros((3, n), dtype=torch.float32, device=dev)
+        typ = torch.zeros(n, dtype=torch.int32, device=dev)
+        ids = torch.arange(n, dtype=torch.int32, device=dev)
+        b = M.md_batch_create(cfg_for(n, boxes[0], container=container), offs, boxes)
+        M.md_batch_build_cells(b, pos, vel, force, typ, ids)
+        out = torch.zeros(4 * nsys, dtype=torch.float64, device=dev)
+        M.md_batch_compute_forces(b, pos, typ, lj, force, out)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        M.md_batch_step(b, pos, vel, force, typ, ids, im, lj, 0.005, steps, use_graph=graph)
-        torch.cuda.synchronize()
-        res[graph] = (time.perf_counter() - t0) / steps
-    bc = M.md_batch_get_counters(b)
-    b.close()
+        pairs = float(out.view(nsys, 4)[:, 2].sum().item())
+        res = {}
+        for graph in graphs:
+            M.md_batch_step(b, pos, vel, force, typ, ids, im, lj, 0.005, warmup, use_graph=graph)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            M.md_batch_step(b, pos, vel, force, typ, ids, im, lj, 0.005, steps, use_graph=graph)
+            torch.cuda.synchronize()
+            res[graph] = (time.perf_counter() - t0) / steps
+        bc = M.md_batch_get_counters(b)
+        b.close()
+        return pairs, res, bc
+
+    pairs, res, bc = run(M.MD_CONTAINER_VL, (True, False))
+    _, res_lc, bc_lc = run(M.MD_CONTAINER_LC, (True,))
     # one handle per system, on a seeded sample
     pick = np.random.default_rng(11).choice(nsys, sample, replace=False)
     t_sum, n_sum = 0.0, 0
@@ -547,6 +554,7 @@ def bench_batched(M, W, steps, warmup, sample=64):
         t = torch.zeros(nn, dtype=torch.int32, device=dev)
         i = torch.arange(nn, dtype=torch.int32, device=dev)
         M.md_build_cells(h, p, v, f, t, i)
+        M.md_build_neighbors(h, p, t)
         M.md_compute_forces(h, p, t, lj, f)
         M.md_step(h, p, v, f, t, i, im, lj, 0.005, warmup)
         torch.cuda.synchronize()
@@ -563,10 +571,12 @@ def bench_batched(M, W, steps, warmup, sample=64):
             "warmup": warmup, "ms_per_step": 1e3 * res[True], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "lj-batched-4096", "systems": nsys, "n": n, "pairs_per_step": pairs,
-                       "container": "linked cells CSF 1, gather-only", "rebuild_interval_max": 5,
+                       "container": "Verlet lists CSF 1, gather-only", "rebuild_interval_max": 5,
                        "rebuild_interval_at_end": bc["rebuild_interval"], "dt": 0.005},
             "batch_counters": bc,
             "direct_launches_ms_per_step": 1e3 * res[False],
+            "linked_cells_ms_per_step": 1e3 * res_lc[True],
+            "linked_cells_batch_counters": bc_lc,
             "one_handle_per_system_ms_per_step": 1e3 * per_system,
             "one_handle_per_system_how": "md_step per system on %d seeded systems (%d particles), rebuilt "
                                          "every %d steps, scaled by 4096/%d" % (sample, n_sum,

@@ -2,7 +2,7 @@
 // step (integration, cell build, forces) is one launch over all particles of
 // all systems, and one rebuild interval of steps is captured into a HIP graph
 // and replayed.  Each system has its own cubic box, cells and fixed-point
-// scale; one particle type; linked cells, gather-only.
+// scale; one particle type; linked cells or (FP32) Verlet lists, gather-only.
 //
 // Particles of system s occupy [offsets[s], offsets[s+1]) of every array.
 // Global cell ids are system-major (cell_base[s] + local id), so the counting
@@ -28,6 +28,7 @@ struct BSys {
     int cell_base;          // first global cell id
     double L, inv_w, S;     // box, cells per length, fixed-point scale
     float disp2;            // skin check threshold in fixed-point units
+    float hl;               // upper edge of the list radius's guard band, fixed-point units squared
     // pair constants in this box's fixed-point units (filled from lj on the device)
     float lo, hi, sig2, eps24, eps4, eps24w;
     double rc2, eps, sig;
@@ -253,20 +254,33 @@ __global__ __launch_bounds__(256) void k_bforce(int n, const int4 *__restrict__ 
     }
 }
 
-// FP32 forces over work items of z-slabs: an item is a system and a range of
-// z cell layers [z0, z0 + t), the largest items first.  The workgroup stages
-// the layers the slab's stencils reach (the slab and h halo layers on either
-// side, or the whole system) into LDS: their cell starts, as LDS indices, and
-// their fixed-point positions.  Each thread then takes the slab's particles in
-// turn and tests its stencil candidates 32 at a time (distance test into a bit
-// mask), evaluating the pair force only for those within the cutoff band
-// (guard-band pairs decided from the FP64 positions).  When the staged layers
-// hold more particles than the LDS tile (the slabs are sized from the mean
-// density), the item reads its candidates from global memory instead.
+// Work items of z-slabs: an item is a system and a range of z cell layers
+// [z0, z0 + t), the largest items first.  The workgroup stages the layers the
+// slab's stencils reach (the slab and h halo layers on either side, or the
+// whole system) into LDS: their cell starts, as LDS indices, and their
+// fixed-point positions.  When the staged layers hold more particles than the
+// LDS tile (the slabs are sized from the mean density), the item reads its
+// candidates from global memory instead.  Three kernels share the staging:
+//  - kSlabCells, the linked-cell force: each thread takes the slab's particles
+//    in turn and tests its stencil candidates 32 at a time (distance test into
+//    a bit mask), evaluating the pair force only for those within the cutoff
+//    band (guard-band pairs decided from the FP64 positions);
+//  - kSlabBuild, the Verlet lists (Sec. 2.2.1): the same candidate tests
+//    against the upper edge of the list radius's band (a superset of the
+//    pairs within r_c + skin), the hits appended as 16-bit entries, eight to
+//    a 16-byte chunk, chunk k of particle i at nbr[k N + i]: the LDS index of
+//    the partner in the item's staging, or its index in its system when the
+//    item reads global memory; cnt[i] is the full count;
+//  - kSlabList, the force over those lists: each entry evaluated as above.  A
+//    particle whose list outgrew the capacity (cnt[i] > maxn) walks its
+//    stencil instead, so an overflow costs time, never a pair.
+// The staging depends only on the cells, so the build and the force passes
+// between two rebuilds make the same tile decision for every item.
 #ifndef MDLJ_BATCH_LDS_KB
 #define MDLJ_BATCH_LDS_KB 40
 #endif
 constexpr int kBSysLdsBytes = MDLJ_BATCH_LDS_KB * 1024;  // LDS tile per workgroup, at most
+constexpr int kSlabCells = 0, kSlabBuild = 1, kSlabList = 2;
 
 // LDS words of an item's tables: layer bases (K + 1), layer offsets (K), cell
 // starts (K nc^2 + 1) and 16 words of positions read past the last batch.
@@ -275,11 +289,26 @@ __host__ __device__ static inline int64_t bslab_table_words(int64_t K, int64_t n
     return 2 * K + 2 + K * nc2 + 12;
 }
 
-__global__ __launch_bounds__(256) void k_bforce_slab(const int4 *__restrict__ items, const int64_t *__restrict__ offs,
-                                                     const int4 *__restrict__ st, const double *__restrict__ pos,
-                                                     int n, const BSys *__restrict__ sys, const int32_t *__restrict__ cs,
-                                                     const int32_t *__restrict__ cell_sorted, float *__restrict__ F,
-                                                     double *__restrict__ pe, int lds_bytes)
+// Eight pending 16-bit list entries in four words: entry 2k in the low half
+// of word k, entry 2k + 1 in the high half once eight have been pushed.
+struct BChunk {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    __device__ __forceinline__ void push(uint32_t e)
+    {
+        w[0] = (w[0] >> 16) | (w[1] << 16);
+        w[1] = (w[1] >> 16) | (w[2] << 16);
+        w[2] = (w[2] >> 16) | (w[3] << 16);
+        w[3] = (w[3] >> 16) | (e << 16);
+    }
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, const int64_t *__restrict__ offs,
+                                               const int4 *__restrict__ st, const double *__restrict__ pos, int n,
+                                               const BSys *__restrict__ sys, const int32_t *__restrict__ cs,
+                                               const int32_t *__restrict__ cell_sorted, float *__restrict__ F,
+                                               double *__restrict__ pe, int lds_bytes, uint4 *__restrict__ nbr,
+                                               int32_t *__restrict__ cnt, int maxn)
 {
     extern __shared__ int sm[];
     const int4 it = items[blockIdx.x];
@@ -288,6 +317,7 @@ __global__ __launch_bounds__(256) void k_bforce_slab(const int4 *__restrict__ it
     const int p0 = (int)offs[it.x];
     const int nc = b.nc, nofs = b.nofs, nc2 = nc * nc, cbase = b.cell_base;
     const float lo = b.lo, hi = b.hi, sig2 = b.sig2, eps24 = b.eps24, eps4 = b.eps4, eps24w = b.eps24w;
+    const float thr = MODE == kSlabBuild ? b.hl : hi;  // the candidate test
     const double rc2 = b.rc2, L = b.L;
     const bool whole = t + 2 * h >= nc;
     const int K = whole ? nc : t + 2 * h;          // staged layers
@@ -335,18 +365,26 @@ __global__ __launch_bounds__(256) void k_bforce_slab(const int4 *__restrict__ it
     size_t N = (size_t)n;
     for (int il = i0 + (int)threadIdx.x; il < i1; il += blockDim.x) {
         const int i = p0 + il;
-        const int local = cell_sorted[i] - cbase;
-        const int cx = local % nc, cy = (local / nc) % nc, cz = local / nc2;
         const int4 pi = st[i];
         float fx = 0.f, fy = 0.f, fz = 0.f, eus = 0.f, ews = 0.f;
         int np = 0;
-        auto pair = [&](int jg, int qx, int qy, int qz) {
+        // pair with partner j (its global index, or with staged its LDS index,
+        // converted only for a guard-band decision)
+        auto pair = [&](int j, bool staged, bool valid, int qx, int qy, int qz) {
             float dx = (float)(int)((uint32_t)pi.x - (uint32_t)qx);
             float dy = (float)(int)((uint32_t)pi.y - (uint32_t)qy);
             float dz = (float)(int)((uint32_t)pi.z - (uint32_t)qz);
             float r2 = dx * dx + dy * dy + dz * dz;
-            bool in = r2 < lo;
-            if (r2 >= lo && r2 < hi) in = exact_r2(pos, n, i, jg, L, L, L) < rc2;
+            bool in = valid && r2 < lo;
+            if (valid && r2 >= lo && r2 < hi) {
+                int jg = j;
+                if (staged) {
+                    int k = 0;
+                    while (lb[k + 1] <= j) k++;
+                    jg = j + gofs[k] + p0;
+                }
+                in = exact_r2(pos, n, i, jg, L, L, L) < rc2;
+            }
             float ir2 = __builtin_amdgcn_rcpf(r2);
             float s2 = sig2 * ir2;
             float q = s2 * s2 * s2;
@@ -361,64 +399,120 @@ __global__ __launch_bounds__(256) void k_bforce_slab(const int4 *__restrict__ it
                 np += in ? 1 : 0;
             }
         };
-        const int self = tile ? il - gofs[(cz - zlo + nc) % nc] : 0;  // the particle's LDS index
-        for (int a = 0; a < nofs; a++) {
-            int zz = cz + b.ofs[a];
-            zz = zz >= nc ? zz - nc : zz;
-            const int k = (zz - zlo + nc) % nc;  // < K: the slab's stencils stay in the staged layers
-            const int gz = tile ? gofs[k] + p0 : 0;
-            for (int bb = 0; bb < nofs; bb++) {
-                int yy = cy + b.ofs[bb];
-                yy = yy >= nc ? yy - nc : yy;
-                for (int e = 0; e < nofs; e++) {
-                    int xx = cx + b.ofs[e];
-                    xx = xx >= nc ? xx - nc : xx;
-                    if (tile) {
-                        const int c = (k * nc + yy) * nc + xx;
-                        const int jb = scs[c], je = scs[c + 1];
-                        for (int base = jb; base < je; base += 32) {
-                            const int m = min(32, je - base);
-                            uint32_t mask = 0;
-                            int nb = 0;
-                            for (; nb < m; nb += 4)
-                                for (int u = 0; u < 4; u++) {
-                                    const int *q = pp + 3 * (base + nb + u);
-                                    float dx = (float)(int)((uint32_t)pi.x - (uint32_t)q[0]);
-                                    float dy = (float)(int)((uint32_t)pi.y - (uint32_t)q[1]);
-                                    float dz = (float)(int)((uint32_t)pi.z - (uint32_t)q[2]);
-                                    float r2 = dx * dx + dy * dy + dz * dz;
-                                    mask = mask + mask + (r2 < hi ? 1u : 0u);
-                                }
-                            mask >>= nb - m;  // the reads past the batch
-                            unsigned us = (unsigned)(self - base);
-                            if (us < (unsigned)m) mask &= ~(1u << (m - 1 - us));
-                            while (mask) {
-                                int hb = 31 - __builtin_clz(mask);
-                                mask ^= 1u << hb;
-                                int jl = base + m - 1 - hb;
-                                const int *q = pp + 3 * jl;
-                                pair(jl + gz, q[0], q[1], q[2]);
-                            }
+        int c = 0;  // list entries (build)
+        BChunk ck;
+        uint4 *row = nbr + i;
+        auto hit = [&](int jl, int jg, int qx, int qy, int qz) {
+            if (MODE == kSlabBuild) {
+                ck.push((uint32_t)(tile ? jl : jg - p0));
+                c++;
+                if ((c & 7) == 0 && c <= maxn) row[(size_t)((c >> 3) - 1) * N] = make_uint4(ck.w[0], ck.w[1], ck.w[2], ck.w[3]);
+            } else {
+                pair(jg, false, true, qx, qy, qz);
+            }
+        };
+        bool stencil = true;
+        if (MODE == kSlabList) {
+            const int cl = cnt[i];
+            if (cl <= maxn) {
+                stencil = false;
+                const uint4 *lrow = nbr + i;
+                uint4 nx = cl > 0 ? lrow[0] : make_uint4(0u, 0u, 0u, 0u);
+                for (int q0 = 0; q0 < cl; q0 += 8) {
+                    const uint32_t w[4] = {nx.x, nx.y, nx.z, nx.w};
+                    if (q0 + 8 < cl) nx = lrow[(size_t)((q0 >> 3) + 1) * N];  // the next chunk in flight
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const int e = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
+                        const bool valid = q0 + u < cl;
+                        if (tile) {
+                            const int *q = pp + 3 * e;
+                            pair(e, true, valid, q[0], q[1], q[2]);
+                        } else {
+                            const int4 q = st[p0 + e];
+                            pair(p0 + e, false, valid, q.x, q.y, q.z);
                         }
-                    } else {
-                        const int c = cbase + (zz * nc + yy) * nc + xx;
-                        const int jb = cs[c], je = cs[c + 1];
-                        for (int j = jb; j < je; j++)
-                            if (j != i) {
-                                int4 q = st[j];
-                                pair(j, q.x, q.y, q.z);
-                            }
                     }
                 }
             }
         }
-        F[i] = fx;
-        F[N + i] = fy;
-        F[2 * N + i] = fz;
-        if (pe) {
-            pe[i] = eus;
-            pe[N + i] = ews;
-            pe[2 * N + i] = (double)np;
+        if (stencil) {
+            const int local = cell_sorted[i] - cbase;
+            const int cx = local % nc, cy = (local / nc) % nc, cz = local / nc2;
+            const int self = tile ? il - gofs[(cz - zlo + nc) % nc] : 0;  // the particle's LDS index
+            for (int a = 0; a < nofs; a++) {
+                int zz = cz + b.ofs[a];
+                zz = zz >= nc ? zz - nc : zz;
+                const int k = (zz - zlo + nc) % nc;  // < K: the slab's stencils stay in the staged layers
+                const int gz = tile ? gofs[k] + p0 : 0;
+                for (int bb = 0; bb < nofs; bb++) {
+                    int yy = cy + b.ofs[bb];
+                    yy = yy >= nc ? yy - nc : yy;
+                    for (int e = 0; e < nofs; e++) {
+                        int xx = cx + b.ofs[e];
+                        xx = xx >= nc ? xx - nc : xx;
+                        if (tile) {
+                            const int cc = (k * nc + yy) * nc + xx;
+                            const int jb = scs[cc], je = scs[cc + 1];
+                            for (int base = jb; base < je; base += 32) {
+                                const int m = min(32, je - base);
+                                uint32_t mask = 0;
+                                int nb = 0;
+                                for (; nb < m; nb += 4)
+                                    for (int u = 0; u < 4; u++) {
+                                        const int *q = pp + 3 * (base + nb + u);
+                                        float dx = (float)(int)((uint32_t)pi.x - (uint32_t)q[0]);
+                                        float dy = (float)(int)((uint32_t)pi.y - (uint32_t)q[1]);
+                                        float dz = (float)(int)((uint32_t)pi.z - (uint32_t)q[2]);
+                                        float r2 = dx * dx + dy * dy + dz * dz;
+                                        mask = mask + mask + (r2 < thr ? 1u : 0u);
+                                    }
+                                mask >>= nb - m;  // the reads past the batch
+                                unsigned us = (unsigned)(self - base);
+                                if (us < (unsigned)m) mask &= ~(1u << (m - 1 - us));
+                                while (mask) {
+                                    int hb = 31 - __builtin_clz(mask);
+                                    mask ^= 1u << hb;
+                                    int jl = base + m - 1 - hb;
+                                    const int *q = pp + 3 * jl;
+                                    hit(jl, jl + gz, q[0], q[1], q[2]);
+                                }
+                            }
+                        } else {
+                            const int cc = cbase + (zz * nc + yy) * nc + xx;
+                            const int jb = cs[cc], je = cs[cc + 1];
+                            for (int j = jb; j < je; j++)
+                                if (j != i) {
+                                    int4 q = st[j];
+                                    if (MODE == kSlabBuild) {
+                                        float dx = (float)(int)((uint32_t)pi.x - (uint32_t)q.x);
+                                        float dy = (float)(int)((uint32_t)pi.y - (uint32_t)q.y);
+                                        float dz = (float)(int)((uint32_t)pi.z - (uint32_t)q.z);
+                                        if (dx * dx + dy * dy + dz * dz < thr) hit(0, j, q.x, q.y, q.z);
+                                    } else {
+                                        hit(0, j, q.x, q.y, q.z);
+                                    }
+                                }
+                        }
+                    }
+                }
+            }
+        }
+        if (MODE == kSlabBuild) {
+            if ((c & 7) != 0 && c < maxn) {
+                for (int e = c & 7; e < 8; e++) ck.push(0u);
+                row[(size_t)(c >> 3) * N] = make_uint4(ck.w[0], ck.w[1], ck.w[2], ck.w[3]);
+            }
+            cnt[i] = c;
+        } else {
+            F[i] = fx;
+            F[N + i] = fy;
+            F[2 * N + i] = fz;
+            if (pe) {
+                pe[i] = eus;
+                pe[N + i] = ews;
+                pe[2 * N + i] = (double)np;
+            }
         }
     }
 }
@@ -518,6 +612,12 @@ struct md_batch {
     int4 *items = nullptr;  // the FP32 force kernel's work items (system, z0, t, halo), largest first
     int n_items = 0;
     int sys_lds = 0;        // that kernel's LDS tile (bytes)
+    // Verlet lists (FP32): chunks of eight 16-bit entries, [maxn / 8][n], and
+    // each particle's full count; built with the cells
+    bool lists = false;
+    int maxn = 0;
+    uint4 *nbr = nullptr;
+    int32_t *bcnt = nullptr;
     // Rebuild interval in use (at most cfg.rebuild_interval): shortened to the
     // block step of a skin violation, lengthened by one after `backoff` blocks
     // in a row without one (the backoff doubling after each failed try).
@@ -552,7 +652,8 @@ static void batch_free(md_batch *b)
 {
     void *p[] = {b->sys,   b->d_offs, b->items, b->sys_of, b->cell_id,  b->slot,      b->perm,       b->perm2,
                  b->count, b->cell_start, b->cell_sorted, b->scan, b->tpos,  b->tvel,       b->tforce,
-                 b->ttype, b->tids,   b->stage,  b->stage_ref, b->pe,       b->snap_pos,   b->snap_vel, b->flags};
+                 b->ttype, b->tids,   b->stage,  b->stage_ref, b->pe,       b->snap_pos,   b->snap_vel, b->flags,
+                 b->nbr,   b->bcnt};
     for (void *q : p)
         if (q) (void)hipFree(q);
     if (b->host_flags) (void)hipHostFree(b->host_flags);
@@ -622,9 +723,19 @@ extern "C" int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_
     if (!(cfg->rc2[0] > 0.0) || !(cfg->skin >= 0.0) || !(cfg->csf >= 0.5 && cfg->csf <= 1.0))
         return fail(MD_ERR_INVALID_ARG, "bad cutoff, skin or csf");
     if (cfg->rebuild_interval < 1) return fail(MD_ERR_INVALID_ARG, "rebuild_interval must be >= 1");
+    if (cfg->container != MD_CONTAINER_LC && cfg->container != MD_CONTAINER_VL)
+        return fail(MD_ERR_INVALID_ARG, "batched systems use linked cells or Verlet lists");
+    if (cfg->newton3 != MD_N3L_OFF) return fail(MD_ERR_INVALID_ARG, "batched systems are gather-only (newton3 off)");
+    const bool lists = cfg->container == MD_CONTAINER_VL;
+    if (lists && cfg->precision != MD_FP32) return fail(MD_ERR_INVALID_ARG, "batched Verlet lists are FP32");
+    if (lists && !(cfg->max_neighbors >= 1 && cfg->max_neighbors <= 4096))
+        return fail(MD_ERR_INVALID_ARG, "max_neighbors out of range");
     if (offsets[0] != 0) return fail(MD_ERR_INVALID_ARG, "offsets[0] must be 0");
-    for (int s = 0; s < n_sys; s++)
+    for (int s = 0; s < n_sys; s++) {
         if (offsets[s + 1] < offsets[s]) return fail(MD_ERR_INVALID_ARG, "offsets must be non-decreasing");
+        if (lists && offsets[s + 1] - offsets[s] > 65536)
+            return fail(MD_ERR_INVALID_ARG, "batched Verlet lists hold systems of at most 65536 particles");
+    }
     if (offsets[n_sys] > (int64_t)INT32_MAX / 3) return fail(MD_ERR_INVALID_ARG, "too many particles");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(MD_ERR_NO_DEVICE, "no HIP device");
@@ -660,6 +771,10 @@ extern "C" int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_
         y.inv_w = g.inv_w[0];
         y.S = g.S[0];
         y.disp2 = g.disp2;
+        {
+            const double u = bx[0] / 4294967296.0, rl = sqrt(cfg->rc2[0]) + cfg->skin;
+            y.hl = (float)(rl * rl / (u * u) * (1.0 + kBand));
+        }
         cells += g.ncell;
         if (cells > (int64_t)1 << 30) {
             delete b;
@@ -700,6 +815,22 @@ extern "C" int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_
     A((void **)&b->snap_pos, 24 * n);
     A(&b->snap_vel, 3 * rs * n);
     A((void **)&b->flags, 16);
+    if (lists) {
+        // capacity: the configured row length, or 1.3 times the mean count
+        // within the list radius of the densest system if that is more, in
+        // whole chunks (a longer list falls back to the stencil)
+        double rho = 0.0, rl = sqrt(cfg->rc2[0]) + cfg->skin;
+        for (int s = 0; s < n_sys; s++) {
+            const double L = boxes[3 * s];
+            rho = std::max(rho, (double)(offsets[s + 1] - offsets[s]) / (L * L * L));
+        }
+        const double est = 1.3 * rho * 4.0 / 3.0 * M_PI * rl * rl * rl + 8.0;
+        int maxn = std::max(cfg->max_neighbors, (int)std::min(est, 1024.0));
+        b->maxn = (maxn + 7) / 8 * 8;
+        b->lists = true;
+        A((void **)&b->nbr, (size_t)2 * b->maxn * n);
+        A((void **)&b->bcnt, 4 * n);
+    }
     if (ok && hipHostMalloc((void **)&b->host_flags, 16, 0) != hipSuccess) ok = false;
     if (ok) ok = hipMemcpy(b->sys, b->hsys.data(), sizeof(BSys) * n_sys, hipMemcpyHostToDevice) == hipSuccess;
     if (ok) ok = hipMemcpy(b->d_offs, offsets, sizeof(int64_t) * (n_sys + 1), hipMemcpyHostToDevice) == hipSuccess;
@@ -758,6 +889,10 @@ static int batch_rebuild(md_batch *b, double *pos, void *vel, void *force, int32
                                                         (const float *)force, type, ids, b->tpos, (float *)b->tvel,
                                                         (float *)b->tforce, b->ttype, b->tids, b->cell_id,
                                                         b->cell_sorted, b->stage, b->stage_ref);
+        if (b->lists)
+            k_bslab<kSlabBuild><<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, b->tpos, n, b->sys,
+                                                                   b->cell_start, b->cell_sorted, nullptr, nullptr,
+                                                                   b->sys_lds, b->nbr, b->bcnt, b->maxn);
         MD_HIP(hipMemcpyAsync(pos, b->tpos, 24 * (size_t)n, hipMemcpyDeviceToDevice, s));
         MD_HIP(hipMemcpyAsync(vel, b->tvel, 3 * rs * n, hipMemcpyDeviceToDevice, s));
         MD_HIP(hipMemcpyAsync(force, b->tforce, 3 * rs * n, hipMemcpyDeviceToDevice, s));
@@ -775,10 +910,16 @@ static void batch_forces(md_batch *b, const double *pos, void *force, bool energ
     if (b->cfg.precision == MD_FP64)
         k_bforce<double><<<bblocks(n), 256, 0, s>>>(n, b->stage, pos, b->sys_of, b->sys, b->cell_start,
                                                     b->cell_sorted, (double *)force, energy ? b->pe : nullptr);
+    else if (b->lists)
+        k_bslab<kSlabList><<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, pos, n, b->sys,
+                                                              b->cell_start, b->cell_sorted, (float *)force,
+                                                              energy ? b->pe : nullptr, b->sys_lds, b->nbr, b->bcnt,
+                                                              b->maxn);
     else
-        k_bforce_slab<<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, pos, n, b->sys,
-                                                         b->cell_start, b->cell_sorted, (float *)force,
-                                                         energy ? b->pe : nullptr, b->sys_lds);
+        k_bslab<kSlabCells><<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, pos, n, b->sys,
+                                                               b->cell_start, b->cell_sorted, (float *)force,
+                                                               energy ? b->pe : nullptr, b->sys_lds, nullptr, nullptr,
+                                                               0);
 }
 
 static void batch_integrate(md_batch *b, double *pos, void *vel, const void *force, const int32_t *type,

@@ -1,6 +1,7 @@
 """Batched independent systems through the C-ABI: per-system forces and
-energies against the FP64 oracle, the batched time step against the oracle's
-trajectories, and graph replays against eager execution."""
+energies against the FP64 oracle (linked cells in both precisions, Verlet
+lists in FP32), the batched time step against the oracle's trajectories, and
+graph replays against eager execution."""
 import numpy as np
 import pytest
 
@@ -36,11 +37,12 @@ def _concat(syss):
 
 
 class Dev:
-    def __init__(self, M, syss, prec, R=5, csf=1.0, skin=0.3):
+    def __init__(self, M, syss, prec, R=5, csf=1.0, skin=0.3, container=0, max_neighbors=160):
         import torch
         self.offs, pos, vel, boxes = _concat(syss)
         n = pos.shape[1]
-        cfg = make_config(n, boxes[0], container=0, precision=prec, R=R, csf=csf, skin=skin)
+        cfg = make_config(n, boxes[0], container=container, precision=prec, R=R, csf=csf, skin=skin,
+                          max_neighbors=max_neighbors)
         self.b = M.md_batch_create(cfg, self.offs, boxes)
         real = self.b.real
         self.pos = torch.tensor(pos, dtype=torch.float64, device="cuda")
@@ -59,11 +61,11 @@ class Dev:
         return out
 
 
-@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
-def test_batched_forces_match_oracle(orc, M, prec):
+@pytest.mark.parametrize("prec,container", [(1, 0), (0, 0), (0, 1)], ids=["fp64", "fp32", "fp32-vl"])
+def test_batched_forces_match_oracle(orc, M, prec, container):
     import torch
     syss = _systems()
-    d = Dev(M, syss, prec)
+    d = Dev(M, syss, prec, container=container)
     M.md_batch_build_cells(d.b, d.pos, d.vel, d.force, d.type, d.ids)
     out = torch.zeros(4 * len(syss), dtype=torch.float64, device="cuda")
     M.md_batch_compute_forces(d.b, d.pos, d.type, d.lj, d.force, out)
@@ -86,22 +88,25 @@ def test_batched_forces_match_oracle(orc, M, prec):
         assert abs(out[s, 1] - W0) <= tolE * abs(W0), s
 
 
+@pytest.mark.parametrize("container", [0, 1], ids=["lc", "vl"])
 @pytest.mark.parametrize("csf", [1.0, 0.5], ids=["csf1", "csf05"])
-def test_batched_fp32_slab_items(orc, M, csf):
+def test_batched_fp32_slab_items(orc, M, csf, container):
     """FP32 forces of systems the force kernel splits differently: a system
     staged whole in LDS (300 particles), systems cut into z-slabs (4,000 and
     14,000), and a system packed into one corner of its box (6,000 particles in
     an eighth of the volume), whose slabs are sized from the mean density so
     that the dense ones overflow the LDS tile and read global memory.  At
     CSF 1/2 the stencil reaches two cells each way (rows of five cells, halos
-    of two layers)."""
+    of two layers).  With Verlet lists the lists are built over the same
+    items (LDS indices where the item is staged, indices in the system where
+    it reads global memory)."""
     import torch
     corner = W.batched_systems(n_sys=1, n_min=6000, n_max=6000, seed=44)[0]
     corner = dict(corner, box=2.0 * corner["box"])
     syss = (W.batched_systems(n_sys=2, n_min=300, n_max=300, seed=41)
             + W.batched_systems(n_sys=2, n_min=4000, n_max=4000, seed=42)
             + W.batched_systems(n_sys=1, n_min=14000, n_max=14000, seed=43) + [corner])
-    d = Dev(M, syss, 0, csf=csf)
+    d = Dev(M, syss, 0, csf=csf, container=container)
     M.md_batch_build_cells(d.b, d.pos, d.vel, d.force, d.type, d.ids)
     out = torch.zeros(4 * len(syss), dtype=torch.float64, device="cuda")
     M.md_batch_compute_forces(d.b, d.pos, d.type, d.lj, d.force, out)
@@ -186,3 +191,75 @@ def test_graph_replays_equal_eager(M):
         results.append(snaps)
     for a, b in zip(*results):
         assert np.array_equal(a, b)
+
+
+def test_batched_list_overflow_falls_back(orc, M):
+    """Verlet lists whose capacity the clumped system outgrows: the batch's
+    only system holds 6,000 particles in an eighth of its box, so the capacity
+    estimated from its mean density (1.3 times the mean count within the list
+    radius plus 8, in whole chunks of 8; max_neighbors 8 is lower) is below
+    the partners of a particle inside the clump.  Those particles take their
+    forces from the stencil instead; every force and the pair count still
+    match the oracle."""
+    import torch
+    corner = W.batched_systems(n_sys=1, n_min=6000, n_max=6000, seed=44)[0]
+    corner = dict(corner, box=2.0 * corner["box"])
+    syss = [corner]
+    d = Dev(M, syss, 0, container=1, max_neighbors=8)
+    M.md_batch_build_cells(d.b, d.pos, d.vel, d.force, d.type, d.ids)
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    M.md_batch_compute_forces(d.b, d.pos, d.type, d.lj, d.force, out)
+    torch.cuda.synchronize()
+    F = d.by_id(d.force)
+    out = out.cpu().numpy()
+    F0, U0, W0, P0 = orc.forces(corner["pos"], corner["box"], orc.single())
+    # the mean particle has more partners within r_c alone than the capacity
+    n = corner["pos"].shape[1]
+    rho = n / float(corner["box"][0]) ** 3
+    cap = 8 * int(np.ceil(max(8, int(1.3 * rho * 4 / 3 * np.pi * 2.8 ** 3 + 8)) / 8))
+    assert 2 * P0 / n > 1.5 * cap
+    assert int(out[2]) == P0
+    assert_forces(F, F0, False)
+    assert abs(out[0] - U0) <= 1e-6 * abs(U0)
+
+
+def test_batched_lists_step_fp32(orc, M):
+    """Forty FP32 steps with Verlet lists, graph-captured after the first
+    interval: positions within 1e-6 of the oracle's FP64 trajectories, and the
+    same steps with linked cells agree with them as closely."""
+    import torch
+    syss = _systems(n_sys=6, n_max=900, seed=7)
+    X = {}
+    for container in (0, 1):
+        d = Dev(M, syss, 0, R=5, container=container)
+        M.md_batch_build_cells(d.b, d.pos, d.vel, d.force, d.type, d.ids)
+        M.md_batch_compute_forces(d.b, d.pos, d.type, d.lj, d.force)
+        M.md_batch_step(d.b, d.pos, d.vel, d.force, d.type, d.ids, d.im, d.lj, 0.005, 40, use_graph=True)
+        torch.cuda.synchronize()
+        X[container] = d.by_id(d.pos)
+    for s, sy in enumerate(syss):
+        p1, _, _, _ = orc.velocity_verlet(sy["pos"], sy["vel"], sy["box"], orc.single(), 0.005, 40)
+        r = slice(d.offs[s], d.offs[s + 1])
+        for container in (0, 1):
+            dx = X[container][:, r] - p1
+            dx -= sy["box"][0] * np.rint(dx / sy["box"][0])
+            assert np.abs(dx).max() < 1e-6, (s, container)
+
+
+def test_batched_lists_rejected_outside_their_range(M):
+    """Batched Verlet lists are FP32, gather-only, for systems of at most
+    65536 particles (16-bit entries); anything else is refused at creation."""
+    syss = _systems(n_sys=2, n_max=400, seed=3)
+    offs, pos, vel, boxes = _concat(syss)
+    n = pos.shape[1]
+    for kw in (dict(precision=1), dict(newton3=1)):
+        cfg = make_config(n, boxes[0], container=1, **{"precision": 0, **kw})
+        with pytest.raises(RuntimeError):
+            M.md_batch_create(cfg, offs, boxes)
+    big = np.array([0, 70000], np.int64)
+    cfg = make_config(70000, [40.0] * 3, container=1, precision=0)
+    with pytest.raises(RuntimeError, match="65536"):
+        M.md_batch_create(cfg, big, np.array([[40.0] * 3]))
+    cfg = make_config(n, boxes[0], container=2, precision=0)
+    with pytest.raises(RuntimeError):
+        M.md_batch_create(cfg, offs, boxes)

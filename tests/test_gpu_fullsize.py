@@ -48,12 +48,13 @@ def test_inhomogeneous_2m_forces(orc, kind):
         del s
 
 
-def test_batched_4096_systems(orc):
-    """All 4096 systems in one batch: forces and energies of 16 sampled
-    systems (the smallest and largest boxes among them) against the oracle,
-    every system's pair count against the cell-list oracle's total, and ten
-    graph-captured steps of four sampled systems against the oracle's
-    trajectories."""
+@pytest.mark.parametrize("container", [0, 1], ids=["lc", "vl"])
+def test_batched_4096_systems(orc, container):
+    """All 4096 systems in one batch (linked cells, or Verlet lists): forces
+    and energies of 16 sampled systems (the smallest and largest boxes among
+    them) against the oracle, every system's pair count against the
+    cell-list oracle's total, and ten graph-captured steps of four sampled
+    systems against the oracle's trajectories."""
     import torch
     syss = W.batched_systems()
     assert len(syss) == 4096
@@ -63,7 +64,7 @@ def test_batched_4096_systems(orc):
     vel = np.concatenate([s["vel"] for s in syss], axis=1)
     boxes = np.stack([s["box"] for s in syss])
     n = pos.shape[1]
-    cfg = make_config(n, boxes[0], container=0, precision=0, R=5)
+    cfg = make_config(n, boxes[0], container=container, precision=0, R=5)
     b = M.md_batch_create(cfg, offs, boxes)
     dpos = torch.tensor(pos, dtype=torch.float64, device="cuda")
     dvel = torch.tensor(vel, dtype=torch.float32, device="cuda")
