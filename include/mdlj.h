@@ -289,7 +289,14 @@ const char *md_last_error(void);
  * [offsets[s], offsets[s+1]) of every particle array, and offsets (HOST
  * int64[n_sys + 1]) is non-decreasing from 0.  boxes is HOST double[3 n_sys].
  * The per-pair cutoffs, skin, csf and precision come from cfg (cfg->n and
- * cfg->box are ignored).  Only linked cells, gather-only, FP32 or FP64. */
+ * cfg->box are ignored).  cfg->container is MD_CONTAINER_LC (FP32 or FP64)
+ * or MD_CONTAINER_VL (FP32, every system at most 65536 particles), newton3
+ * MD_N3L_OFF; anything else is MD_ERR_INVALID_ARG.  The Verlet lists are
+ * built with the cells (Sec. 2.2.1: every pair within r_c + skin), with room
+ * per particle for max(max_neighbors, min(1024, 1.3 times the mean count
+ * within the list radius of the densest system + 8)) entries, rounded up to
+ * a multiple of 8; a particle with more walks its cell stencil instead (same
+ * forces, more time). */
 typedef struct md_batch md_batch;
 
 int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_t *offsets,
@@ -297,7 +304,8 @@ int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_t *offsets,
 void md_batch_destroy(md_batch *b);
 
 /* Bin every system into its own cells and reorder the arrays in place (cell
- * order within each system's range; systems keep their ranges). */
+ * order within each system's range; systems keep their ranges); with Verlet
+ * lists, build them. */
 int md_batch_build_cells(md_batch *b, double *pos, void *vel, void *force,
                          int32_t *type, int32_t *ids, void *stream);
 

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "pair.h"
@@ -302,7 +303,7 @@ struct BChunk {
     }
 };
 
-template <int MODE>
+template <int MODE, bool ENERGY>
 __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, const int64_t *__restrict__ offs,
                                                const int4 *__restrict__ st, const double *__restrict__ pos, int n,
                                                const BSys *__restrict__ sys, const int32_t *__restrict__ cs,
@@ -368,23 +369,14 @@ __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, c
         const int4 pi = st[i];
         float fx = 0.f, fy = 0.f, fz = 0.f, eus = 0.f, ews = 0.f;
         int np = 0;
-        // pair with partner j (its global index, or with staged its LDS index,
-        // converted only for a guard-band decision)
-        auto pair = [&](int j, bool staged, bool valid, int qx, int qy, int qz) {
+        // pair with partner jg (global index) in the cell traversal
+        auto pair = [&](int jg, int qx, int qy, int qz) {
             float dx = (float)(int)((uint32_t)pi.x - (uint32_t)qx);
             float dy = (float)(int)((uint32_t)pi.y - (uint32_t)qy);
             float dz = (float)(int)((uint32_t)pi.z - (uint32_t)qz);
             float r2 = dx * dx + dy * dy + dz * dz;
-            bool in = valid && r2 < lo;
-            if (valid && r2 >= lo && r2 < hi) {
-                int jg = j;
-                if (staged) {
-                    int k = 0;
-                    while (lb[k + 1] <= j) k++;
-                    jg = j + gofs[k] + p0;
-                }
-                in = exact_r2(pos, n, i, jg, L, L, L) < rc2;
-            }
+            bool in = r2 < lo;
+            if (r2 >= lo && r2 < hi) in = exact_r2(pos, n, i, jg, L, L, L) < rc2;
             float ir2 = __builtin_amdgcn_rcpf(r2);
             float s2 = sig2 * ir2;
             float q = s2 * s2 * s2;
@@ -393,7 +385,7 @@ __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, c
             fx += phi * dx;
             fy += phi * dy;
             fz += phi * dz;
-            if (pe) {
+            if (ENERGY) {
                 eus += in ? eps4 * q * (q - 1.0f) : 0.0f;
                 ews += in ? eps24w * aa : 0.0f;
                 np += in ? 1 : 0;
@@ -408,7 +400,7 @@ __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, c
                 c++;
                 if ((c & 7) == 0 && c <= maxn) row[(size_t)((c >> 3) - 1) * N] = make_uint4(ck.w[0], ck.w[1], ck.w[2], ck.w[3]);
             } else {
-                pair(jg, false, true, qx, qy, qz);
+                pair(jg, qx, qy, qz);
             }
         };
         bool stencil = true;
@@ -416,23 +408,93 @@ __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, c
             const int cl = cnt[i];
             if (cl <= maxn) {
                 stencil = false;
-                const uint4 *lrow = nbr + i;
-                uint4 nx = cl > 0 ? lrow[0] : make_uint4(0u, 0u, 0u, 0u);
-                for (int q0 = 0; q0 < cl; q0 += 8) {
-                    const uint32_t w[4] = {nx.x, nx.y, nx.z, nx.w};
-                    if (q0 + 8 < cl) nx = lrow[(size_t)((q0 >> 3) + 1) * N];  // the next chunk in flight
-#pragma unroll
-                    for (int u = 0; u < 8; u++) {
-                        const int e = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
-                        const bool valid = q0 + u < cl;
-                        if (tile) {
+                // sums in units of the one type's factors (24 eps for the
+                // force and the virial, 4 eps for the energy), applied once
+                float gx = 0.f, gy = 0.f, gz = 0.f, gu = 0.f, gw = 0.f;
+                const uint32_t lob = __float_as_uint(lo), wb = __float_as_uint(hi) - lob;
+                auto walk = [&](auto tile_c) {
+                    constexpr bool TILE = decltype(tile_c)::value;
+                    auto at = [&](int e, float &dx, float &dy, float &dz) {
+                        int qx, qy, qz;
+                        if (TILE) {
                             const int *q = pp + 3 * e;
-                            pair(e, true, valid, q[0], q[1], q[2]);
+                            qx = q[0];
+                            qy = q[1];
+                            qz = q[2];
                         } else {
                             const int4 q = st[p0 + e];
-                            pair(p0 + e, false, valid, q.x, q.y, q.z);
+                            qx = q.x;
+                            qy = q.y;
+                            qz = q.z;
+                        }
+                        dx = (float)(int)((uint32_t)pi.x - (uint32_t)qx);
+                        dy = (float)(int)((uint32_t)pi.y - (uint32_t)qy);
+                        dz = (float)(int)((uint32_t)pi.z - (uint32_t)qz);
+                        return dx * dx + dy * dy + dz * dz;
+                    };
+                    auto add = [&](float r2, float dx, float dy, float dz, bool in) {
+                        // a pair outside gets 1/r^2 = 0, which zeroes every term
+                        float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.0f;
+                        float s2 = sig2 * ir2;
+                        float q = s2 * s2 * s2;
+                        float aa = q * (2.0f * q - 1.0f);
+                        float phi = ir2 * aa;
+                        gx += phi * dx;
+                        gy += phi * dy;
+                        gz += phi * dz;
+                        if (ENERGY) {
+                            gu += q * (q - 1.0f);
+                            gw += aa;
+                            np += in ? 1 : 0;
+                        }
+                    };
+                    const uint4 *lrow = nbr + i;
+                    uint4 nx = lrow[0];
+                    for (int q0 = 0; q0 < cl; q0 += 8) {
+                        const uint32_t w[4] = {nx.x, nx.y, nx.z, nx.w};
+                        if (q0 + 8 < cl) nx = lrow[(size_t)((q0 >> 3) + 1) * N];  // the next chunk in flight
+                        bool band = false;
+#pragma unroll
+                        for (int u = 0; u < 8; u++) {
+                            const int e = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
+                            const bool valid = q0 + u < cl;
+                            float dx, dy, dz;
+                            const float r2 = at(e, dx, dy, dz);
+                            band = band || (valid && __float_as_uint(r2) - lob < wb);
+                            add(r2, dx, dy, dz, valid && r2 < lo);
+                        }
+                        if (band) {
+                            // rare: the chunk's guard-band entries, decided
+                            // from the FP64 positions
+                            for (int u = 0; u < 8 && q0 + u < cl; u++) {
+                                const int e = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
+                                float dx, dy, dz;
+                                const float r2 = at(e, dx, dy, dz);
+                                if (__float_as_uint(r2) - lob < wb) {
+                                    int jg = p0 + e;
+                                    if (TILE) {
+                                        int k = 0;
+                                        while (lb[k + 1] <= e) k++;
+                                        jg = e + gofs[k] + p0;
+                                    }
+                                    add(r2, dx, dy, dz, exact_r2(pos, n, i, jg, L, L, L) < rc2);
+                                }
+                            }
                         }
                     }
+                };
+                if (cl > 0) {
+                    if (tile)
+                        walk(std::true_type{});
+                    else
+                        walk(std::false_type{});
+                }
+                fx = eps24 * gx;
+                fy = eps24 * gy;
+                fz = eps24 * gz;
+                if (ENERGY) {
+                    eus = eps4 * gu;
+                    ews = eps24w * gw;
                 }
             }
         }
@@ -440,6 +502,34 @@ __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, c
             const int local = cell_sorted[i] - cbase;
             const int cx = local % nc, cy = (local / nc) % nc, cz = local / nc2;
             const int self = tile ? il - gofs[(cz - zlo + nc) % nc] : 0;  // the particle's LDS index
+            // staged candidates jb .. je - 1 (LDS indices; layer offset gz):
+            // tested 32 at a time, the hits passed on
+            auto scan = [&](int jb, int je, int gz) {
+                for (int base = jb; base < je; base += 32) {
+                    const int m = min(32, je - base);
+                    uint32_t mask = 0;
+                    int nb = 0;
+                    for (; nb < m; nb += 4)
+                        for (int u = 0; u < 4; u++) {
+                            const int *q = pp + 3 * (base + nb + u);
+                            float dx = (float)(int)((uint32_t)pi.x - (uint32_t)q[0]);
+                            float dy = (float)(int)((uint32_t)pi.y - (uint32_t)q[1]);
+                            float dz = (float)(int)((uint32_t)pi.z - (uint32_t)q[2]);
+                            float r2 = dx * dx + dy * dy + dz * dz;
+                            mask = mask + mask + (r2 < thr ? 1u : 0u);
+                        }
+                    mask >>= nb - m;  // the reads past the batch
+                    unsigned us = (unsigned)(self - base);
+                    if (us < (unsigned)m) mask &= ~(1u << (m - 1 - us));
+                    while (mask) {
+                        int hb = 31 - __builtin_clz(mask);
+                        mask ^= 1u << hb;
+                        int jl = base + m - 1 - hb;
+                        const int *q = pp + 3 * jl;
+                        hit(jl, jl + gz, q[0], q[1], q[2]);
+                    }
+                }
+            };
             for (int a = 0; a < nofs; a++) {
                 int zz = cz + b.ofs[a];
                 zz = zz >= nc ? zz - nc : zz;
@@ -453,31 +543,7 @@ __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, c
                         xx = xx >= nc ? xx - nc : xx;
                         if (tile) {
                             const int cc = (k * nc + yy) * nc + xx;
-                            const int jb = scs[cc], je = scs[cc + 1];
-                            for (int base = jb; base < je; base += 32) {
-                                const int m = min(32, je - base);
-                                uint32_t mask = 0;
-                                int nb = 0;
-                                for (; nb < m; nb += 4)
-                                    for (int u = 0; u < 4; u++) {
-                                        const int *q = pp + 3 * (base + nb + u);
-                                        float dx = (float)(int)((uint32_t)pi.x - (uint32_t)q[0]);
-                                        float dy = (float)(int)((uint32_t)pi.y - (uint32_t)q[1]);
-                                        float dz = (float)(int)((uint32_t)pi.z - (uint32_t)q[2]);
-                                        float r2 = dx * dx + dy * dy + dz * dz;
-                                        mask = mask + mask + (r2 < thr ? 1u : 0u);
-                                    }
-                                mask >>= nb - m;  // the reads past the batch
-                                unsigned us = (unsigned)(self - base);
-                                if (us < (unsigned)m) mask &= ~(1u << (m - 1 - us));
-                                while (mask) {
-                                    int hb = 31 - __builtin_clz(mask);
-                                    mask ^= 1u << hb;
-                                    int jl = base + m - 1 - hb;
-                                    const int *q = pp + 3 * jl;
-                                    hit(jl, jl + gz, q[0], q[1], q[2]);
-                                }
-                            }
+                            scan(scs[cc], scs[cc + 1], gz);
                         } else {
                             const int cc = cbase + (zz * nc + yy) * nc + xx;
                             const int jb = cs[cc], je = cs[cc + 1];
@@ -508,7 +574,7 @@ __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, c
             F[i] = fx;
             F[N + i] = fy;
             F[2 * N + i] = fz;
-            if (pe) {
+            if (ENERGY) {
                 pe[i] = eus;
                 pe[N + i] = ews;
                 pe[2 * N + i] = (double)np;
@@ -890,7 +956,7 @@ static int batch_rebuild(md_batch *b, double *pos, void *vel, void *force, int32
                                                         (float *)b->tforce, b->ttype, b->tids, b->cell_id,
                                                         b->cell_sorted, b->stage, b->stage_ref);
         if (b->lists)
-            k_bslab<kSlabBuild><<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, b->tpos, n, b->sys,
+            k_bslab<kSlabBuild, false><<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, b->tpos, n, b->sys,
                                                                    b->cell_start, b->cell_sorted, nullptr, nullptr,
                                                                    b->sys_lds, b->nbr, b->bcnt, b->maxn);
         MD_HIP(hipMemcpyAsync(pos, b->tpos, 24 * (size_t)n, hipMemcpyDeviceToDevice, s));
@@ -910,16 +976,17 @@ static void batch_forces(md_batch *b, const double *pos, void *force, bool energ
     if (b->cfg.precision == MD_FP64)
         k_bforce<double><<<bblocks(n), 256, 0, s>>>(n, b->stage, pos, b->sys_of, b->sys, b->cell_start,
                                                     b->cell_sorted, (double *)force, energy ? b->pe : nullptr);
-    else if (b->lists)
-        k_bslab<kSlabList><<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, pos, n, b->sys,
-                                                              b->cell_start, b->cell_sorted, (float *)force,
-                                                              energy ? b->pe : nullptr, b->sys_lds, b->nbr, b->bcnt,
-                                                              b->maxn);
-    else
-        k_bslab<kSlabCells><<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, pos, n, b->sys,
-                                                               b->cell_start, b->cell_sorted, (float *)force,
-                                                               energy ? b->pe : nullptr, b->sys_lds, nullptr, nullptr,
-                                                               0);
+    else {
+        auto go = [&](auto kern) {
+            kern<<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, pos, n, b->sys, b->cell_start,
+                                                     b->cell_sorted, (float *)force, energy ? b->pe : nullptr,
+                                                     b->sys_lds, b->nbr, b->bcnt, b->maxn);
+        };
+        if (b->lists)
+            energy ? go(k_bslab<kSlabList, true>) : go(k_bslab<kSlabList, false>);
+        else
+            energy ? go(k_bslab<kSlabCells, true>) : go(k_bslab<kSlabCells, false>);
+    }
 }
 
 static void batch_integrate(md_batch *b, double *pos, void *vel, const void *force, const int32_t *type,
