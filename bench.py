@@ -504,11 +504,16 @@ def bench_batched(M, W, steps, warmup, sample=64):
     n = int(offs[-1])
     dev = "cuda"
 
+    # each container at its best skin of a sweep over 0.3-0.6 (the lists rebuild every 4 steps
+    # at 0.4, every 3 at 0.3; the cells gain nothing from a wider skin)
+    skin = {M.MD_CONTAINER_VL: 0.4, M.MD_CONTAINER_LC: 0.3}
+
     def cfg_for(nn, box, R=5, container=M.MD_CONTAINER_VL):
         c = M.config_default(nn, float(box[0]))
         c.precision = M.MD_FP32
         c.container = container
         c.rebuild_interval = R
+        c.skin = skin[container]
         return c
 
     lj = torch.tensor([1.0, 1.0], dtype=torch.float64, device=dev)
@@ -571,7 +576,8 @@ def bench_batched(M, W, steps, warmup, sample=64):
             "warmup": warmup, "ms_per_step": 1e3 * res[True], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "lj-batched-4096", "systems": nsys, "n": n, "pairs_per_step": pairs,
-                       "container": "Verlet lists CSF 1, gather-only", "rebuild_interval_max": 5,
+                       "container": "Verlet lists CSF 1, gather-only", "skin": skin[M.MD_CONTAINER_VL],
+                       "linked_cells_skin": skin[M.MD_CONTAINER_LC], "rebuild_interval_max": 5,
                        "rebuild_interval_at_end": bc["rebuild_interval"], "dt": 0.005},
             "batch_counters": bc,
             "direct_launches_ms_per_step": 1e3 * res[False],
