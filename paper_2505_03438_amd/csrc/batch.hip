@@ -303,13 +303,109 @@ struct BChunk {
     }
 };
 
-template <int MODE, bool ENERGY>
+// Velocity Verlet update of particle i (the single-system integrator's
+// steps, per-system box): with kick_prev the second half kick of the last
+// step, with start the first half kick, drift, wrap, staging and skin check
+// of the next (step: its index in the block, for the check).  The inputs are
+// loaded first (bload) so that a force pass can have them in flight during
+// its pair loop; positions are written to pos_out (the array they were read
+// from in the integrator pass; another one when the force pass integrates,
+// since other work items still read the current positions).
+template <typename real>
+struct BState {
+    real vx, vy, vz;
+    double x, y, z;
+    int t, s;
+    int4 ref;
+};
+
+template <typename real>
+__device__ __forceinline__ BState<real> bload(int i, size_t N, const double *pos_in, const real *v,
+                                              const int32_t *__restrict__ type, const int32_t *__restrict__ sys_of,
+                                              const int4 *__restrict__ stage_ref)
+{
+    BState<real> b;
+    b.vx = v[i];
+    b.vy = v[N + i];
+    b.vz = v[2 * N + i];
+    b.x = pos_in[i];
+    b.y = pos_in[N + i];
+    b.z = pos_in[2 * N + i];
+    b.t = type[i];
+    b.s = sys_of[i];
+    b.ref = stage_ref[i];
+    return b;
+}
+
+template <typename real>
+__device__ __forceinline__ void bupdate(int i, size_t N, const BState<real> &p, real fx, real fy, real fz,
+                                        double *pos_out, real *__restrict__ v, const double *__restrict__ inv_mass,
+                                        const BSys *__restrict__ sys, double hdt, double dt, int kick_prev,
+                                        int start, int step, int4 *__restrict__ stage, int32_t *__restrict__ flags)
+{
+#pragma clang fp contract(off)
+    real c = (real)(hdt * inv_mass[p.t]);
+    real vx = p.vx, vy = p.vy, vz = p.vz;
+    real ax = c * fx, ay = c * fy, az = c * fz;
+    if (kick_prev) {
+        vx += ax;
+        vy += ay;
+        vz += az;
+    }
+    if (start) {
+        vx += ax;
+        vy += ay;
+        vz += az;
+        const BSys &b = sys[p.s];
+        double L = b.L;
+        double xs[3] = {p.x + dt * (double)vx, p.y + dt * (double)vy, p.z + dt * (double)vz};
+        uint32_t q[3];
+        for (int d = 0; d < 3; d++) {
+            double x = xs[d];
+            if (x >= L) x -= L;
+            else if (x < 0.0) x += L;
+            if (x >= L) x = 0.0;
+            pos_out[d * N + i] = x;
+            q[d] = bquant(x, b.S);
+            if (!(x == x)) atomicOr(&flags[0], (int)MD_FLAG_NONFINITE);
+        }
+        stage[i] = make_int4((int)q[0], (int)q[1], (int)q[2], p.t);
+        float dx = (float)(int)(q[0] - (uint32_t)p.ref.x);
+        float dy = (float)(int)(q[1] - (uint32_t)p.ref.y);
+        float dz = (float)(int)(q[2] - (uint32_t)p.ref.z);
+        if (dx * dx + dy * dy + dz * dz >= b.disp2) {
+            atomicOr(&flags[0], (int)MD_FLAG_SKIN_EXCEEDED);
+            atomicMin(&flags[1], step);
+        }
+    }
+    v[i] = vx;
+    v[N + i] = vy;
+    v[2 * N + i] = vz;
+}
+
+// The next step's update fused into a force pass: the arrays and constants
+// of bload and bupdate; positions and staged positions go to pos_out and
+// stage_out.
+struct BFuse {
+    double *pos_out;
+    float *v;
+    const int32_t *type;
+    const double *inv_mass;
+    const int32_t *sys_of;
+    double hdt, dt;
+    int step;
+    int4 *stage_out;
+    const int4 *stage_ref;
+    int32_t *flags;
+};
+
+template <int MODE, bool ENERGY, bool FUSED = false>
 __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, const int64_t *__restrict__ offs,
                                                const int4 *__restrict__ st, const double *__restrict__ pos, int n,
                                                const BSys *__restrict__ sys, const int32_t *__restrict__ cs,
                                                const int32_t *__restrict__ cell_sorted, float *__restrict__ F,
                                                double *__restrict__ pe, int lds_bytes, uint4 *__restrict__ nbr,
-                                               int32_t *__restrict__ cnt, int maxn)
+                                               int32_t *__restrict__ cnt, int maxn, BFuse fu)
 {
     extern __shared__ int sm[];
     const int4 it = items[blockIdx.x];
@@ -367,6 +463,8 @@ __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, c
     for (int il = i0 + (int)threadIdx.x; il < i1; il += blockDim.x) {
         const int i = p0 + il;
         const int4 pi = st[i];
+        BState<float> up;  // the next step's update: inputs in flight during the pair loop
+        if (FUSED) up = bload<float>(i, N, pos, fu.v, fu.type, fu.sys_of, fu.stage_ref);
         float fx = 0.f, fy = 0.f, fz = 0.f, eus = 0.f, ews = 0.f;
         int np = 0;
         // pair with partner jg (global index) in the cell traversal
@@ -574,6 +672,9 @@ __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, c
             F[i] = fx;
             F[N + i] = fy;
             F[2 * N + i] = fz;
+            if (FUSED)
+                bupdate<float>(i, N, up, fx, fy, fz, fu.pos_out, fu.v, fu.inv_mass, sys, fu.hdt, fu.dt, 1, 1, fu.step,
+                               fu.stage_out, fu.flags);
             if (ENERGY) {
                 pe[i] = eus;
                 pe[N + i] = ews;
@@ -592,49 +693,12 @@ __global__ __launch_bounds__(256) void k_bintegrate(int n, double *__restrict__ 
                                                     int start, int step, int4 *__restrict__ stage,
                                                     const int4 *__restrict__ stage_ref, int32_t *__restrict__ flags)
 {
-#pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     size_t N = (size_t)n;
-    int t = type[i];
-    real c = (real)(hdt * inv_mass[t]);
-    real vx = v[i], vy = v[N + i], vz = v[2 * N + i];
-    real ax = c * F[i], ay = c * F[N + i], az = c * F[2 * N + i];
-    if (kick_prev) {
-        vx += ax;
-        vy += ay;
-        vz += az;
-    }
-    if (start) {
-        vx += ax;
-        vy += ay;
-        vz += az;
-        const BSys &b = sys[sys_of[i]];
-        double L = b.L;
-        double xs[3] = {pos[i] + dt * (double)vx, pos[N + i] + dt * (double)vy, pos[2 * N + i] + dt * (double)vz};
-        uint32_t q[3];
-        for (int d = 0; d < 3; d++) {
-            double x = xs[d];
-            if (x >= L) x -= L;
-            else if (x < 0.0) x += L;
-            if (x >= L) x = 0.0;
-            pos[d * N + i] = x;
-            q[d] = bquant(x, b.S);
-            if (!(x == x)) atomicOr(&flags[0], (int)MD_FLAG_NONFINITE);
-        }
-        stage[i] = make_int4((int)q[0], (int)q[1], (int)q[2], t);
-        int4 r = stage_ref[i];
-        float dx = (float)(int)(q[0] - (uint32_t)r.x);
-        float dy = (float)(int)(q[1] - (uint32_t)r.y);
-        float dz = (float)(int)(q[2] - (uint32_t)r.z);
-        if (dx * dx + dy * dy + dz * dz >= b.disp2) {
-            atomicOr(&flags[0], (int)MD_FLAG_SKIN_EXCEEDED);
-            atomicMin(&flags[1], step);
-        }
-    }
-    v[i] = vx;
-    v[N + i] = vy;
-    v[2 * N + i] = vz;
+    const BState<real> p = bload<real>(i, N, pos, v, type, sys_of, stage_ref);
+    bupdate<real>(i, N, p, F[i], F[N + i], F[2 * N + i], pos, v, inv_mass, sys, hdt, dt, kick_prev, start, step,
+                  stage, flags);
 }
 
 // Per-system sums of the per-particle energy partials, in a fixed order.
@@ -697,6 +761,7 @@ struct md_batch {
     void *tvel = nullptr, *tforce = nullptr;
     int32_t *ttype = nullptr, *tids = nullptr;
     int4 *stage = nullptr, *stage_ref = nullptr;
+    int4 *stage2 = nullptr;  // FP32: the staged positions a fused force pass writes
     double *pe = nullptr;
     double *snap_pos = nullptr;
     void *snap_vel = nullptr;
@@ -719,7 +784,7 @@ static void batch_free(md_batch *b)
     void *p[] = {b->sys,   b->d_offs, b->items, b->sys_of, b->cell_id,  b->slot,      b->perm,       b->perm2,
                  b->count, b->cell_start, b->cell_sorted, b->scan, b->tpos,  b->tvel,       b->tforce,
                  b->ttype, b->tids,   b->stage,  b->stage_ref, b->pe,       b->snap_pos,   b->snap_vel, b->flags,
-                 b->nbr,   b->bcnt};
+                 b->nbr,   b->bcnt,   b->stage2};
     for (void *q : p)
         if (q) (void)hipFree(q);
     if (b->host_flags) (void)hipHostFree(b->host_flags);
@@ -877,6 +942,7 @@ extern "C" int md_batch_create(const md_config *cfg, int32_t n_sys, const int64_
     A((void **)&b->tids, 4 * n);
     A((void **)&b->stage, 16 * n);
     A((void **)&b->stage_ref, 16 * n);
+    if (cfg->precision == MD_FP32) A((void **)&b->stage2, 16 * n);
     A((void **)&b->pe, 24 * n);
     A((void **)&b->snap_pos, 24 * n);
     A(&b->snap_vel, 3 * rs * n);
@@ -956,9 +1022,9 @@ static int batch_rebuild(md_batch *b, double *pos, void *vel, void *force, int32
                                                         (float *)b->tforce, b->ttype, b->tids, b->cell_id,
                                                         b->cell_sorted, b->stage, b->stage_ref);
         if (b->lists)
-            k_bslab<kSlabBuild, false><<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, b->tpos, n, b->sys,
-                                                                   b->cell_start, b->cell_sorted, nullptr, nullptr,
-                                                                   b->sys_lds, b->nbr, b->bcnt, b->maxn);
+            k_bslab<kSlabBuild, false><<<b->n_items, 256, b->sys_lds, s>>>(
+                b->items, b->d_offs, b->stage, b->tpos, n, b->sys, b->cell_start, b->cell_sorted, nullptr, nullptr,
+                b->sys_lds, b->nbr, b->bcnt, b->maxn, BFuse{});
         MD_HIP(hipMemcpyAsync(pos, b->tpos, 24 * (size_t)n, hipMemcpyDeviceToDevice, s));
         MD_HIP(hipMemcpyAsync(vel, b->tvel, 3 * rs * n, hipMemcpyDeviceToDevice, s));
         MD_HIP(hipMemcpyAsync(force, b->tforce, 3 * rs * n, hipMemcpyDeviceToDevice, s));
@@ -969,23 +1035,34 @@ static int batch_rebuild(md_batch *b, double *pos, void *vel, void *force, int32
     return MD_OK;
 }
 
-static void batch_forces(md_batch *b, const double *pos, void *force, bool energy, hipStream_t s)
+// Forces at positions pos (staged copy st).  FP32 with fu: the pass also
+// advances every particle to the next step (BFuse).
+static void batch_forces(md_batch *b, const double *pos, void *force, bool energy, hipStream_t s,
+                         const int4 *st = nullptr, const BFuse *fu = nullptr)
 {
     int n = (int)b->n;
     if (n <= 0) return;
+    if (!st) st = b->stage;
     if (b->cfg.precision == MD_FP64)
-        k_bforce<double><<<bblocks(n), 256, 0, s>>>(n, b->stage, pos, b->sys_of, b->sys, b->cell_start,
+        k_bforce<double><<<bblocks(n), 256, 0, s>>>(n, st, pos, b->sys_of, b->sys, b->cell_start,
                                                     b->cell_sorted, (double *)force, energy ? b->pe : nullptr);
     else {
+        const BFuse f = fu ? *fu : BFuse{};
         auto go = [&](auto kern) {
-            kern<<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, b->stage, pos, n, b->sys, b->cell_start,
+            kern<<<b->n_items, 256, b->sys_lds, s>>>(b->items, b->d_offs, st, pos, n, b->sys, b->cell_start,
                                                      b->cell_sorted, (float *)force, energy ? b->pe : nullptr,
-                                                     b->sys_lds, b->nbr, b->bcnt, b->maxn);
+                                                     b->sys_lds, b->nbr, b->bcnt, b->maxn, f);
         };
-        if (b->lists)
+        if (fu) {
+            if (b->lists)
+                go(k_bslab<kSlabList, false, true>);
+            else
+                go(k_bslab<kSlabCells, false, true>);
+        } else if (b->lists) {
             energy ? go(k_bslab<kSlabList, true>) : go(k_bslab<kSlabList, false>);
-        else
+        } else {
             energy ? go(k_bslab<kSlabCells, true>) : go(k_bslab<kSlabCells, false>);
+        }
     }
 }
 
@@ -1057,6 +1134,26 @@ static int batch_block_ops(md_batch *b, const BatchCtx &c, int len, bool first_o
     if (n > 0) {
         MD_HIP(hipMemcpyAsync(b->snap_pos, c.pos, 24 * n, hipMemcpyDeviceToDevice, c.s));
         MD_HIP(hipMemcpyAsync(b->snap_vel, c.vel, 3 * rs * n, hipMemcpyDeviceToDevice, c.s));
+    }
+    if (b->cfg.precision == MD_FP32 && n > 0) {
+        // the force pass of step k - 1 also advances the particles to step k;
+        // positions and staged positions alternate between two buffers
+        // (other work items read the current ones during the pass), the
+        // cell build's output standing in for the second position buffer
+        double *cur = c.pos, *alt = b->tpos;
+        int4 *cst = b->stage, *ast = b->stage2;
+        for (int k = 1; k < len; k++) {
+            const BFuse fu{alt,   (float *)c.vel, c.type, c.inv_mass, b->sys_of, 0.5 * c.dt, c.dt, k,
+                           ast, b->stage_ref,   b->flags};
+            batch_forces(b, cur, c.force, false, c.s, cst, &fu);
+            std::swap(cur, alt);
+            std::swap(cst, ast);
+        }
+        batch_forces(b, cur, c.force, false, c.s, cst);
+        // the block ends with the positions in the caller's array (the next
+        // block's integrator and any restore stage them again from there)
+        if (cur != c.pos) MD_HIP(hipMemcpyAsync(c.pos, cur, 24 * n, hipMemcpyDeviceToDevice, c.s));
+        return MD_OK;
     }
     batch_forces(b, c.pos, c.force, false, c.s);
     for (int k = 1; k < len; k++) {
