@@ -653,8 +653,11 @@ static int ensure_cube_part(md_handle *h)
     return MD_OK;
 }
 
-// Verlet list cells: entries [maxn][n], segment ends [4][n], per-cube
-// energy partials [ncell][4].
+// Verlet list cells: a row of entries per particle, [n][ld] with ld the
+// capacity rounded up to a multiple of 8 (so that a row is whole 16-byte
+// chunks), segment ends [4][n], per-cube energy partials [ncell][4].
+static int vlc_ld(const md_handle *h) { return (h->cfg.max_neighbors + 7) & ~7; }
+
 static int ensure_vlc(md_handle *h, int32_t maxn)
 {
     Buffers &b = h->b;
@@ -666,7 +669,8 @@ static int ensure_vlc(md_handle *h, int32_t maxn)
         b.vlc_nbr = b.vlc_seg = nullptr;
         b.vlc_cap = 0;
         b.vlc_maxn = 0;
-        if ((rc = dalloc(&b.vlc_nbr, (size_t)maxn * n)) || (rc = dalloc(&b.vlc_seg, (size_t)4 * n))) return rc;
+        const size_t ld = (size_t)((maxn + 7) & ~7);
+        if ((rc = dalloc(&b.vlc_nbr, ld * n)) || (rc = dalloc(&b.vlc_seg, (size_t)4 * n))) return rc;
         b.vlc_cap = n;
         b.vlc_maxn = maxn;
     }
@@ -695,7 +699,7 @@ static int build_lists_impl(md_handle *h, const double *pos, hipStream_t s)
         if (rc) return rc;
         launch_fill_i32(b.flags + 2, 0, 1, s);
         launch_vlc_build(n, b.stage, b.cell_start, b.cell_sorted, pos, h->g, b.vlc_nbr, b.vlc_seg, b.nbr_count,
-                         h->cfg.max_neighbors, b.flags, s);
+                         vlc_ld(h), b.flags, s);
     } else if (h->cfg.container == MD_CONTAINER_PVL) {
         int rc = ensure_pvl(h);
         if (rc) return rc;
@@ -770,6 +774,7 @@ static ForceArgs force_args(md_handle *h, const double *pos, const int32_t *type
     a.pvl_cnt = h->b.pvl_cnt;
     a.vlc_nbr = h->b.vlc_nbr;
     a.vlc_seg = h->b.vlc_seg;
+    a.vlc_ld = vlc_ld(h);
     a.vlc_part = h->b.vlc_part;
     a.vlc_blocks = vlc_force_blocks(h->g);
     a.tab = h->b.tab;
@@ -1487,8 +1492,8 @@ extern "C" int md_get_neighbors(md_handle *h, int32_t *counts, int32_t *rows, in
     int n = (int)h->n;
     if (h->cfg.container == MD_CONTAINER_VLC) {
         const Buffers &b = h->b;
-        launch_vlc_rows(n, b.cell_start, b.cell_sorted, h->g, b.vlc_nbr, b.vlc_seg, max_per_row, counts, rows,
-                        (hipStream_t)stream);
+        launch_vlc_rows(n, b.cell_start, b.cell_sorted, h->g, b.vlc_nbr, vlc_ld(h), b.vlc_seg, max_per_row, counts,
+                        rows, (hipStream_t)stream);
     } else if (h->cfg.container == MD_CONTAINER_PVL) {
         const Buffers &b = h->b;
         launch_pvl_rows(n, b.cell_start, b.cell_sorted, h->g, b.pvl_perm, b.pvl_cnt, max_per_row, counts, rows,

@@ -15,6 +15,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "entry_chunk.h"
 #include "pair.h"
 
 namespace mdlj {
@@ -290,19 +291,6 @@ __host__ __device__ static inline int64_t bslab_table_words(int64_t K, int64_t n
     return 2 * K + 2 + K * nc2 + 12;
 }
 
-// Eight pending 16-bit list entries in four words: entry 2k in the low half
-// of word k, entry 2k + 1 in the high half once eight have been pushed.
-struct BChunk {
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
-    __device__ __forceinline__ void push(uint32_t e)
-    {
-        w[0] = (w[0] >> 16) | (w[1] << 16);
-        w[1] = (w[1] >> 16) | (w[2] << 16);
-        w[2] = (w[2] >> 16) | (w[3] << 16);
-        w[3] = (w[3] >> 16) | (e << 16);
-    }
-};
-
 // Velocity Verlet update of particle i (the single-system integrator's
 // steps, per-system box): with kick_prev the second half kick of the last
 // step, with start the first half kick, drift, wrap, staging and skin check
@@ -490,13 +478,13 @@ __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, c
             }
         };
         int c = 0;  // list entries (build)
-        BChunk ck;
+        EntryChunk ck;
         uint4 *row = nbr + i;
         auto hit = [&](int jl, int jg, int qx, int qy, int qz) {
             if (MODE == kSlabBuild) {
                 ck.push((uint32_t)(tile ? jl : jg - p0));
                 c++;
-                if ((c & 7) == 0 && c <= maxn) row[(size_t)((c >> 3) - 1) * N] = make_uint4(ck.w[0], ck.w[1], ck.w[2], ck.w[3]);
+                if ((c & 7) == 0 && c <= maxn) row[(size_t)((c >> 3) - 1) * N] = ck.word();
             } else {
                 pair(jg, qx, qy, qz);
             }
@@ -665,7 +653,7 @@ __global__ __launch_bounds__(256) void k_bslab(const int4 *__restrict__ items, c
         if (MODE == kSlabBuild) {
             if ((c & 7) != 0 && c < maxn) {
                 for (int e = c & 7; e < 8; e++) ck.push(0u);
-                row[(size_t)(c >> 3) * N] = make_uint4(ck.w[0], ck.w[1], ck.w[2], ck.w[3]);
+                row[(size_t)(c >> 3) * N] = ck.word();
             }
             cnt[i] = c;
         } else {

@@ -112,7 +112,7 @@ struct Buffers {
     int64_t pvl_cap = 0;
     unsigned long long *pvl_entries = nullptr;
     // Verlet list cells: entries [max][n], segment ends [4][n], per-cube partials
-    uint16_t *vlc_nbr = nullptr, *vlc_seg = nullptr;
+    uint16_t *vlc_nbr = nullptr, *vlc_seg = nullptr;  // entries [n][ld] (ld: capacity rounded to 8), ends [4][n]
     double *vlc_part = nullptr;
     int64_t vlc_cap = 0, vlc_part_cap = 0;
     int32_t vlc_maxn = 0;
@@ -203,6 +203,7 @@ struct ForceArgs {
     const int32_t *cl_ncl;  // device: number of clusters
     const uint16_t *pvl_perm, *pvl_cnt;  // pairwise Verlet lists: sorted orders, prefix lengths
     const uint16_t *vlc_nbr, *vlc_seg;   // Verlet list cells: entries, segment ends per role
+    int vlc_ld;                          // Verlet list cells: entries per particle row (a multiple of 8)
     double *vlc_part;                    // Verlet list cells: per-cube energy partials
     int vlc_blocks;                      // Verlet list cells: partial slots written with energies
     const PairTab *tab;
@@ -297,6 +298,7 @@ void launch_pvl_entries(int n, const int32_t *cs, const int32_t *cell_sorted, co
 
 // vlcells.hip (Verlet list cells traversed with the C08 colouring; the same
 // geometry needs as pairwise lists)
+// maxn: the row capacity and stride of nbr, a multiple of 8
 void launch_vlc_build(int n, const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const double *pos,
                       const Geom &g, uint16_t *nbr, uint16_t *seg, int32_t *cnt, int maxn, int32_t *flags,
                       hipStream_t s);
@@ -304,7 +306,7 @@ void launch_vlc_force(const ForceArgs &a, const Geom &g, hipStream_t s);
 void launch_lc08_force(const ForceArgs &a, const Geom &g, hipStream_t s);
 int vlc_force_blocks(const Geom &g);
 void launch_vlc_rows(int n, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, const uint16_t *nbr,
-                     const uint16_t *seg, int maxr, int32_t *counts, int32_t *rows, hipStream_t s);
+                     int ld, const uint16_t *seg, int maxr, int32_t *counts, int32_t *rows, hipStream_t s);
 
 // clusters.hip
 int cluster_force_blocks();

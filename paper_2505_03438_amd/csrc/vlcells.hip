@@ -17,9 +17,11 @@
 // every pair are summed in the workgroup's LDS (64-bit fixed point, integer
 // atomics) and added to the forces with plain stores.
 //
-// Entries are (cube cell index e_Q << 13) | (offset in cell Q): FP32 pair
-// arithmetic on the fixed-point staging, cutoff decisions in FP64 inside the
-// guard band, as every other kernel.
+// Entries are (cube cell index e_Q << 13) | (offset in cell Q), a row of
+// maxn (a multiple of 8) per particle, written and read as 16-byte chunks of
+// eight: FP32 pair arithmetic on the fixed-point staging, cutoff decisions in
+// FP64 inside the guard band, as every other kernel.
+#include "entry_chunk.h"
 #include "pair.h"
 
 namespace mdlj {
@@ -65,8 +67,8 @@ __device__ __forceinline__ int vlc_cell(const Geom &g, int x, int y, int z)
 
 // Build: thread per particle i (cell P).  For each role r, the base cell is
 // P minus the role cell's offset; the partners are tested against r_c + skin
-// (FP64 inside the guard band); entries append in role order, segment ends
-// in seg[r][i].
+// (FP64 inside the guard band); entries append in role order to the
+// particle's row, eight at a time, segment ends in seg[r][i].
 template <bool ISO>
 __global__ __launch_bounds__(kBlock) void k_vlc_build(int n, const int4 *__restrict__ st,
                                                       const int32_t *__restrict__ cs,
@@ -83,6 +85,8 @@ __global__ __launch_bounds__(kBlock) void k_vlc_build(int n, const int4 *__restr
     int px, py, pz;
     vlc_cell_xyz(cell_sorted[i], g, px, py, pz);
     int c = 0;
+    EntryChunk ck;
+    uint4 *row = (uint4 *)nbr + (size_t)i * (maxn >> 3);
     for (int r = 0; r < 4; r++) {
         int ex, ey, ez;
         vlc_e(vlc_role_cell(r), ex, ey, ez);
@@ -98,12 +102,17 @@ __global__ __launch_bounds__(kBlock) void k_vlc_build(int n, const int4 *__restr
                 staged_delta<ISO>(pi, st[j], g, dx, dy, dz);
                 float r2 = dx * dx + dy * dy + dz * dz;
                 if (within(r2, g.rl2_lo, g.rl2_hi, g.rl2, pos, n, i, j, g)) {
-                    if (c < maxn) nbr[(size_t)c * N + i] = (uint16_t)((eq << 13) | (j - jb));
+                    ck.push((uint32_t)((eq << 13) | (j - jb)));
                     c++;
+                    if ((c & 7) == 0 && c <= maxn) row[(c >> 3) - 1] = ck.word();
                 }
             }
         }
         seg[(size_t)r * N + i] = (uint16_t)(c < maxn ? c : maxn);
+    }
+    if ((c & 7) != 0 && c < maxn) {
+        for (int e = c & 7; e < 8; e++) ck.push(0u);
+        row[c >> 3] = ck.word();
     }
     if (c > maxn) atomicOr(&flags[0], (int)MD_FLAG_LIST_OVERFLOW);
     atomicMax(&flags[2], c);
@@ -130,7 +139,7 @@ struct VlcColour {
 template <int NT, bool ISO, bool ENERGY>
 __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, const int4 *__restrict__ st,
                                                          const int32_t *__restrict__ cs,
-                                                         const uint16_t *__restrict__ nbr,
+                                                         const uint16_t *__restrict__ nbr, int ld,
                                                          const uint16_t *__restrict__ seg,
                                                          const PairTab *__restrict__ tabp, Geom g,
                                                          const double *__restrict__ pos, float *__restrict__ F,
@@ -193,17 +202,18 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
             off = p - nr0 - nr1 - nr2;
         }
     };
-    // entries q0 .. q1 - 1 (at most eight) of the list of particle i:
-    // loaded before any is used, so that their loads overlap; the j sides go
-    // to the accumulators, the i side is returned in f
-    auto walk = [&](int i, const int4 &pi, int q0, int q1, float &fx, float &fy, float &fz) {
-        uint32_t ents[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) ents[u] = q0 + u < q1 ? (uint32_t)nbr[(size_t)(q0 + u) * N + i] : 0u;
+    // chunk c of particle i's row (entries 8c .. 8c + 7, one 16-byte load),
+    // its entries in [e0, e1) taken: the j sides go to the accumulators, the
+    // i side is returned in f
+    const uint4 *rows = (const uint4 *)nbr;
+    const size_t ld8 = (size_t)(ld >> 3);
+    auto walk = [&](int i, const int4 &pi, int c, int e0, int e1, float &fx, float &fy, float &fz) {
+        const uint4 chunk = rows[(size_t)i * ld8 + c];
 #pragma unroll
         for (int u = 0; u < 8; u++) {
-            if (q0 + u >= q1) break;
-            uint32_t ent = ents[u];
+            const int q = 8 * c + u;
+            if (q < e0 || q >= e1) continue;
+            uint32_t ent = chunk_entry(chunk, u);
             int eq = (int)(ent >> 13), oq = (int)(ent & 8191u);
             int lj = base[eq] + oq, j = cst[eq] + oq;
             int4 pj = lds ? wp[lj] : st[j];
@@ -231,10 +241,11 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
         }
     };
     if (lds) {
-        // the role particles' lists dealt to the threads in tasks of up to
-        // eight entries: the long lists (the base cell's particles pair with
-        // eight cells, the others with fewer) take several threads each, so
-        // no thread waits on the longest list of its wavefront
+        // the role particles' segments dealt to the threads in tasks of one
+        // 16-byte chunk of a row (the chunks a segment touches): the long
+        // segments (the base cell's particles pair with eight cells, the
+        // others with fewer) take several threads each, so no thread waits
+        // on the longest one of its wavefront
         for (int p = threadIdx.x; p < Mr; p += kVlcThreads) {
             int r, off;
             role_of(p, r, off);
@@ -242,7 +253,7 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
             int e0 = r == 0 ? 0 : seg[(size_t)(r - 1) * N + i], e1 = seg[(size_t)r * N + i];
             te0[p] = e0;
             te1[p] = e1;
-            tq[p + 1] = (e1 - e0 + 7) >> 3;
+            tq[p + 1] = e1 > e0 ? ((e1 + 7) >> 3) - (e0 >> 3) : 0;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -264,9 +275,9 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
             role_of(lo, r, off);
             int ep = vlc_role_cell(r);
             int li = base[ep] + off, i = cst[ep] + off;
-            int q0 = te0[lo] + 8 * (task - tq[lo]), q1 = min(te1[lo], q0 + 8);
+            const int c = (te0[lo] >> 3) + (task - tq[lo]);
             float fx = 0.f, fy = 0.f, fz = 0.f;
-            walk(i, wp[li], q0, q1, fx, fy, fz);
+            walk(i, wp[li], c, te0[lo], te1[lo], fx, fy, fz);
             atomicAdd(&ax[li], to_fix(fx));
             atomicAdd(&ay[li], to_fix(fy));
             atomicAdd(&az[li], to_fix(fz));
@@ -280,7 +291,8 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
             int4 pi = st[i];
             int e0 = r == 0 ? 0 : seg[(size_t)(r - 1) * N + i], e1 = seg[(size_t)r * N + i];
             float fx = 0.f, fy = 0.f, fz = 0.f;
-            for (int q0 = e0; q0 < e1; q0 += 8) walk(i, pi, q0, min(e1, q0 + 8), fx, fy, fz);
+            if (e1 > e0)
+                for (int c = e0 >> 3; c <= (e1 - 1) >> 3; c++) walk(i, pi, c, e0, e1, fx, fy, fz);
             atomicAdd(&F[i], fx);
             atomicAdd(&F[N + i], fy);
             atomicAdd(&F[2 * N + i], fz);
@@ -491,7 +503,7 @@ __global__ void k_vlc_fold(const double *__restrict__ cube_part, int ncell, int 
 // The lists as global indices (each pair once, in the row of the particle
 // whose cell comes first in its base step), for inspection.
 __global__ void k_vlc_rows(int n, const int32_t *__restrict__ cs, const int32_t *__restrict__ cell_sorted, Geom g,
-                           const uint16_t *__restrict__ nbr, const uint16_t *__restrict__ seg, int maxr,
+                           const uint16_t *__restrict__ nbr, int ld, const uint16_t *__restrict__ seg, int maxr,
                            int32_t *__restrict__ counts, int32_t *__restrict__ rows)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -505,7 +517,7 @@ __global__ void k_vlc_rows(int n, const int32_t *__restrict__ cs, const int32_t 
         vlc_e(vlc_role_cell(r), ex, ey, ez);
         int q1 = seg[(size_t)r * N + i];
         for (int q = q0; q < q1; q++) {
-            uint32_t ent = nbr[(size_t)q * N + i];
+            uint32_t ent = nbr[(size_t)i * ld + q];
             int qx, qy, qz;
             vlc_e((int)(ent >> 13), qx, qy, qz);
             int Q = vlc_cell(g, px - ex + qx, py - ey + qy, pz - ez + qz);
@@ -561,7 +573,7 @@ static void launch_vlc_t(const ForceArgs &a, const Geom &g, hipStream_t s)
         int grid = cols[k].cnt[0] * cols[k].cnt[1] * cols[k].cnt[2];
         if (grid <= 0) continue;
         k_vlc_f32<NT, ISO, EN><<<grid, kVlcThreads, 0, s>>>(cols[k], a.n, a.stage, a.cell_start, a.vlc_nbr,
-                                                            a.vlc_seg, a.tab, g, a.pos, (float *)a.force,
+                                                            a.vlc_ld, a.vlc_seg, a.tab, g, a.pos, (float *)a.force,
                                                             a.vlc_part);
     }
     if (EN) {
@@ -612,10 +624,10 @@ void launch_lc08_force(const ForceArgs &a, const Geom &g, hipStream_t s)
 }
 
 void launch_vlc_rows(int n, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, const uint16_t *nbr,
-                     const uint16_t *seg, int maxr, int32_t *counts, int32_t *rows, hipStream_t s)
+                     int ld, const uint16_t *seg, int maxr, int32_t *counts, int32_t *rows, hipStream_t s)
 {
     if (n <= 0) return;
-    k_vlc_rows<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(n, cs, cell_sorted, g, nbr, seg, maxr, counts, rows);
+    k_vlc_rows<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(n, cs, cell_sorted, g, nbr, ld, seg, maxr, counts, rows);
 }
 
 }  // namespace mdlj
