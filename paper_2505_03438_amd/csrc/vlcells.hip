@@ -149,6 +149,7 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
     __shared__ unsigned long long ax[kVlcMax], ay[kVlcMax], az[kVlcMax];
     __shared__ int cst[8], base[9];
     __shared__ int tq[kVlcMax + 1], te0[kVlcMax], te1[kVlcMax];  // tasks per role particle, segments
+    __shared__ int wsum[2 * kVlcThreads / 64];                     // wavefront totals of the task scan
     __shared__ double sh[4 * kVlcThreads / 64];
     int b = blockIdx.x;
     int ix = b % col.cnt[0], t = b / col.cnt[0];
@@ -246,20 +247,44 @@ __global__ __launch_bounds__(kVlcThreads) void k_vlc_f32(VlcColour col, int n, c
         // segments (the base cell's particles pair with eight cells, the
         // others with fewer) take several threads each, so no thread waits
         // on the longest one of its wavefront
-        for (int p = threadIdx.x; p < Mr; p += kVlcThreads) {
-            int r, off;
-            role_of(p, r, off);
-            int i = cst[vlc_role_cell(r)] + off;
-            int e0 = r == 0 ? 0 : seg[(size_t)(r - 1) * N + i], e1 = seg[(size_t)r * N + i];
-            te0[p] = e0;
-            te1[p] = e1;
-            tq[p + 1] = e1 > e0 ? ((e1 + 7) >> 3) - (e0 >> 3) : 0;
+        // thread t takes role particles t and t + kVlcThreads (Mr <= kVlcMax
+        // = 2 kVlcThreads); the prefix of their task counts is a scan within
+        // each wavefront (shuffles) plus the wavefronts' totals
+        static_assert(kVlcMax == 2 * kVlcThreads, "two role particles per thread");
+        int cnt2[2];
+        for (int h = 0; h < 2; h++) {
+            const int p = threadIdx.x + h * kVlcThreads;
+            cnt2[h] = 0;
+            if (p < Mr) {
+                int r, off;
+                role_of(p, r, off);
+                int i = cst[vlc_role_cell(r)] + off;
+                int e0 = r == 0 ? 0 : seg[(size_t)(r - 1) * N + i], e1 = seg[(size_t)r * N + i];
+                te0[p] = e0;
+                te1[p] = e1;
+                cnt2[h] = e1 > e0 ? ((e1 + 7) >> 3) - (e0 >> 3) : 0;
+            }
+        }
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        constexpr int kWaves = kVlcThreads / 64;
+        int inc[2];
+        for (int h = 0; h < 2; h++) {
+            int x = cnt2[h];
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            inc[h] = x;
+            if (lane == 63) wsum[h * kWaves + wave] = x;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            tq[0] = 0;
-            for (int p = 0; p < Mr; p++) tq[p + 1] += tq[p];
+        for (int h = 0; h < 2; h++) {
+            int before = 0;  // the totals of the wavefronts (and halves) before this one
+            for (int k = 0; k < h * kWaves + wave; k++) before += wsum[k];
+            const int p = threadIdx.x + h * kVlcThreads;
+            tq[p + 1] = before + inc[h];  // inclusive: tq[p + 1] counts the tasks of particles 0 .. p
         }
+        if (threadIdx.x == 0) tq[0] = 0;
         __syncthreads();
         const int T = tq[Mr];
         for (int task = threadIdx.x; task < T; task += kVlcThreads) {
