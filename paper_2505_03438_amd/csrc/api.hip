@@ -1361,6 +1361,15 @@ extern "C" int md_forces_backward(md_handle *h, const double *pos, const int32_t
     a.grad_pos = grad_pos;
     a.gpart = h->b.gpart;
     a.flags = h->b.flags;
+    if (use_window(h) && h->cfg.newton3 == MD_N3L_OFF && h->cfg.container == MD_CONTAINER_VL &&
+        h->cfg.layout == MD_LAYOUT_PACKED && h->lists && !h->truncated) {
+        // the full lists of the current build, over the same windows
+        launch_adjoint_lists(h->b.stage, h->b.cell_start, h->b.cell_sorted, h->g, (int)h->n,
+                             h->b.w_rowb + window_nbands(h->g), h->b.w_blk, h->b.w_nbr, h->b.nbr_count, h->b.tab,
+                             pos, (const float *)grad_force, grad_pos, h->b.gpart, h->b.flags, s);
+        launch_adjoint_finish(h->b.gpart, h->n > 0 ? window_force_blocks() : 0, lj, h->cfg.n_types, grad_lj, s);
+        return MD_OK;
+    }
     if (use_window(h) && h->cfg.newton3 == MD_N3L_OFF) {
         // the blocks of the current cell build were packed for full windows
         launch_adjoint_window(h->b.stage, h->b.cell_start, h->b.cell_sorted, h->g, (int)h->n,

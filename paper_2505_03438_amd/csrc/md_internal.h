@@ -277,10 +277,20 @@ struct AdjointArgs {
 int adjoint_blocks(int n);
 void launch_adjoint(const AdjointArgs &a, const Geom &g, hipStream_t s);
 // The adjoint over the gather windows (FP32; blocks packed for full windows);
-// per-workgroup partials in gpart[window_force_blocks()][8].
+// per-workgroup partials in gpart[window_force_blocks()][8].  only_if_overflow:
+// return at once unless flags[0] holds MD_FLAG_LIST_OVERFLOW.
 void launch_adjoint_window(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, int n,
                            const int32_t *nblk_p, const int4 *blocks, const PairTab *tab, const double *pos,
-                           const float *G, double *grad_pos, double *gpart, int32_t *flags, hipStream_t s);
+                           const float *G, double *grad_pos, double *gpart, int32_t *flags, hipStream_t s,
+                           int only_if_overflow = 0);
+// The same over the full Verlet lists of the window build (packed layout),
+// followed by the window kernel that takes over when flags[0] holds
+// MD_FLAG_LIST_OVERFLOW (the lists may be truncated): exactly one of the two
+// does the work, decided on the device.
+void launch_adjoint_lists(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, int n,
+                          const int32_t *nblk_p, const int4 *blocks, const uint16_t *nbr, const int32_t *cnt,
+                          const PairTab *tab, const double *pos, const float *G, double *grad_pos, double *gpart,
+                          int32_t *flags, hipStream_t s);
 void launch_adjoint_finish(const double *gpart, int nblocks, const double *lj, int nt,
                            double *grad_lj, hipStream_t s);
 

@@ -977,6 +977,60 @@ __global__ __launch_bounds__(256) void k_lcw_f32(const int4 *__restrict__ st, co
 
 // ------------------------------------------------------------------ adjoint
 
+// The pair constants of particle i's type against each partner type (the
+// adjoint picks them per pair by the partner's type alone).
+struct AdjParams {
+    float lo[2], hi[2], eps[2], ieps[2], sig2[2], c144[2];
+    double rc2[2];
+    template <int NT>
+    __device__ __forceinline__ void load(const PairTab *__restrict__ tabp, int ti)
+    {
+        for (int tj = 0; tj < NT; tj++) {
+            int ab = ti * NT + tj;
+            lo[tj] = tabp->rc2_lo[ab];
+            hi[tj] = tabp->rc2_hi[ab];
+            rc2[tj] = tabp->rc2[ab];
+            float e = (float)tabp->eps[ab], sg = (float)tabp->sig[ab];
+            eps[tj] = e;
+            ieps[tj] = 1.0f / e;
+            sig2[tj] = sg * sg;
+            c144[tj] = 144.0f * e / sg;
+        }
+    }
+};
+
+// The adjoint terms of one pair within the cutoff (Sec. 2.1's force f_ij =
+// phi(r) d, differentiated): with dg = g_i - g_j, the position gradient of
+// i gains phi dg + 2 phi'(r^2) (d . dg) d, and the parameter gradients of the
+// partner type (t1: the second type) gain (dphi/d eps, dphi/d sigma) (d . dg).
+// d in fixed-point units (scaled here by uf), sums in FP64.
+__device__ __forceinline__ void adj_pair(float dx, float dy, float dz, float uf, bool t1, float dgx, float dgy,
+                                         float dgz, const AdjParams &pp, double &ax, double &ay, double &az,
+                                         double &ge0, double &ge1, double &gs0, double &gs1)
+{
+    dx *= uf;
+    dy *= uf;
+    dz *= uf;
+    float r2 = dx * dx + dy * dy + dz * dz;
+    float eps = t1 ? pp.eps[1] : pp.eps[0];
+    float ir2 = __builtin_amdgcn_rcpf(r2);
+    float s2 = (t1 ? pp.sig2[1] : pp.sig2[0]) * ir2;
+    float q = s2 * s2 * s2;
+    float phi = 24.0f * eps * ir2 * q * (2.0f * q - 1.0f);
+    float dphi = -48.0f * eps * ir2 * ir2 * q * (7.0f * q - 2.0f);
+    float ddg = dx * dgx + dy * dgy + dz * dgz;
+    float k2 = 2.0f * dphi * ddg;
+    ax += (double)(phi * dgx + k2 * dx);
+    ay += (double)(phi * dgy + k2 * dy);
+    az += (double)(phi * dgz + k2 * dz);
+    double de = (double)(phi * (t1 ? pp.ieps[1] : pp.ieps[0]) * ddg);
+    double ds = (double)((t1 ? pp.c144[1] : pp.c144[0]) * ir2 * q * (4.0f * q - 1.0f) * ddg);
+    ge0 += t1 ? 0.0 : de;
+    ge1 += t1 ? de : 0.0;
+    gs0 += t1 ? 0.0 : ds;
+    gs1 += t1 ? ds : 0.0;
+}
+
 // Adjoint of the forces (the differentiable extension) over the gather
 // windows, FP32 pairs: each thread gathers its particle's row
 //   dL/dx_i = sum_j J_ij (g_i - g_j),  J = phi I + 2 (dphi/dr2) d d^T,
@@ -996,8 +1050,12 @@ __global__ __launch_bounds__(256) void k_adjw_f32(
     const int4 *__restrict__ st, const int32_t *__restrict__ cs, const int32_t *__restrict__ cell_sorted, Geom g,
     int n, const int32_t *__restrict__ nblk_p, int cap, const int4 *__restrict__ blocks,
     const PairTab *__restrict__ tabp, const double *__restrict__ pos, const float *__restrict__ G,
-    double *__restrict__ grad_pos, double *__restrict__ gpart, int32_t *__restrict__ flags)
+    double *__restrict__ grad_pos, double *__restrict__ gpart, int32_t *__restrict__ flags, int only_if_overflow)
 {
+    // behind the list adjoint: the work is this kernel's only when the lists
+    // may be truncated (the overflow flag is set), and then the list kernel
+    // did none (a uniform exit either way)
+    if (only_if_overflow && !(flags[0] & (int)MD_FLAG_LIST_OVERFLOW)) return;
     __shared__ WinEntry<NT> win[kWinMax + 4];  // + the reads past a batch
     __shared__ Window w;
     __shared__ double sh[8][256 / 64];
@@ -1022,19 +1080,10 @@ __global__ __launch_bounds__(256) void k_adjw_f32(
             // the pair parameters for this particle's type against each
             // partner type (picked per pair by the partner's type alone)
             const int ti = NT == 1 ? 0 : pi.w;
-            float lo_[2], hi_[2], eps_[2], ieps_[2], sig2_[2], c144_[2];
-            double rc2_[2];
-            for (int tj = 0; tj < NT; tj++) {
-                int ab = ti * NT + tj;
-                lo_[tj] = tabp->rc2_lo[ab];
-                hi_[tj] = tabp->rc2_hi[ab];
-                rc2_[tj] = tabp->rc2[ab];
-                float e = (float)tabp->eps[ab], sg = (float)tabp->sig[ab];
-                eps_[tj] = e;
-                ieps_[tj] = 1.0f / e;
-                sig2_[tj] = sg * sg;
-                c144_[tj] = 144.0f * e / sg;
-            }
+            AdjParams pp;
+            pp.load<NT>(tabp, ti);
+            const float *lo_ = pp.lo, *hi_ = pp.hi;
+            const double *rc2_ = pp.rc2;
             // parameter terms per partner type (FP64)
             double ge0 = 0.0, ge1 = 0.0, gs0 = 0.0, gs1 = 0.0;
             auto batches = [&](int b, int en) {
@@ -1063,28 +1112,8 @@ __global__ __launch_bounds__(256) void k_adjw_f32(
                         if (!within(r2u, t1 ? lo_[1] : lo_[0], t1 ? hi_[1] : hi_[0], t1 ? rc2_[1] : rc2_[0], pos, n,
                                     i, j, g))
                             continue;
-                        float dgx = gix - gjx, dgy = giy - gjy, dgz = giz - gjz;
-                        dx *= uf;
-                        dy *= uf;
-                        dz *= uf;
-                        float r2 = dx * dx + dy * dy + dz * dz;
-                        float eps = t1 ? eps_[1] : eps_[0];
-                        float ir2 = __builtin_amdgcn_rcpf(r2);
-                        float s2 = (t1 ? sig2_[1] : sig2_[0]) * ir2;
-                        float q = s2 * s2 * s2;
-                        float phi = 24.0f * eps * ir2 * q * (2.0f * q - 1.0f);
-                        float dphi = -48.0f * eps * ir2 * ir2 * q * (7.0f * q - 2.0f);
-                        float ddg = dx * dgx + dy * dgy + dz * dgz;
-                        float k2 = 2.0f * dphi * ddg;
-                        ax += (double)(phi * dgx + k2 * dx);
-                        ay += (double)(phi * dgy + k2 * dy);
-                        az += (double)(phi * dgz + k2 * dz);
-                        double de = (double)(phi * (t1 ? ieps_[1] : ieps_[0]) * ddg);
-                        double ds = (double)((t1 ? c144_[1] : c144_[0]) * ir2 * q * (4.0f * q - 1.0f) * ddg);
-                        ge0 += t1 ? 0.0 : de;
-                        ge1 += t1 ? de : 0.0;
-                        gs0 += t1 ? 0.0 : ds;
-                        gs1 += t1 ? ds : 0.0;
+                        adj_pair(dx, dy, dz, uf, t1, gix - gjx, giy - gjy, giz - gjz, pp, ax, ay, az, ge0, ge1, gs0,
+                                 gs1);
                     }
                 }
             };
@@ -1119,26 +1148,155 @@ __global__ __launch_bounds__(256) void k_adjw_f32(
     }
 }
 
+// The adjoint over the gather Verlet lists (packed window layout): the same
+// blocks, windows and lists as the list force, each particle walking its own
+// list in chunks of eight, so that no candidate outside the list radius is
+// tested.  The window's fourth word holds the position's global index (with
+// two types, times two plus the type): the partner's g is read from global
+// memory by that index.  Terms and sums as k_adjw_f32.
+template <int NT, bool ISO>
+__global__ __launch_bounds__(256) void k_adjvl_f32(
+    const int4 *__restrict__ st, const int32_t *__restrict__ cs, const int32_t *__restrict__ cell_sorted, Geom g,
+    int n, const int32_t *__restrict__ nblk_p, int cap, const int4 *__restrict__ blocks,
+    const uint16_t *__restrict__ nbr, const int32_t *__restrict__ cnt, const PairTab *__restrict__ tabp,
+    const double *__restrict__ pos, const float *__restrict__ G, double *__restrict__ grad_pos,
+    double *__restrict__ gpart, int32_t *__restrict__ flags)
+{
+    // lists that may be truncated (a build overflowed them) are left to the
+    // stencil kernel launched after this one
+    if (flags[0] & (int)MD_FLAG_LIST_OVERFLOW) return;
+    constexpr int kEsz = (int)sizeof(WinEntry<NT>);  // the lists' entries are window positions times this
+    __shared__ int4 win[kWinMax + 1];                // + the far entry
+    __shared__ Window w;
+    __shared__ double sh[8][256 / 64];
+    const float uf = (float)(g.L[0] / 4294967296.0);
+    double gp[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // eps_ab[4], sig_ab[4]
+    size_t N = (size_t)n;
+    for (BlockIter it(min(*nblk_p, cap)); it.blk < it.end; it.blk += it.stride) {
+        const int4 blk = blocks[it.blk];
+        __syncthreads();
+        make_window<false, false>(g, cs, blk, w);
+        if (w.W > kWinMax || w.npart > 256) {  // never made by the packer
+            if (threadIdx.x == 0) atomicOr(&flags[3], 2);
+            continue;
+        }
+        {
+            int k = 0;
+            for (int p = threadIdx.x; p < w.W; p += blockDim.x) {
+                k = piece_from(w, k, p);
+                const int j = w.pc_start[k] + (p - w.pc_win[k]);
+                int4 q = st[j];
+                q.w = NT == 1 ? j : 2 * j + q.w;
+                win[p] = q;
+            }
+            if (threadIdx.x == 0) win[kWinMax] = far_entry(g, blk);
+        }
+        __syncthreads();
+        int i, k, x;
+        if (!my_particle(g, w, cell_sorted, i, k, x)) continue;
+        const int4 pi = st[i];
+        const float gix = G[i], giy = G[N + i], giz = G[2 * N + i];
+        const int ti = NT == 1 ? 0 : pi.w;
+        AdjParams pp;
+        pp.load<NT>(tabp, ti);
+        double ax = 0.0, ay = 0.0, az = 0.0, ge0 = 0.0, ge1 = 0.0, gs0 = 0.0, gs1 = 0.0;
+        const int nch = (cnt[i] + 7) >> 3;
+        const uint4 *row = (const uint4 *)nbr + i;
+        uint4 cur = *row;
+        for (int ch = 0; ch < nch; ch++) {
+            row += N;
+            const uint4 nxt = *row;  // the list has one chunk row more than it fills
+            const uint32_t off[8] = {cur.x & 0xffff, cur.x >> 16, cur.y & 0xffff, cur.y >> 16,
+                                     cur.z & 0xffff, cur.z >> 16, cur.w & 0xffff, cur.w >> 16};
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int4 e = win[off[u] / kEsz];
+                const bool t1 = NT > 1 && (e.w & 1);
+                const int j = NT == 1 ? e.w : (e.w >> 1);
+                float dx, dy, dz;
+                staged_delta<ISO>(pi, e, g, dx, dy, dz);
+                const float r2u = dx * dx + dy * dy + dz * dz;
+                if (!within(r2u, t1 ? pp.lo[1] : pp.lo[0], t1 ? pp.hi[1] : pp.hi[0], t1 ? pp.rc2[1] : pp.rc2[0],
+                            pos, n, i, j, g))
+                    continue;
+                adj_pair(dx, dy, dz, uf, t1, gix - G[j], giy - G[N + j], giz - G[2 * N + j], pp, ax, ay, az, ge0,
+                         ge1, gs0, gs1);
+            }
+            cur = nxt;
+        }
+        gp[ti * NT] += ge0;
+        gp[4 + ti * NT] += gs0;
+        if (NT > 1) {
+            gp[ti * NT + 1] += ge1;
+            gp[4 + ti * NT + 1] += gs1;
+        }
+        grad_pos[i] = ax;
+        grad_pos[N + i] = ay;
+        grad_pos[2 * N + i] = az;
+    }
+    // the workgroup's parameter sums, fixed order
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+        for (int off = 32; off > 0; off >>= 1) gp[q] += __shfl_down(gp[q], off, 64);
+    __syncthreads();
+    int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 8; q++) sh[q][wv] = gp[q];
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double t = 0.0;
+        for (int v = 0; v < 256 / 64; v++) t += sh[threadIdx.x][v];
+        gpart[blockIdx.x * 8 + threadIdx.x] = t;
+    }
+}
+
+void launch_adjoint_lists(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, int n,
+                          const int32_t *nblk_p, const int4 *blocks, const uint16_t *nbr, const int32_t *cnt,
+                          const PairTab *tab, const double *pos, const float *G, double *grad_pos, double *gpart,
+                          int32_t *flags, hipStream_t s)
+{
+    if (n <= 0) return;
+    int cap = (int)window_block_cap(n, g);
+    if (g.nt == 1) {
+        if (g.iso)
+            k_adjvl_f32<1, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, nbr, cnt,
+                                                           tab, pos, G, grad_pos, gpart, flags);
+        else
+            k_adjvl_f32<1, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, nbr, cnt,
+                                                            tab, pos, G, grad_pos, gpart, flags);
+    } else {
+        if (g.iso)
+            k_adjvl_f32<2, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, nbr, cnt,
+                                                           tab, pos, G, grad_pos, gpart, flags);
+        else
+            k_adjvl_f32<2, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, nbr, cnt,
+                                                            tab, pos, G, grad_pos, gpart, flags);
+    }
+    // the stencil kernel does the work instead when the lists overflowed
+    launch_adjoint_window(st, cs, cell_sorted, g, n, nblk_p, blocks, tab, pos, G, grad_pos, gpart, flags, s, 1);
+}
+
 void launch_adjoint_window(const int4 *st, const int32_t *cs, const int32_t *cell_sorted, const Geom &g, int n,
                            const int32_t *nblk_p, const int4 *blocks, const PairTab *tab, const double *pos,
-                           const float *G, double *grad_pos, double *gpart, int32_t *flags, hipStream_t s)
+                           const float *G, double *grad_pos, double *gpart, int32_t *flags, hipStream_t s,
+                           int only_if_overflow)
 {
     if (n <= 0) return;
     int cap = (int)window_block_cap(n, g);
     if (g.nt == 1) {
         if (g.iso)
             k_adjw_f32<1, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, tab, pos,
-                                                          G, grad_pos, gpart, flags);
+                                                          G, grad_pos, gpart, flags, only_if_overflow);
         else
             k_adjw_f32<1, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, tab, pos,
-                                                           G, grad_pos, gpart, flags);
+                                                           G, grad_pos, gpart, flags, only_if_overflow);
     } else {
         if (g.iso)
             k_adjw_f32<2, true><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, tab, pos,
-                                                          G, grad_pos, gpart, flags);
+                                                          G, grad_pos, gpart, flags, only_if_overflow);
         else
             k_adjw_f32<2, false><<<kWinGrid, 256, 0, s>>>(st, cs, cell_sorted, g, n, nblk_p, cap, blocks, tab, pos,
-                                                           G, grad_pos, gpart, flags);
+                                                           G, grad_pos, gpart, flags, only_if_overflow);
     }
 }
 

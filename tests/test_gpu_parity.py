@@ -638,8 +638,9 @@ def test_live_stats(orc):
                          ids=["fp64", "fp32-lc", "fp32-vl", "fp32-lc-n3l", "fp32-cl"])
 def test_adjoint_matches_oracle(orc, prec, cont):
     """dL/dx and dL/d(eps, sigma) of the force-matching loss against the
-    oracle: FP32 gather structures run the windowed adjoint, the others (and
-    FP64) the per-particle kernel."""
+    oracle: FP32 gather structures run the windowed adjoint (over the Verlet
+    lists for Verlet lists, over the cut stencil for linked cells), the others
+    (and FP64) the per-particle kernel."""
     import torch
     d = W.binary_mixture(ncell=6, seed=11)
     pos, box, types = d["pos"], d["box"], d["types"]
@@ -666,6 +667,37 @@ def test_adjoint_matches_oracle(orc, prec, cont):
     tol_x, tol_t = (1e-12, 1e-12) if prec == 1 else (1e-4, 1e-5)
     assert rel_l2(s.by_id(gpos), gx) <= tol_x
     assert rel_l2(glj.cpu().numpy(), gt) <= tol_t
+
+
+def test_adjoint_over_truncated_lists(orc):
+    """Verlet lists built with too small a row (max_neighbors 8, so that the
+    build overflows and sets MD_FLAG_LIST_OVERFLOW): the adjoint does not walk
+    the truncated lists but the stencil, decided on the device, and still
+    matches the oracle.  The loss gradient g is the oracle's (the forward pass
+    over the truncated lists is not what is tested here)."""
+    import torch
+    d = W.binary_mixture(ncell=6, seed=11)
+    pos, box, types = d["pos"], d["box"], d["types"]
+    n = pos.shape[1]
+    theta0 = np.array(d["eps"] + d["sig"])
+    e0, s0 = orc.mix(d["eps"], d["sig"])
+    rc2 = (2.5 * s0) ** 2
+    _, target, _, _ = orc.force_matching(pos, box, types, theta0, rc2, np.zeros((3, n)))
+    theta = W.perturb_params(theta0, seed=2)
+    L, F, gx, gt = orc.force_matching(pos, box, types, theta, rc2, target)
+    cfg = make_config(n, box, container=1, precision=0, n_types=2, rc2=rc2, max_neighbors=8)
+    s = DeviceSystem(cfg, pos, types=types, eps=list(theta[:2]), sig=list(theta[2:]))
+    s.build()
+    torch.cuda.synchronize()
+    ids = s.ids_np()
+    g = torch.tensor((2.0 / (3 * n)) * (F - target)[:, ids], device="cuda").to(s.h.real).contiguous()
+    gpos = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+    glj = torch.zeros(4, dtype=torch.float64, device="cuda")
+    M.md_forces_backward(s.h, s.pos, s.type, s.lj, g, gpos, glj)
+    torch.cuda.synchronize()
+    assert M.md_status(s.h) & M.MD_FLAG_LIST_OVERFLOW
+    assert rel_l2(s.by_id(gpos), gx) <= 1e-4
+    assert rel_l2(glj.cpu().numpy(), gt) <= 1e-5
 
 
 @pytest.mark.parametrize("cont", [(0, 0, 1.0), (1, 0, 1.0)], ids=["lc", "vl"])
