@@ -151,14 +151,16 @@ __global__ void k_bstage(int n, const double *__restrict__ pos, const int32_t *_
     stage[k] = make_int4((int)bquant(pos[k], S), (int)bquant(pos[N + k], S), (int)bquant(pos[2 * N + k], S), type[k]);
 }
 
-// Linked-cell gather force, one thread per particle, its system's geometry.
-// Writes per-particle energy partials when pe != nullptr.
-template <typename real>
-__global__ __launch_bounds__(256) void k_bforce(int n, const int4 *__restrict__ st, const double *__restrict__ pos,
-                                                const int32_t *__restrict__ sys_of, const BSys *__restrict__ sys,
-                                                const int32_t *__restrict__ cs, const int32_t *__restrict__ cell_sorted,
-                                                real *__restrict__ F, double *__restrict__ pe)
+// FP64 linked-cell gather force, one thread per particle, its system's
+// geometry (the FP32 passes are the work-item kernels below).  Writes
+// per-particle energy partials when pe != nullptr.
+__global__ __launch_bounds__(256) void k_bforce_f64(int n, const double *__restrict__ pos,
+                                                    const int32_t *__restrict__ sys_of, const BSys *__restrict__ sys,
+                                                    const int32_t *__restrict__ cs,
+                                                    const int32_t *__restrict__ cell_sorted, double *__restrict__ F,
+                                                    double *__restrict__ pe)
 {
+#pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     size_t N = (size_t)n;
@@ -167,81 +169,34 @@ __global__ __launch_bounds__(256) void k_bforce(int n, const int4 *__restrict__ 
     int local = cell_sorted[i] - b.cell_base;
     int cx = local % nc, cy = (local / nc) % nc, cz = local / (nc * nc);
     double eu = 0.0, ew = 0.0, np = 0.0;
-    real fx = 0, fy = 0, fz = 0;
-    if (sizeof(real) == 4) {
-        int4 pi = st[i];
-        float lo = b.lo, hi = b.hi, sig2 = b.sig2, eps24 = b.eps24;
-        float eus = 0.f, ews = 0.f;
-        for (int a = 0; a < nofs; a++) {
-            int zz = cz + b.ofs[a];
-            zz = zz >= nc ? zz - nc : zz;
-            for (int bb = 0; bb < nofs; bb++) {
-                int yy = cy + b.ofs[bb];
-                yy = yy >= nc ? yy - nc : yy;
-                int row = b.cell_base + (zz * nc + yy) * nc;
-                for (int e = 0; e < nofs; e++) {
-                    int xx = cx + b.ofs[e];
-                    xx = xx >= nc ? xx - nc : xx;
-                    int jb = cs[row + xx], je = cs[row + xx + 1];
-                    for (int j = jb; j < je; j++) {
-                        if (j == i) continue;
-                        int4 pj = st[j];
-                        float dx, dy, dz;
-                        dx = (float)(int)((uint32_t)pi.x - (uint32_t)pj.x);
-                        dy = (float)(int)((uint32_t)pi.y - (uint32_t)pj.y);
-                        dz = (float)(int)((uint32_t)pi.z - (uint32_t)pj.z);
-                        float r2 = dx * dx + dy * dy + dz * dz;
-                        bool in = r2 < lo;
-                        if (r2 >= lo && r2 < hi) in = exact_r2(pos, n, i, j, b.L, b.L, b.L) < b.rc2;
-                        float ir2 = __builtin_amdgcn_rcpf(r2);
-                        float s2 = sig2 * ir2;
-                        float q = s2 * s2 * s2;
-                        float aa = q * (2.0f * q - 1.0f);
-                        float phi = in ? eps24 * ir2 * aa : 0.0f;
-                        fx += phi * dx;
-                        fy += phi * dy;
-                        fz += phi * dz;
-                        if (pe) {
-                            eus += in ? b.eps4 * q * (q - 1.0f) : 0.0f;
-                            ews += in ? b.eps24w * aa : 0.0f;
-                            np += in ? 1.0 : 0.0;
-                        }
-                    }
-                }
-            }
-        }
-        eu = eus;
-        ew = ews;
-    } else {
-#pragma clang fp contract(off)
-        double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
-        for (int a = 0; a < nofs; a++) {
-            int zz = cz + b.ofs[a];
-            zz = zz >= nc ? zz - nc : zz;
-            for (int bb = 0; bb < nofs; bb++) {
-                int yy = cy + b.ofs[bb];
-                yy = yy >= nc ? yy - nc : yy;
-                int row = b.cell_base + (zz * nc + yy) * nc;
-                for (int e = 0; e < nofs; e++) {
-                    int xx = cx + b.ofs[e];
-                    xx = xx >= nc ? xx - nc : xx;
-                    int jb = cs[row + xx], je = cs[row + xx + 1];
-                    for (int j = jb; j < je; j++) {
-                        if (j == i) continue;
-                        double dx = min_image(xi - pos[j], b.L);
-                        double dy = min_image(yi - pos[N + j], b.L);
-                        double dz = min_image(zi - pos[2 * N + j], b.L);
-                        double r2 = dx * dx + dy * dy + dz * dz;
-                        if (!(r2 < b.rc2)) continue;
-                        double phi, u;
-                        lj_f64(r2, b.eps, b.sig, phi, u);
-                        fx += (real)(phi * dx);
-                        fy += (real)(phi * dy);
-                        fz += (real)(phi * dz);
-                        eu += u;
-                        ew += phi * r2;
-                        np += 1.0;
-                    }
+    double fx = 0, fy = 0, fz = 0;
+    double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
+    for (int a = 0; a < nofs; a++) {
+        int zz = cz + b.ofs[a];
+        zz = zz >= nc ? zz - nc : zz;
+        for (int bb = 0; bb < nofs; bb++) {
+            int yy = cy + b.ofs[bb];
+            yy = yy >= nc ? yy - nc : yy;
+            int row = b.cell_base + (zz * nc + yy) * nc;
+            for (int e = 0; e < nofs; e++) {
+                int xx = cx + b.ofs[e];
+                xx = xx >= nc ? xx - nc : xx;
+                int jb = cs[row + xx], je = cs[row + xx + 1];
+                for (int j = jb; j < je; j++) {
+                    if (j == i) continue;
+                    double dx = min_image(xi - pos[j], b.L);
+                    double dy = min_image(yi - pos[N + j], b.L);
+                    double dz = min_image(zi - pos[2 * N + j], b.L);
+                    double r2 = dx * dx + dy * dy + dz * dz;
+                    if (!(r2 < b.rc2)) continue;
+                    double phi, u;
+                    lj_f64(r2, b.eps, b.sig, phi, u);
+                    fx += phi * dx;
+                    fy += phi * dy;
+                    fz += phi * dz;
+                    eu += u;
+                    ew += phi * r2;
+                    np += 1.0;
                 }
             }
         }
@@ -1032,8 +987,8 @@ static void batch_forces(md_batch *b, const double *pos, void *force, bool energ
     if (n <= 0) return;
     if (!st) st = b->stage;
     if (b->cfg.precision == MD_FP64)
-        k_bforce<double><<<bblocks(n), 256, 0, s>>>(n, st, pos, b->sys_of, b->sys, b->cell_start,
-                                                    b->cell_sorted, (double *)force, energy ? b->pe : nullptr);
+        k_bforce_f64<<<bblocks(n), 256, 0, s>>>(n, pos, b->sys_of, b->sys, b->cell_start, b->cell_sorted,
+                                                 (double *)force, energy ? b->pe : nullptr);
     else {
         const BFuse f = fu ? *fu : BFuse{};
         auto go = [&](auto kern) {
