@@ -79,6 +79,37 @@ def test_batch_counters_null(M):
     assert M.lib().md_batch_get_counters(None, None) == M.MD_ERR_INVALID_ARG
 
 
+def test_batch_create_rejects_unsupported_configs(M):
+    """md_batch_create checks its configuration before it touches a device:
+    linked cells or (FP32, systems of at most 65536 particles) Verlet lists,
+    gather-only; the reason is in md_last_error."""
+    import ctypes
+    import numpy as np
+
+    def rc_of(cfg, offs, boxes):
+        b = ctypes.c_void_p()
+        offs = np.ascontiguousarray(offs, dtype=np.int64)
+        boxes = np.ascontiguousarray(boxes, dtype=np.float64)
+        rc = M.lib().md_batch_create(ctypes.byref(cfg), len(offs) - 1, ctypes.c_void_p(offs.ctypes.data),
+                                     ctypes.c_void_p(boxes.ctypes.data), ctypes.byref(b))
+        if rc == 0:
+            M.lib().md_batch_destroy(b)
+        return rc
+
+    offs, boxes = [0, 500, 900], [[9.0] * 3, [8.0] * 3]
+    for container, newton3, prec, what in ((M.MD_CONTAINER_CL, 0, M.MD_FP32, "linked cells or Verlet lists"),
+                                          (M.MD_CONTAINER_LC, 1, M.MD_FP32, "gather-only"),
+                                          (M.MD_CONTAINER_VL, 0, M.MD_FP64, "FP32")):
+        c = M.config_default(900, 9.0)
+        c.container, c.newton3, c.precision = container, newton3, prec
+        assert rc_of(c, offs, boxes) == M.MD_ERR_INVALID_ARG
+        assert what in M.md_last_error()
+    c = M.config_default(70000, 40.0)
+    c.container, c.precision = M.MD_CONTAINER_VL, M.MD_FP32
+    assert rc_of(c, [0, 70000], [[40.0] * 3]) == M.MD_ERR_INVALID_ARG
+    assert "65536" in M.md_last_error()
+
+
 @pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
                     reason="a device may be present")
 def test_create_without_device_fails_cleanly(M):
