@@ -270,3 +270,46 @@ def test_batched_lists_rejected_outside_their_range(M):
     cfg = make_config(n, boxes[0], container=2, precision=0)
     with pytest.raises(RuntimeError):
         M.md_batch_create(cfg, offs, boxes)
+
+
+@pytest.mark.parametrize("prec,container", [(1, 0), (0, 0), (0, 1)], ids=["fp64", "fp32", "fp32-vl"])
+def test_batched_empty_and_tiny_systems(orc, M, prec, container):
+    """A batch holding an empty system (offsets equal) and a system of two
+    particles 1.1 apart (a 6-sigma box: two cells per dimension, every cell in
+    every stencil) beside an ordinary one: forces, energies and pair counts of
+    every system, and ten steps (graph-captured after the first interval),
+    against the oracle."""
+    import torch
+    big = W.batched_systems(n_sys=1, n_min=500, n_max=500, seed=71)[0]
+    pair = dict(pos=np.array([[1.0, 2.1], [3.0, 3.0], [3.0, 3.0]]), vel=np.array([[0.3, -0.2], [0.0, 0.1],
+                [0.0, 0.0]], dtype=np.float32), box=np.array([6.0, 6.0, 6.0]))
+    empty = dict(pos=np.zeros((3, 0)), vel=np.zeros((3, 0), np.float32), box=np.array([7.0, 7.0, 7.0]))
+    syss = [big, empty, pair]
+    d = Dev(M, syss, prec, R=3, container=container)
+    assert list(d.offs) == [0, 500, 500, 502]
+    M.md_batch_build_cells(d.b, d.pos, d.vel, d.force, d.type, d.ids)
+    out = torch.zeros(4 * len(syss), dtype=torch.float64, device="cuda")
+    M.md_batch_compute_forces(d.b, d.pos, d.type, d.lj, d.force, out)
+    torch.cuda.synchronize()
+    F = d.by_id(d.force)
+    out = out.cpu().numpy().reshape(-1, 4)
+    assert out[1, 2] == 0 and out[1, 0] == 0
+    for s in (0, 2):
+        sy = syss[s]
+        F0, U0, W0, P0 = orc.forces(sy["pos"], sy["box"], orc.single())
+        r = slice(d.offs[s], d.offs[s + 1])
+        assert int(out[s, 2]) == P0, s
+        assert_forces(F[:, r], F0, prec == 1, what=s)
+        assert abs(out[s, 0] - U0) <= (1e-12 if prec == 1 else 1e-6) * abs(U0), s
+    M.md_batch_step(d.b, d.pos, d.vel, d.force, d.type, d.ids, d.im, d.lj, 0.005, 10, use_graph=True)
+    torch.cuda.synchronize()
+    X = d.by_id(d.pos)
+    tol = 1e-9 if prec == 1 else 1e-6
+    for s in (0, 2):
+        sy = syss[s]
+        p1, _, _, _ = orc.velocity_verlet(sy["pos"], sy["vel"].astype(np.float64), sy["box"], orc.single(), 0.005,
+                                          10)
+        r = slice(d.offs[s], d.offs[s + 1])
+        dx = X[:, r] - p1
+        dx -= sy["box"][0] * np.rint(dx / sy["box"][0])
+        assert np.abs(dx).max() < tol, s
