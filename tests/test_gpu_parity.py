@@ -590,13 +590,16 @@ def test_skin_violation_replay_fp32(orc):
         assert np.array_equal(log[:20, 3], log0[:20, 3]), cont
 
 
-@pytest.mark.parametrize("cont", [(1, 0, 20, 78), (2, 0, 4, 20)], ids=["vl", "cl"])
+@pytest.mark.parametrize("cont", [(1, 0, 20, 78), (2, 0, 4, 20), (4, 1, 13, 39)], ids=["vl", "cl", "vlc"])
 def test_list_overflow_grows(orc, cont):
+    """Lists built with too small a row overflow; md_step grows the row (the
+    list cells' row stride, a multiple of 8, with it), rebuilds and keeps the
+    trajectory on the oracle's."""
     import torch
     d = W.plain_fcc_864()
     n = 864
-    prec = 0 if cont[0] == 2 else 1
-    cfg = make_config(n, d["box"], container=cont[0], precision=prec, max_neighbors=cont[2])
+    prec = 0 if cont[0] in (2, 4) else 1
+    cfg = make_config(n, d["box"], container=cont[0], newton3=cont[1], precision=prec, max_neighbors=cont[2])
     s = DeviceSystem(cfg, d["pos"], d["vel"])
     s.build()
     s.forces(energy=False)  # truncated lists give wrong forces, and a flag
