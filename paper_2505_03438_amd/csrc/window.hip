@@ -1485,11 +1485,15 @@ __global__ __launch_bounds__(256) void k_vlw_build(const int4 *__restrict__ st, 
                             mask ^= 1u << h;
                     }
                 }
-                // entries are window positions times esz (< 2^16: a 24-bit product)
+                // entries are window positions times esz (< 2^16): bit 31 - z
+                // is position base + m - 32 + z, its entry z0 + z esz (mod
+                // 2^32), with a 24-bit product per entry
+                const unsigned esz8 = (unsigned)esz & 0xffu;
+                const unsigned z0 = (unsigned)(base + m - 32) * (unsigned)esz;
                 while (mask) {
-                    int h = 31 - __builtin_clz(mask);
-                    mask ^= 1u << h;
-                    list_append(__umul24((unsigned)(base + m - 1 - h), (unsigned)esz), c, ck, row, N, maxn);
+                    unsigned z = (unsigned)__builtin_clz(mask);
+                    mask ^= 0x80000000u >> z;
+                    list_append(z0 + z * esz8, c, ck, row, N, maxn);
                 }
             }
         };
